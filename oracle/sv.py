@@ -1,0 +1,235 @@
+"""State-vector oracle in complex128 (test infrastructure only; never on the product path).
+
+* Evolution follows the paper's state-vector mode (Sec. 3.1, the equation psi = U psi_0):
+  every gate is a small matrix applied to the qubit axes it acts on, in program order.
+  The register is held as an ndarray of shape (2,)*n whose axis q is qubit q, so the
+  flattened state has qubit 0 as the most significant bit (Sec. 5.1, qubits counted
+  from 0 with the zeroth on the left).
+* The default initial state is |0...0>; a user state of length 2**n is used as given
+  (Sec. 3.1 and its initial-state listing). A length mismatch raises.
+* Expectation values are the exact quadratic form of the VQC cost in Sec. 4
+  (f = <0|U^dag O U|0>), evaluated for sums of Pauli-Z strings.
+* Gradients: the parameter-shift rule of Sec. 4.2 (its equation for k[f(mu+s)-f(mu-s)])
+  with s = pi/2, k = 1/2 for every gate here (generators with eigenvalues +-1/2), applied
+  to each parameter occurrence and summed with its scale factor; central finite
+  differences as an independent cross-check (the paper's difference quotient, taken
+  centrally).
+
+Gate matrices are the textbook ones. RY is the matrix the paper prints in Sec. 3.2.1;
+CNOT has the block form printed there (identity block for control 0, X block for
+control 1). U3 follows OpenQASM 2; Rot(phi, theta, omega) = RZ(omega) RY(theta) RZ(phi).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from paper_2301_05451_amd import workloads as W
+
+_SQ2 = 1.0 / math.sqrt(2.0)
+
+
+def rx(t):
+    c, s = math.cos(t / 2), math.sin(t / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+
+
+def ry(t):
+    c, s = math.cos(t / 2), math.sin(t / 2)
+    return np.array([[c, -s], [s, c]], dtype=np.complex128)
+
+
+def rz(t):
+    return np.array([[np.exp(-0.5j * t), 0], [0, np.exp(0.5j * t)]], dtype=np.complex128)
+
+
+def u3(theta, phi, lam):
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array(
+        [[c, -np.exp(1j * lam) * s], [np.exp(1j * phi) * s, np.exp(1j * (phi + lam)) * c]],
+        dtype=np.complex128,
+    )
+
+
+def rot(phi, theta, omega):
+    return rz(omega) @ ry(theta) @ rz(phi)
+
+
+def gate_matrix(op, angles):
+    """2x2 (one qubit) or 4x4 (two qubits, first listed qubit = high index bit)."""
+    if op == W.H:
+        return np.array([[_SQ2, _SQ2], [_SQ2, -_SQ2]], dtype=np.complex128)
+    if op == W.X:
+        return np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    if op == W.Y:
+        return np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    if op == W.Z:
+        return np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    if op == W.RX:
+        return rx(angles[0])
+    if op == W.RY:
+        return ry(angles[0])
+    if op == W.RZ:
+        return rz(angles[0])
+    if op == W.U3:
+        return u3(*angles[:3])
+    if op == W.ROT:
+        return rot(*angles[:3])
+    if op == W.CNOT:
+        m = np.eye(4, dtype=np.complex128)
+        m[2:, 2:] = [[0, 1], [1, 0]]
+        return m
+    if op == W.CZ:
+        return np.diag([1, 1, 1, -1]).astype(np.complex128)
+    if op == W.RZZ:
+        g = angles[0]
+        e, f = np.exp(-0.5j * g), np.exp(0.5j * g)
+        return np.diag([e, f, f, e]).astype(np.complex128)
+    raise ValueError(f"unknown op {op}")
+
+
+def gate_angles(gate, params, shift=None):
+    """Angles of one gate record; ``shift`` = (slot, delta) adds delta to one angle."""
+    na = W.N_ANGLES[int(gate["op"])]
+    out = []
+    for j in range(na):
+        pi = int(gate["pidx"][j])
+        a = float(gate["pscale"][j]) * float(params[pi]) if pi >= 0 else float(gate["pscale"][j])
+        if shift is not None and shift[0] == j:
+            a += shift[1]
+        out.append(a)
+    return out
+
+
+def gate_qubits(gate):
+    return [int(q) for q in gate["q"][: W.N_QUBITS[int(gate["op"])]]]
+
+
+def apply_matrix(psi, U, qubits):
+    """psi has shape (2,)*n; contract U's input legs with the listed qubit axes."""
+    k = len(qubits)
+    Ut = U.reshape((2,) * (2 * k))
+    out = np.tensordot(Ut, psi, axes=(list(range(k, 2 * k)), list(qubits)))
+    return np.moveaxis(out, list(range(k)), list(qubits))
+
+
+def initial_state(n, init=None):
+    if init is None:
+        psi = np.zeros(2**n, dtype=np.complex128)
+        psi[0] = 1.0
+        return psi
+    v = np.asarray(init, dtype=np.complex128).reshape(-1)
+    if v.shape[0] != 2**n:
+        raise ValueError(f"initial state has length {v.shape[0]}, expected 2**{n}")
+    return v.copy()
+
+
+def run(n, gates, params, init=None, shift=None):
+    """Final state (flat, length 2**n). ``shift`` = (gate index, slot, delta)."""
+    psi = initial_state(n, init).reshape((2,) * n) if n > 0 else initial_state(n, init)
+    for k, g in enumerate(gates):
+        sh = (shift[1], shift[2]) if (shift is not None and shift[0] == k) else None
+        U = gate_matrix(int(g["op"]), gate_angles(g, params, sh))
+        psi = apply_matrix(psi, U, gate_qubits(g))
+    return psi.reshape(-1)
+
+
+def zstring_diag(n, qubits):
+    """Diagonal of prod_{q in qubits} Z_q as a float vector of length 2**n."""
+    d = np.ones((2,) * n)
+    for q in qubits:
+        shape = [1] * n
+        shape[q] = 2
+        d = d * np.array([1.0, -1.0]).reshape(shape)
+    return d.reshape(-1)
+
+
+def mask_qubits(mask):
+    m = int(mask)
+    return [q for q in range(64) if (m >> q) & 1]
+
+
+def expvals(psi, n, terms, n_obs):
+    """Real expectation values <O_o> = sum over terms of coeff * <Z_S>."""
+    prob = np.abs(psi) ** 2
+    out = np.zeros(n_obs)
+    for t in terms:
+        out[int(t["obs"])] += float(t["coeff"]) * float(np.dot(prob, zstring_diag(n, mask_qubits(t["mask"]))))
+    return out
+
+
+def expval_hermitian(psi, O):
+    """Re(psi^dag O psi) for a general Hermitian matrix O."""
+    return float(np.real(np.vdot(psi, O @ psi)))
+
+
+def circuit_f(c: W.Circuit, params=None, shift=None, init=None):
+    p = c.params if params is None else params
+    return expvals(run(c.n, c.gates, p, init, shift), c.n, c.terms, c.n_obs)
+
+
+# ---- brute force -------------------------------------------------------------------
+
+def embed(n, U, qubits):
+    """Full 2**n x 2**n matrix of U acting on ``qubits`` (textbook kron construction)."""
+    k = len(qubits)
+    if k == 1:
+        q = qubits[0]
+        return np.kron(np.kron(np.eye(2**q), U), np.eye(2 ** (n - q - 1)))
+    # two qubits: expand U = sum_{ab,cd} U[ab,cd] |ab><cd| as a sum of kron products
+    full = np.zeros((2**n, 2**n), dtype=np.complex128)
+    qa, qb = qubits
+    for r in range(4):
+        for s in range(4):
+            if U[r, s] == 0:
+                continue
+            ops = [np.eye(2, dtype=np.complex128)] * n
+            ea = np.zeros((2, 2)); ea[r >> 1, s >> 1] = 1
+            eb = np.zeros((2, 2)); eb[r & 1, s & 1] = 1
+            ops = list(ops)
+            ops[qa] = ea
+            ops[qb] = eb
+            m = ops[0]
+            for o in ops[1:]:
+                m = np.kron(m, o)
+            full += U[r, s] * m
+    return full
+
+
+def full_unitary(n, gates, params):
+    Uf = np.eye(2**n, dtype=np.complex128)
+    for g in gates:
+        U = gate_matrix(int(g["op"]), gate_angles(g, params))
+        Uf = embed(n, U, gate_qubits(g)) @ Uf
+    return Uf
+
+
+# ---- gradients ---------------------------------------------------------------------
+
+def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None):
+    """d(sum_o w_o <O_o>)/d params by the two-term shift rule, per parameter occurrence."""
+    p = c.params if params is None else np.asarray(params, dtype=np.float64)
+    w = np.ones(c.n_obs) if weights is None else np.asarray(weights, dtype=np.float64)
+    grad = np.zeros(p.shape[0])
+    for k, g in enumerate(c.gates):
+        for j in range(W.N_ANGLES[int(g["op"])]):
+            pi = int(g["pidx"][j])
+            if pi < 0:
+                continue
+            fp = circuit_f(c, p, (k, j, math.pi / 2), init)
+            fm = circuit_f(c, p, (k, j, -math.pi / 2), init)
+            grad[pi] += float(g["pscale"][j]) * 0.5 * float(np.dot(w, fp - fm))
+    return grad
+
+
+def fd_grad(c: W.Circuit, params=None, weights=None, h=1e-5, init=None):
+    """Central finite differences with respect to each parameter."""
+    p = (c.params if params is None else np.asarray(params, dtype=np.float64)).copy()
+    w = np.ones(c.n_obs) if weights is None else np.asarray(weights, dtype=np.float64)
+    grad = np.zeros(p.shape[0])
+    for i in range(p.shape[0]):
+        pp = p.copy(); pp[i] += h
+        pm = p.copy(); pm[i] -= h
+        grad[i] = float(np.dot(w, circuit_f(c, pp, None, init) - circuit_f(c, pm, None, init))) / (2 * h)
+    return grad

@@ -1,0 +1,166 @@
+"""Pins of the state-vector oracle against values fixed by the paper and by mathematics."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sv
+from paper_2301_05451_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_gate_tensors.txt")
+
+
+def _golden():
+    rows = {}
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        rows[(parts[0], parts[1])] = np.array([float(v) for v in parts[2:]]).reshape(2, 2)
+    return rows
+
+
+def test_ry_matches_printed_matrix():
+    g = _golden()
+    assert np.allclose(sv.ry(math.pi / 2), g[("RY", "pi/2")], atol=1e-15)
+    assert np.allclose(sv.ry(math.pi), g[("RY", "pi")], atol=1e-15)
+
+
+def test_cnot_blocks_match_printed_tensor():
+    g = _golden()
+    m = sv.gate_matrix(W.CNOT, [])
+    T = m.reshape(2, 2, 2, 2)  # [c_out, t_out, c_in, t_in]
+    for co in range(2):
+        for ci in range(2):
+            assert np.allclose(T[co, :, ci, :], g[("CNOT", f"{co}{ci}")]), (co, ci)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.1, math.pi / 2, 2.5, math.pi, 4.0, 5.9])
+def test_paper_worked_example(theta):
+    # X on q0, RY(theta) on q1, CNOT(0,1); <I x Z> = sin^2(theta/2) - cos^2(theta/2)
+    c = W.Circuit(2, W.GateList().const(W.X, [0]).const(W.RY, [1], [theta]).add(W.CNOT, [0, 1]).array(),
+                  np.zeros(1), 1, W.zterms([([1], 1.0, 0)]))
+    want = math.sin(theta / 2) ** 2 - math.cos(theta / 2) ** 2
+    assert abs(sv.circuit_f(c)[0] - want) < 1e-14
+
+
+def test_bit_order_qubit0_is_msb():
+    c = W.GateList().const(W.X, [0]).array()
+    psi = sv.run(3, c, np.zeros(1))
+    assert psi[4] == 1.0 and np.sum(np.abs(psi)) == 1.0
+
+
+def test_bell_and_ghz():
+    bell = sv.run(2, W.GateList().const(W.H, [0]).add(W.CNOT, [0, 1]).array(), np.zeros(1))
+    assert np.allclose(bell, [1 / math.sqrt(2), 0, 0, 1 / math.sqrt(2)], atol=1e-15)
+    g = W.GateList().const(W.H, [0])
+    for q in range(4):
+        g.add(W.CNOT, [q, q + 1])
+    ghz = sv.run(5, g.array(), np.zeros(1))
+    want = np.zeros(32); want[0] = want[31] = 1 / math.sqrt(2)
+    assert np.allclose(ghz, want, atol=1e-15)
+
+
+@pytest.mark.parametrize("op", [W.RX, W.RY])
+@pytest.mark.parametrize("theta", [0.2, 1.7, 3.3, 5.0])
+def test_single_rotation_z_is_cos(op, theta):
+    c = W.Circuit(1, W.GateList().add(op, [0], [0]).array(), np.array([theta]), 1, W.zterms([([0], 1.0, 0)]))
+    assert abs(sv.circuit_f(c)[0] - math.cos(theta)) < 1e-14
+    g_ps = sv.param_shift_grad(c)
+    g_fd = sv.fd_grad(c)
+    assert abs(g_ps[0] + math.sin(theta)) < 1e-13
+    assert abs(g_fd[0] + math.sin(theta)) < 1e-9
+
+
+@pytest.mark.parametrize("theta", [0.4, 2.2])
+def test_rz_between_hadamards(theta):
+    c = W.Circuit(1, W.GateList().const(W.H, [0]).add(W.RZ, [0], [0]).const(W.H, [0]).array(),
+                  np.array([theta]), 1, W.zterms([([0], 1.0, 0)]))
+    assert abs(sv.circuit_f(c)[0] - math.cos(theta)) < 1e-14
+
+
+@pytest.mark.parametrize("gam", [0.3, 1.9])
+def test_rzz_closed_form(gam):
+    g = W.GateList().const(W.H, [0]).const(W.H, [1]).add(W.RZZ, [0, 1], [0]).const(W.H, [0]).const(W.H, [1])
+    c = W.Circuit(2, g.array(), np.array([gam]), 2, W.zterms([([0], 1.0, 0), ([0, 1], 1.0, 1)]))
+    f = sv.circuit_f(c)
+    assert abs(f[0] - math.cos(gam)) < 1e-14
+    assert abs(f[1] - 1.0) < 1e-14
+
+
+def test_product_state_zz():
+    a, b = 0.7, 2.1
+    g = W.GateList().add(W.RX, [0], [0]).add(W.RY, [1], [1])
+    c = W.Circuit(2, g.array(), np.array([a, b]), 1, W.zterms([([0, 1], 1.0, 0)]))
+    assert abs(sv.circuit_f(c)[0] - math.cos(a) * math.cos(b)) < 1e-14
+
+
+def test_u3_special_cases():
+    t = 1.234
+    assert np.allclose(sv.u3(t, 0, 0), sv.ry(t), atol=1e-15)
+    assert np.allclose(sv.u3(0, 0, t), np.diag([1, np.exp(1j * t)]), atol=1e-15)
+    # U3(theta, -pi/2, pi/2) = RX(theta) (OpenQASM 2 identity)
+    assert np.allclose(sv.u3(t, -math.pi / 2, math.pi / 2), sv.rx(t), atol=1e-15)
+
+
+def test_rot_decomposition_against_euler():
+    # Rot(phi, theta, omega) equals U3(theta, omega, phi) up to the phase e^{-i(phi+omega)/2}
+    p, t, o = 0.3, 1.1, -0.8
+    assert np.allclose(sv.rot(p, t, o), np.exp(-0.5j * (p + o)) * sv.u3(t, o, p), atol=1e-15)
+
+
+@pytest.mark.parametrize("op", range(12))
+def test_every_gate_unitary(op):
+    rng = np.random.default_rng(op)
+    ang = rng.uniform(0, 2 * math.pi, size=3)
+    U = sv.gate_matrix(op, ang)
+    assert np.allclose(U.conj().T @ U, np.eye(U.shape[0]), atol=1e-14)
+
+
+def test_sum_z_is_popcount_form():
+    n = 6
+    for x in [0, 5, 17, 63]:
+        init = np.zeros(2**n); init[x] = 1
+        c = W.Circuit(n, W.GateList().array(), np.zeros(1), 1, W.zterms([([q], 1.0, 0) for q in range(n)]))
+        assert sv.circuit_f(c, init=init)[0] == n - 2 * bin(x).count("1")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_full_unitary(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 7))
+    c = W.random_circuit(n, 25, rng)
+    Uf = sv.full_unitary(n, c.gates, c.params)
+    assert np.allclose(Uf.conj().T @ Uf, np.eye(2**n), atol=1e-13)
+    psi = sv.run(n, c.gates, c.params)
+    assert np.allclose(psi, Uf[:, 0], atol=1e-13)
+    assert abs(np.linalg.norm(psi) - 1) < 1e-13
+    # a user initial state goes through unchanged in norm and matches U_full v
+    v = rng.normal(size=2**n) + 1j * rng.normal(size=2**n)
+    assert np.allclose(sv.run(n, c.gates, c.params, init=v), Uf @ v, atol=1e-12)
+
+
+def test_user_state_length_mismatch_raises():
+    with pytest.raises(ValueError):
+        sv.run(3, W.GateList().array(), np.zeros(1), init=np.ones(4))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_param_shift_vs_central_fd(seed):
+    rng = np.random.default_rng(200 + seed)
+    n = int(rng.integers(2, 5))
+    c = W.random_circuit(n, 14, rng, n_params=6)
+    c.terms = W.zterms([([0], 1.0, 0), ([n - 1], 0.5, 0), ([0, 1], -0.3, 1)])
+    c.n_obs = 2
+    w = np.array([0.7, -1.3])
+    assert np.allclose(sv.param_shift_grad(c, weights=w), sv.fd_grad(c, weights=w), atol=1e-8)
+
+
+def test_hermitian_expval_matches_z_string():
+    rng = np.random.default_rng(5)
+    c = W.random_circuit(3, 10, rng)
+    psi = sv.run(3, c.gates, c.params)
+    O = np.diag(sv.zstring_diag(3, [0, 2]))
+    assert abs(sv.expval_hermitian(psi, O) - sv.expvals(psi, 3, W.zterms([([0, 2], 1.0, 0)]), 1)[0]) < 1e-14
