@@ -1,0 +1,158 @@
+/*
+ * tq.h -- C ABI of libtq, an MI355X (gfx950) simulator for parameterised quantum circuits.
+ *
+ * The operations follow the TeD-Q paper (arXiv 2301.05451):
+ *   - state-vector mode, Sec. 3.1: |psi> = U |psi_0>, gates applied in program order to a
+ *     2^n complex vector, initial state |0..0> or a caller vector of length 2^n;
+ *   - the VQC cost of Sec. 4: f = <psi| O |psi> for O a real combination of Pauli-Z strings;
+ *   - gradients of f with respect to gate parameters (Sec. 4; the values are those of the
+ *     parameter-shift rule of Sec. 4.2, computed here by one reverse adjoint sweep);
+ *   - tensor-network mode, Sec. 3.2: a closed network with every index of dimension 2,
+ *     contracted pairwise along a binary tree (Sec. 3.2.2), optionally sliced (Sec. 3.2.3);
+ *   - the small MLP kernels used by the runtime cost model that ranks contraction trees.
+ *
+ * Conventions (all entry points):
+ *   - Qubit q of an n-qubit register is bit position n-1-q of the amplitude index (qubit 0
+ *     is the most significant bit; Sec. 5.1, zeroth qubit on the left).
+ *   - States are interleaved complex arrays: float2 (TQ_C64) or double2 (TQ_C128).
+ *     Parameters are real arrays of the matching precision (float or double).
+ *   - Pointers named d_* are device pointers owned by the caller; the library never frees
+ *     or reallocates them. Pointers without the prefix are host pointers, read during the
+ *     call only. The context owns its internal device scratch (schedules, gate matrices,
+ *     reduction partials).
+ *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = default stream) and
+ *     validates its arguments on the host before anything is launched. On failure it
+ *     returns a non-zero tq_status and tq_last_error() describes the problem; nothing has
+ *     been launched. A kernel fault surfaces as TQ_EHIP from a later call.
+ *   - A context is bound to one device and is not thread-safe.
+ */
+#ifndef LIBTQ_TQ_H_
+#define LIBTQ_TQ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TQ_OK = 0,
+  TQ_EINVAL = 1,     /* bad argument: op code, qubit index, duplicate qubits, null pointer */
+  TQ_ESIZE = 2,      /* size mismatch, e.g. a state that is not 2^n long (Sec. 3.1) */
+  TQ_ENOTSUP = 3,    /* valid but unsupported request (e.g. n > 34) */
+  TQ_EHIP = 4,       /* a HIP runtime call failed */
+  TQ_EWORKSPACE = 5, /* caller workspace smaller than the size query returned */
+  TQ_ENOMEM = 6      /* internal device allocation failed */
+} tq_status;
+
+typedef enum { TQ_C64 = 0, TQ_C128 = 1 } tq_dtype;
+
+/* Gate codes. Matrices (c = cos(a/2), s = sin(a/2)):
+ *   H, X, Y, Z: textbook; RX(a) = [[c,-is],[-is,c]]; RY(a) = [[c,-s],[s,c]] (printed in
+ *   Sec. 3.2.1); RZ(a) = diag(e^{-ia/2}, e^{ia/2}); U3(th,ph,la) = [[c,-e^{i la}s],
+ *   [e^{i ph}s, e^{i(ph+la)}c]] (c,s of th); ROT(ph,th,om) = RZ(om) RY(th) RZ(ph);
+ *   CNOT(control, target) = |0><0| x I + |1><1| x X (the block form of Sec. 3.2.1);
+ *   CZ = diag(1,1,1,-1); RZZ(a) = exp(-i a Z Z / 2). */
+enum {
+  TQ_H = 0, TQ_X, TQ_Y, TQ_Z, TQ_RX, TQ_RY, TQ_RZ, TQ_U3, TQ_ROT, TQ_CNOT, TQ_CZ, TQ_RZZ,
+  TQ_NUM_OPS
+};
+
+/* One gate. Angle slot j (j < number of angles of op) is pscale[j] * params[pidx[j]] when
+ * pidx[j] >= 0 (index into this circuit's parameter vector), else the constant pscale[j].
+ * Unused q / pidx entries should be -1. 48 bytes. */
+typedef struct {
+  int32_t op;
+  int32_t q[2];
+  int32_t pidx[3];
+  double pscale[3];
+} tq_gate;
+
+/* One term of an observable: coeff * prod_{q: bit q of mask set} Z_q, added to output
+ * `obs`. 24 bytes. */
+typedef struct {
+  uint64_t mask;
+  double coeff;
+  int32_t obs;
+  int32_t _pad;
+} tq_zterm;
+
+/* A batch of circuits sharing one gate array, one parameter array and one state array.
+ * All member arrays are host arrays of length `count`. Circuit i has n_qubits[i] qubits,
+ * gates gates[gate_off[i] .. gate_off[i] + n_gates[i]), parameters
+ * d_params[param_off[i] ..] and amplitudes d_states[state_off[i] .. + 2^n_qubits[i]).
+ * Circuits whose (n_qubits, gate_off, n_gates) agree share one schedule. */
+typedef struct {
+  int32_t count;
+  const int32_t* n_qubits;
+  const int64_t* gate_off;
+  const int32_t* n_gates;
+  const int64_t* param_off;
+  const int64_t* state_off;
+} tq_batch;
+
+/* State-vector execution options (NULL = defaults: fused, autotuned shapes).
+ *   mode:      0 = fused (gates grouped into LDS-tile stages, one HBM sweep per stage),
+ *              1 = plain (one HBM sweep per gate), 2 = batched persistent work queue
+ *              (one launch for a whole batch of circuits of uneven size).
+ *   tile_bits: local qubits per fused tile (0 = autotune / default), 6..14.
+ *   reg_bits:  amplitude-index bits held in registers per thread, 2..5 (0 = default).
+ *   coal_bits: low index bits always kept local for coalesced HBM access (0 = default). */
+typedef struct {
+  int32_t mode;
+  int32_t tile_bits;
+  int32_t reg_bits;
+  int32_t coal_bits;
+} tq_sv_opts;
+
+typedef struct tq_ctx tq_ctx;
+
+/* Context on HIP device `device`. Owns schedule caches, the autotune table and scratch. */
+tq_status tq_ctx_create(int device, tq_ctx** out);
+void tq_ctx_destroy(tq_ctx* ctx);
+/* Thread-local description of the last failure (empty string if none). */
+const char* tq_last_error(void);
+int tq_version(void);
+/* HIP_VERSION the library was compiled with, and hipRuntimeGetVersion() of the runtime it
+ * is bound to in this process (-1 if that call fails; no device needed). Kernels built by
+ * a newer toolchain are not supported on an older runtime: callers must not use the
+ * library when runtime < build. */
+int tq_hip_build_version(void);
+int tq_hip_runtime_version(void);
+
+/* Sec. 3.1: apply every circuit of the batch to its state in place (|psi> <- U |psi>).
+ * The caller fills d_states beforehand (|0..0> or its own vector: the library does not
+ * normalise it). d_params holds real angles-parameters of the dtype's precision.
+ * Errors: TQ_EINVAL (bad op / qubit / duplicate qubit / pidx out of the circuit's
+ * parameter range is NOT checked: the caller guarantees it), TQ_ENOTSUP (n < 1 or n > 34). */
+tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                      const int32_t* n_params, const void* d_params, void* d_states,
+                      const tq_sv_opts* opts, void* stream);
+
+/* Sec. 4 cost: d_out[i * n_obs + o] = sum over terms with obs == o of
+ * coeff * <psi_i| Z-string |psi_i> (real; accumulated in double with a fixed reduction
+ * order, written in the dtype's real precision). Terms name qubits (bit q = qubit q). */
+tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states,
+                    const tq_zterm* terms, int32_t n_terms, int32_t n_obs, void* d_out,
+                    void* stream);
+
+/* Gradient of L = sum_i sum_o d_grad_out[i*n_obs+o] * <O_o>_i with respect to every
+ * circuit's parameters, by one reverse (adjoint) sweep per circuit. d_states holds the
+ * final states as left by tq_sv_apply (read only). Internally psi is copied to context
+ * scratch, lambda = sum_o w_o O_o psi, then for each gate in reverse psi <- U^dag psi,
+ * g += 2 Re<lambda| dU psi>, lambda <- U^dag lambda. The values equal the parameter-shift
+ * gradients of Sec. 4.2. d_grad[param_off[i] + k] receives dL/d params_i[k] (overwritten,
+ * dtype's real precision); gradients of all occurrences of a parameter are summed with
+ * their pscale factors. d_grad_out is [count][n_obs] in the dtype's real precision. */
+tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                         const int32_t* n_params, const void* d_params, const void* d_states,
+                         const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
+                         const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBTQ_TQ_H_ */

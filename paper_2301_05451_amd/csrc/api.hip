@@ -1,0 +1,384 @@
+// C ABI entry points of libtq: context, errors, schedule cache, state-vector calls.
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <tuple>
+
+#include "sv_device.h"
+
+namespace tq {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+tq_status fail(tq_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+Schedule::~Schedule() {
+  void* ptrs[] = {d_gates, d_rec, d_rec_gates, d_ops, d_phases, d_stages};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->scratch_bytes[slot] < bytes) {
+    if (ctx->scratch[slot]) {
+      TQ_HIP(hipDeviceSynchronize());
+      TQ_HIP(hipFree(ctx->scratch[slot]));
+      ctx->scratch[slot] = nullptr;
+      ctx->scratch_bytes[slot] = 0;
+    }
+    size_t want = std::max(bytes, (size_t)4096);
+    if (hipMalloc(&ctx->scratch[slot], want) != hipSuccess)
+      return fail(TQ_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes of context scratch failed");
+    ctx->scratch_bytes[slot] = want;
+  }
+  *out = ctx->scratch[slot];
+  return TQ_OK;
+}
+
+// Immutable small host tables (offset maps, observable terms) live in device memory cached
+// by content, so repeated calls neither re-upload nor synchronise (and can be captured in a
+// hipGraph once warmed up).
+static tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev) {
+  const unsigned char* b = (const unsigned char*)host;
+  uint64_t h1 = 0xCBF29CE484222325ull, h2 = 0x84222325CBF29CE4ull;
+  for (size_t i = 0; i < bytes; ++i) {
+    h1 = (h1 ^ b[i]) * 0x100000001B3ull;
+    h2 = (h2 + b[i]) * 0xFF51AFD7ED558CCDull;
+    h2 ^= h2 >> 29;
+  }
+  char key[64];
+  snprintf(key, sizeof key, "%016llx%016llx:%zu", (unsigned long long)h1, (unsigned long long)h2, bytes);
+  auto it = ctx->tables.find(key);
+  if (it != ctx->tables.end()) {
+    *dev = it->second;
+    return TQ_OK;
+  }
+  void* d = nullptr;
+  TQ_HIP(hipMalloc(&d, std::max<size_t>(bytes, 16)));
+  if (bytes) TQ_HIP(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+  ctx->tables.emplace(key, d);
+  *dev = d;
+  return TQ_OK;
+}
+
+template <typename V>
+static tq_status to_device(const std::vector<V>& v, void** dev) {
+  size_t bytes = std::max<size_t>(v.size() * sizeof(V), 16);
+  TQ_HIP(hipMalloc(dev, bytes));
+  if (!v.empty()) TQ_HIP(hipMemcpy(*dev, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
+  return TQ_OK;
+}
+
+// 128-bit content hash of a gate list (two 64-bit multiply-xorshift lanes over 8-byte words).
+static std::string schedule_key(const tq_gate* g, int n_gates, int n, int mode, int t, int R, int c) {
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(g);
+  const size_t nw = (size_t)n_gates * sizeof(tq_gate) / 8;
+  uint64_t h1 = 0x9E3779B97F4A7C15ull ^ (uint64_t)n_gates, h2 = 0xC2B2AE3D27D4EB4Full + (uint64_t)n;
+  for (size_t i = 0; i < nw; ++i) {
+    uint64_t x = w[i];
+    h1 = (h1 ^ x) * 0x100000001B3ull;
+    h1 ^= h1 >> 29;
+    h2 = (h2 + x) * 0xFF51AFD7ED558CCDull;
+    h2 ^= h2 >> 31;
+  }
+  char buf[128];
+  snprintf(buf, sizeof buf, "%016llx%016llx:%d:%d:%d:%d:%d:%d", (unsigned long long)h1, (unsigned long long)h2, n,
+           n_gates, mode, t, R, c);
+  return buf;
+}
+
+static tq_status upload_schedule(Schedule& s, const tq_gate* g, int n_gates) {
+  std::vector<tq_gate> gv(g, g + n_gates);
+  TQ_TRY(to_device(gv, &s.d_gates));
+  std::vector<int32_t> rec, rg;
+  for (const Recipe& r : s.recipes) {
+    rec.push_back(r.kind);
+    rec.push_back(r.qa);
+    rec.push_back(r.qb);
+    rec.push_back((int32_t)rg.size());
+    rg.insert(rg.end(), r.gates.begin(), r.gates.end());
+  }
+  rec.push_back(0); rec.push_back(0); rec.push_back(0); rec.push_back((int32_t)rg.size());  // sentinel
+  TQ_TRY(to_device(rec, &s.d_rec));
+  TQ_TRY(to_device(rg, &s.d_rec_gates));
+  TQ_TRY(to_device(s.dops, &s.d_ops));
+  TQ_TRY(to_device(s.phases, &s.d_phases));
+  TQ_TRY(to_device(s.dstages, &s.d_stages));
+  return TQ_OK;
+}
+
+// Default fused shapes: the largest tile that fits LDS with room for two work-groups
+// per CU for complex64, one for complex128 (the autotuner may override).
+static void default_shape(int dt, int n, int* t, int* R, int* c) {
+  *t = dt == TQ_C64 ? 13 : 12;
+  *R = 4;
+  *c = dt == TQ_C64 ? 5 : 4;
+  if (*t > n) *t = n;
+}
+
+tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, int mode, const tq_sv_opts* opts,
+                       Schedule** out) {
+  int t, R, c;
+  default_shape(dt, n, &t, &R, &c);
+  if (opts) {
+    if (opts->tile_bits) t = std::min(opts->tile_bits, n);
+    if (opts->reg_bits) R = opts->reg_bits;
+    if (opts->coal_bits) c = opts->coal_bits;
+  }
+  if (mode == 0) {
+    const size_t csz = dt == TQ_C64 ? 8 : 16;
+    if (t < 1 || t > 14 || (csz << t) > ctx->lds_max)
+      return fail(TQ_EINVAL, "tile_bits " + std::to_string(t) + " does not fit LDS for this dtype");
+    if (R < 1 || R > 5) return fail(TQ_EINVAL, "reg_bits must be in 1..5");
+    if (t - std::min(R, t) > 10) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 10 (1024 threads)");
+    if (c < 0 || c > 10) return fail(TQ_EINVAL, "coal_bits must be in 0..10");
+  } else {
+    t = R = c = 0;
+  }
+  std::string key = schedule_key(g, n_gates, n, mode, t, R, c);
+  auto it = ctx->schedules.find(key);
+  if (it != ctx->schedules.end()) {
+    *out = it->second.get();
+    return TQ_OK;
+  }
+  auto s = std::make_unique<Schedule>();
+  s->n = n;
+  s->mode = mode;
+  s->t = t;
+  s->R = R;
+  s->c = c;
+  s->n_gates = n_gates;
+  lower_ops(g, n_gates, n, mode == 0, s->recipes, s->ops);
+  if (mode == 0) build_stages(*s);
+  TQ_TRY(upload_schedule(*s, g, n_gates));
+  *out = s.get();
+  ctx->schedules.emplace(key, std::move(s));
+  return TQ_OK;
+}
+
+// Circuits of a batch grouped by structure (n, gate_off, n_gates), in first-seen order.
+struct Group {
+  int n;
+  int64_t gate_off;
+  int n_gates;
+  int n_params;
+  std::vector<int> members;
+};
+
+tq_status group_batch(const tq_batch* b, const int32_t* n_params, std::vector<Group>& groups) {
+  if (!b) return fail(TQ_EINVAL, "null batch");
+  if (b->count < 0) return fail(TQ_EINVAL, "negative batch count");
+  if (b->count == 0) return TQ_OK;
+  if (!b->n_qubits || !b->gate_off || !b->n_gates || !b->param_off || !b->state_off)
+    return fail(TQ_EINVAL, "batch arrays must not be null");
+  std::map<std::tuple<int, int64_t, int>, int> idx;
+  for (int i = 0; i < b->count; ++i) {
+    const int n = b->n_qubits[i];
+    if (n < 1 || n > 34) return fail(TQ_ENOTSUP, "circuit " + std::to_string(i) + ": n_qubits must be in 1..34");
+    if (b->n_gates[i] < 0 || b->gate_off[i] < 0 || b->param_off[i] < 0 || b->state_off[i] < 0)
+      return fail(TQ_EINVAL, "circuit " + std::to_string(i) + ": negative offset or count");
+    auto key = std::make_tuple(n, b->gate_off[i], b->n_gates[i]);
+    auto it = idx.find(key);
+    int np = n_params ? n_params[i] : 0x7fffffff;
+    if (it == idx.end()) {
+      idx[key] = (int)groups.size();
+      groups.push_back({n, b->gate_off[i], b->n_gates[i], np, {i}});
+    } else {
+      groups[it->second].members.push_back(i);
+      groups[it->second].n_params = std::min(groups[it->second].n_params, np);
+    }
+  }
+  return TQ_OK;
+}
+
+// Offsets of a group's members: affine (base + i * stride) when possible, else uploaded.
+tq_status member_map(tq_ctx* ctx, int slot, const int64_t* all, const std::vector<int>& m, hipStream_t stream,
+                     BatchMap* out) {
+  out->off = nullptr;
+  out->base = all[m[0]];
+  out->stride = m.size() > 1 ? all[m[1]] - all[m[0]] : 0;
+  bool affine = true;
+  for (size_t i = 0; i < m.size() && affine; ++i) affine = all[m[i]] == out->base + out->stride * (int64_t)i;
+  if (affine) return TQ_OK;
+  std::vector<int64_t> v(m.size());
+  for (size_t i = 0; i < m.size(); ++i) v[i] = all[m[i]];
+  void* d;
+  (void)slot;
+  (void)stream;
+  TQ_TRY(cached_table(ctx, v.data(), v.size() * sizeof(int64_t), &d));
+  out->off = (const int64_t*)d;
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status sv_apply_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                            const void* d_params, void* d_states, const tq_sv_opts* opts, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  std::vector<Group> groups;
+  TQ_TRY(group_batch(batch, n_params, groups));
+  const int mode = opts ? opts->mode : 0;
+  if (mode != 0 && mode != 1) return fail(TQ_ENOTSUP, "sv mode must be 0 (fused) or 1 (plain)");
+  if (!groups.empty() && (!d_params || !d_states)) return fail(TQ_EINVAL, "null device pointer");
+  for (const Group& gr : groups) {
+    const tq_gate* g = gates + gr.gate_off;
+    TQ_TRY(validate_gates(g, gr.n_gates, gr.n, gr.n_params));
+  }
+  for (const Group& gr : groups) {
+    const tq_gate* g = gates + gr.gate_off;
+    Schedule* s;
+    TQ_TRY(get_schedule(ctx, sizeof(T) == 4 ? TQ_C64 : TQ_C128, g, gr.n_gates, gr.n, mode, opts, &s));
+    const int count = (int)gr.members.size();
+    BatchMap pmap, smap;
+    TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, gr.members, stream, &pmap));
+    TQ_TRY(member_map(ctx, S_MISC, batch->state_off, gr.members, stream, &smap));
+    void* mats;
+    TQ_TRY(scratch(ctx, S_MATS, (size_t)count * std::max<size_t>(s->recipes.size(), 1) * 4 * sizeof(C), &mats));
+    TQ_TRY(launch_gate_build<T>(*s, d_params, pmap, mats, count, stream));
+    if (mode == 1)
+      TQ_TRY(launch_plain<T>(*s, d_states, smap, mats, count, ctx->n_cu, stream));
+    else
+      TQ_TRY(launch_stages<T>(*s, d_states, smap, mats, count, stream));
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status expval_t(tq_ctx* ctx, const tq_batch* batch, const void* d_states, const tq_zterm* terms,
+                          int n_terms, int n_obs, void* d_out, hipStream_t stream) {
+  std::vector<Group> groups;
+  TQ_TRY(group_batch(batch, nullptr, groups));
+  if (n_obs < 1) return fail(TQ_EINVAL, "n_obs must be >= 1");
+  if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(TQ_EINVAL, "bad terms");
+  if (!groups.empty() && (!d_states || !d_out)) return fail(TQ_EINVAL, "null device pointer");
+  for (int k = 0; k < n_terms; ++k)
+    if (terms[k].obs < 0 || terms[k].obs >= n_obs) return fail(TQ_EINVAL, "term obs index out of range");
+  // output rows follow batch order: out[i * n_obs + o]. Groups are computed per distinct n.
+  for (const Group& gr : groups) {
+    for (int k = 0; k < n_terms; ++k)
+      if (gr.n < 64 && (terms[k].mask >> gr.n) != 0) return fail(TQ_EINVAL, "term names a qubit >= n");
+  }
+  // group by n only (gates do not matter here)
+  std::map<int, std::vector<int>> by_n;
+  for (const Group& gr : groups)
+    for (int i : gr.members) by_n[gr.n].push_back(i);
+  for (auto& kv : by_n) {
+    const int n = kv.first;
+    std::vector<int>& mem = kv.second;
+    std::sort(mem.begin(), mem.end());
+    std::vector<uint64_t> pm(n_terms);
+    std::vector<double> cf(n_terms);
+    std::vector<int32_t> ob(n_terms);
+    for (int k = 0; k < n_terms; ++k) {
+      uint64_t m = 0;
+      for (int q = 0; q < n; ++q)
+        if ((terms[k].mask >> q) & 1ull) m |= 1ull << (n - 1 - q);
+      pm[k] = m;
+      cf[k] = terms[k].coeff;
+      ob[k] = terms[k].obs;
+    }
+    std::vector<unsigned char> blob(n_terms * 20 + 64);
+    std::memcpy(blob.data(), pm.data(), n_terms * 8);
+    std::memcpy(blob.data() + n_terms * 8, cf.data(), n_terms * 8);
+    std::memcpy(blob.data() + n_terms * 16, ob.data(), n_terms * 4);
+    void* dterms;
+    TQ_TRY(cached_table(ctx, blob.data(), blob.size(), &dterms));
+    const unsigned char* db = (const unsigned char*)dterms;
+    BatchMap smap, omap;
+    TQ_TRY(member_map(ctx, S_MISC, batch->state_off, mem, stream, &smap));
+    // outputs: contiguous rows when the members are consecutive batch entries
+    bool consecutive = true;
+    for (size_t i = 1; i < mem.size(); ++i) consecutive = consecutive && mem[i] == mem[0] + (int)i;
+    const int64_t namps = int64_t(1) << n;
+    int64_t nblocks = std::min<int64_t>((namps + 4095) / 4096, 2048);
+    void* partial;
+    size_t pcap = std::min<size_t>(mem.size(), 65535) * nblocks * 8 * sizeof(double);
+    TQ_TRY(scratch(ctx, S_PARTIAL, pcap, &partial));
+    T* out = (T*)d_out;
+    if (consecutive) {
+      TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, smap, n, (int)mem.size(),
+                              (const uint64_t*)db, (const double*)(db + n_terms * 8),
+                              (const int32_t*)(db + n_terms * 16), n_terms, n_obs, (double*)partial, pcap,
+                              out + (int64_t)mem[0] * n_obs, ctx->n_cu, stream));
+    } else {
+      for (int i : mem) {
+        BatchMap one{nullptr, batch->state_off[i], 0};
+        TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, one, n, 1, (const uint64_t*)db,
+                                (const double*)(db + n_terms * 8), (const int32_t*)(db + n_terms * 16), n_terms,
+                                n_obs, (double*)partial, pcap, out + (int64_t)i * n_obs, ctx->n_cu, stream));
+      }
+    }
+    (void)omap;
+  }
+  return TQ_OK;
+}
+
+}  // namespace tq
+
+using namespace tq;
+
+extern "C" {
+
+const char* tq_last_error(void) { return g_last_error.c_str(); }
+
+int tq_version(void) { return 100; }
+
+int tq_hip_build_version(void) { return HIP_VERSION; }
+
+int tq_hip_runtime_version(void) {
+  int v = 0;
+  if (hipRuntimeGetVersion(&v) != hipSuccess) return -1;
+  return v;
+}
+
+tq_status tq_ctx_create(int device, tq_ctx** out) {
+  if (!out) return fail(TQ_EINVAL, "null output pointer");
+  *out = nullptr;
+  int ndev = 0;
+  TQ_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TQ_EINVAL, "device index out of range");
+  TQ_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  TQ_HIP(hipGetDeviceProperties(&prop, device));
+  auto* c = new tq_ctx();
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->lds_max = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 64 * 1024;
+  *out = c;
+  return TQ_OK;
+}
+
+void tq_ctx_destroy(tq_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->schedules.clear();
+  for (int i = 0; i < 8; ++i)
+    if (ctx->scratch[i]) (void)hipFree(ctx->scratch[i]);
+  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
+  delete ctx;
+}
+
+tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                      const void* d_params, void* d_states, const tq_sv_opts* opts, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (dt == TQ_C64) return sv_apply_t<float>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream);
+  if (dt == TQ_C128)
+    return sv_apply_t<double>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream);
+  return fail(TQ_EINVAL, "unknown dtype");
+}
+
+tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states, const tq_zterm* terms,
+                    int32_t n_terms, int32_t n_obs, void* d_out, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (dt == TQ_C64) return expval_t<float>(ctx, batch, d_states, terms, n_terms, n_obs, d_out, (hipStream_t)stream);
+  if (dt == TQ_C128) return expval_t<double>(ctx, batch, d_states, terms, n_terms, n_obs, d_out, (hipStream_t)stream);
+  return fail(TQ_EINVAL, "unknown dtype");
+}
+
+}  // extern "C"

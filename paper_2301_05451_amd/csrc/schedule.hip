@@ -1,0 +1,276 @@
+// Host lowering of a gate list into scheduled operations and fused LDS-tile stages.
+//
+// The state-vector mode of the paper (Sec. 3.1) applies the gate matrices one after
+// another. The lowering keeps that product exactly and only regroups it:
+//   * consecutive one-qubit gates on the same qubit are multiplied into one 2x2
+//     (gates on other qubits commute with them);
+//   * diagonal gates (Z, RZ, CZ, RZZ) never need their qubits to be tile-local: the
+//     value of every index bit is known inside a tile, so they are applied in place;
+//   * a stage is one read and one write of the state: a tile holds 2^t amplitudes whose
+//     index varies over t "local" qubits (the lowest index bits always among them so that
+//     HBM accesses are contiguous), and every operation whose non-diagonal target is
+//     local and whose earlier dependencies are done is applied in LDS/registers;
+//   * inside a stage, phases hold R target bits per thread in registers; moving between
+//     phases is one LDS exchange.
+// The schedule depends only on the circuit structure, so it is built once and reused for
+// new parameter values (the paper's reuse of compiled circuits and contraction paths).
+#include <algorithm>
+#include <set>
+
+#include "tq_internal.h"
+
+namespace tq {
+
+static int n_angles(int op) {
+  switch (op) {
+    case TQ_RX: case TQ_RY: case TQ_RZ: case TQ_RZZ: return 1;
+    case TQ_U3: case TQ_ROT: return 3;
+    default: return 0;
+  }
+}
+static int n_qubits_of(int op) { return (op == TQ_CNOT || op == TQ_CZ || op == TQ_RZZ) ? 2 : 1; }
+static bool diag1(int op) { return op == TQ_Z || op == TQ_RZ; }
+
+tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params) {
+  if (n_gates < 0) return fail(TQ_EINVAL, "negative gate count");
+  if (n_gates > 0 && g == nullptr) return fail(TQ_EINVAL, "null gate array");
+  for (int k = 0; k < n_gates; ++k) {
+    const tq_gate& x = g[k];
+    if (x.op < 0 || x.op >= TQ_NUM_OPS)
+      return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": unknown op " + std::to_string(x.op));
+    int nq = n_qubits_of(x.op);
+    for (int i = 0; i < nq; ++i)
+      if (x.q[i] < 0 || x.q[i] >= n)
+        return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": qubit " + std::to_string(x.q[i]) +
+                                   " outside [0," + std::to_string(n) + ")");
+    if (nq == 2 && x.q[0] == x.q[1])
+      return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": duplicate qubit");
+    for (int j = 0; j < n_angles(x.op); ++j)
+      if (x.pidx[j] >= n_params)
+        return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": parameter index " +
+                                   std::to_string(x.pidx[j]) + " >= n_params " + std::to_string(n_params));
+  }
+  return TQ_OK;
+}
+
+void lower_ops(const tq_gate* g, int n_gates, int n, bool fuse, std::vector<Recipe>& recipes,
+               std::vector<HostOp>& ops) {
+  recipes.clear();
+  ops.clear();
+  if (!fuse) {
+    for (int k = 0; k < n_gates; ++k) {
+      const tq_gate& x = g[k];
+      if (x.op == TQ_CNOT) {
+        ops.push_back({K_CX, x.q[1], x.q[0], -1, k});
+      } else if (x.op == TQ_CZ) {
+        ops.push_back({K_CZ, x.q[0], x.q[1], -1, k});
+      } else if (x.op == TQ_RZZ) {
+        recipes.push_back({R_DIAG2, x.q[0], x.q[1], {k}});
+        ops.push_back({K_DIAG2, x.q[0], x.q[1], (int)recipes.size() - 1, -1});
+      } else if (diag1(x.op)) {
+        recipes.push_back({R_DIAG1, x.q[0], -1, {k}});
+        ops.push_back({K_DIAG1, x.q[0], -1, (int)recipes.size() - 1, -1});
+      } else {
+        recipes.push_back({R_MAT2, x.q[0], -1, {k}});
+        ops.push_back({K_MAT1, x.q[0], -1, (int)recipes.size() - 1, -1});
+      }
+    }
+    return;
+  }
+  std::vector<std::vector<int>> pending(n);
+  std::vector<int> last(n, -1);  // last emitted op touching each qubit
+  auto flush = [&](int q) {
+    if (pending[q].empty()) return;
+    bool all_diag = true;
+    for (int k : pending[q]) all_diag = all_diag && diag1(g[k].op);
+    recipes.push_back({all_diag ? R_DIAG1 : R_MAT2, q, -1, pending[q]});
+    ops.push_back({all_diag ? K_DIAG1 : K_MAT1, q, -1, (int)recipes.size() - 1, -1});
+    last[q] = (int)ops.size() - 1;
+    pending[q].clear();
+  };
+  auto pending_all_diag = [&](int q) {
+    for (int k : pending[q])
+      if (!diag1(g[k].op)) return false;
+    return true;
+  };
+  for (int k = 0; k < n_gates; ++k) {
+    const tq_gate& x = g[k];
+    if (n_qubits_of(x.op) == 1) {
+      pending[x.q[0]].push_back(k);
+      continue;
+    }
+    int a = x.q[0], b = x.q[1];
+    if (x.op == TQ_CNOT) {
+      flush(a);
+      flush(b);
+      ops.push_back({K_CX, b, a, -1, k});
+      last[a] = last[b] = (int)ops.size() - 1;
+      continue;
+    }
+    // CZ / RZZ: diagonal on (a, b). Pending diagonal one-qubit gates merge into it.
+    bool pa = pending_all_diag(a), pb = pending_all_diag(b);
+    std::vector<int> pre;
+    if (pa) { pre.insert(pre.end(), pending[a].begin(), pending[a].end()); pending[a].clear(); } else flush(a);
+    if (pb) { pre.insert(pre.end(), pending[b].begin(), pending[b].end()); pending[b].clear(); } else flush(b);
+    int lo = last[a];
+    bool merge = lo >= 0 && lo == last[b] && (ops[lo].kind == K_DIAG2 || ops[lo].kind == K_CZ);
+    if (merge) {
+      HostOp& o = ops[lo];
+      if (o.kind == K_CZ) {  // the earlier CZ had no recipe: give it one
+        recipes.push_back({R_DIAG2, o.qa, o.qb, {o.src}});
+        o.kind = K_DIAG2;
+        o.mat = (int)recipes.size() - 1;
+      }
+      Recipe& r = recipes[o.mat];
+      r.gates.insert(r.gates.end(), pre.begin(), pre.end());
+      r.gates.push_back(k);
+    } else if (x.op == TQ_CZ && pre.empty()) {
+      ops.push_back({K_CZ, a, b, -1, k});
+      last[a] = last[b] = (int)ops.size() - 1;
+    } else {
+      std::vector<int> gl = pre;
+      gl.push_back(k);
+      recipes.push_back({R_DIAG2, a, b, gl});
+      ops.push_back({K_DIAG2, a, b, (int)recipes.size() - 1, -1});
+      last[a] = last[b] = (int)ops.size() - 1;
+    }
+  }
+  for (int q = 0; q < n; ++q) flush(q);
+}
+
+static void op_qubits(const HostOp& o, int* qs, int* nq, int* need) {
+  *nq = 0;
+  qs[(*nq)++] = o.qa;
+  if (o.qb >= 0) qs[(*nq)++] = o.qb;
+  *need = (o.kind == K_MAT1 || o.kind == K_CX) ? o.qa : -1;
+}
+
+// Greedy selection of a set of at most `cap` "need" resources (qubits or tile positions)
+// starting from `fixed`; takes every op, in order, that is not blocked by an earlier
+// skipped op on a shared qubit and whose need fits. Returns taken ops; the rest stay.
+static void greedy_take(const std::vector<HostOp>& all, std::vector<int>& remaining, std::set<int>& S,
+                        int cap, const std::vector<int>& res_of_qubit, std::vector<int>& taken) {
+  std::set<int> blocked;
+  std::vector<int> rest;
+  for (int oi : remaining) {
+    int qs[2], nq, need;
+    op_qubits(all[oi], qs, &nq, &need);
+    bool blk = false;
+    for (int i = 0; i < nq; ++i) blk = blk || blocked.count(qs[i]);
+    int r = need >= 0 ? res_of_qubit[need] : -1;
+    bool ok = !blk && (r < 0 || S.count(r) || (int)S.size() < cap);
+    if (ok) {
+      if (r >= 0) S.insert(r);
+      taken.push_back(oi);
+    } else {
+      for (int i = 0; i < nq; ++i) blocked.insert(qs[i]);
+      rest.push_back(oi);
+    }
+  }
+  remaining.swap(rest);
+}
+
+void build_stages(Schedule& s) {
+  const int n = s.n;
+  s.stages.clear();
+  s.phases.clear();
+  s.dops.clear();
+  s.dstages.clear();
+  const int t = std::min(s.t, n);
+  const int R = std::min(s.R, t);
+  const int c = std::min(s.c, std::max(0, t - 1));
+  std::vector<int> remaining(s.ops.size());
+  for (size_t i = 0; i < s.ops.size(); ++i) remaining[i] = (int)i;
+  std::vector<int> pos_of_q(n);
+  for (int q = 0; q < n; ++q) pos_of_q[q] = n - 1 - q;
+  while (!remaining.empty()) {
+    std::set<int> S;  // global positions of local qubits
+    if (t == n) {
+      for (int p = 0; p < n; ++p) S.insert(p);
+    } else {
+      for (int p = 0; p < c; ++p) S.insert(p);
+    }
+    std::vector<int> taken;
+    greedy_take(s.ops, remaining, S, t, pos_of_q, taken);
+    // fill the local set up to t with the lowest free positions
+    for (int p = 0; (int)S.size() < t && p < n; ++p) S.insert(p);
+    StageHost st;
+    st.t = t;
+    st.lpos.assign(S.begin(), S.end());
+    for (int p = 0; p < n; ++p)
+      if (!S.count(p)) st.npos.push_back(p);
+    std::vector<int> loc_of_pos(n, -1);
+    for (int i = 0; i < t; ++i) loc_of_pos[st.lpos[i]] = i;
+    auto xpos = [&](int q) {
+      int p = pos_of_q[q];
+      if (loc_of_pos[p] >= 0) return loc_of_pos[p];
+      int k = (int)(std::lower_bound(st.npos.begin(), st.npos.end(), p) - st.npos.begin());
+      return t + k;
+    };
+    // phases: register sets over tile-local positions
+    std::vector<int> loc_of_q(n);
+    for (int q = 0; q < n; ++q) loc_of_q[q] = loc_of_pos[pos_of_q[q]];
+    st.phase_begin = (int)s.phases.size();
+    std::vector<int> prem = taken;
+    std::vector<uint8_t> cur_r, cur_t;  // current layout (starts as the load layout)
+    for (int k = 0; k < R; ++k) cur_r.push_back((uint8_t)(t - R + k));
+    for (int k = 0; k < t - R; ++k) cur_t.push_back((uint8_t)k);
+    while (!prem.empty()) {
+      std::set<int> Rs;
+      std::vector<int> ptaken;
+      greedy_take(s.ops, prem, Rs, R, loc_of_q, ptaken);
+      // keep bits of the current layout where possible (fewer changes is not required for
+      // correctness; it only makes the register order stable), then fill
+      std::vector<int> rv(Rs.begin(), Rs.end());
+      for (int k = t - 1; (int)rv.size() < R && k >= 0; --k)
+        if (!Rs.count(k)) { rv.push_back(k); Rs.insert(k); }
+      std::sort(rv.begin(), rv.end());
+      DevPhase ph{};
+      ph.op_begin = (int)s.dops.size();
+      std::vector<uint8_t> nr, nt;
+      for (int k = 0; k < R; ++k) nr.push_back((uint8_t)rv[k]);
+      for (int k = 0; k < t; ++k)
+        if (!Rs.count(k)) nt.push_back((uint8_t)k);
+      ph.xchg = (nr != cur_r) ? 1 : 0;
+      cur_r = nr;
+      cur_t = nt;
+      for (int k = 0; k < R; ++k) ph.rpos[k] = nr[k];
+      for (int k = 0; k < t - R; ++k) ph.tpos[k] = nt[k];
+      for (int oi : ptaken) {
+        const HostOp& o = s.ops[oi];
+        DevOp d{};
+        d.kind = (uint8_t)o.kind;
+        d.mat = o.mat;
+        if (o.kind == K_MAT1 || o.kind == K_CX) {
+          int lp = loc_of_q[o.qa];
+          d.rbit = (uint8_t)(std::find(rv.begin(), rv.end(), lp) - rv.begin());
+          if (o.kind == K_CX) d.pa = (uint8_t)xpos(o.qb);
+        } else {
+          d.pa = (uint8_t)xpos(o.qa);
+          d.pb = o.qb >= 0 ? (uint8_t)xpos(o.qb) : 0;
+        }
+        s.dops.push_back(d);
+      }
+      ph.op_end = (int)s.dops.size();
+      s.phases.push_back(ph);
+      st.n_ops += (int)ptaken.size();
+    }
+    st.phase_end = (int)s.phases.size();
+    DevStage ds{};
+    {
+      std::vector<uint8_t> load_r;
+      for (int k = 0; k < R; ++k) load_r.push_back((uint8_t)(t - R + k));
+      ds.store_xchg = (cur_r != load_r) ? 1 : 0;
+    }
+    ds.t = t;
+    ds.phase_begin = st.phase_begin;
+    ds.phase_end = st.phase_end;
+    ds.n_nonlocal = n - t;
+    for (int i = 0; i < t; ++i) ds.lpos[i] = (uint8_t)st.lpos[i];
+    for (int i = 0; i < n - t; ++i) ds.npos[i] = (uint8_t)st.npos[i];
+    s.dstages.push_back(ds);
+    s.stages.push_back(std::move(st));
+  }
+}
+
+}  // namespace tq

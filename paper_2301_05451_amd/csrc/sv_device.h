@@ -1,0 +1,180 @@
+// Device helpers for the state-vector kernels: complex arithmetic, gate matrices built
+// from angles in double precision, batch offset maps.
+#pragma once
+
+#include <type_traits>
+
+#include "tq_internal.h"
+
+namespace tq {
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+
+struct dcx {
+  double x, y;
+};
+
+// Per-circuit offsets of a batch: off[i] if given, else base + i * stride.
+struct BatchMap {
+  const int64_t* off;
+  int64_t base, stride;
+  __host__ __device__ __forceinline__ int64_t at(int i) const { return off ? off[i] : base + stride * (int64_t)i; }
+  __host__ BatchMap shifted(int c0) const {
+    BatchMap m = *this;
+    if (off) m.off = off + c0; else m.base += stride * (int64_t)c0;
+    return m;
+  }
+};
+
+template <typename C>
+__host__ __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// m0 * a + m1 * b
+template <typename C>
+__device__ __forceinline__ C cfma2(C m0, C a, C m1, C b) {
+  C r;
+  r.x = m0.x * a.x - m0.y * a.y + m1.x * b.x - m1.y * b.y;
+  r.y = m0.x * a.y + m0.y * a.x + m1.x * b.y + m1.y * b.x;
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ typename Cx<T>::type to_cx(dcx v) {
+  typename Cx<T>::type r;
+  r.x = (T)v.x;
+  r.y = (T)v.y;
+  return r;
+}
+
+struct dmat2 {
+  dcx m[4];  // row-major: m[0]=u00 m[1]=u01 m[2]=u10 m[3]=u11
+  __device__ static dmat2 identity() { return dmat2{{{1, 0}, {0, 0}, {0, 0}, {1, 0}}}; }
+};
+
+__device__ __forceinline__ dmat2 mat_mul(const dmat2& A, const dmat2& B) {
+  dmat2 C;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      dcx a = cmul(A.m[2 * i + 0], B.m[0 + j]);
+      dcx b = cmul(A.m[2 * i + 1], B.m[2 + j]);
+      C.m[2 * i + j] = dcx{a.x + b.x, a.y + b.y};
+    }
+  return C;
+}
+
+__device__ __forceinline__ dcx expi(double a) {
+  double s, c;
+  sincos(a, &s, &c);
+  return dcx{c, s};
+}
+
+template <typename T>
+__device__ __forceinline__ void gate_angles(const tq_gate& g, const T* p, double* a) {
+  for (int j = 0; j < 3; ++j) {
+    const int pi = g.pidx[j];
+    a[j] = pi >= 0 ? g.pscale[j] * (double)p[pi] : g.pscale[j];
+  }
+}
+
+// 2x2 matrix of a one-qubit gate.
+__device__ inline dmat2 gate_mat2(int op, const double* a) {
+  const double r = 0.70710678118654752440;
+  dmat2 M = dmat2::identity();
+  double s, c;
+  switch (op) {
+    case TQ_H: M = dmat2{{{r, 0}, {r, 0}, {r, 0}, {-r, 0}}}; break;
+    case TQ_X: M = dmat2{{{0, 0}, {1, 0}, {1, 0}, {0, 0}}}; break;
+    case TQ_Y: M = dmat2{{{0, 0}, {0, -1}, {0, 1}, {0, 0}}}; break;
+    case TQ_Z: M = dmat2{{{1, 0}, {0, 0}, {0, 0}, {-1, 0}}}; break;
+    case TQ_RX:
+      sincos(0.5 * a[0], &s, &c);
+      M = dmat2{{{c, 0}, {0, -s}, {0, -s}, {c, 0}}};
+      break;
+    case TQ_RY:
+      sincos(0.5 * a[0], &s, &c);
+      M = dmat2{{{c, 0}, {-s, 0}, {s, 0}, {c, 0}}};
+      break;
+    case TQ_RZ: {
+      dcx e = expi(-0.5 * a[0]);
+      M = dmat2{{e, {0, 0}, {0, 0}, {e.x, -e.y}}};
+      break;
+    }
+    case TQ_U3: {
+      sincos(0.5 * a[0], &s, &c);
+      dcx el = expi(a[2]), ep = expi(a[1]), epl = expi(a[1] + a[2]);
+      M = dmat2{{{c, 0}, {-el.x * s, -el.y * s}, {ep.x * s, ep.y * s}, {epl.x * c, epl.y * c}}};
+      break;
+    }
+    case TQ_ROT: {
+      // RZ(omega) RY(theta) RZ(phi) with (phi, theta, omega) = (a0, a1, a2)
+      double a0[1] = {a[0]}, a1[1] = {a[1]}, a2[1] = {a[2]};
+      M = mat_mul(gate_mat2(TQ_RZ, a2), mat_mul(gate_mat2(TQ_RY, a1), gate_mat2(TQ_RZ, a0)));
+      break;
+    }
+    default: break;
+  }
+  return M;
+}
+
+// Factor that diagonal gate g contributes to the diagonal entry with bit values (ba, bb)
+// of the recipe's qubits (qa and the other one).
+__device__ inline dcx diag_entry(const tq_gate& g, int qa, int ba, int bb, const double* a) {
+  switch (g.op) {
+    case TQ_CZ: return dcx{(ba & bb) ? -1.0 : 1.0, 0};
+    case TQ_RZZ: return expi((ba ^ bb) ? 0.5 * a[0] : -0.5 * a[0]);
+    case TQ_RZ: {
+      int b = (g.q[0] == qa) ? ba : bb;
+      return expi(b ? 0.5 * a[0] : -0.5 * a[0]);
+    }
+    case TQ_Z: {
+      int b = (g.q[0] == qa) ? ba : bb;
+      return dcx{b ? -1.0 : 1.0, 0};
+    }
+    default: return dcx{1, 0};
+  }
+}
+
+// Read one 8-byte op descriptor as a single aligned 64-bit word and unpack its byte
+// fields. Reading the fields one by one let the compiler split a field's address into a
+// misaligned scalar base plus a misaligned immediate offset; the scalar unit does not
+// add those before dropping the low address bits, so the matrix index came back as the
+// op header and the matrix load left its buffer.
+__device__ __forceinline__ DevOp load_op(const DevOp* ops, int o) {
+  const uint2 w = reinterpret_cast<const uint2*>(ops)[o];
+  DevOp d;
+  d.kind = (uint8_t)(w.x & 0xffu);
+  d.rbit = (uint8_t)((w.x >> 8) & 0xffu);
+  d.pa = (uint8_t)((w.x >> 16) & 0xffu);
+  d.pb = (uint8_t)(w.x >> 24);
+  d.mat = (int32_t)w.y;
+  return d;
+}
+
+__host__ __device__ __forceinline__ int64_t insert_zero(int64_t k, int pos) {
+  const int64_t lo = k & ((int64_t(1) << pos) - 1);
+  return ((k >> pos) << (pos + 1)) | lo;
+}
+
+// launchers (sv_kernels.hip)
+template <typename T>
+tq_status launch_gate_build(const Schedule& s, const void* d_params, BatchMap pmap, void* d_mats, int count,
+                            hipStream_t stream);
+template <typename T>
+tq_status launch_plain(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count, int n_cu,
+                       hipStream_t stream);
+template <typename T>
+tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
+                        hipStream_t stream);
+template <typename T>
+tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count, const uint64_t* d_pmask,
+                        const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs, double* d_partial,
+                        size_t partial_cap, T* d_out, int n_cu, hipStream_t stream);
+
+}  // namespace tq

@@ -1,0 +1,508 @@
+// State-vector kernels for gfx950 (wave64): gate-matrix build, plain one-gate sweeps,
+// fused LDS-tile stages, and Z-string expectation values.
+//
+// Layout: one circuit's state is 2^n interleaved complex amplitudes (float2 or double2);
+// qubit q is bit n-1-q of the index. A batch of states sits in one allocation at per-
+// circuit offsets (BatchMap).
+#include "sv_device.h"
+
+namespace tq {
+
+// ---------------------------------------------------------------------------------
+// Gate-matrix build: one thread per (circuit, matrix-table entry). Products are formed in
+// double precision from the circuit's parameters and rounded once to the state dtype.
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void gate_build_kernel(const tq_gate* __restrict__ gates, const int32_t* __restrict__ rec,
+                                  const int32_t* __restrict__ rec_gates, int n_mats,
+                                  const T* __restrict__ params, BatchMap pmap,
+                                  typename Cx<T>::type* __restrict__ mats, int count) {
+  using C = typename Cx<T>::type;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_mats * count) return;
+  const int m = (int)(gid % n_mats);
+  const int circ = (int)(gid / n_mats);
+  const T* p = params + pmap.at(circ);
+  const int kind = rec[4 * m + 0], qa = rec[4 * m + 1];
+  const int b0 = rec[4 * m + 3], b1 = rec[4 * (m + 1) + 3];
+  C* out = mats + ((int64_t)circ * n_mats + m) * 4;
+  if (kind == R_MAT2) {
+    dmat2 M = dmat2::identity();
+    for (int i = b0; i < b1; ++i) {
+      const tq_gate& g = gates[rec_gates[i]];
+      double a[3];
+      gate_angles(g, p, a);
+      M = mat_mul(gate_mat2(g.op, a), M);
+    }
+    for (int k = 0; k < 4; ++k) out[k] = to_cx<T>(M.m[k]);
+  } else {
+    // diagonal: entries indexed by 2*bit(qa) + bit(qb) (R_DIAG2) or bit(qa) (R_DIAG1)
+    dcx d[4] = {{1, 0}, {1, 0}, {1, 0}, {1, 0}};
+    for (int i = b0; i < b1; ++i) {
+      const tq_gate& g = gates[rec_gates[i]];
+      double a[3];
+      gate_angles(g, p, a);
+      for (int idx = 0; idx < 4; ++idx) {
+        int ba = (kind == R_DIAG2) ? (idx >> 1) : (idx & 1);
+        int bb = idx & 1;
+        d[idx] = cmul(d[idx], diag_entry(g, qa, ba, bb, a));
+      }
+    }
+    for (int k = 0; k < 4; ++k) out[k] = to_cx<T>(d[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Plain sweeps: one HBM pass per scheduled op (grid-stride; y = circuit).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) plain_mat1_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
+                                                         int pos, int64_t npairs,
+                                                         const typename Cx<T>::type* __restrict__ mats,
+                                                         int64_t mats_stride, int mat) {
+  using C = typename Cx<T>::type;
+  C* s = st + smap.at(blockIdx.y);
+  const C* M = mats + (int64_t)blockIdx.y * mats_stride + 4 * (int64_t)mat;
+  const C m0 = M[0], m1 = M[1], m2 = M[2], m3 = M[3];
+  const int64_t lo_mask = (int64_t(1) << pos) - 1;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < npairs; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i0 = ((k & ~lo_mask) << 1) | (k & lo_mask);
+    int64_t i1 = i0 | (int64_t(1) << pos);
+    C a = s[i0], b = s[i1];
+    s[i0] = cfma2(m0, a, m1, b);
+    s[i1] = cfma2(m2, a, m3, b);
+  }
+}
+
+// Controlled-X: swap the target pair where the control bit is 1 (touches half the state).
+template <typename T>
+__global__ void __launch_bounds__(256) plain_cx_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
+                                                       int pc, int pt, int64_t nquads) {
+  using C = typename Cx<T>::type;
+  C* s = st + smap.at(blockIdx.y);
+  const int plo = pc < pt ? pc : pt, phi = pc < pt ? pt : pc;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nquads; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = insert_zero(insert_zero(k, plo), phi) | (int64_t(1) << pc);
+    int64_t j = i | (int64_t(1) << pt);
+    C a = s[i], b = s[j];
+    s[i] = b;
+    s[j] = a;
+  }
+}
+
+// CZ: negate the quarter of amplitudes with both bits 1.
+template <typename T>
+__global__ void __launch_bounds__(256) plain_cz_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
+                                                       int pa, int pb, int64_t nquads) {
+  using C = typename Cx<T>::type;
+  C* s = st + smap.at(blockIdx.y);
+  const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nquads; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = insert_zero(insert_zero(k, plo), phi) | (int64_t(1) << pa) | (int64_t(1) << pb);
+    C a = s[i];
+    a.x = -a.x;
+    a.y = -a.y;
+    s[i] = a;
+  }
+}
+
+// Diagonal on one or two qubits: every amplitude times d[2*bit(pa)+bit(pb)] (pb < 0: d[bit(pa)]).
+template <typename T>
+__global__ void __launch_bounds__(256) plain_diag_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
+                                                         int pa, int pb, int64_t namps,
+                                                         const typename Cx<T>::type* __restrict__ mats,
+                                                         int64_t mats_stride, int mat) {
+  using C = typename Cx<T>::type;
+  C* s = st + smap.at(blockIdx.y);
+  const C* D = mats + (int64_t)blockIdx.y * mats_stride + 4 * (int64_t)mat;
+  const C d0 = D[0], d1 = D[1], d2 = D[2], d3 = D[3];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
+    const int ba = (int)((i >> pa) & 1);
+    const int bb = pb < 0 ? ba : (int)((i >> pb) & 1);
+    const bool two = pb >= 0;
+    C d;
+    d.x = ba ? (two ? (bb ? d3.x : d2.x) : d1.x) : (two ? (bb ? d1.x : d0.x) : d0.x);
+    d.y = ba ? (two ? (bb ? d3.y : d2.y) : d1.y) : (two ? (bb ? d1.y : d0.y) : d0.y);
+    s[i] = cmul(d, s[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Fused LDS-tile stage. A work-group owns one tile: 2^t amplitudes whose index varies
+// over the stage's local bit positions (lpos) with the other bits fixed by the tile id.
+// Each thread holds 2^R amplitudes in registers. Loads and stores use the layout where
+// the register bits are the top R local bits, so consecutive threads touch consecutive
+// addresses (the lowest local positions are the lowest index bits). Each phase applies
+// its ops on the register-resident target bits; switching the register bit set is one
+// exchange through LDS (XOR-swizzled to spread banks).
+// ---------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ uint32_t lds_swz(uint32_t li) {
+  // fold higher G-bit groups into the low G bits (a bijection on [0, 2^t))
+  constexpr int G = sizeof(T) == 4 ? 5 : 4;
+  constexpr uint32_t mask = (1u << G) - 1;
+  return li ^ (((li >> G) ^ (li >> (2 * G)) ^ (li >> (3 * G))) & mask);
+}
+
+template <typename T, int R, int B>
+__device__ __forceinline__ void reg_mat(typename Cx<T>::type (&v)[1 << R], typename Cx<T>::type m0,
+                                        typename Cx<T>::type m1, typename Cx<T>::type m2,
+                                        typename Cx<T>::type m3) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    if (j & (1 << B)) continue;
+    const int j1 = j | (1 << B);
+    auto a = v[j], b = v[j1];
+    v[j] = cfma2(m0, a, m1, b);
+    v[j1] = cfma2(m2, a, m3, b);
+  }
+}
+
+template <typename T, int R, int B>
+__device__ __forceinline__ void reg_cx(typename Cx<T>::type (&v)[1 << R], const uint32_t (&li)[1 << R],
+                                       int pc, int t, uint32_t tile) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    if (j & (1 << B)) continue;
+    const int j1 = j | (1 << B);
+    const uint32_t cb = pc < t ? ((li[j] >> pc) & 1u) : ((tile >> (pc - t)) & 1u);
+    auto a = v[j], b = v[j1];
+    v[j] = cb ? b : a;
+    v[j1] = cb ? a : b;
+  }
+}
+
+template <typename T, int R, typename F>
+__device__ __forceinline__ void dispatch_bit(int b, F&& f) {
+  switch (b) {
+    case 0: if constexpr (R > 0) f(std::integral_constant<int, 0>{}); break;
+    case 1: if constexpr (R > 1) f(std::integral_constant<int, 1>{}); break;
+    case 2: if constexpr (R > 2) f(std::integral_constant<int, 2>{}); break;
+    case 3: if constexpr (R > 3) f(std::integral_constant<int, 3>{}); break;
+    case 4: if constexpr (R > 4) f(std::integral_constant<int, 4>{}); break;
+    case 5: if constexpr (R > 5) f(std::integral_constant<int, 5>{}); break;
+    default: break;
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], const uint32_t (&li)[1 << R],
+                                                const DevOp* __restrict__ ops, int ob, int oe,
+                                                const typename Cx<T>::type* __restrict__ M, int t,
+                                                uint32_t tile) {
+  using C = typename Cx<T>::type;
+  for (int o = ob; o < oe; ++o) {
+    const DevOp op = load_op(ops, o);
+    if (op.kind == K_MAT1) {
+      const C* m = M + 4 * (int64_t)op.mat;
+      const C m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+#define TQ_MAT_CASE(B) \
+  case B:              \
+    if constexpr (R > B) reg_mat<T, R, (R > B ? B : 0)>(v, m0, m1, m2, m3); \
+    break;
+      switch (op.rbit) { TQ_MAT_CASE(0) TQ_MAT_CASE(1) TQ_MAT_CASE(2) TQ_MAT_CASE(3) TQ_MAT_CASE(4) default: break; }
+#undef TQ_MAT_CASE
+    } else if (op.kind == K_CX) {
+#define TQ_CX_CASE(B) \
+  case B:             \
+    if constexpr (R > B) reg_cx<T, R, (R > B ? B : 0)>(v, li, op.pa, t, tile); \
+    break;
+      switch (op.rbit) { TQ_CX_CASE(0) TQ_CX_CASE(1) TQ_CX_CASE(2) TQ_CX_CASE(3) TQ_CX_CASE(4) default: break; }
+#undef TQ_CX_CASE
+    } else if (op.kind == K_CZ) {
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
+        uint32_t bb = op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u);
+        if (ba & bb) { v[j].x = -v[j].x; v[j].y = -v[j].y; }
+      }
+    } else {
+      const C* d = M + 4 * (int64_t)op.mat;
+      const C d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+      const bool two = op.kind == K_DIAG2;
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        const uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
+        const uint32_t bb = !two ? ba : (op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u));
+        C f;
+        f.x = ba ? (two ? (bb ? d3.x : d2.x) : d1.x) : (two ? (bb ? d1.x : d0.x) : d0.x);
+        f.y = ba ? (two ? (bb ? d3.y : d2.y) : d1.y) : (two ? (bb ? d1.y : d0.y) : d0.y);
+        v[j] = cmul(f, v[j]);
+      }
+    }
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restrict__ stg,
+                                                        const DevPhase* __restrict__ phases,
+                                                        const DevOp* __restrict__ ops,
+                                                        const typename Cx<T>::type* __restrict__ mats,
+                                                        int64_t mats_stride, typename Cx<T>::type* __restrict__ state,
+                                                        BatchMap smap) {
+  using C = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int t = stg->t;
+  const int tb = t - R;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  C* st = state + smap.at(blockIdx.y);
+  const C* M = mats + (int64_t)blockIdx.y * mats_stride;
+
+  // global offsets of this thread's amplitudes in the load/store layout
+  int64_t base = 0;
+  for (int k = 0; k < stg->n_nonlocal; ++k) base |= (int64_t)((tile >> k) & 1u) << stg->npos[k];
+  int64_t thr = 0;
+  for (int k = 0; k < tb; ++k) thr |= (int64_t)((tid >> k) & 1u) << stg->lpos[k];
+  C* const sb = st + (base | thr);
+  C v[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    int64_t hi = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    v[j] = sb[hi];
+  }
+
+  // local indices in the current layout (load layout: registers = top R local bits)
+  uint32_t li[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
+
+  bool first_x = true;
+  for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
+    const DevPhase& ph = phases[p];
+    if (ph.xchg) {
+      if (!first_x) __syncthreads();
+      first_x = false;
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
+      uint32_t tp = 0;
+      for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        uint32_t rp = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << ph.rpos[k];
+        li[j] = tp | rp;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(li[j])];
+    }
+    apply_phase_ops<T, R>(v, li, ops, ph.op_begin, ph.op_end, M, t, tile);
+  }
+  if (stg->store_xchg) {
+    if (!first_x) __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(tid | ((uint32_t)j << tb))];
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    int64_t hi = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    sb[hi] = v[j];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Expectation values of Z-strings: per-block partial sums (double, fixed tree), then a
+// per-(circuit, observable) pass over the partials in block order.
+// ---------------------------------------------------------------------------------
+constexpr int kMaxObs = 8;
+constexpr int kExpThreads = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kExpThreads) expval_partial_kernel(
+    const typename Cx<T>::type* __restrict__ st, BatchMap smap, int64_t namps, int64_t per_block,
+    const uint64_t* __restrict__ pmask, const double* __restrict__ coeff, const int32_t* __restrict__ obs,
+    int n_terms, int obs_lo, int n_obs_here, double* __restrict__ partial, int nblocks) {
+  using C = typename Cx<T>::type;
+  const C* s = st + smap.at(blockIdx.y);
+  double acc[kMaxObs];
+#pragma unroll
+  for (int o = 0; o < kMaxObs; ++o) acc[o] = 0.0;
+  const int64_t b0 = (int64_t)blockIdx.x * per_block;
+  const int64_t b1 = b0 + per_block < namps ? b0 + per_block : namps;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    C a = s[i];
+    double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    for (int k = 0; k < n_terms; ++k) {
+      int o = obs[k] - obs_lo;
+      if (o < 0 || o >= n_obs_here) continue;
+      double sg = (__popcll((uint64_t)i & pmask[k]) & 1) ? -coeff[k] : coeff[k];
+#pragma unroll
+      for (int q = 0; q < kMaxObs; ++q)
+        if (q == o) acc[q] += sg * pr;
+    }
+  }
+  __shared__ double red[kExpThreads / 64][kMaxObs];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 0; o < kMaxObs; ++o) {
+    double x = acc[o];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wv][o] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < n_obs_here) {
+    double x = 0.0;
+    for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][threadIdx.x];
+    partial[((int64_t)blockIdx.y * nblocks + blockIdx.x) * kMaxObs + threadIdx.x] = x;
+  }
+}
+
+template <typename T>
+__global__ void expval_final_kernel(const double* __restrict__ partial, int nblocks, int count, int n_obs_here,
+                                    int obs_lo, int n_obs, T* __restrict__ out) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= count * n_obs_here) return;
+  const int circ = gid / n_obs_here, o = gid % n_obs_here;
+  double x = 0.0;
+  for (int b = 0; b < nblocks; ++b) x += partial[((int64_t)circ * nblocks + b) * kMaxObs + o];
+  out[(int64_t)circ * n_obs + obs_lo + o] = (T)x;
+}
+
+// ---------------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------------
+template <typename T>
+tq_status launch_gate_build(const Schedule& s, const void* d_params, BatchMap pmap, void* d_mats, int count,
+                            hipStream_t stream) {
+  const int n_mats = (int)s.recipes.size();
+  if (n_mats == 0 || count == 0) return TQ_OK;
+  const int64_t total = (int64_t)n_mats * count;
+  const int threads = 128;
+  const int64_t blocks = (total + threads - 1) / threads;
+  hipLaunchKernelGGL(gate_build_kernel<T>, dim3((unsigned)blocks), dim3(threads), 0, stream,
+                     (const tq_gate*)s.d_gates, (const int32_t*)s.d_rec, (const int32_t*)s.d_rec_gates, n_mats,
+                     (const T*)d_params, pmap, (typename Cx<T>::type*)d_mats, count);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+static inline unsigned sweep_blocks(int64_t work, int n_cu) {
+  int64_t b = (work + 255) / 256;
+  int64_t cap = (int64_t)n_cu * 16;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <typename T>
+tq_status launch_plain(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
+                       int n_cu, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int n = s.n;
+  const int64_t namps = int64_t(1) << n;
+  const int64_t mstride = 4 * (int64_t)s.recipes.size();
+  C* st = (C*)d_states;
+  const C* M = (const C*)d_mats;
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    BatchMap sm = smap.shifted(c0);
+    const C* Mc = M + (int64_t)c0 * mstride;
+    for (const HostOp& o : s.ops) {
+      const int pa = n - 1 - o.qa;
+      const int pb = o.qb >= 0 ? n - 1 - o.qb : -1;
+      if (o.kind == K_MAT1) {
+        hipLaunchKernelGGL(plain_mat1_kernel<T>, dim3(sweep_blocks(namps / 2, n_cu), cn), dim3(256), 0, stream,
+                           st, sm, pa, namps / 2, Mc, mstride, o.mat);
+      } else if (o.kind == K_CX) {
+        // qa = target, qb = control
+        hipLaunchKernelGGL(plain_cx_kernel<T>, dim3(sweep_blocks(namps / 4, n_cu), cn), dim3(256), 0, stream,
+                           st, sm, pb, pa, namps / 4);
+      } else if (o.kind == K_CZ) {
+        hipLaunchKernelGGL(plain_cz_kernel<T>, dim3(sweep_blocks(namps / 4, n_cu), cn), dim3(256), 0, stream,
+                           st, sm, pa, pb, namps / 4);
+      } else {
+        hipLaunchKernelGGL(plain_diag_kernel<T>, dim3(sweep_blocks(namps, n_cu), cn), dim3(256), 0, stream, st, sm,
+                           pa, o.kind == K_DIAG2 ? pb : -1, namps, Mc, mstride, o.mat);
+      }
+      TQ_HIP(hipGetLastError());
+    }
+  }
+  return TQ_OK;
+}
+
+template <typename T, int R>
+static tq_status launch_stages_R(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
+                                 hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int64_t mstride = 4 * (int64_t)s.recipes.size();
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    BatchMap sm = smap.shifted(c0);
+    const C* Mc = (const C*)d_mats + (int64_t)c0 * mstride;
+    for (size_t k = 0; k < s.stages.size(); ++k) {
+      const int t = s.stages[k].t;
+      const unsigned tiles = 1u << (s.n - t);
+      const unsigned threads = 1u << (t - R);
+      const size_t lds = sizeof(C) << t;
+      hipLaunchKernelGGL((sv_stage_kernel<T, R>), dim3(tiles, cn), dim3(threads), lds, stream,
+                         (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
+                         mstride, (C*)d_states, sm);
+      TQ_HIP(hipGetLastError());
+    }
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
+                        hipStream_t stream) {
+  const int R = std::min(s.R, std::min(s.t, s.n));
+  switch (R) {
+    case 1: return launch_stages_R<T, 1>(s, d_states, smap, d_mats, count, stream);
+    case 2: return launch_stages_R<T, 2>(s, d_states, smap, d_mats, count, stream);
+    case 3: return launch_stages_R<T, 3>(s, d_states, smap, d_mats, count, stream);
+    case 4: return launch_stages_R<T, 4>(s, d_states, smap, d_mats, count, stream);
+    case 5: return launch_stages_R<T, 5>(s, d_states, smap, d_mats, count, stream);
+    default: return fail(TQ_ENOTSUP, "register bits must be 1..5");
+  }
+}
+
+template <typename T>
+tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count, const uint64_t* d_pmask,
+                        const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs, double* d_partial,
+                        size_t partial_cap, T* d_out, int n_cu, hipStream_t stream) {
+  const int64_t namps = int64_t(1) << n;
+  int64_t nblocks = (namps + 4095) / 4096;  // >= 4096 amplitudes per block
+  if (nblocks > 2048) nblocks = 2048;
+  const int64_t per_block = (namps + nblocks - 1) / nblocks;
+  (void)n_cu;
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    if ((size_t)cn * nblocks * kMaxObs * sizeof(double) > partial_cap) return fail(TQ_ENOMEM, "expval partial buffer");
+    for (int o0 = 0; o0 < n_obs; o0 += kMaxObs) {
+      const int no = std::min(kMaxObs, n_obs - o0);
+      hipLaunchKernelGGL(expval_partial_kernel<T>, dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
+                         d_states, smap.shifted(c0), namps, per_block, d_pmask, d_coeff, d_obs, n_terms, o0, no,
+                         d_partial, (int)nblocks);
+      TQ_HIP(hipGetLastError());
+      const int fin = cn * no;
+      hipLaunchKernelGGL(expval_final_kernel<T>, dim3((fin + 127) / 128), dim3(128), 0, stream, d_partial,
+                         (int)nblocks, cn, no, o0, n_obs, d_out + (int64_t)c0 * n_obs);
+      TQ_HIP(hipGetLastError());
+    }
+  }
+  return TQ_OK;
+}
+
+template tq_status launch_gate_build<float>(const Schedule&, const void*, BatchMap, void*, int, hipStream_t);
+template tq_status launch_gate_build<double>(const Schedule&, const void*, BatchMap, void*, int, hipStream_t);
+template tq_status launch_plain<float>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
+template tq_status launch_plain<double>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
+template tq_status launch_stages<float>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
+template tq_status launch_stages<double>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
+template tq_status launch_expval<float>(const float2*, BatchMap, int, int, const uint64_t*, const double*,
+                                        const int32_t*, int, int, double*, size_t, float*, int, hipStream_t);
+template tq_status launch_expval<double>(const double2*, BatchMap, int, int, const uint64_t*, const double*,
+                                         const int32_t*, int, int, double*, size_t, double*, int, hipStream_t);
+
+}  // namespace tq

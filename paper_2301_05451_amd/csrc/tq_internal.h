@@ -1,0 +1,150 @@
+// Internal declarations shared by the libtq translation units (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tq.h"
+
+namespace tq {
+
+// ---------------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+tq_status fail(tq_status st, const std::string& msg);
+
+#define TQ_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::tq::fail(TQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+#define TQ_TRY(expr)                 \
+  do {                               \
+    tq_status s_ = (expr);           \
+    if (s_ != TQ_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------------------------
+// Schedule: the host lowering of a gate list (built once per circuit structure).
+// ---------------------------------------------------------------------------------
+
+// Kinds of scheduled operations.
+enum OpKind : uint8_t {
+  K_MAT1 = 0,   // general 2x2 on one target qubit (a fused run of one-qubit gates)
+  K_CX = 1,     // controlled-X: target must be register-resident, control read from index
+  K_DIAG1 = 2,  // diagonal on one qubit (2 entries)
+  K_DIAG2 = 3,  // diagonal on two qubits (4 entries, index 2*bit(qa)+bit(qb))
+  K_CZ = 4,     // sign flip where both qubits are 1
+};
+
+// A matrix-table entry: how the gate-build kernel forms it from the original gates.
+enum RecipeKind : int32_t { R_MAT2 = 0, R_DIAG1 = 1, R_DIAG2 = 2 };
+
+struct HostOp {
+  int kind;
+  int qa;   // target (MAT1/CX) or first qubit (DIAG/CZ)
+  int qb;   // control (CX) or second qubit (DIAG2/CZ), else -1
+  int mat;  // matrix-table index or -1
+  int src;  // original gate index for recipe-less ops (CX, CZ), else -1
+};
+
+struct Recipe {
+  int kind;
+  int qa, qb;
+  std::vector<int> gates;  // original gate indices, application order
+};
+
+// Device-side descriptors (plain structs, copied verbatim to device memory).
+struct DevOp {
+  uint8_t kind;
+  uint8_t rbit;  // MAT1/CX: target's register-bit index within the phase
+  uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX)
+  uint8_t pb;    // x-position of qb (DIAG2/CZ)
+  int32_t mat;
+};
+static_assert(sizeof(DevOp) == 8, "DevOp layout");
+
+constexpr int kMaxReg = 6;
+struct DevPhase {
+  int32_t op_begin, op_end;
+  int32_t xchg;      // 1: the register layout differs from the previous one (LDS exchange)
+  uint8_t rpos[8];   // tile-local positions of the register bits (kMaxReg used)
+  uint8_t tpos[24];  // tile-local positions of the thread bits, ascending
+};
+
+constexpr int kMaxQ = 40;
+struct DevStage {
+  int32_t t;            // local bits
+  int32_t phase_begin, phase_end;
+  int32_t n_nonlocal;
+  int32_t store_xchg;   // 1: last phase layout differs from the store layout
+  uint8_t lpos[kMaxQ];  // global bit positions of local bits, ascending
+  uint8_t npos[kMaxQ];  // global bit positions of non-local bits, ascending
+};
+
+struct StageHost {
+  int t = 0;
+  std::vector<int> lpos, npos;
+  int phase_begin = 0, phase_end = 0;
+  int n_ops = 0;
+};
+
+struct Schedule {
+  int n = 0;
+  int mode = 0;  // 0 fused, 1 plain
+  int t = 0, R = 0, c = 0;
+  std::vector<Recipe> recipes;
+  std::vector<HostOp> ops;  // fused/plain op list, in a valid execution order
+  // fused form
+  std::vector<StageHost> stages;
+  std::vector<DevPhase> phases;
+  std::vector<DevOp> dops;
+  std::vector<DevStage> dstages;
+  // device copies (owned)
+  void* d_gates = nullptr;      // tq_gate[n_gates]
+  void* d_rec = nullptr;        // int32 [n_mats][4]: kind, qa, qb, begin ; + end in next
+  void* d_rec_gates = nullptr;  // int32 flat constituent gate indices
+  void* d_ops = nullptr;        // DevOp
+  void* d_phases = nullptr;     // DevPhase
+  void* d_stages = nullptr;     // DevStage
+  int n_gates = 0;
+  ~Schedule();
+};
+
+// Lowering passes (schedule.cpp).
+void lower_ops(const tq_gate* g, int n_gates, int n, bool fuse, std::vector<Recipe>& recipes,
+               std::vector<HostOp>& ops);
+void build_stages(Schedule& s);
+tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params);
+
+}  // namespace tq
+
+// The context (opaque in the public header).
+struct tq_ctx {
+  int device = 0;
+  int n_cu = 256;
+  size_t lds_max = 160 * 1024;
+  std::unordered_map<std::string, std::unique_ptr<tq::Schedule>> schedules;
+  // grow-only device scratch buffers
+  void* scratch[8] = {nullptr};
+  size_t scratch_bytes[8] = {0};
+  // immutable small device tables cached by content hash
+  std::unordered_map<std::string, void*> tables;
+  // autotune results: key -> (t, R)
+  std::unordered_map<std::string, std::pair<int, int>> tuned;
+};
+
+namespace tq {
+// scratch slots
+enum { S_MATS = 0, S_PARTIAL = 1, S_OFFS = 2, S_LAMBDA = 3, S_PSI = 4, S_GRADP = 5, S_TERMS = 6, S_MISC = 7 };
+tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out);
+}  // namespace tq

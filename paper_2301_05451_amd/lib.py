@@ -1,0 +1,235 @@
+"""ctypes binding of ``libtq.so`` (argument marshalling only; every step runs in HIP kernels).
+
+Raises at import if the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtq.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_05451_amd.build`")
+_lib = ct.CDLL(LIB_PATH)
+
+HIP_BUILD_VERSION = _lib.tq_hip_build_version()
+HIP_RUNTIME_VERSION = _lib.tq_hip_runtime_version()
+
+
+def _major_minor(v):
+    return (v // 10000000, (v // 100000) % 100) if v >= 0 else (-1, -1)
+
+
+if _major_minor(HIP_RUNTIME_VERSION) < _major_minor(HIP_BUILD_VERSION):
+    raise ImportError(
+        f"libtq.so was built for HIP {HIP_BUILD_VERSION} but is bound to an older HIP runtime "
+        f"{HIP_RUNTIME_VERSION} (torch's bundled one): import paper_2301_05451_amd before torch")
+
+TQ_C64, TQ_C128 = 0, 1
+STATUS = {0: "TQ_OK", 1: "TQ_EINVAL", 2: "TQ_ESIZE", 3: "TQ_ENOTSUP", 4: "TQ_EHIP", 5: "TQ_EWORKSPACE", 6: "TQ_ENOMEM"}
+
+
+class TQError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Batch(ct.Structure):
+    _fields_ = [("count", ct.c_int32), ("n_qubits", ct.c_void_p), ("gate_off", ct.c_void_p),
+                ("n_gates", ct.c_void_p), ("param_off", ct.c_void_p), ("state_off", ct.c_void_p)]
+
+
+class SvOpts(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("tile_bits", ct.c_int32), ("reg_bits", ct.c_int32), ("coal_bits", ct.c_int32)]
+
+
+_vp = ct.c_void_p
+_i32 = ct.c_int32
+_lib.tq_last_error.restype = ct.c_char_p
+_lib.tq_version.restype = ct.c_int
+_lib.tq_ctx_create.argtypes = [ct.c_int, ct.POINTER(_vp)]
+_lib.tq_ctx_create.restype = ct.c_int
+_lib.tq_ctx_destroy.argtypes = [_vp]
+_lib.tq_ctx_destroy.restype = None
+_lib.tq_sv_apply.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, ct.POINTER(SvOpts), _vp]
+_lib.tq_sv_apply.restype = ct.c_int
+_lib.tq_expval.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _i32, _i32, _vp, _vp]
+_lib.tq_expval.restype = ct.c_int
+if hasattr(_lib, "tq_sv_backward"):
+    _lib.tq_sv_backward.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
+                                    _vp, ct.POINTER(SvOpts), _vp]
+    _lib.tq_sv_backward.restype = ct.c_int
+
+
+def raw():
+    """The loaded ctypes library (for tests that call the C ABI directly)."""
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        raise TQError(status, _lib.tq_last_error().decode())
+
+
+def last_error():
+    return _lib.tq_last_error().decode()
+
+
+class Context:
+    def __init__(self, device=0):
+        h = _vp()
+        check(_lib.tq_ctx_create(int(device), ct.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _lib.tq_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ctx = {}
+
+
+def context(device=None):
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]
+
+
+class BatchSpec:
+    """Host arrays of a tq_batch plus the concatenated gate list and per-circuit sizes."""
+
+    def __init__(self, n_qubits, gate_off, n_gates, param_off, state_off, n_params, gates):
+        self.n_qubits = np.ascontiguousarray(n_qubits, dtype=np.int32)
+        self.gate_off = np.ascontiguousarray(gate_off, dtype=np.int64)
+        self.n_gates = np.ascontiguousarray(n_gates, dtype=np.int32)
+        self.param_off = np.ascontiguousarray(param_off, dtype=np.int64)
+        self.state_off = np.ascontiguousarray(state_off, dtype=np.int64)
+        self.n_params = np.ascontiguousarray(n_params, dtype=np.int32)
+        self.gates = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+        self.count = int(self.n_qubits.shape[0])
+        self.total_amps = int(max((self.state_off + (1 << self.n_qubits.astype(np.int64))).max(), 0)) if self.count else 0
+        self.total_params = int((self.param_off + self.n_params).max()) if self.count else 0
+        self._c = Batch(self.count, self.n_qubits.ctypes.data, self.gate_off.ctypes.data, self.n_gates.ctypes.data,
+                        self.param_off.ctypes.data, self.state_off.ctypes.data)
+
+    @property
+    def c(self):
+        return self._c
+
+    @staticmethod
+    def uniform(n, gates, count, n_params):
+        """``count`` circuits sharing one gate list; params [count, n_params], states [count, 2^n]."""
+        g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+        return BatchSpec(np.full(count, n), np.zeros(count), np.full(count, g.shape[0]),
+                         np.arange(count) * n_params, np.arange(count) * (1 << n), np.full(count, n_params), g)
+
+    @staticmethod
+    def from_circuits(circs):
+        """Circuits of different structure packed one after another."""
+        gates, goff, poff, soff = [], [], [], []
+        go = po = so = 0
+        for c in circs:
+            goff.append(go); poff.append(po); soff.append(so)
+            gates.append(c.gates)
+            go += c.gates.shape[0]; po += c.n_params; so += 1 << c.n
+        g = np.concatenate(gates) if gates else np.zeros(0, dtype=W.GATE_DTYPE)
+        return BatchSpec([c.n for c in circs], goff, [c.gates.shape[0] for c in circs], poff, soff,
+                         [c.n_params for c in circs], g)
+
+
+def _dt(states):
+    import torch
+    if states.dtype == torch.complex64:
+        return TQ_C64
+    if states.dtype == torch.complex128:
+        return TQ_C128
+    raise TypeError("states must be complex64 or complex128")
+
+
+def _stream():
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _opts(mode=0, tile_bits=0, reg_bits=0, coal_bits=0):
+    return SvOpts(int(mode), int(tile_bits), int(reg_bits), int(coal_bits))
+
+
+def _check_tensors(states, params, spec):
+    import torch
+    if not states.is_cuda or not states.is_contiguous():
+        raise ValueError("states must be a contiguous CUDA tensor")
+    if states.numel() < spec.total_amps:
+        raise ValueError(f"states has {states.numel()} amplitudes, batch needs {spec.total_amps}")
+    want = torch.float32 if states.dtype == torch.complex64 else torch.float64
+    if params is not None:
+        if params.dtype != want or not params.is_cuda or not params.is_contiguous():
+            raise ValueError(f"params must be a contiguous CUDA {want} tensor")
+        if params.numel() < spec.total_params:
+            raise ValueError("params tensor too small for the batch")
+
+
+def sv_apply(states, params, spec: BatchSpec, mode=0, tile_bits=0, reg_bits=0, coal_bits=0, ctx=None):
+    """In-place |psi_i> <- U_i |psi_i> for every circuit of ``spec`` (tq_sv_apply)."""
+    _check_tensors(states, params, spec)
+    ctx = ctx or context(states.device.index)
+    o = _opts(mode, tile_bits, reg_bits, coal_bits)
+    check(_lib.tq_sv_apply(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data, spec.n_params.ctypes.data,
+                           params.data_ptr(), states.data_ptr(), ct.byref(o), _stream()))
+    return states
+
+
+def expval(states, spec: BatchSpec, terms, n_obs, ctx=None):
+    """[count, n_obs] real expectation values of Z-string sums (tq_expval)."""
+    import torch
+    _check_tensors(states, None, spec)
+    ctx = ctx or context(states.device.index)
+    terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
+    rdt = torch.float32 if states.dtype == torch.complex64 else torch.float64
+    out = torch.empty((spec.count, n_obs), dtype=rdt, device=states.device)
+    check(_lib.tq_expval(ctx.h, _dt(states), ct.byref(spec.c), states.data_ptr(), terms.ctypes.data,
+                         int(terms.shape[0]), int(n_obs), out.data_ptr(), _stream()))
+    return out
+
+
+def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0, tile_bits=0, reg_bits=0, ctx=None):
+    """Adjoint gradients d(sum grad_out * <O>)/d params, same layout as params (tq_sv_backward)."""
+    import torch
+    _check_tensors(states, params, spec)
+    ctx = ctx or context(states.device.index)
+    terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
+    grad_out = grad_out.contiguous()
+    grad = torch.empty_like(params)
+    o = _opts(mode, tile_bits, reg_bits, 0)
+    check(_lib.tq_sv_backward(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data,
+                              spec.n_params.ctypes.data, params.data_ptr(), states.data_ptr(), terms.ctypes.data,
+                              int(terms.shape[0]), int(n_obs), grad_out.data_ptr(), grad.data_ptr(), ct.byref(o),
+                              _stream()))
+    return grad
+
+
+def zero_states(spec: BatchSpec, dtype, device="cuda"):
+    """|0..0> for every circuit of the batch (torch fill on the device)."""
+    import torch
+    st = torch.zeros(spec.total_amps, dtype=dtype, device=device)
+    idx = torch.as_tensor(spec.state_off, device=device)
+    st[idx] = 1.0
+    return st
