@@ -130,6 +130,20 @@ tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_
                       const int32_t* n_params, const void* d_params, void* d_states,
                       const tq_sv_opts* opts, void* stream);
 
+/* Writes the computational basis state |basis> into every circuit's state (the default
+ * initial state of Sec. 3.1 is basis = 0). Errors: TQ_EINVAL if basis is outside [0, 2^n). */
+tq_status tq_sv_init(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, int64_t basis, void* d_states,
+                     void* stream);
+
+/* Shape of the schedule tq_sv_apply uses for one circuit structure (host only, builds and
+ * caches it like tq_sv_apply does). out[0] = HBM sweeps (kernel launches: stages in fused
+ * mode, ops in plain mode), out[1] = scheduled ops after fusion, out[2] = register phases,
+ * out[3] = LDS exchanges, out[4] = tile bits used, out[5] = register bits used,
+ * out[6] = real flops per amplitude summed over ops (14 per 2x2, 6 per diagonal, 0 for
+ * CNOT/CZ), out[7] = one-qubit matrices built per circuit. */
+tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_gate* gates,
+                          int32_t n_gates, const tq_sv_opts* opts, int64_t out[8]);
+
 /* Sec. 4 cost: d_out[i * n_obs + o] = sum over terms with obs == o of
  * coeff * <psi_i| Z-string |psi_i> (real; accumulated in double with a fixed reduction
  * order, written in the dtype's real precision). Terms name qubits (bit q = qubit q). */

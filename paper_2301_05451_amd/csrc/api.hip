@@ -18,7 +18,8 @@ tq_status fail(tq_status st, const std::string& msg) {
 }
 
 Schedule::~Schedule() {
-  void* ptrs[] = {d_gates, d_rec, d_rec_gates, d_ops, d_phases, d_stages};
+  void* ptrs[] = {d_gates,  d_rec,       d_rec_gates,   d_ops,         d_phases,
+                  d_stages, d_dslot,     d_pslot_ptr,   d_pslot_idx,   d_pslot_scale, d_stage_slot0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -136,6 +137,7 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
     if (t < 1 || t > 14 || (csz << t) > ctx->lds_max)
       return fail(TQ_EINVAL, "tile_bits " + std::to_string(t) + " does not fit LDS for this dtype");
     if (R < 1 || R > 5) return fail(TQ_EINVAL, "reg_bits must be in 1..5");
+    if (dt == TQ_C128 && R > 4) return fail(TQ_EINVAL, "reg_bits must be <= 4 for complex128 (register file)");
     if (t - std::min(R, t) > 10) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 10 (1024 threads)");
     if (c < 0 || c > 10) return fail(TQ_EINVAL, "coal_bits must be in 0..10");
   } else {
@@ -159,6 +161,66 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
   TQ_TRY(upload_schedule(*s, g, n_gates));
   *out = s.get();
   ctx->schedules.emplace(key, std::move(s));
+  return TQ_OK;
+}
+
+// Reverse-sweep schedule of a circuit structure (cached; key mode 2).
+tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, const tq_sv_opts* opts,
+                               Schedule** out) {
+  int t = dt == TQ_C64 ? 12 : 11, R = dt == TQ_C64 ? 4 : 3, c = dt == TQ_C64 ? 5 : 4;
+  if (opts) {
+    if (opts->tile_bits) t = opts->tile_bits;
+    if (opts->reg_bits) R = opts->reg_bits;
+    if (opts->coal_bits) c = opts->coal_bits;
+  }
+  t = std::min(t, n);
+  const size_t csz = dt == TQ_C64 ? 8 : 16;
+  if (t < 1 || t > 13 || 2 * (csz << t) + 16384 > ctx->lds_max)
+    return fail(TQ_EINVAL, "adjoint tile_bits " + std::to_string(t) + " does not fit LDS (two tiles)");
+  if (R < 1 || R > 4) return fail(TQ_EINVAL, "adjoint reg_bits must be in 1..4");
+  if (t - std::min(R, t) > 9) return fail(TQ_EINVAL, "adjoint tile_bits - reg_bits must be <= 9 (512 threads)");
+  std::string key = schedule_key(g, n_gates, n, 2, t, R, c);
+  auto it = ctx->schedules.find(key);
+  if (it != ctx->schedules.end()) {
+    *out = it->second.get();
+    return TQ_OK;
+  }
+  auto s = std::make_unique<Schedule>();
+  s->n = n;
+  s->mode = 2;
+  s->adjoint = true;
+  s->t = t;
+  s->R = R;
+  s->c = c;
+  s->n_gates = n_gates;
+  lower_adjoint_ops(g, n_gates, s->ops);
+  build_stages(*s);
+  build_adjoint_slots(*s, g, n_gates);
+  TQ_TRY(upload_schedule(*s, g, n_gates));
+  TQ_TRY(to_device(s->dslot, &s->d_dslot));
+  TQ_TRY(to_device(s->pslot_ptr, &s->d_pslot_ptr));
+  TQ_TRY(to_device(s->pslot_idx, &s->d_pslot_idx));
+  TQ_TRY(to_device(s->pslot_scale, &s->d_pslot_scale));
+  *out = s.get();
+  ctx->schedules.emplace(key, std::move(s));
+  return TQ_OK;
+}
+
+// Observable terms in device form: [pos masks (u64)] [coeffs (f64)] [obs (i32)], masks over
+// bit positions of an n-qubit index.
+static tq_status term_table(tq_ctx* ctx, int n, const tq_zterm* terms, int n_terms, const unsigned char** dev) {
+  std::vector<unsigned char> blob((size_t)n_terms * 20 + 64, 0);
+  for (int k = 0; k < n_terms; ++k) {
+    uint64_t m = 0;
+    for (int q = 0; q < n; ++q)
+      if ((terms[k].mask >> q) & 1ull) m |= 1ull << (n - 1 - q);
+    std::memcpy(blob.data() + 8 * k, &m, 8);
+    std::memcpy(blob.data() + (size_t)n_terms * 8 + 8 * k, &terms[k].coeff, 8);
+    std::memcpy(blob.data() + (size_t)n_terms * 16 + 4 * k, &terms[k].obs, 4);
+  }
+  void* d;
+  TQ_TRY(cached_table(ctx, blob.data(), blob.size(), &d));
+  *dev = (const unsigned char*)d;
   return TQ_OK;
 }
 
@@ -294,26 +356,83 @@ static tq_status expval_t(tq_ctx* ctx, const tq_batch* batch, const void* d_stat
     // outputs: contiguous rows when the members are consecutive batch entries
     bool consecutive = true;
     for (size_t i = 1; i < mem.size(); ++i) consecutive = consecutive && mem[i] == mem[0] + (int)i;
-    const int64_t namps = int64_t(1) << n;
-    int64_t nblocks = std::min<int64_t>((namps + 4095) / 4096, 2048);
+    const size_t pcap = expval_scratch_doubles(n, (int)mem.size(), n_obs);
     void* partial;
-    size_t pcap = std::min<size_t>(mem.size(), 65535) * nblocks * 8 * sizeof(double);
-    TQ_TRY(scratch(ctx, S_PARTIAL, pcap, &partial));
+    TQ_TRY(scratch(ctx, S_PARTIAL, pcap * sizeof(double), &partial));
     T* out = (T*)d_out;
     if (consecutive) {
       TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, smap, n, (int)mem.size(),
                               (const uint64_t*)db, (const double*)(db + n_terms * 8),
                               (const int32_t*)(db + n_terms * 16), n_terms, n_obs, (double*)partial, pcap,
-                              out + (int64_t)mem[0] * n_obs, ctx->n_cu, stream));
+                              out + (int64_t)mem[0] * n_obs, stream));
     } else {
       for (int i : mem) {
         BatchMap one{nullptr, batch->state_off[i], 0};
         TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, one, n, 1, (const uint64_t*)db,
                                 (const double*)(db + n_terms * 8), (const int32_t*)(db + n_terms * 16), n_terms,
-                                n_obs, (double*)partial, pcap, out + (int64_t)i * n_obs, ctx->n_cu, stream));
+                                n_obs, (double*)partial, pcap, out + (int64_t)i * n_obs, stream));
       }
     }
     (void)omap;
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                               const void* d_params, const void* d_states, const tq_zterm* terms, int n_terms,
+                               int n_obs, const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
+                               hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int dt = sizeof(T) == 4 ? TQ_C64 : TQ_C128;
+  if (!n_params) return fail(TQ_EINVAL, "n_params is required for the backward pass");
+  std::vector<Group> groups;
+  TQ_TRY(group_batch(batch, n_params, groups));
+  if (n_obs < 1) return fail(TQ_EINVAL, "n_obs must be >= 1");
+  if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(TQ_EINVAL, "bad terms");
+  for (int k = 0; k < n_terms; ++k)
+    if (terms[k].obs < 0 || terms[k].obs >= n_obs) return fail(TQ_EINVAL, "term obs index out of range");
+  if (!groups.empty() && (!d_params || !d_states || !d_grad_out || !d_grad))
+    return fail(TQ_EINVAL, "null device pointer");
+  for (const Group& gr : groups) {
+    TQ_TRY(validate_gates(gates + gr.gate_off, gr.n_gates, gr.n, gr.n_params));
+    for (int i : gr.members)
+      if (n_params[i] != gr.n_params)
+        return fail(TQ_EINVAL, "circuits sharing a gate list must have equal n_params for the backward pass");
+    for (int k = 0; k < n_terms; ++k)
+      if (gr.n < 64 && (terms[k].mask >> gr.n) != 0) return fail(TQ_EINVAL, "term names a qubit >= n");
+  }
+  for (const Group& gr : groups) {
+    const tq_gate* g = gates + gr.gate_off;
+    Schedule* s;
+    TQ_TRY(get_adjoint_schedule(ctx, dt, g, gr.n_gates, gr.n, opts, &s));
+    const unsigned char* tt;
+    TQ_TRY(term_table(ctx, gr.n, terms, n_terms, &tt));
+    // members in runs of consecutive batch indices share one launch sequence
+    size_t i0 = 0;
+    while (i0 < gr.members.size()) {
+      size_t i1 = i0 + 1;
+      while (i1 < gr.members.size() && gr.members[i1] == gr.members[i1 - 1] + 1) ++i1;
+      std::vector<int> mem(gr.members.begin() + i0, gr.members.begin() + i1);
+      const int count = (int)mem.size();
+      BatchMap pmap, smap;
+      TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, mem, stream, &pmap));
+      TQ_TRY(member_map(ctx, S_MISC, batch->state_off, mem, stream, &smap));
+      const int64_t namps = int64_t(1) << gr.n;
+      const int64_t ntiles = s->stages.empty() ? 1 : (int64_t(1) << (gr.n - s->stages[0].t));
+      void *psi, *lam, *mats, *partial;
+      TQ_TRY(scratch(ctx, S_PSI, (size_t)count * namps * sizeof(C), &psi));
+      TQ_TRY(scratch(ctx, S_LAMBDA, (size_t)count * namps * sizeof(C), &lam));
+      TQ_TRY(scratch(ctx, S_MATS, (size_t)count * std::max(gr.n_gates, 1) * kAdjMatEntries * sizeof(C), &mats));
+      TQ_TRY(scratch(ctx, S_GRADP, (size_t)count * std::max(s->n_slots, 1) * ntiles * sizeof(double), &partial));
+      BatchMap wmap{nullptr, 0, namps};
+      TQ_TRY(launch_adjoint<T>(*s, d_params, pmap, d_states, smap, psi, lam, wmap, mats, (double*)partial,
+                               (const uint64_t*)tt, (const double*)(tt + n_terms * 8),
+                               (const int32_t*)(tt + n_terms * 16), n_terms,
+                               (const T*)d_grad_out + (int64_t)mem[0] * n_obs, n_obs, (T*)d_grad, gr.n_params,
+                               count, stream));
+      i0 = i1;
+    }
   }
   return TQ_OK;
 }
@@ -373,6 +492,61 @@ tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_
   return fail(TQ_EINVAL, "unknown dtype");
 }
 
+tq_status tq_sv_init(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, int64_t basis, void* d_states, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (dt != TQ_C64 && dt != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
+  std::vector<Group> groups;
+  TQ_TRY(group_batch(batch, nullptr, groups));
+  if (!groups.empty() && !d_states) return fail(TQ_EINVAL, "null device pointer");
+  std::map<int, std::vector<int>> by_n;
+  for (const Group& gr : groups) {
+    if (basis < 0 || (gr.n < 63 && basis >= (int64_t(1) << gr.n)))
+      return fail(TQ_EINVAL, "basis index outside [0, 2^n)");
+    for (int i : gr.members) by_n[gr.n].push_back(i);
+  }
+  for (auto& kv : by_n) {
+    std::sort(kv.second.begin(), kv.second.end());
+    BatchMap smap;
+    TQ_TRY(member_map(ctx, S_MISC, batch->state_off, kv.second, (hipStream_t)stream, &smap));
+    if (dt == TQ_C64)
+      TQ_TRY(launch_init_basis<float>(d_states, smap, kv.first, (int)kv.second.size(), basis, ctx->n_cu,
+                                      (hipStream_t)stream));
+    else
+      TQ_TRY(launch_init_basis<double>(d_states, smap, kv.first, (int)kv.second.size(), basis, ctx->n_cu,
+                                       (hipStream_t)stream));
+  }
+  return TQ_OK;
+}
+
+tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_gate* gates, int32_t n_gates,
+                          const tq_sv_opts* opts, int64_t out[8]) {
+  if (!ctx || !out) return fail(TQ_EINVAL, "null argument");
+  if (dt != TQ_C64 && dt != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
+  if (n_qubits < 1 || n_qubits > 34) return fail(TQ_ENOTSUP, "n_qubits must be in 1..34");
+  TQ_TRY(validate_gates(gates, n_gates, n_qubits, 0x7fffffff));
+  const int mode = opts ? opts->mode : 0;
+  if (mode != 0 && mode != 1) return fail(TQ_ENOTSUP, "sv mode must be 0 (fused) or 1 (plain)");
+  Schedule* s;
+  TQ_TRY(get_schedule(ctx, dt, gates, n_gates, n_qubits, mode, opts, &s));
+  int64_t flops = 0, mats = 0;
+  for (const HostOp& o : s->ops) {
+    if (o.kind == K_MAT1) flops += 14, ++mats;
+    else if (o.kind == K_DIAG1 || o.kind == K_DIAG2) flops += 6;
+  }
+  int64_t xch = 0;
+  for (const DevPhase& p : s->phases) xch += p.xchg;
+  for (const DevStage& d : s->dstages) xch += d.store_xchg;
+  out[0] = mode == 0 ? (int64_t)s->stages.size() : (int64_t)s->ops.size();
+  out[1] = (int64_t)s->ops.size();
+  out[2] = (int64_t)s->phases.size();
+  out[3] = xch;
+  out[4] = mode == 0 ? std::min(s->t, n_qubits) : 0;
+  out[5] = mode == 0 ? std::min(s->R, std::min(s->t, n_qubits)) : 0;
+  out[6] = flops;
+  out[7] = mats;
+  return TQ_OK;
+}
+
 tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states, const tq_zterm* terms,
                     int32_t n_terms, int32_t n_obs, void* d_out, void* stream) {
   if (!ctx) return fail(TQ_EINVAL, "null context");
@@ -382,3 +556,17 @@ tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void*
 }
 
 }  // extern "C"
+
+extern "C" tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                                    const int32_t* n_params, const void* d_params, const void* d_states,
+                                    const tq_zterm* terms, int32_t n_terms, int32_t n_obs, const void* d_grad_out,
+                                    void* d_grad, const tq_sv_opts* opts, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (dt == TQ_C64)
+    return sv_backward_t<float>(ctx, batch, gates, n_params, d_params, d_states, terms, n_terms, n_obs, d_grad_out,
+                                d_grad, opts, (hipStream_t)stream);
+  if (dt == TQ_C128)
+    return sv_backward_t<double>(ctx, batch, gates, n_params, d_params, d_states, terms, n_terms, n_obs, d_grad_out,
+                                 d_grad, opts, (hipStream_t)stream);
+  return fail(TQ_EINVAL, "unknown dtype");
+}

@@ -1,0 +1,138 @@
+// Expectation values of sums of Pauli-Z strings (the VQC cost of Sec. 4):
+// <O_o> = sum over terms k with obs_k = o of coeff_k * sum_x |psi_x|^2 (-1)^popcount(x & m_k).
+//
+// A work-group owns 2^pb contiguous amplitudes, so the index bits at and above pb are fixed
+// per group: their parity is one uniform sign per term, and each amplitude only needs a
+// 32-bit popcount of its low bits. Per-thread sums run in the state's precision over a
+// few dozen amplitudes; everything above (waves, the group, the groups of a circuit) is a
+// fixed-order double tree, so repeated runs are bitwise equal.
+#include "sv_device.h"
+
+namespace tq {
+
+constexpr int kExpThreads = 256;
+
+template <typename T, int KT>
+__global__ void __launch_bounds__(kExpThreads)
+    expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int pb,
+                          const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial, int nblocks) {
+  using C = typename Cx<T>::type;
+  const C* s = st + smap.at(blockIdx.y);
+  const uint64_t base = (uint64_t)blockIdx.x << pb;
+  const uint32_t lo_mask = (uint32_t)((uint64_t(1) << pb) - 1);
+  uint32_t mlo[KT];
+  T acc[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    mlo[k] = k < nk ? (uint32_t)(pmask[k] & lo_mask) : 0u;
+    acc[k] = (T)0;
+  }
+  const uint32_t namp = 1u << pb;
+  for (uint32_t loc = threadIdx.x; loc < namp; loc += kExpThreads) {
+    const C a = s[base + loc];
+    const T p = a.x * a.x + a.y * a.y;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) acc[k] += (__popc(loc & mlo[k]) & 1) ? -p : p;
+  }
+  __shared__ double red[kExpThreads / 64][KT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    double x = (double)acc[k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wv][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < nk && threadIdx.x < KT) {
+    const int k = threadIdx.x;
+    double x = 0.0;
+    for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][k];
+    const bool hi_odd = __popcll(base & pmask[k]) & 1;
+    partial[((int64_t)blockIdx.y * nblocks + blockIdx.x) * KT + k] = hi_odd ? -x : x;
+  }
+}
+
+// One work-group per circuit: for every term, a fixed-order tree over the groups' partials,
+// then thread 0 accumulates coeff * S_k into its observable, in term order.
+template <typename T, int KT>
+__global__ void __launch_bounds__(kExpThreads)
+    expval_final_kernel(const double* __restrict__ partial, int nblocks, int nk, const double* __restrict__ coeff,
+                        const int32_t* __restrict__ obs, int n_obs, double* __restrict__ outacc, int first,
+                        int last, T* __restrict__ out) {
+  __shared__ double red[kExpThreads];
+  const int circ = blockIdx.x;
+  double* acc = outacc + (int64_t)circ * n_obs;
+  if (first && threadIdx.x == 0)
+    for (int o = 0; o < n_obs; ++o) acc[o] = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kExpThreads) x += partial[((int64_t)circ * nblocks + b) * KT + k];
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = kExpThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[obs[k]] += coeff[k] * red[0];
+    __syncthreads();
+  }
+  if (last && threadIdx.x == 0)
+    for (int o = 0; o < n_obs; ++o) out[(int64_t)circ * n_obs + o] = (T)acc[o];
+}
+
+template <typename T, int KT>
+static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, int pb, int nblocks, int cn,
+                         const uint64_t* pm, const double* cf, const int32_t* ob, int nk, int n_obs, double* partial,
+                         double* outacc, int first, int last, T* out, hipStream_t stream) {
+  hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
+                     d_states, smap, pb, pm, nk, partial, nblocks);
+  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3(cn), dim3(kExpThreads), 0, stream, partial, nblocks, nk, cf, ob,
+                     n_obs, outacc, first, last, out);
+}
+
+int expval_block_bits(int n) { return n < 13 ? n : 13; }
+
+size_t expval_scratch_doubles(int n, int count, int n_obs) {
+  const int pb = expval_block_bits(n);
+  const int64_t nblocks = int64_t(1) << (n - pb);
+  const int cn = std::min(count, 65535);
+  return (size_t)cn * nblocks * 32 + (size_t)cn * n_obs + 64;
+}
+
+template <typename T>
+tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,
+                        const uint64_t* d_pmask, const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs,
+                        double* d_scratch, size_t scratch_doubles, T* d_out, hipStream_t stream) {
+  const int pb = expval_block_bits(n);
+  const int64_t nblocks = int64_t(1) << (n - pb);
+  if (expval_scratch_doubles(n, count, n_obs) > scratch_doubles) return fail(TQ_ENOMEM, "expval scratch too small");
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    double* partial = d_scratch;
+    double* outacc = d_scratch + (size_t)cn * nblocks * 32;
+    T* out = d_out + (int64_t)c0 * n_obs;
+    if (n_terms == 0) {
+      launch_chunk<T, 1>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask, d_coeff, d_obs, 0, n_obs, partial,
+                         outacc, 1, 1, out, stream);
+    }
+    for (int k0 = 0; k0 < n_terms; k0 += 32) {
+      const int nk = std::min(32, n_terms - k0);
+      const int first = k0 == 0, last = k0 + 32 >= n_terms;
+      if (nk <= 4)
+        launch_chunk<T, 4>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
+                           nk, n_obs, partial, outacc, first, last, out, stream);
+      else
+        launch_chunk<T, 32>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
+                            nk, n_obs, partial, outacc, first, last, out, stream);
+    }
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+template tq_status launch_expval<float>(const float2*, BatchMap, int, int, const uint64_t*, const double*,
+                                        const int32_t*, int, int, double*, size_t, float*, hipStream_t);
+template tq_status launch_expval<double>(const double2*, BatchMap, int, int, const uint64_t*, const double*,
+                                         const int32_t*, int, int, double*, size_t, double*, hipStream_t);
+
+}  // namespace tq

@@ -21,7 +21,7 @@
 
 namespace tq {
 
-static int n_angles(int op) {
+int gate_n_angles(int op) {
   switch (op) {
     case TQ_RX: case TQ_RY: case TQ_RZ: case TQ_RZZ: return 1;
     case TQ_U3: case TQ_ROT: return 3;
@@ -45,7 +45,7 @@ tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params) {
                                    " outside [0," + std::to_string(n) + ")");
     if (nq == 2 && x.q[0] == x.q[1])
       return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": duplicate qubit");
-    for (int j = 0; j < n_angles(x.op); ++j)
+    for (int j = 0; j < gate_n_angles(x.op); ++j)
       if (x.pidx[j] >= n_params)
         return fail(TQ_EINVAL, "gate " + std::to_string(k) + ": parameter index " +
                                    std::to_string(x.pidx[j]) + " >= n_params " + std::to_string(n_params));
@@ -192,6 +192,19 @@ void build_stages(Schedule& s) {
     }
     std::vector<int> taken;
     greedy_take(s.ops, remaining, S, t, pos_of_q, taken);
+    if (s.adjoint) {
+      // cap the gradient slots of one stage (their partial sums live in LDS); the ops cut
+      // off are later in program order than every op kept, so they return to `remaining`
+      int slots = 0;
+      size_t keep = 0;
+      while (keep < taken.size() && slots + s.ops[taken[keep]].nang <= kAdjMaxSlotsPerStage)
+        slots += s.ops[taken[keep++]].nang;
+      if (keep < taken.size()) {
+        remaining.insert(remaining.end(), taken.begin() + keep, taken.end());
+        std::sort(remaining.begin(), remaining.end());
+        taken.resize(keep);
+      }
+    }
     // fill the local set up to t with the lowest free positions
     for (int p = 0; (int)S.size() < t && p < n; ++p) S.insert(p);
     StageHost st;
@@ -270,6 +283,80 @@ void build_stages(Schedule& s) {
     for (int i = 0; i < n - t; ++i) ds.npos[i] = (uint8_t)st.npos[i];
     s.dstages.push_back(ds);
     s.stages.push_back(std::move(st));
+  }
+}
+
+}  // namespace tq
+
+namespace tq {
+
+// Reverse-sweep op list: every original gate in reverse order as its own op (parameterised
+// gates keep their own matrices so that each angle's derivative is available). mat holds
+// the gate index; nang its angle count.
+void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops) {
+  ops.clear();
+  for (int k = n_gates - 1; k >= 0; --k) {
+    const tq_gate& x = g[k];
+    HostOp o{};
+    o.mat = k;
+    o.src = k;
+    o.nang = gate_n_angles(x.op);
+    if (x.op == TQ_CNOT) { o.kind = K_CX; o.qa = x.q[1]; o.qb = x.q[0]; }
+    else if (x.op == TQ_CZ) { o.kind = K_CZ; o.qa = x.q[0]; o.qb = x.q[1]; }
+    else if (x.op == TQ_RZZ) { o.kind = K_DIAG2; o.qa = x.q[0]; o.qb = x.q[1]; }
+    else if (diag1(x.op)) { o.kind = K_DIAG1; o.qa = x.q[0]; o.qb = -1; }
+    else { o.kind = K_MAT1; o.qa = x.q[0]; o.qb = -1; }
+    ops.push_back(o);
+  }
+}
+
+// Gradient slots: one per (gate, angle), numbered stage by stage in execution order, plus
+// the parameter -> slots table used by the final reduction.
+void build_adjoint_slots(Schedule& s, const tq_gate* g, int n_gates) {
+  s.dslot.assign(s.dops.size(), 0);
+  s.stage_slot0.clear();
+  s.stage_nslot.clear();
+  s.slot_gate.clear();
+  s.slot_angle.clear();
+  int global = 0;
+  for (size_t st = 0; st < s.dstages.size(); ++st) {
+    s.stage_slot0.push_back(global);
+    int local = 0;
+    for (int p = s.dstages[st].phase_begin; p < s.dstages[st].phase_end; ++p)
+      for (int o = s.phases[p].op_begin; o < s.phases[p].op_end; ++o) {
+        const int k = s.dops[o].mat;
+        const int na = gate_n_angles(g[k].op);
+        s.dslot[o] = (local << 2) | na;
+        for (int j = 0; j < na; ++j) {
+          s.slot_gate.push_back(k);
+          s.slot_angle.push_back(j);
+        }
+        local += na;
+      }
+    s.stage_nslot.push_back(local);
+    global += local;
+  }
+  s.n_slots = global;
+  int np = 0;
+  for (int k = 0; k < n_gates; ++k)
+    for (int j = 0; j < gate_n_angles(g[k].op); ++j) np = std::max(np, g[k].pidx[j] + 1);
+  s.n_params_used = np;
+  std::vector<std::vector<std::pair<int, double>>> by(np);
+  for (int sl = 0; sl < global; ++sl) {
+    const tq_gate& x = g[s.slot_gate[sl]];
+    const int pi = x.pidx[s.slot_angle[sl]];
+    if (pi >= 0) by[pi].push_back({sl, x.pscale[s.slot_angle[sl]]});
+  }
+  s.pslot_ptr.assign(1, 0);
+  s.pslot_idx.clear();
+  s.pslot_scale.clear();
+  for (int p = 0; p < np; ++p) {
+    std::sort(by[p].begin(), by[p].end());
+    for (auto& e : by[p]) {
+      s.pslot_idx.push_back(e.first);
+      s.pslot_scale.push_back(e.second);
+    }
+    s.pslot_ptr.push_back((int)s.pslot_idx.size());
   }
 }
 

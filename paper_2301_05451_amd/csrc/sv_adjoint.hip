@@ -1,0 +1,479 @@
+// Adjoint (reverse-sweep) gradients of Z-string expectation values.
+//
+// For f = <psi_N| O |psi_N> with psi_k = U_k psi_{k-1}, the derivative with respect to an
+// angle a of gate k is 2 Re <lambda_k| dU_k/da |psi_{k-1}>, where lambda_k =
+// U_{k+1}^dag .. U_N^dag O psi_N. One reverse pass produces every such term: starting from
+// lambda = O psi_N, for k = N..1: psi <- U_k^dag psi, record 2 Re <lambda| dU_k psi>,
+// lambda <- U_k^dag lambda. These are the exact derivatives, equal to the parameter-shift
+// values of the paper's Sec. 4.2; the paper itself obtains them by library backpropagation
+// (Sec. 4.1), which stores every intermediate state instead of two.
+//
+// The reverse gate list is scheduled into LDS-tile stages exactly like the forward pass
+// (one op per original gate). Each stage keeps tiles of psi and lambda in registers/LDS,
+// and every angle gets a "slot": per-thread partial inner products are wave-reduced into
+// LDS and written once per tile; a final pass sums tiles and parameter occurrences in a
+// fixed order (deterministic).
+#include "sv_device.h"
+
+namespace tq {
+
+constexpr int kAdjMatStride = 16;  // per gate: U (4 entries) then dU/da_j (4 entries each)
+
+// ---- matrices of a gate and of its angle derivatives (double precision) ----------------
+__device__ inline dmat2 d_rz(double a) {  // dRZ/da = diag(-i/2 e^{-ia/2}, i/2 e^{ia/2})
+  dcx e = expi(-0.5 * a);                  // e^{-ia/2}; e^{ia/2} = conj(e)
+  return dmat2{{{0.5 * e.y, -0.5 * e.x}, {0, 0}, {0, 0}, {0.5 * e.y, 0.5 * e.x}}};
+}
+__device__ inline dmat2 d_ry(double a) {
+  double s, c;
+  sincos(0.5 * a, &s, &c);
+  return dmat2{{{-0.5 * s, 0}, {-0.5 * c, 0}, {0.5 * c, 0}, {-0.5 * s, 0}}};
+}
+__device__ inline dmat2 d_rx(double a) {
+  double s, c;
+  sincos(0.5 * a, &s, &c);
+  return dmat2{{{-0.5 * s, 0}, {0, -0.5 * c}, {0, -0.5 * c}, {-0.5 * s, 0}}};
+}
+
+// Fills U and the derivative with respect to each angle (rows of 4, row-major 2x2, or the
+// diagonal for Z/RZ (2 entries, repeated) and RZZ (4 entries, index 2*bit(q0)+bit(q1))).
+__device__ inline void gate_and_derivs(int op, const double* a, dcx (&out)[kAdjMatStride]) {
+  for (int i = 0; i < kAdjMatStride; ++i) out[i] = dcx{0, 0};
+  auto put = [&](int slot, const dmat2& M) {
+    for (int i = 0; i < 4; ++i) out[4 * slot + i] = M.m[i];
+  };
+  switch (op) {
+    case TQ_RX: put(0, gate_mat2(TQ_RX, a)); put(1, d_rx(a[0])); break;
+    case TQ_RY: put(0, gate_mat2(TQ_RY, a)); put(1, d_ry(a[0])); break;
+    case TQ_RZ: {
+      dcx e0 = expi(-0.5 * a[0]), e1 = expi(0.5 * a[0]);
+      out[0] = e0; out[1] = e1; out[2] = e0; out[3] = e1;
+      dcx d0{0.5 * e0.y, -0.5 * e0.x}, d1{-0.5 * e1.y, 0.5 * e1.x};
+      out[4] = d0; out[5] = d1; out[6] = d0; out[7] = d1;
+      break;
+    }
+    case TQ_Z: out[0] = {1, 0}; out[1] = {-1, 0}; out[2] = {1, 0}; out[3] = {-1, 0}; break;
+    case TQ_RZZ: {
+      dcx em = expi(-0.5 * a[0]), ep = expi(0.5 * a[0]);
+      out[0] = em; out[1] = ep; out[2] = ep; out[3] = em;
+      dcx dm{0.5 * em.y, -0.5 * em.x}, dp{-0.5 * ep.y, 0.5 * ep.x};
+      out[4] = dm; out[5] = dp; out[6] = dp; out[7] = dm;
+      break;
+    }
+    case TQ_U3: {
+      // U3(th, ph, la) = [[c, -e^{i la} s], [e^{i ph} s, e^{i(ph+la)} c]]
+      double s, c;
+      sincos(0.5 * a[0], &s, &c);
+      dcx el = expi(a[2]), ep = expi(a[1]), epl = expi(a[1] + a[2]);
+      put(0, gate_mat2(TQ_U3, a));
+      out[4] = {-0.5 * s, 0}; out[5] = {-0.5 * c * el.x, -0.5 * c * el.y};
+      out[6] = {0.5 * c * ep.x, 0.5 * c * ep.y}; out[7] = {-0.5 * s * epl.x, -0.5 * s * epl.y};
+      out[8] = {0, 0}; out[9] = {0, 0};
+      out[10] = {-s * ep.y, s * ep.x}; out[11] = {-c * epl.y, c * epl.x};
+      out[12] = {0, 0}; out[13] = {s * el.y, -s * el.x};
+      out[14] = {0, 0}; out[15] = {-c * epl.y, c * epl.x};
+      break;
+    }
+    case TQ_ROT: {
+      // RZ(om) RY(th) RZ(ph) with (ph, th, om) = (a0, a1, a2)
+      double a0[1] = {a[0]}, a1[1] = {a[1]}, a2[1] = {a[2]};
+      dmat2 Z0 = gate_mat2(TQ_RZ, a0), Y1 = gate_mat2(TQ_RY, a1), Z2 = gate_mat2(TQ_RZ, a2);
+      put(0, mat_mul(Z2, mat_mul(Y1, Z0)));
+      put(1, mat_mul(Z2, mat_mul(Y1, d_rz(a[0]))));
+      put(2, mat_mul(Z2, mat_mul(d_ry(a[1]), Z0)));
+      put(3, mat_mul(d_rz(a[2]), mat_mul(Y1, Z0)));
+      break;
+    }
+    default: put(0, gate_mat2(op, a)); break;  // H, X, Y (no angles); CNOT/CZ unused
+  }
+}
+
+template <typename T>
+__global__ void adj_gate_build_kernel(const tq_gate* __restrict__ gates, int n_gates, const T* __restrict__ params,
+                                      BatchMap pmap, typename Cx<T>::type* __restrict__ mats, int count) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_gates * count) return;
+  const int k = (int)(gid % n_gates);
+  const int circ = (int)(gid / n_gates);
+  const tq_gate& g = gates[k];
+  double a[3];
+  gate_angles(g, params + pmap.at(circ), a);
+  dcx m[kAdjMatStride];
+  gate_and_derivs(g.op, a, m);
+  typename Cx<T>::type* out = mats + ((int64_t)circ * n_gates + k) * kAdjMatStride;
+  for (int i = 0; i < kAdjMatStride; ++i) out[i] = to_cx<T>(m[i]);
+}
+
+// lambda = sum_o w_o O_o psi with w = grad_out; psi copied to the working buffer.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    adj_init_kernel(const typename Cx<T>::type* __restrict__ psi_in, BatchMap smap_in,
+                    typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam, BatchMap smap_w,
+                    int64_t namps, const uint64_t* __restrict__ pmask, const double* __restrict__ coeff,
+                    const int32_t* __restrict__ obs, int n_terms, const T* __restrict__ grad_out, int n_obs) {
+  using C = typename Cx<T>::type;
+  const int circ = blockIdx.y;
+  const C* src = psi_in + smap_in.at(circ);
+  C* p = psi + smap_w.at(circ);
+  C* l = lam + smap_w.at(circ);
+  const T* w = grad_out + (int64_t)circ * n_obs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
+    double sgn = 0.0;
+    for (int k = 0; k < n_terms; ++k) {
+      const double wc = (double)w[obs[k]] * coeff[k];
+      sgn += (__popcll((uint64_t)i & pmask[k]) & 1) ? -wc : wc;
+    }
+    const C a = src[i];
+    p[i] = a;
+    C b;
+    b.x = (T)(sgn * (double)a.x);
+    b.y = (T)(sgn * (double)a.y);
+    l[i] = b;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t adj_swz(uint32_t li) {
+  constexpr int G = sizeof(T) == 4 ? 5 : 4;
+  constexpr uint32_t mask = (1u << G) - 1;
+  return li ^ (((li >> G) ^ (li >> (2 * G)) ^ (li >> (3 * G))) & mask);
+}
+
+template <typename C>
+__device__ __forceinline__ C cconj_mul(C a, C b) {  // conj(a) * b
+  C r;
+  r.x = a.x * b.x + a.y * b.y;
+  r.y = a.x * b.y - a.y * b.x;
+  return r;
+}
+
+// Re(conj(x) * y)
+template <typename C>
+__device__ __forceinline__ auto re_dot(C x, C y) -> decltype(x.x) {
+  return x.x * y.x + x.y * y.y;
+}
+
+// Sum over the active lanes of a wave; `active` lanes (a power of two, or 64) are 0..active-1.
+// Lanes past `active` (a work-group smaller than one wave) hold stale registers and are
+// masked out of every butterfly step.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v, int lane, int active) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(v, off, 64);
+    v += ((lane ^ off) < active) ? o : (T)0;
+  }
+  return v;
+}
+
+// One register-resident target bit B: psi <- U^dag psi, gradient terms, lam <- U^dag lam.
+template <typename T, int R, int B>
+__device__ __forceinline__ void adj_mat(typename Cx<T>::type (&vp)[1 << R], typename Cx<T>::type (&vl)[1 << R],
+                                        const typename Cx<T>::type* __restrict__ m, int na, T (&acc)[3]) {
+  using C = typename Cx<T>::type;
+  const C u00 = m[0], u01 = m[1], u10 = m[2], u11 = m[3];
+  // U^dag = [[conj u00, conj u10], [conj u01, conj u11]]
+  C h00{u00.x, -u00.y}, h01{u10.x, -u10.y}, h10{u01.x, -u01.y}, h11{u11.x, -u11.y};
+  C d[3][4];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[j][i] = j < na ? m[4 + 4 * j + i] : C{0, 0};
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    if (j & (1 << B)) continue;
+    const int j1 = j | (1 << B);
+    const C a = cfma2(h00, vp[j], h01, vp[j1]);
+    const C b = cfma2(h10, vp[j], h11, vp[j1]);
+    vp[j] = a;
+    vp[j1] = b;
+    const C la = vl[j], lb = vl[j1];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q < na) {
+        const C x0 = cfma2(d[q][0], a, d[q][1], b);
+        const C x1 = cfma2(d[q][2], a, d[q][3], b);
+        acc[q] += re_dot(la, x0) + re_dot(lb, x1);
+      }
+    }
+    vl[j] = cfma2(h00, la, h01, lb);
+    vl[j1] = cfma2(h10, la, h11, lb);
+  }
+}
+
+template <typename T, int R, int B>
+__device__ __forceinline__ void adj_cx(typename Cx<T>::type (&vp)[1 << R], typename Cx<T>::type (&vl)[1 << R],
+                                       const uint32_t (&li)[1 << R], int pc, int t, uint32_t tile) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    if (j & (1 << B)) continue;
+    const int j1 = j | (1 << B);
+    const uint32_t cb = pc < t ? ((li[j] >> pc) & 1u) : ((tile >> (pc - t)) & 1u);
+    auto a = vp[j], b = vp[j1];
+    vp[j] = cb ? b : a;
+    vp[j1] = cb ? a : b;
+    a = vl[j];
+    b = vl[j1];
+    vl[j] = cb ? b : a;
+    vl[j1] = cb ? a : b;
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512)
+    adj_stage_kernel(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
+                     const DevOp* __restrict__ ops, const int32_t* __restrict__ dslot,
+                     const typename Cx<T>::type* __restrict__ mats, int64_t mats_stride,
+                     typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam, BatchMap smap,
+                     int slot0, int nslot, int n_slots, double* __restrict__ partial) {
+  using C = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int t = stg->t;
+  const int tb = t - R;
+  C* lds_p = reinterpret_cast<C*>(smem_raw);
+  C* lds_l = lds_p + (1u << t);
+  T* red = reinterpret_cast<T*>(lds_l + (1u << t));  // [nslot][waves]
+  const int nwaves = (int)((blockDim.x + 63) >> 6);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t tile = blockIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int active = (int)blockDim.x < 64 ? (int)blockDim.x : 64;
+  C* sp = psi + smap.at(blockIdx.y);
+  C* sl = lam + smap.at(blockIdx.y);
+  const C* M = mats + (int64_t)blockIdx.y * mats_stride;
+
+  int64_t base = 0;
+  for (int k = 0; k < stg->n_nonlocal; ++k) base |= (int64_t)((tile >> k) & 1u) << stg->npos[k];
+  int64_t thr = 0;
+  for (int k = 0; k < tb; ++k) thr |= (int64_t)((tid >> k) & 1u) << stg->lpos[k];
+  C vp[1 << R], vl[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    int64_t hi = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    vp[j] = sp[(base | thr) + hi];
+    vl[j] = sl[(base | thr) + hi];
+  }
+  uint32_t li[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
+
+  for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
+    const DevPhase& ph = phases[p];
+    if (ph.xchg) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        lds_p[adj_swz<T>(li[j])] = vp[j];
+        lds_l[adj_swz<T>(li[j])] = vl[j];
+      }
+      uint32_t tp = 0;
+      for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        uint32_t rp = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << ph.rpos[k];
+        li[j] = tp | rp;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        vp[j] = lds_p[adj_swz<T>(li[j])];
+        vl[j] = lds_l[adj_swz<T>(li[j])];
+      }
+    }
+    for (int o = ph.op_begin; o < ph.op_end; ++o) {
+      const DevOp op = load_op(ops, o);
+      const int sl_info = dslot[o];
+      const int na = sl_info & 3, s0 = sl_info >> 2;
+      const C* m = M + (int64_t)op.mat * kAdjMatStride;
+      T acc[3] = {(T)0, (T)0, (T)0};
+      if (op.kind == K_MAT1) {
+#define TQ_ADJ_CASE(B) \
+  case B:              \
+    if constexpr (R > B) adj_mat<T, R, (R > B ? B : 0)>(vp, vl, m, na, acc); \
+    break;
+        switch (op.rbit) { TQ_ADJ_CASE(0) TQ_ADJ_CASE(1) TQ_ADJ_CASE(2) TQ_ADJ_CASE(3) TQ_ADJ_CASE(4) default: break; }
+#undef TQ_ADJ_CASE
+      } else if (op.kind == K_CX) {
+#define TQ_ADJX_CASE(B) \
+  case B:               \
+    if constexpr (R > B) adj_cx<T, R, (R > B ? B : 0)>(vp, vl, li, op.pa, t, tile); \
+    break;
+        switch (op.rbit) { TQ_ADJX_CASE(0) TQ_ADJX_CASE(1) TQ_ADJX_CASE(2) TQ_ADJX_CASE(3) TQ_ADJX_CASE(4) default: break; }
+#undef TQ_ADJX_CASE
+      } else if (op.kind == K_CZ) {
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) {
+          uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
+          uint32_t bb = op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u);
+          if (ba & bb) {
+            vp[j].x = -vp[j].x; vp[j].y = -vp[j].y;
+            vl[j].x = -vl[j].x; vl[j].y = -vl[j].y;
+          }
+        }
+      } else {
+        const bool two = op.kind == K_DIAG2;
+        const C d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
+        const C e0 = m[4], e1 = m[5], e2 = m[6], e3 = m[7];
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) {
+          const uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
+          const uint32_t bb = !two ? ba : (op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u));
+          C f, g;
+          f.x = ba ? (two ? (bb ? d3.x : d2.x) : d1.x) : (two ? (bb ? d1.x : d0.x) : d0.x);
+          f.y = ba ? (two ? (bb ? d3.y : d2.y) : d1.y) : (two ? (bb ? d1.y : d0.y) : d0.y);
+          g.x = ba ? (two ? (bb ? e3.x : e2.x) : e1.x) : (two ? (bb ? e1.x : e0.x) : e0.x);
+          g.y = ba ? (two ? (bb ? e3.y : e2.y) : e1.y) : (two ? (bb ? e1.y : e0.y) : e0.y);
+          const C a = cconj_mul(f, vp[j]);  // psi <- conj(d) psi
+          vp[j] = a;
+          if (na > 0) acc[0] += re_dot(vl[j], cmul(g, a));
+          vl[j] = cconj_mul(f, vl[j]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (q < na) {
+          const T s = wave_sum<T>(acc[q], lane, active);
+          if (lane == 0) red[(s0 + q) * nwaves + wv] = s;
+        }
+      }
+    }
+  }
+  // store both tiles in the load layout
+  if (stg->store_xchg) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+      lds_p[adj_swz<T>(li[j])] = vp[j];
+      lds_l[adj_swz<T>(li[j])] = vl[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+      const uint32_t l0 = tid | ((uint32_t)j << tb);
+      vp[j] = lds_p[adj_swz<T>(l0)];
+      vl[j] = lds_l[adj_swz<T>(l0)];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    int64_t hi = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    sp[(base | thr) + hi] = vp[j];
+    sl[(base | thr) + hi] = vl[j];
+  }
+  __syncthreads();
+  const int64_t ntiles = gridDim.x;
+  double* part = partial + (int64_t)blockIdx.y * n_slots * ntiles;
+  for (int s = tid; s < nslot; s += blockDim.x) {
+    double x = 0.0;
+    for (int w = 0; w < nwaves; ++w) x += (double)red[s * nwaves + w];
+    part[(int64_t)(slot0 + s) * ntiles + tile] = x;
+  }
+}
+
+// grad[p] = sum over occurrences s of p: pscale_s * 2 * sum_tiles partial[s][tile] (fixed order)
+template <typename T>
+__global__ void adj_final_kernel(const double* __restrict__ partial, int n_slots, int64_t ntiles,
+                                 const int32_t* __restrict__ pptr, const int32_t* __restrict__ pidx,
+                                 const double* __restrict__ pscale, int n_used, int n_params, T* __restrict__ grad,
+                                 BatchMap pmap, int count) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_params * count) return;
+  const int p = (int)(gid % n_params);
+  const int circ = (int)(gid / n_params);
+  double g = 0.0;
+  if (p < n_used) {
+    const double* part = partial + (int64_t)circ * n_slots * ntiles;
+    for (int e = pptr[p]; e < pptr[p + 1]; ++e) {
+      double x = 0.0;
+      const double* row = part + (int64_t)pidx[e] * ntiles;
+      for (int64_t tl = 0; tl < ntiles; ++tl) x += row[tl];
+      g += 2.0 * pscale[e] * x;
+    }
+  }
+  grad[pmap.at(circ) + p] = (T)g;
+}
+
+// ---- host launchers --------------------------------------------------------------------
+template <typename T, int R>
+static tq_status launch_adj_stages_R(const Schedule& s, void* psi, void* lam, BatchMap smap, const void* mats,
+                                     int count, double* partial, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int64_t mstride = (int64_t)s.n_gates * kAdjMatStride;
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    for (size_t k = 0; k < s.stages.size(); ++k) {
+      const int t = s.stages[k].t;
+      const unsigned tiles = 1u << (s.n - t);
+      const unsigned threads = 1u << (t - R);
+      const unsigned waves = (threads + 63) / 64;
+      const size_t lds = 2 * (sizeof(C) << t) + (size_t)std::max(1, s.stage_nslot[k]) * waves * sizeof(T);
+      double* part = partial + (int64_t)c0 * s.n_slots * tiles;
+      hipLaunchKernelGGL((adj_stage_kernel<T, R>), dim3(tiles, cn), dim3(threads), lds, stream,
+                         (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops,
+                         (const int32_t*)s.d_dslot, (const C*)mats + (int64_t)c0 * mstride, mstride, (C*)psi,
+                         (C*)lam, smap.shifted(c0), s.stage_slot0[k], s.stage_nslot[k], s.n_slots, part);
+      TQ_HIP(hipGetLastError());
+    }
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap, const void* d_states_in,
+                         BatchMap smap_in, void* psi, void* lam, BatchMap smap_w, void* mats, double* partial,
+                         const uint64_t* pm, const double* cf, const int32_t* ob, int n_terms, const T* grad_out,
+                         int n_obs, T* grad, int n_params, int count, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int n = s.n;
+  const int64_t namps = int64_t(1) << n;
+  // matrices and derivatives of every gate
+  if (s.n_gates > 0) {
+    const int64_t total = (int64_t)s.n_gates * count;
+    hipLaunchKernelGGL(adj_gate_build_kernel<T>, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, stream,
+                       (const tq_gate*)s.d_gates, s.n_gates, (const T*)d_params, pmap, (C*)mats, count);
+    TQ_HIP(hipGetLastError());
+  }
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    int64_t b = (namps + 255) / 256;
+    b = std::min<int64_t>(b, std::max<int64_t>(1, 4096 / cn));
+    hipLaunchKernelGGL(adj_init_kernel<T>, dim3((unsigned)b, cn), dim3(256), 0, stream, (const C*)d_states_in,
+                       smap_in.shifted(c0), (C*)psi, (C*)lam, smap_w.shifted(c0), namps, pm, cf, ob, n_terms,
+                       grad_out + (int64_t)c0 * n_obs, n_obs);
+    TQ_HIP(hipGetLastError());
+  }
+  const int R = std::min(s.R, std::min(s.t, s.n));
+  tq_status st;
+  switch (R) {
+    case 1: st = launch_adj_stages_R<T, 1>(s, psi, lam, smap_w, mats, count, partial, stream); break;
+    case 2: st = launch_adj_stages_R<T, 2>(s, psi, lam, smap_w, mats, count, partial, stream); break;
+    case 3: st = launch_adj_stages_R<T, 3>(s, psi, lam, smap_w, mats, count, partial, stream); break;
+    case 4: st = launch_adj_stages_R<T, 4>(s, psi, lam, smap_w, mats, count, partial, stream); break;
+    default: return fail(TQ_ENOTSUP, "adjoint register bits must be 1..4");
+  }
+  TQ_TRY(st);
+  const int64_t ntiles = s.stages.empty() ? 1 : (int64_t(1) << (s.n - s.stages[0].t));
+  const int64_t tot = (int64_t)n_params * count;
+  if (tot > 0) {
+    hipLaunchKernelGGL(adj_final_kernel<T>, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, stream,
+                       (const double*)partial, s.n_slots, ntiles, (const int32_t*)s.d_pslot_ptr,
+                       (const int32_t*)s.d_pslot_idx, (const double*)s.d_pslot_scale, s.n_params_used, n_params,
+                       grad, pmap, count);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+template tq_status launch_adjoint<float>(const Schedule&, const void*, BatchMap, const void*, BatchMap, void*, void*,
+                                         BatchMap, void*, double*, const uint64_t*, const double*, const int32_t*, int,
+                                         const float*, int, float*, int, int, hipStream_t);
+template tq_status launch_adjoint<double>(const Schedule&, const void*, BatchMap, const void*, BatchMap, void*, void*,
+                                          BatchMap, void*, double*, const uint64_t*, const double*, const int32_t*,
+                                          int, const double*, int, double*, int, int, hipStream_t);
+
+}  // namespace tq

@@ -173,8 +173,22 @@ template <typename T>
 tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
                         hipStream_t stream);
 template <typename T>
-tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count, const uint64_t* d_pmask,
-                        const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs, double* d_partial,
-                        size_t partial_cap, T* d_out, int n_cu, hipStream_t stream);
+tq_status launch_init_basis(void* d_states, BatchMap smap, int n, int count, int64_t basis, int n_cu,
+                            hipStream_t stream);
+// sv_adjoint.hip
+constexpr int kAdjMatEntries = 16;
+template <typename T>
+tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap, const void* d_states_in,
+                         BatchMap smap_in, void* psi, void* lam, BatchMap smap_w, void* mats, double* partial,
+                         const uint64_t* pm, const double* cf, const int32_t* ob, int n_terms, const T* grad_out,
+                         int n_obs, T* grad, int n_params, int count, hipStream_t stream);
+
+// expval.hip
+int expval_block_bits(int n);
+size_t expval_scratch_doubles(int n, int count, int n_obs);
+template <typename T>
+tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,
+                        const uint64_t* d_pmask, const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs,
+                        double* d_scratch, size_t scratch_doubles, T* d_out, hipStream_t stream);
 
 }  // namespace tq

@@ -310,67 +310,42 @@ __global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restric
   }
 }
 
-// ---------------------------------------------------------------------------------
-// Expectation values of Z-strings: per-block partial sums (double, fixed tree), then a
-// per-(circuit, observable) pass over the partials in block order.
-// ---------------------------------------------------------------------------------
-constexpr int kMaxObs = 8;
-constexpr int kExpThreads = 256;
-
+// Basis-state initialisation |b> (Sec. 3.1 default |0..0> for b = 0): vector stores only.
 template <typename T>
-__global__ void __launch_bounds__(kExpThreads) expval_partial_kernel(
-    const typename Cx<T>::type* __restrict__ st, BatchMap smap, int64_t namps, int64_t per_block,
-    const uint64_t* __restrict__ pmask, const double* __restrict__ coeff, const int32_t* __restrict__ obs,
-    int n_terms, int obs_lo, int n_obs_here, double* __restrict__ partial, int nblocks) {
+__global__ void __launch_bounds__(256) init_basis_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
+                                                         int64_t namps, int64_t basis) {
   using C = typename Cx<T>::type;
-  const C* s = st + smap.at(blockIdx.y);
-  double acc[kMaxObs];
-#pragma unroll
-  for (int o = 0; o < kMaxObs; ++o) acc[o] = 0.0;
-  const int64_t b0 = (int64_t)blockIdx.x * per_block;
-  const int64_t b1 = b0 + per_block < namps ? b0 + per_block : namps;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    C a = s[i];
-    double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-    for (int k = 0; k < n_terms; ++k) {
-      int o = obs[k] - obs_lo;
-      if (o < 0 || o >= n_obs_here) continue;
-      double sg = (__popcll((uint64_t)i & pmask[k]) & 1) ? -coeff[k] : coeff[k];
-#pragma unroll
-      for (int q = 0; q < kMaxObs; ++q)
-        if (q == o) acc[q] += sg * pr;
-    }
+  C* s = st + smap.at(blockIdx.y);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
+    C v;
+    v.x = (i == basis) ? (T)1 : (T)0;
+    v.y = (T)0;
+    s[i] = v;
   }
-  __shared__ double red[kExpThreads / 64][kMaxObs];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 0; o < kMaxObs; ++o) {
-    double x = acc[o];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) red[wv][o] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < n_obs_here) {
-    double x = 0.0;
-    for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][threadIdx.x];
-    partial[((int64_t)blockIdx.y * nblocks + blockIdx.x) * kMaxObs + threadIdx.x] = x;
-  }
-}
-
-template <typename T>
-__global__ void expval_final_kernel(const double* __restrict__ partial, int nblocks, int count, int n_obs_here,
-                                    int obs_lo, int n_obs, T* __restrict__ out) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= count * n_obs_here) return;
-  const int circ = gid / n_obs_here, o = gid % n_obs_here;
-  double x = 0.0;
-  for (int b = 0; b < nblocks; ++b) x += partial[((int64_t)circ * nblocks + b) * kMaxObs + o];
-  out[(int64_t)circ * n_obs + obs_lo + o] = (T)x;
 }
 
 // ---------------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------------
+template <typename T>
+tq_status launch_init_basis(void* d_states, BatchMap smap, int n, int count, int64_t basis, int n_cu,
+                            hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int64_t namps = int64_t(1) << n;
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(65535, count - c0);
+    int64_t b = (namps + 255) / 256;
+    int64_t cap = std::max<int64_t>(1, (int64_t)n_cu * 16 / cn);
+    if (b > cap) b = cap;
+    hipLaunchKernelGGL(init_basis_kernel<T>, dim3((unsigned)b, cn), dim3(256), 0, stream, (C*)d_states,
+                       smap.shifted(c0), namps, basis);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+template tq_status launch_init_basis<float>(void*, BatchMap, int, int, int64_t, int, hipStream_t);
+template tq_status launch_init_basis<double>(void*, BatchMap, int, int, int64_t, int, hipStream_t);
+
 template <typename T>
 tq_status launch_gate_build(const Schedule& s, const void* d_params, BatchMap pmap, void* d_mats, int count,
                             hipStream_t stream) {
@@ -467,42 +442,11 @@ tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const 
   }
 }
 
-template <typename T>
-tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count, const uint64_t* d_pmask,
-                        const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs, double* d_partial,
-                        size_t partial_cap, T* d_out, int n_cu, hipStream_t stream) {
-  const int64_t namps = int64_t(1) << n;
-  int64_t nblocks = (namps + 4095) / 4096;  // >= 4096 amplitudes per block
-  if (nblocks > 2048) nblocks = 2048;
-  const int64_t per_block = (namps + nblocks - 1) / nblocks;
-  (void)n_cu;
-  for (int c0 = 0; c0 < count; c0 += 65535) {
-    const int cn = std::min(65535, count - c0);
-    if ((size_t)cn * nblocks * kMaxObs * sizeof(double) > partial_cap) return fail(TQ_ENOMEM, "expval partial buffer");
-    for (int o0 = 0; o0 < n_obs; o0 += kMaxObs) {
-      const int no = std::min(kMaxObs, n_obs - o0);
-      hipLaunchKernelGGL(expval_partial_kernel<T>, dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
-                         d_states, smap.shifted(c0), namps, per_block, d_pmask, d_coeff, d_obs, n_terms, o0, no,
-                         d_partial, (int)nblocks);
-      TQ_HIP(hipGetLastError());
-      const int fin = cn * no;
-      hipLaunchKernelGGL(expval_final_kernel<T>, dim3((fin + 127) / 128), dim3(128), 0, stream, d_partial,
-                         (int)nblocks, cn, no, o0, n_obs, d_out + (int64_t)c0 * n_obs);
-      TQ_HIP(hipGetLastError());
-    }
-  }
-  return TQ_OK;
-}
-
 template tq_status launch_gate_build<float>(const Schedule&, const void*, BatchMap, void*, int, hipStream_t);
 template tq_status launch_gate_build<double>(const Schedule&, const void*, BatchMap, void*, int, hipStream_t);
 template tq_status launch_plain<float>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
 template tq_status launch_plain<double>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
 template tq_status launch_stages<float>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
 template tq_status launch_stages<double>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
-template tq_status launch_expval<float>(const float2*, BatchMap, int, int, const uint64_t*, const double*,
-                                        const int32_t*, int, int, double*, size_t, float*, int, hipStream_t);
-template tq_status launch_expval<double>(const double2*, BatchMap, int, int, const uint64_t*, const double*,
-                                         const int32_t*, int, int, double*, size_t, double*, int, hipStream_t);
 
 }  // namespace tq

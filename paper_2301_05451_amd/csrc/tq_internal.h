@@ -55,6 +55,7 @@ struct HostOp {
   int qb;   // control (CX) or second qubit (DIAG2/CZ), else -1
   int mat;  // matrix-table index or -1
   int src;  // original gate index for recipe-less ops (CX, CZ), else -1
+  int nang = 0;  // adjoint schedules: angles of the gate (gradient slots)
 };
 
 struct Recipe {
@@ -109,6 +110,23 @@ struct Schedule {
   std::vector<DevPhase> phases;
   std::vector<DevOp> dops;
   std::vector<DevStage> dstages;
+  // adjoint form (reverse sweep, one op per original gate; DevOp.mat = gate index)
+  bool adjoint = false;
+  std::vector<int32_t> dslot;         // per dop: (stage-local first slot << 2) | angle count
+  std::vector<int32_t> stage_slot0;   // per stage: first global slot
+  std::vector<int32_t> stage_nslot;   // per stage: slots
+  int n_slots = 0;                    // total gradient slots = sum of angle counts
+  std::vector<int32_t> slot_gate;     // global slot -> gate index
+  std::vector<int32_t> slot_angle;    // global slot -> angle index j
+  int n_params_used = 0;              // 1 + max parameter index referenced
+  std::vector<int32_t> pslot_ptr;     // CSR: parameter -> global slots (with pscale)
+  std::vector<int32_t> pslot_idx;
+  std::vector<double> pslot_scale;
+  void* d_dslot = nullptr;
+  void* d_pslot_ptr = nullptr;
+  void* d_pslot_idx = nullptr;
+  void* d_pslot_scale = nullptr;
+  void* d_stage_slot0 = nullptr;
   // device copies (owned)
   void* d_gates = nullptr;      // tq_gate[n_gates]
   void* d_rec = nullptr;        // int32 [n_mats][4]: kind, qa, qb, begin ; + end in next
@@ -124,7 +142,11 @@ struct Schedule {
 void lower_ops(const tq_gate* g, int n_gates, int n, bool fuse, std::vector<Recipe>& recipes,
                std::vector<HostOp>& ops);
 void build_stages(Schedule& s);
+void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops);
+void build_adjoint_slots(Schedule& s, const tq_gate* g, int n_gates);
 tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params);
+int gate_n_angles(int op);
+constexpr int kAdjMaxSlotsPerStage = 256;
 
 }  // namespace tq
 

@@ -62,6 +62,10 @@ _lib.tq_sv_apply.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _v
 _lib.tq_sv_apply.restype = ct.c_int
 _lib.tq_expval.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _i32, _i32, _vp, _vp]
 _lib.tq_expval.restype = ct.c_int
+_lib.tq_sv_init.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), ct.c_int64, _vp, _vp]
+_lib.tq_sv_init.restype = ct.c_int
+_lib.tq_sv_plan_info.argtypes = [_vp, ct.c_int, _i32, _vp, _i32, ct.POINTER(SvOpts), ct.POINTER(ct.c_int64)]
+_lib.tq_sv_plan_info.restype = ct.c_int
 if hasattr(_lib, "tq_sv_backward"):
     _lib.tq_sv_backward.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
                                     _vp, ct.POINTER(SvOpts), _vp]
@@ -197,6 +201,20 @@ def sv_apply(states, params, spec: BatchSpec, mode=0, tile_bits=0, reg_bits=0, c
     return states
 
 
+PLAN_FIELDS = ("sweeps", "ops", "phases", "exchanges", "tile_bits", "reg_bits", "flops_per_amp", "mats")
+
+
+def plan_info(n, gates, dtype_c128=False, mode=0, tile_bits=0, reg_bits=0, coal_bits=0, ctx=None):
+    """Schedule shape for one circuit structure (tq_sv_plan_info), as a dict."""
+    ctx = ctx or context()
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    out = (ct.c_int64 * 8)()
+    o = _opts(mode, tile_bits, reg_bits, coal_bits)
+    check(_lib.tq_sv_plan_info(ctx.h, TQ_C128 if dtype_c128 else TQ_C64, int(n), g.ctypes.data, int(g.shape[0]),
+                               ct.byref(o), out))
+    return dict(zip(PLAN_FIELDS, [int(v) for v in out]))
+
+
 def expval(states, spec: BatchSpec, terms, n_obs, ctx=None):
     """[count, n_obs] real expectation values of Z-string sums (tq_expval)."""
     import torch
@@ -216,7 +234,9 @@ def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0,
     _check_tensors(states, params, spec)
     ctx = ctx or context(states.device.index)
     terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
-    grad_out = grad_out.contiguous()
+    grad_out = grad_out.to(device=params.device, dtype=params.dtype).contiguous()
+    if grad_out.numel() < spec.count * n_obs:
+        raise ValueError(f"grad_out needs {spec.count} x {n_obs} entries")
     grad = torch.empty_like(params)
     o = _opts(mode, tile_bits, reg_bits, 0)
     check(_lib.tq_sv_backward(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data,
@@ -226,10 +246,17 @@ def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0,
     return grad
 
 
+def init_states(states, spec: BatchSpec, basis=0, ctx=None):
+    """Write |basis> into every circuit's state (tq_sv_init)."""
+    if not states.is_cuda or not states.is_contiguous() or states.numel() < spec.total_amps:
+        raise ValueError("states must be a contiguous CUDA tensor covering the batch")
+    ctx = ctx or context(states.device.index)
+    check(_lib.tq_sv_init(ctx.h, _dt(states), ct.byref(spec.c), ct.c_int64(int(basis)), states.data_ptr(), _stream()))
+    return states
+
+
 def zero_states(spec: BatchSpec, dtype, device="cuda"):
-    """|0..0> for every circuit of the batch (torch fill on the device)."""
+    """New state tensor holding |0..0> for every circuit of the batch."""
     import torch
-    st = torch.zeros(spec.total_amps, dtype=dtype, device=device)
-    idx = torch.as_tensor(spec.state_off, device=device)
-    st[idx] = 1.0
-    return st
+    st = torch.empty(spec.total_amps, dtype=dtype, device=device)
+    return init_states(st, spec, 0)
