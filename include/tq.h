@@ -165,6 +165,86 @@ tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const 
                          const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
                          void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Tensor-network mode (Sec. 3.2). A closed or open network of leaf tensors whose indices all
+ * have dimension 2; an index may be shared by any number of tensors (hyperedge, Sec. 3.2.1).
+ * A tensor of rank r is 2^r complex numbers, its first index the most significant bit.
+ * The contraction order is a binary tree (Sec. 3.2.2) given in SSA form: step s contracts
+ * ids pairs[2s], pairs[2s+1] (ids < n_leaves are leaves, n_leaves + s is the result of
+ * step s). Sliced indices (Sec. 3.2.3) are fixed to each of their 2^n_sliced assignments;
+ * the value is the sum of the sub-network values. Leaves are packed in one device buffer,
+ * leaf i at complex offset tq_tn_leaf_offset(plan, i), in full (unsliced) size.
+ * ------------------------------------------------------------------------------------- */
+typedef struct tq_tn_plan tq_tn_plan;
+
+typedef struct {
+  int32_t n_leaves;
+  const int32_t* leaf_rank;  /* [n_leaves] */
+  const int32_t* leaf_inds;  /* concatenated index ids, leaf by leaf, first = most significant */
+  const int32_t* pairs;      /* [2 * (n_leaves - 1)] SSA tree */
+  int32_t n_sliced;
+  const int32_t* sliced;     /* index ids fixed per slice (0..20) */
+  int32_t n_out;             /* open indices of the result, in the order wanted (0: scalar) */
+  const int32_t* out_inds;
+  int32_t dtype;             /* tq_dtype */
+  int64_t slice_group;       /* slices contracted together per launch sequence (0 = auto) */
+  int64_t mem_budget;        /* bytes of workspace the auto slice group may use (0 = 4 GiB) */
+} tq_tn_desc;
+
+/* Host-only: classifies every step (batch / contracted / kept / summed-out indices), picks
+ * its kernel (direct bit-indexed contraction, or bit-permute + FP32-MFMA complex GEMM when
+ * M, N, K are all large), and sizes the workspace. Errors: TQ_EINVAL if the tree does not
+ * use every leaf exactly once, an id is out of range, or the result's open indices differ
+ * from out_inds as a set. */
+tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* desc, tq_tn_plan** out);
+void tq_tn_plan_destroy(tq_tn_plan* plan);
+/* Complex elements of the packed leaf buffer, and leaf i's offset in it. */
+int64_t tq_tn_leaf_elems(const tq_tn_plan* plan);
+int64_t tq_tn_leaf_offset(const tq_tn_plan* plan, int32_t leaf);
+/* Workspace bytes for tq_tn_contract (backward = 0) or tq_tn_backward (backward = 1). */
+int64_t tq_tn_workspace(const tq_tn_plan* plan, int32_t backward);
+/* Plan statistics: out[0] steps, [1] direct steps, [2] GEMM steps, [3] slices,
+ * [4] slice group, [5] real flops per contraction (8 per complex multiply-add, all slices),
+ * [6] real flops in GEMM steps, [7] largest intermediate (complex elements, per slice). */
+tq_status tq_tn_plan_info(const tq_tn_plan* plan, int64_t out[8]);
+
+/* Step (e) of Sec. 3.2: d_out (2^n_out complex) = the network's value, summed over slices.
+ * d_leaves is the packed leaf buffer (read only). */
+tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, void* d_out, void* d_work,
+                         int64_t work_bytes, void* stream);
+
+/* Reverse pass over the tree: d_grad_leaves (packed like the leaves) receives, for every
+ * leaf, its environment scaled by the upstream value: sum over the output entries o of
+ * d_grad_out[o] * dT[o]/dL (holomorphic derivative of the multilinear value T). For a
+ * real loss l = Re sum_o conj(g_o) T_o pass d_grad_out = g; dl/dtheta is then
+ * Re sum_leaf sum_x d_grad_leaves[x] * dL[x]/dtheta. Intermediates are recomputed from
+ * the leaves inside the call (nothing is kept between calls). */
+tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, const void* d_grad_out,
+                         void* d_grad_leaves, void* d_work, int64_t work_bytes, void* stream);
+
+/* Leaves of a circuit network from the circuit parameters (Sec. 3.2.1: state, gate and
+ * observable tensors, with conjugate copies for the bra half). kind per leaf: 0 constant
+ * (const_vals[const_off ..], complex128 interleaved), 1 one-qubit gate [out, in],
+ * 2 one-qubit diagonal gate over its wire index, 3 two-qubit diagonal gate over its two wire
+ * indices, 4 two-qubit gate [out_a, out_b, in_a, in_b]; conj = 1 for the bra copy. */
+typedef struct {
+  int32_t kind;
+  int32_t gate;
+  int32_t conj;
+  int32_t const_off;
+} tq_tn_leaf;
+
+tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                             const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const,
+                             const void* d_params, void* d_leaves, void* stream);
+
+/* Chain rule from leaf environments to circuit parameters:
+ * d_grad_params[p] = Re sum over leaves built from a gate using p, of
+ * sum_x d_grad_leaves[x] * d(leaf)[x]/d(params[p]) (overwrites n_params entries). */
+tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                           const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
+                           const void* d_grad_leaves, void* d_grad_params, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -45,7 +45,7 @@ tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out) {
 // Immutable small host tables (offset maps, observable terms) live in device memory cached
 // by content, so repeated calls neither re-upload nor synchronise (and can be captured in a
 // hipGraph once warmed up).
-static tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev) {
+tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev) {
   const unsigned char* b = (const unsigned char*)host;
   uint64_t h1 = 0xCBF29CE484222325ull, h2 = 0x84222325CBF29CE4ull;
   for (size_t i = 0; i < bytes; ++i) {

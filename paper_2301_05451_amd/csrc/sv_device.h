@@ -141,6 +141,82 @@ __device__ inline dcx diag_entry(const tq_gate& g, int qa, int ba, int bb, const
   }
 }
 
+__host__ __device__ inline int gate_n_angles_dev(int op) {
+  return (op == TQ_RX || op == TQ_RY || op == TQ_RZ || op == TQ_RZZ) ? 1 : (op == TQ_U3 || op == TQ_ROT) ? 3 : 0;
+}
+
+constexpr int kAdjMatStride = 16;  // per gate: U (4 entries) then dU/da_j (4 entries each)
+
+// ---- matrices of a gate and of its angle derivatives (double precision) ----------------
+__device__ inline dmat2 d_rz(double a) {  // dRZ/da = diag(-i/2 e^{-ia/2}, i/2 e^{ia/2})
+  dcx e = expi(-0.5 * a);                  // e^{-ia/2}; e^{ia/2} = conj(e)
+  return dmat2{{{0.5 * e.y, -0.5 * e.x}, {0, 0}, {0, 0}, {0.5 * e.y, 0.5 * e.x}}};
+}
+__device__ inline dmat2 d_ry(double a) {
+  double s, c;
+  sincos(0.5 * a, &s, &c);
+  return dmat2{{{-0.5 * s, 0}, {-0.5 * c, 0}, {0.5 * c, 0}, {-0.5 * s, 0}}};
+}
+__device__ inline dmat2 d_rx(double a) {
+  double s, c;
+  sincos(0.5 * a, &s, &c);
+  return dmat2{{{-0.5 * s, 0}, {0, -0.5 * c}, {0, -0.5 * c}, {-0.5 * s, 0}}};
+}
+
+// Fills U and the derivative with respect to each angle (rows of 4, row-major 2x2, or the
+// diagonal for Z/RZ (2 entries, repeated) and RZZ (4 entries, index 2*bit(q0)+bit(q1))).
+__device__ inline void gate_and_derivs(int op, const double* a, dcx (&out)[kAdjMatStride]) {
+  for (int i = 0; i < kAdjMatStride; ++i) out[i] = dcx{0, 0};
+  auto put = [&](int slot, const dmat2& M) {
+    for (int i = 0; i < 4; ++i) out[4 * slot + i] = M.m[i];
+  };
+  switch (op) {
+    case TQ_RX: put(0, gate_mat2(TQ_RX, a)); put(1, d_rx(a[0])); break;
+    case TQ_RY: put(0, gate_mat2(TQ_RY, a)); put(1, d_ry(a[0])); break;
+    case TQ_RZ: {
+      dcx e0 = expi(-0.5 * a[0]), e1 = expi(0.5 * a[0]);
+      out[0] = e0; out[1] = e1; out[2] = e0; out[3] = e1;
+      dcx d0{0.5 * e0.y, -0.5 * e0.x}, d1{-0.5 * e1.y, 0.5 * e1.x};
+      out[4] = d0; out[5] = d1; out[6] = d0; out[7] = d1;
+      break;
+    }
+    case TQ_Z: out[0] = {1, 0}; out[1] = {-1, 0}; out[2] = {1, 0}; out[3] = {-1, 0}; break;
+    case TQ_RZZ: {
+      dcx em = expi(-0.5 * a[0]), ep = expi(0.5 * a[0]);
+      out[0] = em; out[1] = ep; out[2] = ep; out[3] = em;
+      dcx dm{0.5 * em.y, -0.5 * em.x}, dp{-0.5 * ep.y, 0.5 * ep.x};
+      out[4] = dm; out[5] = dp; out[6] = dp; out[7] = dm;
+      break;
+    }
+    case TQ_U3: {
+      // U3(th, ph, la) = [[c, -e^{i la} s], [e^{i ph} s, e^{i(ph+la)} c]]
+      double s, c;
+      sincos(0.5 * a[0], &s, &c);
+      dcx el = expi(a[2]), ep = expi(a[1]), epl = expi(a[1] + a[2]);
+      put(0, gate_mat2(TQ_U3, a));
+      out[4] = {-0.5 * s, 0}; out[5] = {-0.5 * c * el.x, -0.5 * c * el.y};
+      out[6] = {0.5 * c * ep.x, 0.5 * c * ep.y}; out[7] = {-0.5 * s * epl.x, -0.5 * s * epl.y};
+      out[8] = {0, 0}; out[9] = {0, 0};
+      out[10] = {-s * ep.y, s * ep.x}; out[11] = {-c * epl.y, c * epl.x};
+      out[12] = {0, 0}; out[13] = {s * el.y, -s * el.x};
+      out[14] = {0, 0}; out[15] = {-c * epl.y, c * epl.x};
+      break;
+    }
+    case TQ_ROT: {
+      // RZ(om) RY(th) RZ(ph) with (ph, th, om) = (a0, a1, a2)
+      double a0[1] = {a[0]}, a1[1] = {a[1]}, a2[1] = {a[2]};
+      dmat2 Z0 = gate_mat2(TQ_RZ, a0), Y1 = gate_mat2(TQ_RY, a1), Z2 = gate_mat2(TQ_RZ, a2);
+      put(0, mat_mul(Z2, mat_mul(Y1, Z0)));
+      put(1, mat_mul(Z2, mat_mul(Y1, d_rz(a[0]))));
+      put(2, mat_mul(Z2, mat_mul(d_ry(a[1]), Z0)));
+      put(3, mat_mul(d_rz(a[2]), mat_mul(Y1, Z0)));
+      break;
+    }
+    default: put(0, gate_mat2(op, a)); break;  // H, X, Y (no angles); CNOT/CZ unused
+  }
+}
+
+
 // Read one 8-byte op descriptor as a single aligned 64-bit word and unpack its byte
 // fields. Reading the fields one by one let the compiler split a field's address into a
 // misaligned scalar base plus a misaligned immediate offset; the scalar unit does not
@@ -176,7 +252,7 @@ template <typename T>
 tq_status launch_init_basis(void* d_states, BatchMap smap, int n, int count, int64_t basis, int n_cu,
                             hipStream_t stream);
 // sv_adjoint.hip
-constexpr int kAdjMatEntries = 16;
+constexpr int kAdjMatEntries = kAdjMatStride;
 template <typename T>
 tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap, const void* d_states_in,
                          BatchMap smap_in, void* psi, void* lam, BatchMap smap_w, void* mats, double* partial,

@@ -1,0 +1,1022 @@
+// Tensor-network mode: execution of a contraction tree as pairwise complex contractions
+// (the paper's Sec. 3.2, step (e)), optionally sliced (Sec. 3.2.3), and its reverse pass.
+//
+// Every index has dimension 2, so a tensor of rank r is 2^r complex numbers and an index
+// is one bit of the element offset (first index = most significant bit). A pairwise step
+// contracts X and Y into Z; each index of the step falls in one class:
+//   batch      in X, Y and Z          (a hyperedge kept for later tensors)
+//   kept       in X (or Y) and Z      (the M, N of a GEMM)
+//   contracted in X and Y, not in Z   (the K of a GEMM)
+//   summed     in X only (or Y only), not in Z
+//   broadcast  in Z only              (reverse pass of a summed index)
+// The generic "direct" kernel handles all classes with bit deposits. Steps whose indices are
+// only batch / kept / contracted and whose M, N, K are all large go to a bit-permute of X
+// and Y into [batch][M][K] and [batch][K][N] followed by a complex GEMM on FP32 MFMA
+// (a real GEMM on interleaved complex data with Y expanded to 2x2 real blocks, i.e. the
+// four-real-product form with FP32 accumulation).
+//
+// Slices run in groups of G: a tensor that does not depend on a sliced index is computed
+// once and shared by the G slices (stride 0); the others get G copies.
+#include <algorithm>
+#include <map>
+#include <set>
+
+#include "sv_device.h"
+
+namespace tq {
+
+constexpr int kTnMaxBits = 40;
+constexpr uint8_t kNone = 0xff;
+
+// Device-side compact step: bit-position tables.
+struct DevTnStep {
+  int32_t zr;               // output rank
+  int32_t ks;               // summed bits
+  uint8_t xo[kTnMaxBits];   // for output bit i (from LSB): position in X or kNone
+  uint8_t yo[kTnMaxBits];
+  uint8_t xs[kTnMaxBits];   // for summed bit j: position in X or kNone
+  uint8_t ys[kTnMaxBits];
+};
+
+struct TnTensorInfo {
+  int rank = 0;
+  std::vector<int> inds;    // most significant first
+  bool sdep = false;        // depends on a sliced index
+  int64_t off = -1;         // workspace offset (complex elements) of copy 0
+  int leaf = -1;            // leaf id (>= 0 for leaves)
+  std::vector<int> sliced_pos;  // leaves: positions (from LSB, in the full leaf) of sliced indices
+  std::vector<int> sliced_bits; // leaves: for each entry of sliced_pos, its bit in the slice number
+  int gather = -1;              // leaves: row of the plan's gather table
+};
+
+struct TnExec {              // one pairwise contraction as executed
+  int x, y, z;               // tensor ids (z may be an environment slot in the reverse pass)
+  int method = 0;            // 0 direct, 1 gemm
+  DevTnStep dev{};
+  int64_t flops = 0;         // real flops per slice
+  // gemm
+  int64_t B = 1, M = 1, N = 1, K = 1;
+  bool permx = false, permy = false;
+  std::vector<uint8_t> px, py;   // for each bit of the permuted operand (from LSB): source bit
+};
+
+}  // namespace tq
+
+struct tq_tn_plan {
+  int dtype = 0;
+  int n_leaves = 0;
+  std::vector<tq::TnTensorInfo> t;     // leaves then intermediates
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> sliced;
+  std::vector<int> out_inds;
+  int root = -1;
+  std::vector<int64_t> leaf_off;       // packed leaf buffer offsets
+  int64_t leaf_elems = 0;
+  int64_t n_slices = 1, G = 1;
+  std::vector<tq::TnExec> fwd;         // forward steps
+  std::vector<tq::TnExec> bwd;         // reverse steps (2 per forward step)
+  int64_t ws_fwd = 0, ws_bwd = 0;      // complex elements
+  int64_t perm_elems = 0;              // permute scratch (per slice)
+  int64_t perm_off = 0;                // workspace offset of the permute scratch
+  int64_t env_off0 = 0;                // reverse pass: environment offsets per tensor
+  std::vector<int64_t> env_off;
+  int64_t flops = 0, gemm_flops = 0, max_elems = 0;
+  int n_direct = 0, n_gemm = 0;
+  // device copies
+  void* d_fwd = nullptr;               // DevTnStep[fwd.size()]
+  void* d_bwd = nullptr;
+  void* d_perm = nullptr;              // uint8 tables for permutes: [2 * steps][kTnMaxBits]
+  void* d_bperm = nullptr;
+  std::vector<int> sliced_leaves;      // leaf tensor ids that depend on a sliced index
+  void* d_gather = nullptr;            // per sliced leaf: [keep pos][slice pos][slice bit] x kTnMaxBits
+  ~tq_tn_plan();
+};
+
+namespace tq {
+
+// ---------------------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t deposit_bits(uint64_t v, const uint8_t* pos, int n) {
+  int64_t r = 0;
+  for (int i = 0; i < n; ++i)
+    if (pos[i] != kNone) r |= (int64_t)((v >> i) & 1ull) << pos[i];
+  return r;
+}
+
+// Z[e] = sum_s X[xoff(e, s)] * Y[yoff(e, s)]; blockIdx.y = slice copy (stride 0 for shared).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_direct_kernel(const DevTnStep* __restrict__ st, const typename Cx<T>::type* __restrict__ X, int64_t xs,
+                     const typename Cx<T>::type* __restrict__ Y, int64_t ys, typename Cx<T>::type* __restrict__ Z,
+                     int64_t zs) {
+  using C = typename Cx<T>::type;
+  __shared__ int64_t tx[4096], ty[4096];
+  const int zr = st->zr, ks = st->ks;
+  const int kt = ks < 12 ? ks : 12;  // table bits
+  const int nt = 1 << kt;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+    tx[i] = deposit_bits((uint64_t)i, st->xs, kt);
+    ty[i] = deposit_bits((uint64_t)i, st->ys, kt);
+  }
+  __syncthreads();
+  const C* x = X + xs * blockIdx.y;
+  const C* y = Y + ys * blockIdx.y;
+  C* z = Z + zs * blockIdx.y;
+  const int64_t nz = int64_t(1) << zr;
+  const int64_t nouter = int64_t(1) << (ks - kt);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nz; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t xb = deposit_bits((uint64_t)e, st->xo, zr);
+    const int64_t yb = deposit_bits((uint64_t)e, st->yo, zr);
+    T ar = 0, ai = 0;
+    for (int64_t so = 0; so < nouter; ++so) {
+      const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
+      const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
+      for (int s = 0; s < nt; ++s) {
+        const C a = x[xo2 + tx[s]], b = y[yo2 + ty[s]];
+        ar += a.x * b.x - a.y * b.y;
+        ai += a.x * b.y + a.y * b.x;
+      }
+    }
+    C r;
+    r.x = ar;
+    r.y = ai;
+    z[e] = r;
+  }
+}
+
+// Bit permutation: out[j] = in[i(j)], out bit q taken from in bit perm[q].
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_permute_kernel(const typename Cx<T>::type* __restrict__ in, int64_t is, typename Cx<T>::type* __restrict__ out,
+                      int64_t os, const uint8_t* __restrict__ perm, int r) {
+  const typename Cx<T>::type* src = in + is * blockIdx.y;
+  typename Cx<T>::type* dst = out + os * blockIdx.y;
+  const int64_t n = int64_t(1) << r;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    dst[j] = src[deposit_bits((uint64_t)j, perm, r)];
+}
+
+// Batched complex GEMM on FP32 MFMA: C[b] (M x N) = A[b] (M x K) * B[b] (K x N), complex64,
+// row-major, interleaved. Real view: C^ (M x 2N) = A^ (M x 2K) * B^ (2K x 2N) with every
+// complex b of B becoming the real block [[br, bi], [-bi, br]]. Work-group tile 64 x 64 real
+// (64 complex rows x 32 complex columns), 4 waves in 2 x 2, each wave 2 x 2 MFMA 16x16x4
+// blocks. Requires M % 64 == 0, N % 32 == 0, K % 8 == 0.
+constexpr int kGemmBM = 64, kGemmBN = 64, kGemmBK = 16;
+
+__global__ void __launch_bounds__(256)
+    tn_cgemm_mfma_kernel(const float2* __restrict__ A, int64_t as, const float2* __restrict__ B, int64_t bs,
+                         float2* __restrict__ Cm, int64_t cs, int M, int N, int K) {
+  __shared__ float sA[kGemmBK][kGemmBM + 4];   // [k][m]
+  __shared__ float sB[kGemmBK][kGemmBN + 4];   // [k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int m0 = blockIdx.y * kGemmBM;
+  const int n0c = blockIdx.x * (kGemmBN / 2);  // complex column
+  const float2* a = A + as * blockIdx.z;
+  const float2* b = B + bs * blockIdx.z;
+  float2* c = Cm + cs * blockIdx.z;
+  typedef float float4v __attribute__((ext_vector_type(4)));
+  float4v acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += kGemmBK / 2) {  // complex k
+    // A tile: 64 rows x 8 complex = 64 x 16 real; thread loads 2 complex of one row
+    {
+      const int r = tid >> 2, kk = (tid & 3) * 2;
+      const float2 v0 = a[(int64_t)(m0 + r) * K + k0 + kk];
+      const float2 v1 = a[(int64_t)(m0 + r) * K + k0 + kk + 1];
+      sA[2 * kk + 0][r] = v0.x;
+      sA[2 * kk + 1][r] = v0.y;
+      sA[2 * kk + 2][r] = v1.x;
+      sA[2 * kk + 3][r] = v1.y;
+    }
+    // B tile: 8 complex rows x 32 complex cols -> 16 x 64 real
+    {
+      const int kr = tid >> 5, cc = tid & 31;
+      const float2 v = b[(int64_t)(k0 + kr) * N + n0c + cc];
+      sB[2 * kr + 0][2 * cc + 0] = v.x;
+      sB[2 * kr + 0][2 * cc + 1] = v.y;
+      sB[2 * kr + 1][2 * cc + 0] = -v.y;
+      sB[2 * kr + 1][2 * cc + 1] = v.x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmBK; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      float av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = sA[kl][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = sB[kl][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of 16x16x4: lane l, register r -> row 4*(l/16) + r, column l % 16
+  float* cf = reinterpret_cast<float*>(c);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int col = 2 * n0c + wn + 16 * j + (lane & 15);
+        cf[(int64_t)row * (2 * N) + col] = acc[i][j][r];
+      }
+}
+
+// Sliced leaf restriction: out[g][j] = leaf[j with the sliced bits of slice s0+g inserted].
+template <typename T>
+__global__ void tn_slice_gather_kernel(const typename Cx<T>::type* __restrict__ leaf, typename Cx<T>::type* __restrict__ out,
+                                       int r_out, const uint8_t* __restrict__ keep_pos, const uint8_t* __restrict__ sl_pos,
+                                       const uint8_t* __restrict__ sl_bit, int nsl, int64_t s0) {
+  const int g = blockIdx.y;
+  const int64_t s = s0 + g;
+  int64_t base = 0;
+  for (int q = 0; q < nsl; ++q) base |= ((s >> sl_bit[q]) & 1) << sl_pos[q];
+  const int64_t n = int64_t(1) << r_out;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    out[(int64_t)g * n + j] = leaf[base | deposit_bits((uint64_t)j, keep_pos, r_out)];
+}
+
+// Reverse of the gather: grad_leaf[slice bits of s0+g inserted][j] += env[g][j], g in order.
+template <typename T>
+__global__ void tn_slice_scatter_kernel(const typename Cx<T>::type* __restrict__ env, int64_t es, int G,
+                                        typename Cx<T>::type* __restrict__ grad, int r_env,
+                                        const uint8_t* __restrict__ keep_pos, const uint8_t* __restrict__ sl_pos,
+                                        const uint8_t* __restrict__ sl_bit, int nsl, int64_t s0) {
+  using C = typename Cx<T>::type;
+  const int64_t n = int64_t(1) << r_env;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lj = deposit_bits((uint64_t)j, keep_pos, r_env);
+    for (int g = 0; g < G; ++g) {
+      const int64_t s = s0 + g;
+      int64_t base = 0;
+      for (int q = 0; q < nsl; ++q) base |= ((s >> sl_bit[q]) & 1) << sl_pos[q];
+      const C e = env[es * g + j];
+      C v = grad[base | lj];
+      v.x += e.x;
+      v.y += e.y;
+      grad[base | lj] = v;
+    }
+  }
+}
+
+// out[j] (+)= sum_g in[g][j] in slice order.
+template <typename T>
+__global__ void tn_sum_copies_kernel(const typename Cx<T>::type* __restrict__ in, int64_t is, int G,
+                                     typename Cx<T>::type* __restrict__ out, int64_t n, int accumulate) {
+  using C = typename Cx<T>::type;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    C v = accumulate ? out[j] : C{0, 0};
+    for (int g = 0; g < G; ++g) {
+      const C e = in[is * g + j];
+      v.x += e.x;
+      v.y += e.y;
+    }
+    out[j] = v;
+  }
+}
+
+template <typename T>
+__global__ void tn_fill_kernel(typename Cx<T>::type* __restrict__ p, int64_t n, typename Cx<T>::type v) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    p[j] = v;
+}
+
+// ---- leaves from circuit parameters ------------------------------------------------------
+struct DevLeaf {
+  int32_t kind, gate, conj, const_off;
+  int64_t off;
+};
+
+template <typename T>
+__global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leaves, const tq_gate* __restrict__ gates,
+                                     const double* __restrict__ cv, const T* __restrict__ params,
+                                     typename Cx<T>::type* __restrict__ out) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= n_leaves) return;
+  const DevLeaf L = lv[li];
+  typename Cx<T>::type* o = out + L.off;
+  const double sg = L.conj ? -1.0 : 1.0;
+  if (L.kind == 0) {
+    // constants are copied as given (the caller supplies conjugated values if needed)
+    const int r = L.gate;  // number of entries for constants is carried in gate
+    for (int i = 0; i < r; ++i) o[i] = to_cx<T>(dcx{cv[2 * (L.const_off + i)], cv[2 * (L.const_off + i) + 1]});
+    return;
+  }
+  const tq_gate& g = gates[L.gate];
+  double a[3];
+  gate_angles(g, params, a);
+  if (L.kind == 1) {
+    const dmat2 M = gate_mat2(g.op, a);
+    for (int i = 0; i < 4; ++i) o[i] = to_cx<T>(dcx{M.m[i].x, sg * M.m[i].y});
+  } else if (L.kind == 2) {
+    for (int b = 0; b < 2; ++b) {
+      dcx d = diag_entry(g, g.q[0], b, b, a);
+      o[b] = to_cx<T>(dcx{d.x, sg * d.y});
+    }
+  } else if (L.kind == 3) {
+    for (int idx = 0; idx < 4; ++idx) {
+      dcx d = diag_entry(g, g.q[0], idx >> 1, idx & 1, a);
+      o[idx] = to_cx<T>(dcx{d.x, sg * d.y});
+    }
+  } else {  // two-qubit non-diagonal: CNOT [out_c, out_t, in_c, in_t]
+    for (int i = 0; i < 16; ++i) {
+      const int oc = (i >> 3) & 1, ot = (i >> 2) & 1, ic = (i >> 1) & 1, it = i & 1;
+      double v = 0;
+      if (g.op == TQ_CNOT) v = (oc == ic) && (ot == (ic ? 1 - it : it)) ? 1.0 : 0.0;
+      o[i] = to_cx<T>(dcx{v, 0.0});
+    }
+  }
+}
+
+// d(leaf)/d(angle j) for the gate leaf kinds (conjugated for bra copies): the entries of
+// dU/da_j in the leaf's own layout (2x2 [out, in]; diagonal over the wire(s)).
+__device__ inline int leaf_derivative(const DevLeaf& L, const tq_gate& g, const double* a, int j, dcx (&d)[16]) {
+  if (L.kind != 1 && L.kind != 2 && L.kind != 3) return 0;
+  if (j >= gate_n_angles_dev(g.op)) return 0;
+  dcx m[kAdjMatStride];
+  gate_and_derivs(g.op, a, m);
+  const double sg = L.conj ? -1.0 : 1.0;
+  const int n = L.kind == 2 ? 2 : 4;
+  for (int i = 0; i < n; ++i) d[i] = dcx{m[4 + 4 * j + i].x, sg * m[4 + 4 * j + i].y};
+  return n;
+}
+
+// grad[p] = Re sum over (leaf, angle) entries of p: pscale * sum_x env[x] * dleaf[x]
+template <typename T>
+__global__ void tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
+                                     const T* __restrict__ params, const int32_t* __restrict__ pptr,
+                                     const int32_t* __restrict__ pent, const typename Cx<T>::type* __restrict__ env,
+                                     int n_params, T* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_params) return;
+  double acc = 0.0;
+  for (int e = pptr[p]; e < pptr[p + 1]; ++e) {
+    const int li = pent[2 * e], j = pent[2 * e + 1];
+    const DevLeaf L = lv[li];
+    const tq_gate& g = gates[L.gate];
+    double a[3];
+    gate_angles(g, params, a);
+    dcx d[16];
+    const int n = leaf_derivative(L, g, a, j, d);
+    const typename Cx<T>::type* E = env + L.off;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += (double)E[i].x * d[i].x - (double)E[i].y * d[i].y;
+    acc += g.pscale[j] * s;
+  }
+  grad[p] = (T)acc;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host planning
+// ---------------------------------------------------------------------------------------
+static int pos_of(const std::vector<int>& inds, int id) {  // bit position from LSB
+  for (size_t i = 0; i < inds.size(); ++i)
+    if (inds[i] == id) return (int)(inds.size() - 1 - i);
+  return -1;
+}
+
+// Build a pairwise contraction of tensors with index lists xi, yi into zi (order given).
+static TnExec make_exec(const std::vector<int>& xi, const std::vector<int>& yi, const std::vector<int>& zi, bool allow_gemm,
+                        int csz) {
+  TnExec ex;
+  DevTnStep& d = ex.dev;
+  std::memset(&d, 0xff, sizeof d);
+  d.zr = (int)zi.size();
+  std::set<int> zs(zi.begin(), zi.end());
+  for (int i = 0; i < d.zr; ++i) {
+    const int id = zi[d.zr - 1 - i];  // output bit i from LSB
+    const int px = pos_of(xi, id), py = pos_of(yi, id);
+    d.xo[i] = px >= 0 ? (uint8_t)px : kNone;
+    d.yo[i] = py >= 0 ? (uint8_t)py : kNone;
+  }
+  std::vector<int> summed;
+  for (int id : xi)
+    if (!zs.count(id)) summed.push_back(id);
+  for (int id : yi)
+    if (!zs.count(id) && std::find(summed.begin(), summed.end(), id) == summed.end()) summed.push_back(id);
+  d.ks = (int)summed.size();
+  for (int j = 0; j < d.ks; ++j) {
+    const int px = pos_of(xi, summed[j]), py = pos_of(yi, summed[j]);
+    d.xs[j] = px >= 0 ? (uint8_t)px : kNone;
+    d.ys[j] = py >= 0 ? (uint8_t)py : kNone;
+  }
+  ex.flops = (int64_t(8) << d.zr) << d.ks;
+  // GEMM eligibility: every Z index in exactly one of (X and Y) -> batch, or X only (M), or
+  // Y only (N); every summed index in both (K); no broadcast.
+  std::vector<int> bI, mI, nI, kI;
+  bool ok = allow_gemm && csz == 8;
+  for (int id : zi) {
+    const bool inx = pos_of(xi, id) >= 0, iny = pos_of(yi, id) >= 0;
+    if (inx && iny) bI.push_back(id);
+    else if (inx) mI.push_back(id);
+    else if (iny) nI.push_back(id);
+    else ok = false;
+  }
+  for (int id : summed) {
+    if (pos_of(xi, id) < 0 || pos_of(yi, id) < 0) ok = false;
+    kI.push_back(id);
+  }
+  // Z must already be [b][m][n] in the order given: check zi == b + m + n
+  std::vector<int> want;
+  want.insert(want.end(), bI.begin(), bI.end());
+  want.insert(want.end(), mI.begin(), mI.end());
+  want.insert(want.end(), nI.begin(), nI.end());
+  if (want != zi) ok = false;
+  if (ok && mI.size() >= 6 && nI.size() >= 5 && kI.size() >= 3 && (mI.size() + nI.size() + kI.size()) >= 18) {
+    ex.method = 1;
+    ex.B = int64_t(1) << bI.size();
+    ex.M = int64_t(1) << mI.size();
+    ex.N = int64_t(1) << nI.size();
+    ex.K = int64_t(1) << kI.size();
+    // permuted X: [b][m][k], permuted Y: [b][k][n]
+    std::vector<int> xp, yp;
+    xp.insert(xp.end(), bI.begin(), bI.end());
+    xp.insert(xp.end(), mI.begin(), mI.end());
+    xp.insert(xp.end(), kI.begin(), kI.end());
+    yp.insert(yp.end(), bI.begin(), bI.end());
+    yp.insert(yp.end(), kI.begin(), kI.end());
+    yp.insert(yp.end(), nI.begin(), nI.end());
+    ex.permx = xp != xi;
+    ex.permy = yp != yi;
+    ex.px.assign(kTnMaxBits, 0);
+    ex.py.assign(kTnMaxBits, 0);
+    for (size_t q = 0; q < xp.size(); ++q) ex.px[q] = (uint8_t)pos_of(xi, xp[xp.size() - 1 - q]);
+    for (size_t q = 0; q < yp.size(); ++q) ex.py[q] = (uint8_t)pos_of(yi, yp[yp.size() - 1 - q]);
+  }
+  return ex;
+}
+
+}  // namespace tq
+
+tq_tn_plan::~tq_tn_plan() {
+  void* p[] = {d_fwd, d_bwd, d_perm, d_bperm, d_gather};
+  for (void* x : p)
+    if (x) (void)hipFree(x);
+}
+
+using namespace tq;
+
+extern "C" {
+
+tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) {
+  if (!ctx || !d || !out) return fail(TQ_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->dtype != TQ_C64 && d->dtype != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
+  const int L = d->n_leaves;
+  if (L < 1 || !d->leaf_rank || !d->leaf_inds) return fail(TQ_EINVAL, "no leaves");
+  if (L > 1 && !d->pairs) return fail(TQ_EINVAL, "null tree");
+  if (d->n_sliced < 0 || d->n_sliced > 24 || (d->n_sliced && !d->sliced)) return fail(TQ_EINVAL, "bad sliced list");
+  if (d->n_out < 0 || (d->n_out && !d->out_inds)) return fail(TQ_EINVAL, "bad output list");
+  auto p = std::make_unique<tq_tn_plan>();
+  p->dtype = d->dtype;
+  p->n_leaves = L;
+  const int csz = d->dtype == TQ_C64 ? 8 : 16;
+  std::set<int> sl(d->sliced, d->sliced + d->n_sliced);
+  if ((int)sl.size() != d->n_sliced) return fail(TQ_EINVAL, "duplicate sliced index");
+  p->sliced.assign(d->sliced, d->sliced + d->n_sliced);
+  p->out_inds.assign(d->out_inds, d->out_inds + d->n_out);
+  for (int id : p->out_inds)
+    if (sl.count(id)) return fail(TQ_EINVAL, "an output index cannot be sliced");
+  // leaves
+  int64_t off = 0, ii = 0;
+  std::map<int, int> count;
+  for (int l = 0; l < L; ++l) {
+    TnTensorInfo t;
+    const int r = d->leaf_rank[l];
+    if (r < 0 || r > 30) return fail(TQ_EINVAL, "leaf rank out of range");
+    std::vector<int> full(d->leaf_inds + ii, d->leaf_inds + ii + r);
+    ii += r;
+    std::set<int> u(full.begin(), full.end());
+    if ((int)u.size() != r) return fail(TQ_EINVAL, "leaf " + std::to_string(l) + " repeats an index");
+    for (int id : full) {
+      if (id < 0) return fail(TQ_EINVAL, "negative index id");
+      count[id]++;
+    }
+    p->leaf_off.push_back(off);
+    off += int64_t(1) << r;
+    for (int q = 0; q < r; ++q) {
+      if (sl.count(full[q])) {
+        t.sdep = true;
+      } else {
+        t.inds.push_back(full[q]);
+      }
+    }
+    for (size_t si = 0; si < p->sliced.size(); ++si)
+      for (int q = 0; q < r; ++q)
+        if (full[q] == p->sliced[si]) {
+          t.sliced_pos.push_back(r - 1 - q);
+          t.sliced_bits.push_back((int)si);
+        }
+    t.rank = (int)t.inds.size();
+    t.leaf = l;
+    p->t.push_back(t);
+  }
+  p->leaf_elems = off;
+  // tree
+  std::vector<char> used(2 * L, 0);
+  std::map<int, int> live(count);  // index -> live holders
+  for (int id : p->out_inds) live[id] += 1 << 20;  // outputs always kept
+  for (int s = 0; s < L - 1; ++s) {
+    const int a = d->pairs[2 * s], b = d->pairs[2 * s + 1];
+    if (a < 0 || b < 0 || a >= L + s || b >= L + s || a == b || used[a] || used[b])
+      return fail(TQ_EINVAL, "tree step " + std::to_string(s) + " uses an invalid or consumed id");
+    used[a] = used[b] = 1;
+    const TnTensorInfo &A = p->t[a], &B = p->t[b];
+    // kept indices: appear in other live tensors or the output (counts over full leaves;
+    // sliced ids are never in any tensor's index list)
+    std::vector<int> bI, mI, nI;
+    for (int id : A.inds) live[id]--;
+    for (int id : B.inds) live[id]--;
+    for (int id : A.inds) {
+      const bool inB = std::find(B.inds.begin(), B.inds.end(), id) != B.inds.end();
+      if (live[id] > 0) (inB ? bI : mI).push_back(id);
+    }
+    for (int id : B.inds) {
+      const bool inA = std::find(A.inds.begin(), A.inds.end(), id) != A.inds.end();
+      if (!inA && live[id] > 0) nI.push_back(id);
+    }
+    TnTensorInfo C;
+    C.inds = bI;
+    C.inds.insert(C.inds.end(), mI.begin(), mI.end());
+    C.inds.insert(C.inds.end(), nI.begin(), nI.end());
+    for (int id : C.inds) live[id]++;
+    C.rank = (int)C.inds.size();
+    if (C.rank > 34) return fail(TQ_ENOTSUP, "intermediate of rank " + std::to_string(C.rank) + " (slice more)");
+    C.sdep = A.sdep || B.sdep;
+    p->t.push_back(C);
+    p->pairs.push_back({a, b});
+  }
+  p->root = L == 1 ? 0 : 2 * L - 2;
+  // the result's open indices must equal out_inds as a set
+  {
+    std::set<int> got(p->t[p->root].inds.begin(), p->t[p->root].inds.end());
+    std::set<int> want(p->out_inds.begin(), p->out_inds.end());
+    if (got != want) return fail(TQ_EINVAL, "the tree's result indices differ from out_inds");
+  }
+  // forward execs (last step writes the output order requested)
+  p->n_slices = int64_t(1) << p->sliced.size();
+  int64_t per_slice = 0, shared = 0, max_el = 0, perm = 0;
+  for (size_t s = 0; s < p->pairs.size(); ++s) {
+    const int a = p->pairs[s].first, b = p->pairs[s].second, c = L + (int)s;
+    std::vector<int> zi = p->t[c].inds;
+    if (c == p->root && !p->out_inds.empty()) zi = p->out_inds;
+    TnExec ex = make_exec(p->t[a].inds, p->t[b].inds, zi, true, csz);
+    if (c == p->root) p->t[c].inds = zi;
+    ex.x = a;
+    ex.y = b;
+    ex.z = c;
+    if (ex.method == 1) {
+      p->n_gemm++;
+      p->gemm_flops += ex.flops;
+      if (ex.permx) perm = std::max<int64_t>(perm, int64_t(1) << p->t[a].rank);
+      if (ex.permy) perm = std::max<int64_t>(perm, int64_t(1) << p->t[b].rank);
+    } else {
+      p->n_direct++;
+    }
+    p->flops += ex.flops;
+    p->fwd.push_back(ex);
+    const int64_t sz = int64_t(1) << p->t[c].rank;
+    max_el = std::max(max_el, sz);
+    (p->t[c].sdep ? per_slice : shared) += sz;
+  }
+  for (auto& t : p->t)
+    if (t.leaf >= 0 && t.sdep) per_slice += int64_t(1) << t.rank;
+  p->flops *= p->n_slices;
+  p->gemm_flops *= p->n_slices;
+  p->max_elems = max_el;
+  p->perm_elems = 2 * perm;
+  // slice group: G copies of the slice-dependent tensors within the memory budget
+  const int64_t budget = d->mem_budget > 0 ? d->mem_budget : (int64_t(4) << 30);
+  int64_t G = d->slice_group > 0 ? d->slice_group : p->n_slices;
+  G = std::min(G, p->n_slices);
+  while (G > 1 && (shared + G * (per_slice + p->perm_elems)) * 2 * csz > budget) G >>= 1;
+  p->G = std::max<int64_t>(G, 1);
+  // workspace offsets (complex elements): shared tensors once, slice tensors G copies
+  int64_t w = 0;
+  for (auto& t : p->t) {
+    if (t.leaf >= 0 && !t.sdep) continue;  // read from the leaf buffer
+    t.off = w;
+    w += (t.sdep ? p->G : 1) * (int64_t(1) << t.rank);
+  }
+  p->perm_off = w;
+  w += p->G * p->perm_elems;
+  w += p->G;  // root per-slice values (if the root is shared, copies are still G)
+  p->ws_fwd = w + (int64_t(1) << p->t[p->root].rank) * p->G;
+  // reverse pass: environments of every tensor, G copies each
+  p->env_off.assign(p->t.size(), 0);
+  int64_t e = p->ws_fwd;
+  for (size_t i = 0; i < p->t.size(); ++i) {
+    p->env_off[i] = e;
+    e += p->G * (int64_t(1) << p->t[i].rank);
+  }
+  p->ws_bwd = e;
+  // reverse execs: D_x = contract(D_z, y) -> x inds, D_y = contract(D_z, x) -> y inds
+  for (size_t s = p->fwd.size(); s-- > 0;) {
+    const TnExec& f = p->fwd[s];
+    TnExec ex1 = make_exec(p->t[f.z].inds, p->t[f.y].inds, p->t[f.x].inds, false, csz);
+    ex1.x = f.z;
+    ex1.y = f.y;
+    ex1.z = f.x;
+    TnExec ex2 = make_exec(p->t[f.z].inds, p->t[f.x].inds, p->t[f.y].inds, false, csz);
+    ex2.x = f.z;
+    ex2.y = f.x;
+    ex2.z = f.y;
+    p->bwd.push_back(ex1);
+    p->bwd.push_back(ex2);
+  }
+  // every sliced index must occur in some leaf
+  for (int si : p->sliced)
+    if (!count.count(si)) return fail(TQ_EINVAL, "sliced index " + std::to_string(si) + " is in no leaf");
+  // gather tables of the sliced leaves
+  std::vector<uint8_t> gt;
+  for (size_t i = 0; i < p->t.size(); ++i) {
+    TnTensorInfo& t = p->t[i];
+    if (t.leaf < 0 || !t.sdep) continue;
+    t.gather = (int)p->sliced_leaves.size();
+    p->sliced_leaves.push_back((int)i);
+    const int rf = t.rank + (int)t.sliced_pos.size();
+    std::vector<uint8_t> row(3 * kTnMaxBits, 0);
+    std::vector<char> is_sl(rf, 0);
+    for (int q : t.sliced_pos) is_sl[q] = 1;
+    int k = 0;
+    for (int q = 0; q < rf; ++q)
+      if (!is_sl[q]) row[k++] = (uint8_t)q;
+    for (size_t q = 0; q < t.sliced_pos.size(); ++q) {
+      row[kTnMaxBits + q] = (uint8_t)t.sliced_pos[q];
+      row[2 * kTnMaxBits + q] = (uint8_t)t.sliced_bits[q];
+    }
+    gt.insert(gt.end(), row.begin(), row.end());
+  }
+  // device copies of the step tables
+  {
+    std::vector<DevTnStep> fs, bs;
+    std::vector<uint8_t> pt;
+    for (auto& f : p->fwd) {
+      fs.push_back(f.dev);
+      std::vector<uint8_t> px = f.px, py = f.py;
+      px.resize(kTnMaxBits, 0);
+      py.resize(kTnMaxBits, 0);
+      pt.insert(pt.end(), px.begin(), px.end());
+      pt.insert(pt.end(), py.begin(), py.end());
+    }
+    for (auto& b : p->bwd) bs.push_back(b.dev);
+    auto up = [](const void* src, size_t bytes, void** dst) -> tq_status {
+      TQ_HIP(hipMalloc(dst, std::max<size_t>(bytes, 64)));
+      if (bytes) TQ_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+      return TQ_OK;
+    };
+    TQ_TRY(up(fs.data(), fs.size() * sizeof(DevTnStep), &p->d_fwd));
+    TQ_TRY(up(bs.data(), bs.size() * sizeof(DevTnStep), &p->d_bwd));
+    TQ_TRY(up(pt.data(), pt.size(), &p->d_perm));
+    TQ_TRY(up(gt.data(), gt.size(), &p->d_gather));
+  }
+  *out = p.release();
+  return TQ_OK;
+}
+
+void tq_tn_plan_destroy(tq_tn_plan* plan) { delete plan; }
+
+int64_t tq_tn_leaf_elems(const tq_tn_plan* p) { return p ? p->leaf_elems : -1; }
+
+int64_t tq_tn_leaf_offset(const tq_tn_plan* p, int32_t leaf) {
+  if (!p || leaf < 0 || leaf >= p->n_leaves) return -1;
+  return p->leaf_off[leaf];
+}
+
+int64_t tq_tn_workspace(const tq_tn_plan* p, int32_t backward) {
+  if (!p) return -1;
+  const int csz = p->dtype == TQ_C64 ? 8 : 16;
+  return (backward ? p->ws_bwd : p->ws_fwd) * csz + 1024;
+}
+
+tq_status tq_tn_plan_info(const tq_tn_plan* p, int64_t out[8]) {
+  if (!p || !out) return fail(TQ_EINVAL, "null argument");
+  out[0] = (int64_t)p->fwd.size();
+  out[1] = p->n_direct;
+  out[2] = p->n_gemm;
+  out[3] = p->n_slices;
+  out[4] = p->G;
+  out[5] = p->flops;
+  out[6] = p->gemm_flops;
+  out[7] = p->max_elems;
+  return TQ_OK;
+}
+
+}  // extern "C"
+
+namespace tq {
+
+// ---- execution: see tn_exec below ----
+
+}  // namespace tq
+
+namespace tq {
+
+static inline unsigned grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+template <typename T>
+struct TnRun {
+  using C = typename Cx<T>::type;
+  const tq_tn_plan* p;
+  const C* leaves;
+  C* ws;
+  hipStream_t st;
+  int64_t s0 = 0;  // first slice of the group
+  int64_t g = 1;   // slices in this group
+  // forward storage of tensor i: pointer and per-copy stride (0 = shared by the group)
+  C* tptr(int i, int64_t* stride) const {
+    const TnTensorInfo& t = p->t[i];
+    if (t.leaf >= 0 && !t.sdep) {
+      *stride = 0;
+      return const_cast<C*>(leaves) + p->leaf_off[t.leaf];
+    }
+    *stride = t.sdep ? (int64_t(1) << t.rank) : 0;
+    return ws + t.off;
+  }
+  C* eptr(int i) const { return ws + p->env_off[i]; }  // environments: g copies, stride = size
+  int64_t esz(int i) const { return int64_t(1) << p->t[i].rank; }
+};
+
+template <typename T>
+static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const typename Cx<T>::type* x, int64_t xs,
+                           const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs, int zr,
+                           int64_t copies) {
+  const int64_t nz = int64_t(1) << zr;
+  for (int64_t c0 = 0; c0 < copies; c0 += 65535) {
+    const int64_t cn = std::min<int64_t>(65535, copies - c0);
+    hipLaunchKernelGGL(tn_direct_kernel<T>, dim3(grid_for(nz), (unsigned)cn), dim3(256), 0, R.st, dstep, x + xs * c0,
+                       xs, y + ys * c0, ys, z + zs * c0, zs);
+  }
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status tn_forward_group(TnRun<T>& R) {
+  using C = typename Cx<T>::type;
+  const tq_tn_plan* p = R.p;
+  // sliced leaves: restrict each to the group's slices
+  for (int li : p->sliced_leaves) {
+    const TnTensorInfo& t = p->t[li];
+    const uint8_t* tab = (const uint8_t*)p->d_gather + (size_t)t.gather * 3 * kTnMaxBits;
+    const int64_t n = int64_t(1) << t.rank;
+    hipLaunchKernelGGL(tn_slice_gather_kernel<T>, dim3(grid_for(n), (unsigned)R.g), dim3(256), 0, R.st,
+                       R.leaves + p->leaf_off[t.leaf], R.ws + t.off, t.rank, tab, tab + kTnMaxBits,
+                       tab + 2 * kTnMaxBits, (int)t.sliced_pos.size(), R.s0);
+    TQ_HIP(hipGetLastError());
+  }
+  for (size_t s = 0; s < p->fwd.size(); ++s) {
+    const TnExec& ex = p->fwd[s];
+    int64_t xs, ys, zs;
+    const C* x = R.tptr(ex.x, &xs);
+    const C* y = R.tptr(ex.y, &ys);
+    C* z = R.tptr(ex.z, &zs);
+    const int64_t copies = p->t[ex.z].sdep ? R.g : 1;
+    if (ex.method == 1) {
+      if constexpr (sizeof(T) == 4) {
+        // permute X -> [b][m][k], Y -> [b][k][n] into the group's scratch, then GEMM per copy
+        C* pbuf = R.ws + p->perm_off;
+        const int64_t half = p->perm_elems / 2;
+        const uint8_t* perm = (const uint8_t*)p->d_perm + s * 2 * kTnMaxBits;
+        const C* xa = x;
+        const C* ya = y;
+        int64_t xas = xs, yas = ys;
+        if (ex.permx) {
+          const int r = p->t[ex.x].rank;
+          const int64_t cx = xs ? copies : 1;
+          hipLaunchKernelGGL(tn_permute_kernel<T>, dim3(grid_for(int64_t(1) << r), (unsigned)cx), dim3(256), 0, R.st,
+                             x, xs, pbuf, p->perm_elems, perm, r);
+          xa = pbuf;
+          xas = xs ? p->perm_elems : 0;
+        }
+        if (ex.permy) {
+          const int r = p->t[ex.y].rank;
+          const int64_t cy = ys ? copies : 1;
+          hipLaunchKernelGGL(tn_permute_kernel<T>, dim3(grid_for(int64_t(1) << r), (unsigned)cy), dim3(256), 0, R.st,
+                             y, ys, pbuf + half, p->perm_elems, perm + kTnMaxBits, r);
+          ya = pbuf + half;
+          yas = ys ? p->perm_elems : 0;
+        }
+        TQ_HIP(hipGetLastError());
+        for (int64_t c = 0; c < copies; ++c) {
+          hipLaunchKernelGGL(tn_cgemm_mfma_kernel, dim3((unsigned)(ex.N / 32), (unsigned)(ex.M / 64), (unsigned)ex.B),
+                             dim3(256), 0, R.st, (const float2*)(xa + xas * c), ex.M * ex.K,
+                             (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c), ex.M * ex.N, (int)ex.M,
+                             (int)ex.N, (int)ex.K);
+        }
+        TQ_HIP(hipGetLastError());
+        continue;
+      }
+    }
+    TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_fwd + s, x, xs, y, ys, z, zs, p->t[ex.z].rank, copies));
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status tn_contract_t(tq_ctx* ctx, const tq_tn_plan* p, const void* d_leaves, void* d_out, void* d_work,
+                               int64_t work_bytes, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  (void)ctx;
+  if (work_bytes < tq_tn_workspace(p, 0)) return fail(TQ_EWORKSPACE, "tn workspace too small");
+  TnRun<T> R{p, (const C*)d_leaves, (C*)d_work, stream};
+  const int64_t nout = int64_t(1) << p->t[p->root].rank;
+  if (p->fwd.empty()) {  // a single leaf
+    hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(nout)), dim3(256), 0, stream, (const C*)d_leaves, 0, 1,
+                       (C*)d_out, nout, 0);
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
+  for (int64_t s0 = 0; s0 < p->n_slices; s0 += p->G) {
+    R.s0 = s0;
+    R.g = std::min<int64_t>(p->G, p->n_slices - s0);
+    TQ_TRY(tn_forward_group<T>(R));
+    int64_t rs;
+    const C* root = R.tptr(p->root, &rs);
+    hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(nout)), dim3(256), 0, stream, root, rs, (int)R.g,
+                       (C*)d_out, nout, s0 > 0 ? 1 : 0);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+static tq_status tn_backward_t(tq_ctx* ctx, const tq_tn_plan* p, const void* d_leaves, const void* d_grad_out,
+                               void* d_grad, void* d_work, int64_t work_bytes, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  (void)ctx;
+  if (work_bytes < tq_tn_workspace(p, 1)) return fail(TQ_EWORKSPACE, "tn workspace too small for the reverse pass");
+  TnRun<T> R{p, (const C*)d_leaves, (C*)d_work, stream};
+  C* grad = (C*)d_grad;
+  hipLaunchKernelGGL(tn_fill_kernel<T>, dim3(grid_for(p->leaf_elems)), dim3(256), 0, stream, grad, p->leaf_elems,
+                     C{0, 0});
+  TQ_HIP(hipGetLastError());
+  const int64_t nout = int64_t(1) << p->t[p->root].rank;
+  if (p->fwd.empty()) {
+    hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(nout)), dim3(256), 0, stream, (const C*)d_grad_out, 0, 1,
+                       grad, nout, 0);
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
+  for (int64_t s0 = 0; s0 < p->n_slices; s0 += p->G) {
+    R.s0 = s0;
+    R.g = std::min<int64_t>(p->G, p->n_slices - s0);
+    TQ_TRY(tn_forward_group<T>(R));
+    // environment of the result: the upstream value, one copy per slice
+    for (int64_t c = 0; c < R.g; ++c) {
+      hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(nout)), dim3(256), 0, stream, (const C*)d_grad_out, 0,
+                         1, R.eptr(p->root) + c * nout, nout, 0);
+    }
+    TQ_HIP(hipGetLastError());
+    for (size_t k = 0; k < p->bwd.size(); ++k) {
+      const TnExec& ex = p->bwd[k];
+      int64_t ys;
+      const C* y = R.tptr(ex.y, &ys);
+      TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_bwd + k, R.eptr(ex.x), R.esz(ex.x), y, ys, R.eptr(ex.z),
+                          R.esz(ex.z), p->t[ex.z].rank, R.g));
+    }
+    // leaf environments -> gradient buffer (sum over the group's slices, in order)
+    for (int l = 0; l < p->n_leaves; ++l) {
+      const TnTensorInfo& t = p->t[l];
+      const int64_t n = int64_t(1) << t.rank;
+      if (t.sdep) {
+        const uint8_t* tab = (const uint8_t*)p->d_gather + (size_t)t.gather * 3 * kTnMaxBits;
+        hipLaunchKernelGGL(tn_slice_scatter_kernel<T>, dim3(grid_for(n)), dim3(256), 0, stream, R.eptr(l), n,
+                           (int)R.g, grad + p->leaf_off[l], t.rank, tab, tab + kTnMaxBits, tab + 2 * kTnMaxBits,
+                           (int)t.sliced_pos.size(), s0);
+      } else {
+        hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(n)), dim3(256), 0, stream, R.eptr(l), n, (int)R.g,
+                           grad + p->leaf_off[l], n, 1);
+      }
+    }
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+// host tables of a circuit network's leaves
+static tq_status leaf_table(tq_ctx* ctx, const tq_tn_plan* p, const tq_gate* gates, int32_t n_gates,
+                            const tq_tn_leaf* lv, int32_t n_const, std::vector<DevLeaf>& out) {
+  (void)ctx;
+  out.resize(p->n_leaves);
+  for (int l = 0; l < p->n_leaves; ++l) {
+    const tq_tn_leaf& x = lv[l];
+    const int rank = (int)p->t[l].inds.size() + (int)p->t[l].sliced_pos.size();
+    DevLeaf d{x.kind, x.gate, x.conj, x.const_off, p->leaf_off[l]};
+    static const int want_rank[5] = {-1, 2, 1, 2, 4};
+    if (x.kind < 0 || x.kind > 4) return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": unknown kind");
+    if (x.kind == 0) {
+      if (x.const_off < 0 || x.const_off + (1 << rank) > n_const)
+        return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": constant values out of range");
+      d.gate = 1 << rank;  // entry count for constants
+    } else {
+      if (x.gate < 0 || x.gate >= n_gates) return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": bad gate index");
+      if (rank != want_rank[x.kind]) return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": rank does not fit kind");
+    }
+    out[l] = d;
+  }
+  return TQ_OK;
+}
+
+}  // namespace tq
+
+extern "C" {
+
+tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, void* d_out, void* d_work,
+                         int64_t work_bytes, void* stream) {
+  if (!ctx || !plan || !d_leaves || !d_out || !d_work) return fail(TQ_EINVAL, "null argument");
+  if (plan->dtype == TQ_C64)
+    return tn_contract_t<float>(ctx, plan, d_leaves, d_out, d_work, work_bytes, (hipStream_t)stream);
+  return tn_contract_t<double>(ctx, plan, d_leaves, d_out, d_work, work_bytes, (hipStream_t)stream);
+}
+
+tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, const void* d_grad_out,
+                         void* d_grad_leaves, void* d_work, int64_t work_bytes, void* stream) {
+  if (!ctx || !plan || !d_leaves || !d_grad_out || !d_grad_leaves || !d_work) return fail(TQ_EINVAL, "null argument");
+  if (plan->dtype == TQ_C64)
+    return tn_backward_t<float>(ctx, plan, d_leaves, d_grad_out, d_grad_leaves, d_work, work_bytes,
+                                (hipStream_t)stream);
+  return tn_backward_t<double>(ctx, plan, d_leaves, d_grad_out, d_grad_leaves, d_work, work_bytes,
+                               (hipStream_t)stream);
+}
+
+tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                             const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const, const void* d_params,
+                             void* d_leaves, void* stream) {
+  if (!ctx || !plan || !leaves || !d_leaves) return fail(TQ_EINVAL, "null argument");
+  if (n_gates > 0 && (!gates || !d_params)) return fail(TQ_EINVAL, "null gates or params");
+  if (n_const > 0 && !const_vals) return fail(TQ_EINVAL, "null constant values");
+  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, 0x7fffffff));
+  std::vector<DevLeaf> dl;
+  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, n_const, dl));
+  void *dlv, *dg, *dc;
+  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
+  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
+  TQ_TRY(cached_table(ctx, const_vals, (size_t)n_const * 2 * sizeof(double), &dc));
+  const int nl = plan->n_leaves;
+  if (plan->dtype == TQ_C64)
+    hipLaunchKernelGGL(tn_leaf_build_kernel<float>, dim3((nl + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+                       (const DevLeaf*)dlv, nl, (const tq_gate*)dg, (const double*)dc, (const float*)d_params,
+                       (float2*)d_leaves);
+  else
+    hipLaunchKernelGGL(tn_leaf_build_kernel<double>, dim3((nl + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+                       (const DevLeaf*)dlv, nl, (const tq_gate*)dg, (const double*)dc, (const double*)d_params,
+                       (double2*)d_leaves);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                           const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
+                           const void* d_grad_leaves, void* d_grad_params, void* stream) {
+  if (!ctx || !plan || !leaves || !d_grad_leaves || !d_grad_params) return fail(TQ_EINVAL, "null argument");
+  if (n_params < 0) return fail(TQ_EINVAL, "negative n_params");
+  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, n_params));
+  std::vector<DevLeaf> dl;
+  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, 1 << 30, dl));
+  // parameter -> (leaf, angle) entries, in leaf order
+  std::vector<std::vector<std::pair<int, int>>> by(n_params);
+  for (int l = 0; l < plan->n_leaves; ++l) {
+    if (leaves[l].kind == 0) continue;
+    const tq_gate& g = gates[leaves[l].gate];
+    for (int j = 0; j < gate_n_angles(g.op); ++j)
+      if (g.pidx[j] >= 0) by[g.pidx[j]].push_back({l, j});
+  }
+  std::vector<int32_t> ptr(1, 0), ent;
+  for (int q = 0; q < n_params; ++q) {
+    for (auto& e : by[q]) {
+      ent.push_back(e.first);
+      ent.push_back(e.second);
+    }
+    ptr.push_back((int32_t)(ent.size() / 2));
+  }
+  void *dlv, *dg, *dp, *de;
+  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
+  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
+  TQ_TRY(cached_table(ctx, ptr.data(), ptr.size() * sizeof(int32_t), &dp));
+  TQ_TRY(cached_table(ctx, ent.data(), std::max<size_t>(ent.size(), 1) * sizeof(int32_t), &de));
+  if (n_params == 0) return TQ_OK;
+  if (plan->dtype == TQ_C64)
+    hipLaunchKernelGGL(tn_param_grad_kernel<float>, dim3((n_params + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+                       (const DevLeaf*)dlv, (const tq_gate*)dg, (const float*)d_params, (const int32_t*)dp,
+                       (const int32_t*)de, (const float2*)d_grad_leaves, n_params, (float*)d_grad_params);
+  else
+    hipLaunchKernelGGL(tn_param_grad_kernel<double>, dim3((n_params + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+                       (const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)d_params, (const int32_t*)dp,
+                       (const int32_t*)de, (const double2*)d_grad_leaves, n_params, (double*)d_grad_params);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+}  // extern "C"

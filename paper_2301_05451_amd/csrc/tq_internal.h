@@ -169,4 +169,6 @@ namespace tq {
 // scratch slots
 enum { S_MATS = 0, S_PARTIAL = 1, S_OFFS = 2, S_LAMBDA = 3, S_PSI = 4, S_GRADP = 5, S_TERMS = 6, S_MISC = 7 };
 tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out);
+// Immutable device copy of a small host table, cached by content (no per-call upload).
+tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev);
 }  // namespace tq

@@ -260,3 +260,138 @@ def zero_states(spec: BatchSpec, dtype, device="cuda"):
     import torch
     st = torch.empty(spec.total_amps, dtype=dtype, device=device)
     return init_states(st, spec, 0)
+
+
+# ---- tensor-network mode -------------------------------------------------------------------
+class TnDesc(ct.Structure):
+    _fields_ = [("n_leaves", ct.c_int32), ("leaf_rank", ct.c_void_p), ("leaf_inds", ct.c_void_p),
+                ("pairs", ct.c_void_p), ("n_sliced", ct.c_int32), ("sliced", ct.c_void_p), ("n_out", ct.c_int32),
+                ("out_inds", ct.c_void_p), ("dtype", ct.c_int32), ("slice_group", ct.c_int64),
+                ("mem_budget", ct.c_int64)]
+
+
+TN_LEAF_DTYPE = np.dtype([("kind", "<i4"), ("gate", "<i4"), ("conj", "<i4"), ("const_off", "<i4")])
+
+_lib.tq_tn_plan_create.argtypes = [_vp, ct.POINTER(TnDesc), ct.POINTER(_vp)]
+_lib.tq_tn_plan_create.restype = ct.c_int
+_lib.tq_tn_plan_destroy.argtypes = [_vp]
+_lib.tq_tn_plan_destroy.restype = None
+_lib.tq_tn_leaf_elems.argtypes = [_vp]
+_lib.tq_tn_leaf_elems.restype = ct.c_int64
+_lib.tq_tn_leaf_offset.argtypes = [_vp, _i32]
+_lib.tq_tn_leaf_offset.restype = ct.c_int64
+_lib.tq_tn_workspace.argtypes = [_vp, _i32]
+_lib.tq_tn_workspace.restype = ct.c_int64
+_lib.tq_tn_plan_info.argtypes = [_vp, ct.POINTER(ct.c_int64)]
+_lib.tq_tn_plan_info.restype = ct.c_int
+_lib.tq_tn_contract.argtypes = [_vp, _vp, _vp, _vp, _vp, ct.c_int64, _vp]
+_lib.tq_tn_contract.restype = ct.c_int
+_lib.tq_tn_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ct.c_int64, _vp]
+_lib.tq_tn_backward.restype = ct.c_int
+_lib.tq_tn_build_leaves.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]
+_lib.tq_tn_build_leaves.restype = ct.c_int
+_lib.tq_tn_param_grad.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]
+_lib.tq_tn_param_grad.restype = ct.c_int
+
+TN_INFO_FIELDS = ("steps", "direct_steps", "gemm_steps", "slices", "slice_group", "flops", "gemm_flops",
+                  "max_elems")
+
+
+class TnPlan:
+    """Owns a tq_tn_plan built from leaf index lists, an SSA tree and sliced indices."""
+
+    def __init__(self, leaf_inds, pairs, sliced=(), out_inds=(), c128=False, slice_group=0, mem_budget=0,
+                 ctx=None):
+        self.ctx = ctx or context()
+        self.c128 = bool(c128)
+        ranks = np.array([len(x) for x in leaf_inds], dtype=np.int32)
+        flat = np.array([i for x in leaf_inds for i in x] or [0], dtype=np.int32)
+        pr = np.array([v for p in pairs for v in p] or [0], dtype=np.int32)
+        sl = np.array(list(sliced) or [0], dtype=np.int32)
+        oi = np.array(list(out_inds) or [0], dtype=np.int32)
+        self._keep = (ranks, flat, pr, sl, oi)
+        d = TnDesc(len(leaf_inds), ranks.ctypes.data, flat.ctypes.data, pr.ctypes.data, len(sliced), sl.ctypes.data,
+                   len(out_inds), oi.ctypes.data, TQ_C128 if c128 else TQ_C64, int(slice_group), int(mem_budget))
+        h = _vp()
+        check(_lib.tq_tn_plan_create(self.ctx.h, ct.byref(d), ct.byref(h)))
+        self.h = h
+        self.n_leaves = len(leaf_inds)
+        self.leaf_elems = int(_lib.tq_tn_leaf_elems(h))
+        self.leaf_offsets = [int(_lib.tq_tn_leaf_offset(h, i)) for i in range(self.n_leaves)]
+        self.n_out = len(out_inds)
+        out = (ct.c_int64 * 8)()
+        check(_lib.tq_tn_plan_info(h, out))
+        self.info = dict(zip(TN_INFO_FIELDS, [int(v) for v in out]))
+
+    def workspace_bytes(self, backward=False):
+        return int(_lib.tq_tn_workspace(self.h, 1 if backward else 0))
+
+    def __del__(self):
+        try:
+            if self.h:
+                _lib.tq_tn_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _ws(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=device)
+
+
+def tn_contract(plan: TnPlan, leaves, work=None):
+    """Value of the network (2^n_out complex) from the packed leaf buffer (tq_tn_contract)."""
+    import torch
+    cdt = torch.complex128 if plan.c128 else torch.complex64
+    if leaves.dtype != cdt or not leaves.is_cuda or leaves.numel() < plan.leaf_elems:
+        raise ValueError("leaves must be a CUDA tensor of the plan's dtype covering the packed leaf buffer")
+    leaves = leaves.contiguous()
+    out = torch.empty(1 << plan.n_out, dtype=cdt, device=leaves.device)
+    need = plan.workspace_bytes(False)
+    work = work if work is not None and work.numel() >= need else _ws(need, leaves.device)
+    check(_lib.tq_tn_contract(plan.ctx.h, plan.h, leaves.data_ptr(), out.data_ptr(), work.data_ptr(), need,
+                              _stream()))
+    return out
+
+
+def tn_backward(plan: TnPlan, leaves, grad_out, work=None):
+    """Leaf environments scaled by grad_out, packed like the leaves (tq_tn_backward)."""
+    import torch
+    cdt = torch.complex128 if plan.c128 else torch.complex64
+    leaves = leaves.contiguous()
+    g = grad_out.to(device=leaves.device, dtype=cdt).contiguous()
+    if g.numel() < (1 << plan.n_out):
+        raise ValueError("grad_out too small")
+    grad = torch.empty(plan.leaf_elems, dtype=cdt, device=leaves.device)
+    need = plan.workspace_bytes(True)
+    work = work if work is not None and work.numel() >= need else _ws(need, leaves.device)
+    check(_lib.tq_tn_backward(plan.ctx.h, plan.h, leaves.data_ptr(), g.data_ptr(), grad.data_ptr(), work.data_ptr(),
+                              need, _stream()))
+    return grad
+
+
+def tn_build_leaves(plan: TnPlan, gates, leaf_specs, const_vals, params):
+    """Packed leaf buffer of a circuit network from its parameters (tq_tn_build_leaves)."""
+    import torch
+    cdt = torch.complex128 if plan.c128 else torch.complex64
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    ls = np.ascontiguousarray(leaf_specs, dtype=TN_LEAF_DTYPE)
+    cv = np.ascontiguousarray(np.asarray(const_vals, dtype=np.complex128).view(np.float64))
+    out = torch.empty(plan.leaf_elems, dtype=cdt, device=params.device)
+    check(_lib.tq_tn_build_leaves(plan.ctx.h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
+                                  cv.ctypes.data, int(cv.shape[0] // 2), params.data_ptr(), out.data_ptr(),
+                                  _stream()))
+    return out
+
+
+def tn_param_grad(plan: TnPlan, gates, leaf_specs, params, grad_leaves):
+    """Re sum over leaves of env * dLeaf/dparam for every parameter (tq_tn_param_grad)."""
+    import torch
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    ls = np.ascontiguousarray(leaf_specs, dtype=TN_LEAF_DTYPE)
+    out = torch.empty(params.numel(), dtype=params.dtype, device=params.device)
+    check(_lib.tq_tn_param_grad(plan.ctx.h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
+                                params.data_ptr(), int(params.numel()), grad_leaves.contiguous().data_ptr(),
+                                out.data_ptr(), _stream()))
+    return out

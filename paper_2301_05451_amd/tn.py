@@ -1,0 +1,447 @@
+"""Host planner of the tensor-network mode (paper Sec. 3.2).
+
+Steps (a)-(d) of the paper's TN workflow run here, once per circuit structure; step (e),
+the contraction, runs in libtq kernels (tq_tn_contract / tq_tn_backward):
+
+(a) circuit -> network: the expectation value <psi|O|psi> needs the circuit followed by
+    its complex-conjugate copy (Sec. 3.2.1). Gates outside the reverse light cone of the
+    measured qubits cancel against their conjugates and are dropped.
+(b) structural simplification, diagonal part: a diagonal gate (RZ, Z, CZ, RZZ) does not
+    start a new index on its qubits; it becomes a tensor on the existing wire indices, so
+    a wire index may join many tensors (a hyperedge, Sec. 3.2.1 and its figure).
+(c) contraction trees: greedy and random-greedy pairwise orders (the default pathfinders
+    listed in Sec. 3.2.2), scored by the paper's FLOP count p(2q-1) per pairwise step.
+(d) slicing (Sec. 3.2.3): greedily fix indices until every intermediate fits the target
+    size; the value is the sum of the identical sub-network contractions.
+
+Every index has dimension 2. A tensor with index list [i_0, .., i_{r-1}] is stored as 2^r
+complex numbers with i_0 the most significant bit.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List
+
+import numpy as np
+
+from . import workloads as W
+
+# leaf kinds: how the device builds a leaf from the circuit parameters (tq_tn_leaves)
+LEAF_CONST = 0   # constant tensor given by value
+LEAF_GATE1 = 1   # one-qubit gate matrix [out, in] (conj on the bra side)
+LEAF_DIAG1 = 2   # one-qubit diagonal gate as a vector over the wire index
+LEAF_DIAG2 = 3   # two-qubit diagonal gate as a 2x2 over the two wire indices
+LEAF_GATE2 = 4   # two-qubit gate [out_a, out_b, in_a, in_b]
+
+
+@dataclasses.dataclass
+class Leaf:
+    inds: List[int]
+    kind: int
+    gate: int = -1         # index into the circuit's gate list
+    conj: bool = False     # bra-side copy
+    value: np.ndarray = None  # LEAF_CONST data (complex128, 2^rank)
+
+
+@dataclasses.dataclass
+class Network:
+    leaves: List[Leaf]
+    n_index: int
+    output: List[int]
+    gates: np.ndarray      # the circuit's gate records (the leaves refer to them)
+    params: np.ndarray     # parameter vector
+
+
+def light_cone(gates, qubits):
+    """Indices of the gates in the reverse causal cone of ``qubits`` (program order)."""
+    cone = set(qubits)
+    keep = []
+    for k in range(len(gates) - 1, -1, -1):
+        g = gates[k]
+        qs = [int(q) for q in g["q"][: W.N_QUBITS[int(g["op"])]]]
+        if cone & set(qs):
+            keep.append(k)
+            cone |= set(qs)
+    return keep[::-1], cone
+
+
+_DIAG = {W.Z, W.RZ, W.CZ, W.RZZ}
+
+
+def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
+    """Doubled network of <psi| prod Z |psi> for psi = U|0..0>, with diagonal gates as
+    hyperedge tensors. Returns a Network whose leaves reference c.gates."""
+    gates = c.gates
+    if use_light_cone:
+        keep, used = light_cone(gates, zqubits)
+    else:
+        keep, used = list(range(len(gates))), set(range(c.n))
+    used = sorted(set(used) | set(zqubits))
+    nidx = [0]
+
+    def new():
+        nidx[0] += 1
+        return nidx[0] - 1
+
+    leaves = []
+    ket = {q: new() for q in used}
+    bra = {q: new() for q in used}
+    e0 = np.array([1.0, 0.0], dtype=np.complex128)
+    for q in used:
+        leaves.append(Leaf([ket[q]], LEAF_CONST, value=e0))
+        leaves.append(Leaf([bra[q]], LEAF_CONST, value=e0))
+    for k in keep:
+        g = gates[k]
+        op = int(g["op"])
+        qs = [int(q) for q in g["q"][: W.N_QUBITS[op]]]
+        if op in _DIAG:
+            kind = LEAF_DIAG1 if len(qs) == 1 else LEAF_DIAG2
+            leaves.append(Leaf([ket[q] for q in qs], kind, k, False))
+            leaves.append(Leaf([bra[q] for q in qs], kind, k, True))
+            continue
+        kout = [new() for _ in qs]
+        bout = [new() for _ in qs]
+        kind = LEAF_GATE1 if len(qs) == 1 else LEAF_GATE2
+        leaves.append(Leaf(kout + [ket[q] for q in qs], kind, k, False))
+        leaves.append(Leaf(bout + [bra[q] for q in qs], kind, k, True))
+        for i, q in enumerate(qs):
+            ket[q] = kout[i]
+            bra[q] = bout[i]
+    # observable: identity merges the ket and bra wire; Z adds a [1, -1] vector on it
+    merged = {}
+    for q in used:
+        merged[bra[q]] = ket[q]
+    for lf in leaves:
+        lf.inds = [merged.get(i, i) for i in lf.inds]
+    zv = np.array([1.0, -1.0], dtype=np.complex128)
+    for q in zqubits:
+        leaves.append(Leaf([ket[q]], LEAF_CONST, value=zv))
+    # renumber indices densely
+    ren = {}
+    for lf in leaves:
+        for i in lf.inds:
+            if i not in ren:
+                ren[i] = len(ren)
+    for lf in leaves:
+        lf.inds = [ren[i] for i in lf.inds]
+    return Network(leaves, len(ren), [], gates, c.params)
+
+
+def qaoa_edge_network(prob: W.QAOAProblem, edge):
+    """<Z_i Z_j> network of one edge: the light-cone circuit, then the doubled network."""
+    cone = W.light_cone_nodes(prob, edge)
+    c = W.qaoa_circuit(prob, cone)
+    i, j = cone.index(edge[0]), cone.index(edge[1])
+    return circuit_network(c, [i, j], use_light_cone=True), cone
+
+
+# ---- contraction trees -----------------------------------------------------------------
+
+@dataclasses.dataclass
+class Tree:
+    """SSA pairwise order: step s contracts tensors pairs[s] = (a, b) (ids < n_leaves are
+    leaves, id n_leaves + s is the result of step s). The last step yields the output."""
+    pairs: List[tuple]
+    n_leaves: int
+    flops: float = 0.0         # paper's count: sum p(2q-1)
+    max_rank: int = 0
+    sliced: List[int] = dataclasses.field(default_factory=list)
+    step_ranks: List[tuple] = dataclasses.field(default_factory=list)
+
+
+def _index_counts(tensors):
+    cnt = {}
+    for t in tensors:
+        for i in t:
+            cnt[i] = cnt.get(i, 0) + 1
+    return cnt
+
+
+def _out_inds(a, b, cnt, output):
+    """Indices kept after contracting index sets a, b: those appearing in other tensors or
+    in the output (count over all live tensors, minus the two being merged)."""
+    sa, sb = set(a), set(b)
+    keep = []
+    for i in list(dict.fromkeys(list(a) + list(b))):
+        inside = (i in sa) + (i in sb)
+        if cnt[i] > inside or i in output:
+            keep.append(i)
+    return keep
+
+
+def greedy_tree(net: Network, rng=None, temperature=0.0, sliced=()):
+    """Greedy pairwise order: repeatedly contract the connected pair with the smallest
+    cost = size(out) - size(a) - size(b) (random-greedy: Boltzmann-perturbed choice)."""
+    sl = set(sliced)
+    tensors = {i: tuple(x for x in lf.inds if x not in sl) for i, lf in enumerate(net.leaves)}
+    cnt = _index_counts(tensors.values())
+    output = set(net.output)
+    nid = len(net.leaves)
+    # index -> live tensor ids
+    holders = {}
+    for tid, t in tensors.items():
+        for i in t:
+            holders.setdefault(i, set()).add(tid)
+    pairs = []
+
+    def cost(a, b):
+        o = _out_inds(tensors[a], tensors[b], cnt, output)
+        return 2.0 ** len(o) - 2.0 ** len(tensors[a]) - 2.0 ** len(tensors[b]), o
+
+    while len(tensors) > 1:
+        cands = set()
+        for i, hs in holders.items():
+            if len(hs) >= 2:
+                hl = sorted(hs)
+                for x in range(len(hl)):
+                    for y in range(x + 1, len(hl)):
+                        cands.add((hl[x], hl[y]))
+        if not cands:  # disconnected: join the two smallest
+            ids = sorted(tensors, key=lambda t: len(tensors[t]))[:2]
+            cands = {(min(ids), max(ids))}
+        scored = []
+        for a, b in cands:
+            c, o = cost(a, b)
+            scored.append((c, a, b, o))
+        if rng is not None and temperature > 0:
+            cs = np.array([s[0] for s in scored])
+            w = np.exp(-(cs - cs.min()) / (temperature * max(1.0, abs(cs.min())) + 1e-12))
+            k = int(rng.choice(len(scored), p=w / w.sum()))
+            _, a, b, o = scored[k]
+        else:
+            _, a, b, o = min(scored)
+        pairs.append((a, b))
+        for i in tensors[a]:
+            cnt[i] -= 1
+            holders[i].discard(a)
+        for i in tensors[b]:
+            cnt[i] -= 1
+            holders[i].discard(b)
+        del tensors[a], tensors[b]
+        tensors[nid] = tuple(o)
+        for i in o:
+            cnt[i] = cnt.get(i, 0) + 1
+            holders.setdefault(i, set()).add(nid)
+        nid += 1
+    tree = Tree(pairs, len(net.leaves))
+    score_tree(net, tree)
+    return tree
+
+
+def tree_steps(net: Network, tree: Tree, sliced=None):
+    """Index lists of every step: list of (a_inds, b_inds, out_inds)."""
+    sl = set(tree.sliced if sliced is None else sliced)
+    ts = [tuple(x for x in lf.inds if x not in sl) for lf in net.leaves]
+    cnt = _index_counts(ts)
+    output = set(net.output)
+    steps = []
+    for a, b in tree.pairs:
+        o = _out_inds(ts[a], ts[b], cnt, output)
+        for i in ts[a]:
+            cnt[i] -= 1
+        for i in ts[b]:
+            cnt[i] -= 1
+        for i in o:
+            cnt[i] = cnt.get(i, 0) + 1
+        steps.append((ts[a], ts[b], tuple(o)))
+        ts.append(tuple(o))
+    return steps
+
+
+def step_flops(a, b, o):
+    """Paper Sec. 3.2.2: FLOPs = p(2q - 1), p = product of outer dims, q = contracted."""
+    sa, sb, so = set(a), set(b), set(o)
+    q = 2 ** len((sa & sb) - so)
+    p = 2 ** len(so)
+    return p * (2 * q - 1)
+
+
+def score_tree(net: Network, tree: Tree):
+    steps = tree_steps(net, tree)
+    tree.flops = float(sum(step_flops(*s) for s in steps)) * 2 ** len(tree.sliced)
+    tree.max_rank = max([len(s[2]) for s in steps] + [len(s[0]) for s in steps] + [len(s[1]) for s in steps] + [0])
+    tree.step_ranks = [(len(a), len(b), len(o)) for a, b, o in steps]
+    return tree
+
+
+def slice_tree(net: Network, tree: Tree, target_rank, rng=None):
+    """Greedy slicing (Sec. 3.2.3): while some intermediate has more than target_rank
+    indices, fix the index that appears in the most over-size intermediates (ties: the
+    one that lowers the largest rank most, then the lowest id; random repeats pick among
+    ties with ``rng``)."""
+    sliced = list(tree.sliced)
+    while True:
+        steps = tree_steps(net, tree, sliced)
+        big = [s[2] for s in steps if len(s[2]) > target_rank] + [s[0] for s in steps if len(s[0]) > target_rank]
+        if not big:
+            break
+        freq = {}
+        for t in big:
+            for i in t:
+                freq[i] = freq.get(i, 0) + 1
+        best = max(freq.values())
+        ties = sorted(i for i, f in freq.items() if f == best)
+        pick = ties[0] if rng is None else int(rng.choice(ties))
+        sliced.append(pick)
+    t2 = Tree(list(tree.pairs), tree.n_leaves, sliced=sliced)
+    score_tree(net, t2)
+    return t2
+
+
+def elimination_order(net: Network, rng=None, mode="fill", sliced=()):
+    """Index elimination order on the interaction graph (vertices = indices, every tensor
+    a clique): repeatedly remove the index with the fewest fill-in edges (``fill``) or the
+    smallest degree (``degree``); ``rng`` breaks near-ties at random. Returns (order,
+    width) where width = largest neighbourhood met (rank of the biggest intermediate)."""
+    sl = set(sliced)
+    adj = {}
+    for lf in net.leaves:
+        t = set(lf.inds) - sl
+        for i in t:
+            adj.setdefault(i, set()).update(t - {i})
+    for i in net.output:
+        adj.pop(i, None)
+        for x in adj.values():
+            x.discard(i)
+    order, width = [], 0
+    while adj:
+        cand = []
+        for i, nb in adj.items():
+            if mode == "fill":
+                nbl = list(nb)
+                f = sum(1 for x in range(len(nbl)) for y in range(x + 1, len(nbl)) if nbl[y] not in adj[nbl[x]])
+                cand.append(((f, len(nb)), i))
+            else:
+                cand.append(((len(nb), 0), i))
+        cand.sort()
+        if rng is not None:
+            k0 = cand[0][0][0]
+            ties = [c for c in cand[:6] if c[0][0] <= k0 + (1 if mode == "degree" else max(1, k0 // 4))]
+            _, i = ties[int(rng.integers(len(ties)))]
+        else:
+            _, i = cand[0]
+        nb = adj.pop(i)
+        width = max(width, len(nb))
+        for x in nb:
+            adj[x] |= nb - {x}
+            adj[x].discard(i)
+        order.append(i)
+    return order, width
+
+
+def elimination_tree(net: Network, order):
+    """Pairwise tree from an elimination order: for each index in turn, the live tensors
+    holding it are merged (smallest first); the index is summed at the last merge."""
+    live = {i: tuple(lf.inds) for i, lf in enumerate(net.leaves)}
+    nid = len(net.leaves)
+    pairs = []
+    for idx in order:
+        hold = sorted([t for t, inds in live.items() if idx in inds], key=lambda t: (len(live[t]), t))
+        while len(hold) > 1:
+            a, b = hold[0], hold[1]
+            merged = tuple(dict.fromkeys(live[a] + live[b]))
+            pairs.append((a, b))
+            del live[a], live[b]
+            live[nid] = merged
+            hold = sorted([nid] + hold[2:], key=lambda t: (len(live[t]), t))
+            nid += 1
+    rest = sorted(live, key=lambda t: (len(live[t]), t))
+    while len(rest) > 1:  # disconnected parts (scalars): outer products
+        a, b = rest[0], rest[1]
+        pairs.append((a, b))
+        live[nid] = tuple(dict.fromkeys(live[a] + live[b]))
+        del live[a], live[b]
+        rest = sorted([nid] + rest[2:], key=lambda t: (len(live[t]), t))
+        nid += 1
+    tree = Tree(pairs, len(net.leaves))
+    score_tree(net, tree)
+    return tree
+
+
+def candidate_trees(net: Network, n_random=31, seed=0, target_rank=28):
+    """Candidate contraction trees for ranking (flop model or learned cost model): the
+    min-fill and min-degree elimination trees, the pairwise greedy tree, then random
+    restarts of all three heuristics; each sliced to ``target_rank``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for mode in ("fill", "degree"):
+        out.append(slice_tree(net, elimination_tree(net, elimination_order(net, None, mode)[0]), target_rank))
+    out.append(slice_tree(net, greedy_tree(net), target_rank))
+    for r in range(n_random):
+        kind = r % 3
+        if kind == 2:
+            t = greedy_tree(net, rng, temperature=0.3 + 0.7 * rng.random())
+        else:
+            t = elimination_tree(net, elimination_order(net, rng, "fill" if kind == 0 else "degree")[0])
+        out.append(slice_tree(net, t, target_rank, rng))
+    return out
+
+
+# ---- device execution (steps (e) and its reverse) -------------------------------------------
+
+def leaf_specs(net: Network):
+    """tq_tn_leaf records and the constant values of a circuit network."""
+    from . import lib
+
+    specs = np.zeros(len(net.leaves), dtype=lib.TN_LEAF_DTYPE)
+    consts = []
+    for i, lf in enumerate(net.leaves):
+        specs[i]["kind"] = lf.kind
+        specs[i]["gate"] = lf.gate
+        specs[i]["conj"] = 1 if lf.conj else 0
+        if lf.kind == LEAF_CONST:
+            specs[i]["const_off"] = sum(len(c) for c in consts)
+            consts.append(np.asarray(lf.value, dtype=np.complex128).reshape(-1))
+    cv = np.concatenate(consts) if consts else np.zeros(1, dtype=np.complex128)
+    return specs, cv
+
+
+class TNProgram:
+    """A planned circuit network: builds leaves from parameters, contracts, differentiates."""
+
+    def __init__(self, net: Network, tree: Tree, c128=False, slice_group=0, mem_budget=0):
+        from . import lib
+
+        self.net, self.tree = net, tree
+        self.plan = lib.TnPlan([lf.inds for lf in net.leaves], tree.pairs, tree.sliced, net.output, c128,
+                               slice_group, mem_budget)
+        self.specs, self.consts = leaf_specs(net)
+        self.c128 = c128
+
+    def leaves(self, params):
+        from . import lib
+        return lib.tn_build_leaves(self.plan, self.net.gates, self.specs, self.consts, params)
+
+    def value(self, params):
+        from . import lib
+        return lib.tn_contract(self.plan, self.leaves(params))
+
+    def grad(self, params, grad_out=None):
+        """d Re(T) / d params (times grad_out) through the reverse pass and the chain rule."""
+        import torch
+        from . import lib
+
+        L = self.leaves(params)
+        g = torch.ones(1 << self.plan.n_out, dtype=L.dtype, device=L.device) if grad_out is None else grad_out
+        env = lib.tn_backward(self.plan, L, g)
+        return lib.tn_param_grad(self.plan, self.net.gates, self.specs, params, env)
+
+
+def tn_expval(program: TNProgram, params):
+    """Differentiable Re(T) of a scalar network (torch.autograd.Function)."""
+    import torch
+
+    class _F(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, p):
+            ctx.save_for_backward(p)
+            return program.value(p).real.to(p.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            (p,) = ctx.saved_tensors
+            cdt = torch.complex128 if program.c128 else torch.complex64
+            return program.grad(p, g.to(cdt)).to(p.dtype)
+
+    return _F.apply(params)

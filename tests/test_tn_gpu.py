@@ -1,0 +1,151 @@
+"""GPU parity of the tensor-network path (tq_tn_build_leaves, tq_tn_contract,
+tq_tn_backward, tq_tn_param_grad) against the oracle: the paper's worked example, random
+circuits vs state-vector values and parameter-shift gradients, QAOA light cones (sliced
+and unsliced, several slice groups), and a dense step on the FP32-MFMA GEMM path vs einsum."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sv as osv
+from oracle import tn as otn
+from paper_2301_05451_amd import tn
+from paper_2301_05451_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _params(net, c128):
+    return torch.tensor(net.params, dtype=torch.float64 if c128 else torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.7, 2.9])
+def test_worked_example_tn_gpu(theta):
+    g = W.GateList().const(W.X, [0]).const(W.RY, [1], [theta]).add(W.CNOT, [0, 1])
+    c = W.Circuit(2, g.array(), np.zeros(1))
+    net = tn.circuit_network(c, [1])
+    prog = tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]), c128=True)
+    v = prog.value(_params(net, True)).cpu().numpy()[0]
+    assert abs(v.real - (math.sin(theta / 2) ** 2 - math.cos(theta / 2) ** 2)) < 1e-14 and abs(v.imag) < 1e-14
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_random_circuits_value_and_grad(c128):
+    tol = 1e-12 if c128 else 1e-5
+    rng = np.random.default_rng(60)
+    for n in (3, 5, 7):
+        c = W.random_circuit(n, 30, rng, n_params=10)
+        zq = [0, n - 1]
+        net = tn.circuit_network(c, zq)
+        print(f"tn random n={n} c128={c128}", flush=True)
+        prog = tn.TNProgram(net, tn.greedy_tree(net), c128=c128)
+        p = _params(net, c128)
+        v = prog.value(p).cpu().numpy()[0]
+        psi = osv.run(n, c.gates, c.params)
+        want = float(np.dot(np.abs(psi) ** 2, osv.zstring_diag(n, zq)))
+        assert abs(v.real - want) <= tol and abs(v.imag) <= tol
+        g = prog.grad(p).cpu().numpy()
+        c.terms, c.n_obs = W.zterms([(zq, 1.0, 0)]), 1
+        assert np.abs(g - osv.param_shift_grad(c)).max() <= 2 * tol
+
+
+def _qaoa10():
+    r = np.random.default_rng(11)
+    edges = W.random_regular_graph(3, 10, r)
+    return W.QAOAProblem(10, edges, 2, W.f32_angles(r, 2, 0, math.pi), W.f32_angles(r, 2, 0, math.pi))
+
+
+def test_qaoa_sliced_unsliced_groups_and_grad():
+    prob = _qaoa10()
+    for e in prob.edges[:3]:
+        net, cone = tn.qaoa_edge_network(prob, e)
+        t0 = tn.elimination_tree(net, tn.elimination_order(net)[0])
+        ts = tn.slice_tree(net, t0, max(2, t0.max_rank - 3))
+        want = otn.qaoa_edge_zz_sv(prob, e)
+        c = W.qaoa_circuit(prob, cone)
+        i, j = cone.index(e[0]), cone.index(e[1])
+        c.terms, c.n_obs = W.zterms([([i, j], 1.0, 0)]), 1
+        gw = osv.param_shift_grad(c)
+        for tree, G in ((t0, 0), (ts, 0), (ts, 2), (ts, 1)):
+            print(f"qaoa {e} sliced={len(tree.sliced)} G={G}", flush=True)
+            prog = tn.TNProgram(net, tree, slice_group=G)
+            p = _params(net, False)
+            v = prog.value(p).cpu().numpy()[0]
+            assert abs(v.real - want) <= 1e-5 and abs(v.imag) <= 1e-5
+            assert np.abs(prog.grad(p).cpu().numpy() - gw).max() <= 1e-5
+
+
+def test_autograd_tn_expval():
+    prob = _qaoa10()
+    e = prob.edges[5]
+    net, cone = tn.qaoa_edge_network(prob, e)
+    prog = tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]))
+    p = _params(net, False).requires_grad_(True)
+    f = tn.tn_expval(prog, p)
+    (3.0 * f).backward()
+    c = W.qaoa_circuit(prob, cone)
+    i, j = cone.index(e[0]), cone.index(e[1])
+    c.terms, c.n_obs = W.zterms([([i, j], 1.0, 0)]), 1
+    assert abs(f.item() - otn.qaoa_edge_zz_sv(prob, e)) <= 1e-5
+    assert np.abs(p.grad.cpu().numpy() - 3.0 * osv.param_shift_grad(c)).max() <= 3e-5
+
+
+def test_qaoa50_p3_edges_vs_cone_state_vector():
+    """50-node 3-regular graph, p = 3: edges whose light cone has <= 20 qubits, against the
+    oracle's state-vector evolution of the cone."""
+    prob = W.qaoa_maxcut(p=3)
+    done = 0
+    for e in prob.edges:
+        cone = W.light_cone_nodes(prob, e)
+        if len(cone) > 20:
+            continue
+        net, _ = tn.qaoa_edge_network(prob, e)
+        prog = tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]))
+        v = prog.value(_params(net, False)).cpu().numpy()[0]
+        assert abs(v.real - otn.qaoa_edge_zz_sv(prob, e)) <= 1e-5, e
+        done += 1
+        if done == 4:
+            break
+    assert done >= 1
+
+
+def _gemm_network(rs, permuted):
+    b, m, k, nn = [0], list(range(1, 8)), list(range(8, 13)), list(range(13, 19))
+    A = (rs.normal(size=2 ** 13) + 1j * rs.normal(size=2 ** 13))
+    B = (rs.normal(size=2 ** 12) + 1j * rs.normal(size=2 ** 12))
+    Cc = (rs.normal(size=2 ** 14) + 1j * rs.normal(size=2 ** 14))
+    if permuted:
+        inds = [k[::-1] + m + b, nn + b + k, m[::-1] + nn + b]
+    else:
+        inds = [b + m + k, b + k + nn, b + m + nn]
+    return (A, B, Cc), inds
+
+
+@pytest.mark.parametrize("permuted", [False, True])
+def test_dense_step_on_mfma_gemm_path(permuted):
+    from paper_2301_05451_amd import lib
+
+    rs = np.random.default_rng(3)
+    (A, B, Cc), inds = _gemm_network(rs, permuted)
+    plan = lib.TnPlan(inds, [(0, 1), (2, 3)])
+    assert plan.info["gemm_steps"] == 1
+    leaves = torch.tensor(np.concatenate([A, B, Cc]), dtype=torch.complex64, device="cuda")
+    v = lib.tn_contract(plan, leaves).cpu().numpy()[0]
+    At, Bt, Ct = A.reshape((2,) * 13), B.reshape((2,) * 12), Cc.reshape((2,) * 14)
+    want = np.einsum(At, inds[0], Bt, inds[1], Ct, inds[2], [])
+    assert abs(v - want) / abs(want) <= 1e-5
+    env = lib.tn_backward(plan, leaves, torch.ones(1, device="cuda")).cpu().numpy()
+    envA = np.einsum(Bt, inds[1], Ct, inds[2], inds[0]).reshape(-1)
+    assert np.abs(env[: 2 ** 13] - envA).max() / np.abs(envA).max() <= 1e-5
+
+
+def test_plan_validation():
+    from paper_2301_05451_amd import lib
+
+    with pytest.raises(lib.TQError):
+        lib.TnPlan([[0, 1], [1, 0]], [(0, 0)])  # a tree step reusing an id
+    with pytest.raises(lib.TQError):
+        lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], sliced=[7])  # sliced index in no leaf
+    with pytest.raises(lib.TQError):
+        lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], out_inds=[5])  # no tensor carries index 5
