@@ -94,10 +94,10 @@ typedef struct {
 
 /* State-vector execution options (NULL = defaults: fused, autotuned shapes).
  *   mode:      0 = fused (gates grouped into LDS-tile stages, one HBM sweep per stage),
- *              1 = plain (one HBM sweep per gate), 2 = batched persistent work queue
- *              (one launch for a whole batch of circuits of uneven size).
- *   tile_bits: local qubits per fused tile (0 = autotune / default), 6..14.
- *   reg_bits:  amplitude-index bits held in registers per thread, 2..5 (0 = default).
+ *              1 = plain (one HBM sweep per gate). Batches of circuits of uneven size and
+ *              structure run best as a compiled batch (tq_svb_*, below).
+ *   tile_bits: local qubits per fused tile (0 = default: 13 for TQ_C64, 12 for TQ_C128), 1..14.
+ *   reg_bits:  amplitude-index bits held in registers per thread, 1..5 (0 = default 4).
  *   coal_bits: low index bits always kept local for coalesced HBM access (0 = default). */
 typedef struct {
   int32_t mode;
@@ -124,8 +124,9 @@ int tq_hip_runtime_version(void);
 /* Sec. 3.1: apply every circuit of the batch to its state in place (|psi> <- U |psi>).
  * The caller fills d_states beforehand (|0..0> or its own vector: the library does not
  * normalise it). d_params holds real angles-parameters of the dtype's precision.
- * Errors: TQ_EINVAL (bad op / qubit / duplicate qubit / pidx out of the circuit's
- * parameter range is NOT checked: the caller guarantees it), TQ_ENOTSUP (n < 1 or n > 34). */
+ * n_params[i] (may be NULL: then unchecked) bounds the parameter indices of circuit i.
+ * Errors: TQ_EINVAL (bad op / qubit / duplicate qubit / parameter index >= n_params[i]),
+ * TQ_ENOTSUP (n < 1 or n > 34). */
 tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
                       const int32_t* n_params, const void* d_params, void* d_states,
                       const tq_sv_opts* opts, void* stream);
@@ -164,6 +165,63 @@ tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const 
                          const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
                          const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
                          void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Compiled batches. The paper compiles a circuit once and evaluates it many times with new
+ * parameters (Sec. 2, reusable objects), and runs one circuit over a batch of inputs with
+ * vmap (Sec. 5.3). A tq_svb is that compiled form for a whole batch of circuits, which may
+ * differ in size and structure: every circuit's fused schedule, and work lists in which one
+ * kernel per stage level runs the tiles of all circuits that have that level (largest work
+ * items first), so small circuits share launches with large ones. Forward = |0..0> (or the
+ * caller's state) + gate application + expectation values; backward = the adjoint sweep of
+ * every circuit. With opts.graph = 1 each call's launch sequence is captured once per set of
+ * buffer pointers (on the second call with those pointers) and replayed as a HIP graph.
+ * Device buffers owned by the tq_svb (gate matrices, adjoint working states, partial sums)
+ * are allocated on first use and released by tq_svb_destroy.
+ * ------------------------------------------------------------------------------------- */
+typedef struct tq_svb tq_svb;
+
+/* Zero fields take defaults. tile/reg/coal bits as in tq_sv_opts, for the forward stages
+ * and (adj_*) for the reverse sweep (defaults 12/4 for TQ_C64, 11/3 for TQ_C128).
+ * init: 0 = forward starts every circuit from |0..0> (written by the library), 1 = from the
+ * caller's states. graph: 1 = capture and replay HIP graphs. */
+typedef struct {
+  int32_t tile_bits, reg_bits, coal_bits;
+  int32_t adj_tile_bits, adj_reg_bits, adj_coal_bits;
+  int32_t init;
+  int32_t graph;
+} tq_svb_opts;
+
+/* Host-side compile of a batch (gates, n_params and terms are copied; nothing is launched).
+ * Terms and n_obs are shared by all circuits. Errors as tq_sv_apply / tq_expval. */
+tq_status tq_svb_create(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                        const int32_t* n_params, const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
+                        const tq_svb_opts* opts, tq_svb** out);
+void tq_svb_destroy(tq_svb* b);
+
+/* d_states at the batch's state offsets are overwritten with the final states; d_out
+ * ([count][n_obs], may be NULL to skip) receives the expectation values as tq_expval. */
+tq_status tq_svb_forward(tq_ctx* ctx, tq_svb* b, const void* d_params, void* d_states, void* d_out,
+                         void* stream);
+
+/* Adjoint gradients as tq_sv_backward: d_states holds the final states (read only),
+ * d_grad_out is [count][n_obs], d_grad at the parameter offsets is overwritten. */
+tq_status tq_svb_backward(tq_ctx* ctx, tq_svb* b, const void* d_params, const void* d_states,
+                          const void* d_grad_out, void* d_grad, void* stream);
+
+/* Autotuner: times the forward (which = 0; overwrites d_states) or backward (which = 1;
+ * d_states read only, unit upstream gradients) pass for every candidate shape (tile bits,
+ * register bits) on the device, `reps` timed runs each after one warm-up, keeps the fastest
+ * in the tq_svb and in the context (later tq_svb_create calls for the same batch structure
+ * start from it), and reports it in *best (may be NULL) with its mean time in *best_ms.
+ * Synchronises the stream. */
+tq_status tq_svb_autotune(tq_ctx* ctx, tq_svb* b, const void* d_params, void* d_states, int32_t which,
+                          int32_t reps, void* stream, tq_svb_opts* best, double* best_ms);
+
+/* out[0] forward stage levels, [1] forward work items (tiles over all levels), [2] reverse
+ * levels, [3] reverse work items (0 before the first backward call), [4] graphs captured,
+ * [5] graph replays, [6] forward tile bits, [7] forward register bits. */
+tq_status tq_svb_info(const tq_svb* b, int64_t out[8]);
 
 /* ---------------------------------------------------------------------------------------
  * Tensor-network mode (Sec. 3.2). A closed or open network of leaf tensors whose indices all

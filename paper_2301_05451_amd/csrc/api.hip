@@ -138,7 +138,8 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
       return fail(TQ_EINVAL, "tile_bits " + std::to_string(t) + " does not fit LDS for this dtype");
     if (R < 1 || R > 5) return fail(TQ_EINVAL, "reg_bits must be in 1..5");
     if (dt == TQ_C128 && R > 4) return fail(TQ_EINVAL, "reg_bits must be <= 4 for complex128 (register file)");
-    if (t - std::min(R, t) > 10) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 10 (1024 threads)");
+    // the stage kernels are compiled for work-groups of at most 512 threads
+    if (t - std::min(R, t) > 9) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 9 (512 threads)");
     if (c < 0 || c > 10) return fail(TQ_EINVAL, "coal_bits must be in 0..10");
   } else {
     t = R = c = 0;
@@ -198,6 +199,12 @@ tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gate
   build_adjoint_slots(*s, g, n_gates);
   TQ_TRY(upload_schedule(*s, g, n_gates));
   TQ_TRY(to_device(s->dslot, &s->d_dslot));
+  std::vector<int32_t> slot_pairs;  // per stage: (first slot, slot count), read by batched launches
+  for (size_t k = 0; k < s->stage_slot0.size(); ++k) {
+    slot_pairs.push_back(s->stage_slot0[k]);
+    slot_pairs.push_back(s->stage_nslot[k]);
+  }
+  TQ_TRY(to_device(slot_pairs, &s->d_stage_slot0));
   TQ_TRY(to_device(s->pslot_ptr, &s->d_pslot_ptr));
   TQ_TRY(to_device(s->pslot_idx, &s->d_pslot_idx));
   TQ_TRY(to_device(s->pslot_scale, &s->d_pslot_scale));
@@ -208,7 +215,7 @@ tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gate
 
 // Observable terms in device form: [pos masks (u64)] [coeffs (f64)] [obs (i32)], masks over
 // bit positions of an n-qubit index.
-static tq_status term_table(tq_ctx* ctx, int n, const tq_zterm* terms, int n_terms, const unsigned char** dev) {
+tq_status term_table(tq_ctx* ctx, int n, const tq_zterm* terms, int n_terms, const unsigned char** dev) {
   std::vector<unsigned char> blob((size_t)n_terms * 20 + 64, 0);
   for (int k = 0; k < n_terms; ++k) {
     uint64_t m = 0;
@@ -223,15 +230,6 @@ static tq_status term_table(tq_ctx* ctx, int n, const tq_zterm* terms, int n_ter
   *dev = (const unsigned char*)d;
   return TQ_OK;
 }
-
-// Circuits of a batch grouped by structure (n, gate_off, n_gates), in first-seen order.
-struct Group {
-  int n;
-  int64_t gate_off;
-  int n_gates;
-  int n_params;
-  std::vector<int> members;
-};
 
 tq_status group_batch(const tq_batch* b, const int32_t* n_params, std::vector<Group>& groups) {
   if (!b) return fail(TQ_EINVAL, "null batch");
@@ -353,27 +351,17 @@ static tq_status expval_t(tq_ctx* ctx, const tq_batch* batch, const void* d_stat
     const unsigned char* db = (const unsigned char*)dterms;
     BatchMap smap, omap;
     TQ_TRY(member_map(ctx, S_MISC, batch->state_off, mem, stream, &smap));
-    // outputs: contiguous rows when the members are consecutive batch entries
-    bool consecutive = true;
-    for (size_t i = 1; i < mem.size(); ++i) consecutive = consecutive && mem[i] == mem[0] + (int)i;
+    // output rows: the members' batch indices (affine when consecutive)
+    std::vector<int64_t> rows(mem.begin(), mem.end());
+    std::vector<int> ident(mem.size());
+    for (size_t i = 0; i < mem.size(); ++i) ident[i] = (int)i;
+    TQ_TRY(member_map(ctx, S_MISC, rows.data(), ident, stream, &omap));
     const size_t pcap = expval_scratch_doubles(n, (int)mem.size(), n_obs);
     void* partial;
     TQ_TRY(scratch(ctx, S_PARTIAL, pcap * sizeof(double), &partial));
-    T* out = (T*)d_out;
-    if (consecutive) {
-      TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, smap, n, (int)mem.size(),
-                              (const uint64_t*)db, (const double*)(db + n_terms * 8),
-                              (const int32_t*)(db + n_terms * 16), n_terms, n_obs, (double*)partial, pcap,
-                              out + (int64_t)mem[0] * n_obs, stream));
-    } else {
-      for (int i : mem) {
-        BatchMap one{nullptr, batch->state_off[i], 0};
-        TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, one, n, 1, (const uint64_t*)db,
-                                (const double*)(db + n_terms * 8), (const int32_t*)(db + n_terms * 16), n_terms,
-                                n_obs, (double*)partial, pcap, out + (int64_t)i * n_obs, stream));
-      }
-    }
-    (void)omap;
+    TQ_TRY(launch_expval<T>((const typename Cx<T>::type*)d_states, smap, n, (int)mem.size(), (const uint64_t*)db,
+                            (const double*)(db + n_terms * 8), (const int32_t*)(db + n_terms * 16), n_terms, n_obs,
+                            (double*)partial, pcap, (T*)d_out, omap, stream));
   }
   return TQ_OK;
 }

@@ -52,42 +52,42 @@ __global__ void __launch_bounds__(kExpThreads)
   }
 }
 
-// One work-group per circuit: for every term, a fixed-order tree over the groups' partials,
-// then thread 0 accumulates coeff * S_k into its observable, in term order.
+// One work-group per circuit. Each wave sums the block partials of one term at a time
+// (lane-strided, then a butterfly: a fixed order), and thread 0 accumulates coeff * S_k into
+// its observable in term order. Circuit i of the launch writes output row rows.at(i).
 template <typename T, int KT>
 __global__ void __launch_bounds__(kExpThreads)
     expval_final_kernel(const double* __restrict__ partial, int nblocks, int nk, const double* __restrict__ coeff,
                         const int32_t* __restrict__ obs, int n_obs, double* __restrict__ outacc, int first,
-                        int last, T* __restrict__ out) {
-  __shared__ double red[kExpThreads];
+                        int last, T* __restrict__ out, BatchMap rows) {
+  __shared__ double sk[KT];
   const int circ = blockIdx.x;
-  double* acc = outacc + (int64_t)circ * n_obs;
-  if (first && threadIdx.x == 0)
-    for (int o = 0; o < n_obs; ++o) acc[o] = 0.0;
-  for (int k = 0; k < nk; ++k) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = wv; k < nk; k += kExpThreads / 64) {
     double x = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kExpThreads) x += partial[((int64_t)circ * nblocks + b) * KT + k];
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int w = kExpThreads / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) acc[obs[k]] += coeff[k] * red[0];
-    __syncthreads();
+    for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * nblocks + b) * KT + k];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) sk[k] = x;
   }
-  if (last && threadIdx.x == 0)
-    for (int o = 0; o < n_obs; ++o) out[(int64_t)circ * n_obs + o] = (T)acc[o];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* acc = outacc + (int64_t)circ * n_obs;
+    if (first)
+      for (int o = 0; o < n_obs; ++o) acc[o] = 0.0;
+    for (int k = 0; k < nk; ++k) acc[obs[k]] += coeff[k] * sk[k];
+    if (last)
+      for (int o = 0; o < n_obs; ++o) out[rows.at(circ) * n_obs + o] = (T)acc[o];
+  }
 }
 
 template <typename T, int KT>
 static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, int pb, int nblocks, int cn,
                          const uint64_t* pm, const double* cf, const int32_t* ob, int nk, int n_obs, double* partial,
-                         double* outacc, int first, int last, T* out, hipStream_t stream) {
+                         double* outacc, int first, int last, T* out, BatchMap rows, hipStream_t stream) {
   hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
                      d_states, smap, pb, pm, nk, partial, nblocks);
   hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3(cn), dim3(kExpThreads), 0, stream, partial, nblocks, nk, cf, ob,
-                     n_obs, outacc, first, last, out);
+                     n_obs, outacc, first, last, out, rows);
 }
 
 int expval_block_bits(int n) { return n < 13 ? n : 13; }
@@ -102,7 +102,7 @@ size_t expval_scratch_doubles(int n, int count, int n_obs) {
 template <typename T>
 tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,
                         const uint64_t* d_pmask, const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs,
-                        double* d_scratch, size_t scratch_doubles, T* d_out, hipStream_t stream) {
+                        double* d_scratch, size_t scratch_doubles, T* d_out, BatchMap rows, hipStream_t stream) {
   const int pb = expval_block_bits(n);
   const int64_t nblocks = int64_t(1) << (n - pb);
   if (expval_scratch_doubles(n, count, n_obs) > scratch_doubles) return fail(TQ_ENOMEM, "expval scratch too small");
@@ -110,20 +110,21 @@ tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int
     const int cn = std::min(65535, count - c0);
     double* partial = d_scratch;
     double* outacc = d_scratch + (size_t)cn * nblocks * 32;
-    T* out = d_out + (int64_t)c0 * n_obs;
+    T* out = d_out;
+    const BatchMap rm = rows.shifted(c0);
     if (n_terms == 0) {
       launch_chunk<T, 1>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask, d_coeff, d_obs, 0, n_obs, partial,
-                         outacc, 1, 1, out, stream);
+                         outacc, 1, 1, out, rm, stream);
     }
     for (int k0 = 0; k0 < n_terms; k0 += 32) {
       const int nk = std::min(32, n_terms - k0);
       const int first = k0 == 0, last = k0 + 32 >= n_terms;
       if (nk <= 4)
         launch_chunk<T, 4>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
-                           nk, n_obs, partial, outacc, first, last, out, stream);
+                           nk, n_obs, partial, outacc, first, last, out, rm, stream);
       else
         launch_chunk<T, 32>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
-                            nk, n_obs, partial, outacc, first, last, out, stream);
+                            nk, n_obs, partial, outacc, first, last, out, rm, stream);
     }
     TQ_HIP(hipGetLastError());
   }
@@ -131,8 +132,8 @@ tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int
 }
 
 template tq_status launch_expval<float>(const float2*, BatchMap, int, int, const uint64_t*, const double*,
-                                        const int32_t*, int, int, double*, size_t, float*, hipStream_t);
+                                        const int32_t*, int, int, double*, size_t, float*, BatchMap, hipStream_t);
 template tq_status launch_expval<double>(const double2*, BatchMap, int, int, const uint64_t*, const double*,
-                                         const int32_t*, int, int, double*, size_t, double*, hipStream_t);
+                                         const int32_t*, int, int, double*, size_t, double*, BatchMap, hipStream_t);
 
 }  // namespace tq

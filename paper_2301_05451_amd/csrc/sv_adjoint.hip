@@ -147,28 +147,26 @@ __device__ __forceinline__ void adj_cx(typename Cx<T>::type (&vp)[1 << R], typen
   }
 }
 
+// One reverse stage over one tile of psi and lambda. `nact` threads (a power of two) hold
+// amplitudes; the rest of a larger batched work-group only joins the barriers. Partial
+// inner products of the stage's slots go to part[(slot0 + s) * ntiles + tile].
 template <typename T, int R>
-__global__ void __launch_bounds__(512)
-    adj_stage_kernel(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
-                     const DevOp* __restrict__ ops, const int32_t* __restrict__ dslot,
-                     const typename Cx<T>::type* __restrict__ mats, int64_t mats_stride,
-                     typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam, BatchMap smap,
-                     int slot0, int nslot, int n_slots, double* __restrict__ partial) {
+__device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
+                                         const DevOp* __restrict__ ops, const int32_t* __restrict__ dslot,
+                                         const typename Cx<T>::type* __restrict__ M,
+                                         typename Cx<T>::type* __restrict__ sp, typename Cx<T>::type* __restrict__ sl,
+                                         uint32_t tile, uint32_t tid, int nact, int slot0, int nslot, int64_t ntiles,
+                                         double* __restrict__ part, unsigned char* smem_raw) {
   using C = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int t = stg->t;
   const int tb = t - R;
   C* lds_p = reinterpret_cast<C*>(smem_raw);
   C* lds_l = lds_p + (1u << t);
   T* red = reinterpret_cast<T*>(lds_l + (1u << t));  // [nslot][waves]
-  const int nwaves = (int)((blockDim.x + 63) >> 6);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t tile = blockIdx.x;
+  const int nwaves = (nact + 63) >> 6;
   const int lane = tid & 63, wv = tid >> 6;
-  const int active = (int)blockDim.x < 64 ? (int)blockDim.x : 64;
-  C* sp = psi + smap.at(blockIdx.y);
-  C* sl = lam + smap.at(blockIdx.y);
-  const C* M = mats + (int64_t)blockIdx.y * mats_stride;
+  const int active = nact < 64 ? nact : 64;
+  const bool act = (int)tid < nact;
 
   int64_t base = 0;
   for (int k = 0; k < stg->n_nonlocal; ++k) base |= (int64_t)((tile >> k) & 1u) << stg->npos[k];
@@ -180,8 +178,13 @@ __global__ void __launch_bounds__(512)
     int64_t hi = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
-    vp[j] = sp[(base | thr) + hi];
-    vl[j] = sl[(base | thr) + hi];
+    if (act) {
+      vp[j] = sp[(base | thr) + hi];
+      vl[j] = sl[(base | thr) + hi];
+    } else {
+      vp[j] = C{(T)0, (T)0};
+      vl[j] = C{(T)0, (T)0};
+    }
   }
   uint32_t li[1 << R];
 #pragma unroll
@@ -191,11 +194,12 @@ __global__ void __launch_bounds__(512)
     const DevPhase& ph = phases[p];
     if (ph.xchg) {
       __syncthreads();
+      if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) {
-        lds_p[adj_swz<T>(li[j])] = vp[j];
-        lds_l[adj_swz<T>(li[j])] = vl[j];
-      }
+        for (int j = 0; j < (1 << R); ++j) {
+          lds_p[adj_swz<T>(li[j])] = vp[j];
+          lds_l[adj_swz<T>(li[j])] = vl[j];
+        }
       uint32_t tp = 0;
       for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
 #pragma unroll
@@ -206,11 +210,12 @@ __global__ void __launch_bounds__(512)
         li[j] = tp | rp;
       }
       __syncthreads();
+      if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) {
-        vp[j] = lds_p[adj_swz<T>(li[j])];
-        vl[j] = lds_l[adj_swz<T>(li[j])];
-      }
+        for (int j = 0; j < (1 << R); ++j) {
+          vp[j] = lds_p[adj_swz<T>(li[j])];
+          vl[j] = lds_l[adj_swz<T>(li[j])];
+        }
     }
     for (int o = ph.op_begin; o < ph.op_end; ++o) {
       const DevOp op = load_op(ops, o);
@@ -265,7 +270,7 @@ __global__ void __launch_bounds__(512)
       for (int q = 0; q < 3; ++q) {
         if (q < na) {
           const T s = wave_sum<T>(acc[q], lane, active);
-          if (lane == 0) red[(s0 + q) * nwaves + wv] = s;
+          if (lane == 0 && wv < nwaves) red[(s0 + q) * nwaves + wv] = s;
         }
       }
     }
@@ -273,35 +278,68 @@ __global__ void __launch_bounds__(512)
   // store both tiles in the load layout
   if (stg->store_xchg) {
     __syncthreads();
+    if (act)
 #pragma unroll
-    for (int j = 0; j < (1 << R); ++j) {
-      lds_p[adj_swz<T>(li[j])] = vp[j];
-      lds_l[adj_swz<T>(li[j])] = vl[j];
-    }
+      for (int j = 0; j < (1 << R); ++j) {
+        lds_p[adj_swz<T>(li[j])] = vp[j];
+        lds_l[adj_swz<T>(li[j])] = vl[j];
+      }
     __syncthreads();
+    if (act)
+#pragma unroll
+      for (int j = 0; j < (1 << R); ++j) {
+        const uint32_t l0 = tid | ((uint32_t)j << tb);
+        vp[j] = lds_p[adj_swz<T>(l0)];
+        vl[j] = lds_l[adj_swz<T>(l0)];
+      }
+  }
+  if (act)
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
-      const uint32_t l0 = tid | ((uint32_t)j << tb);
-      vp[j] = lds_p[adj_swz<T>(l0)];
-      vl[j] = lds_l[adj_swz<T>(l0)];
+      int64_t hi = 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+      sp[(base | thr) + hi] = vp[j];
+      sl[(base | thr) + hi] = vl[j];
     }
-  }
-#pragma unroll
-  for (int j = 0; j < (1 << R); ++j) {
-    int64_t hi = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
-    sp[(base | thr) + hi] = vp[j];
-    sl[(base | thr) + hi] = vl[j];
-  }
   __syncthreads();
+  if (act)
+    for (int s = tid; s < nslot; s += nact) {
+      double x = 0.0;
+      for (int w = 0; w < nwaves; ++w) x += (double)red[s * nwaves + w];
+      part[(int64_t)(slot0 + s) * ntiles + tile] = x;
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512)
+    adj_stage_kernel(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
+                     const DevOp* __restrict__ ops, const int32_t* __restrict__ dslot,
+                     const typename Cx<T>::type* __restrict__ mats, int64_t mats_stride,
+                     typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam, BatchMap smap,
+                     int slot0, int nslot, int n_slots, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t ntiles = gridDim.x;
-  double* part = partial + (int64_t)blockIdx.y * n_slots * ntiles;
-  for (int s = tid; s < nslot; s += blockDim.x) {
-    double x = 0.0;
-    for (int w = 0; w < nwaves; ++w) x += (double)red[s * nwaves + w];
-    part[(int64_t)(slot0 + s) * ntiles + tile] = x;
-  }
+  adj_tile<T, R>(stg, phases, ops, dslot, mats + (int64_t)blockIdx.y * mats_stride, psi + smap.at(blockIdx.y),
+                 lam + smap.at(blockIdx.y), blockIdx.x, threadIdx.x, (int)blockDim.x, slot0, nslot, ntiles,
+                 partial + (int64_t)blockIdx.y * n_slots * ntiles, smem_raw);
+}
+
+// Heterogeneous batch, one reverse-stage level: work-group i runs items[i]. The circuit's
+// per-stage (first slot, slot count) pairs sit in its `rec` table.
+template <typename T, int R>
+__global__ void __launch_bounds__(512)
+    adj_batch_stage_kernel(const DevCirc* __restrict__ circs, const BatchItem* __restrict__ items, int level,
+                           const typename Cx<T>::type* __restrict__ mats, typename Cx<T>::type* __restrict__ psi,
+                           typename Cx<T>::type* __restrict__ lam, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint2 w = reinterpret_cast<const uint2*>(items)[blockIdx.x];
+  const DevCirc& d = circs[(int)w.x];
+  const DevStage* stg = d.stages + level;
+  const int2 sl = reinterpret_cast<const int2*>(d.rec)[level];
+  const int t = stg->t;
+  adj_tile<T, R>(stg, d.phases, d.ops, d.dslot, mats + d.mats_off, psi + d.work_off, lam + d.work_off, w.y,
+                 threadIdx.x, 1 << (t - R), sl.x, sl.y, int64_t(1) << (d.n - t), partial + d.part_off, smem_raw);
 }
 
 // grad[p] = sum over occurrences s of p: pscale_s * 2 * sum_tiles partial[s][tile] (fixed order)
@@ -397,6 +435,136 @@ tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap,
   }
   return TQ_OK;
 }
+
+// ---- heterogeneous batch ---------------------------------------------------------------
+template <typename T>
+__global__ void adj_batch_gate_build_kernel(const DevCirc* __restrict__ circs, const int64_t* __restrict__ pref,
+                                            int count, const T* __restrict__ params,
+                                            typename Cx<T>::type* __restrict__ mats) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= pref[count]) return;
+  const int c = find_circ(pref, count, gid);
+  const DevCirc& d = circs[c];
+  const int k = (int)(gid - pref[c]);
+  double a[3];
+  gate_angles(d.gates[k], params + d.param_off, a);
+  dcx m[kAdjMatStride];
+  gate_and_derivs(d.gates[k].op, a, m);
+  typename Cx<T>::type* out = mats + d.mats_off + (int64_t)k * kAdjMatStride;
+  for (int i = 0; i < kAdjMatStride; ++i) out[i] = to_cx<T>(m[i]);
+}
+
+// y = circuit; lambda = sum_o w_o O_o psi with the circuit's own term table.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    adj_batch_init_kernel(const DevCirc* __restrict__ circs, const typename Cx<T>::type* __restrict__ states,
+                          typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam,
+                          const T* __restrict__ grad_out, int n_obs) {
+  using C = typename Cx<T>::type;
+  const DevCirc& d = circs[blockIdx.y];
+  const int64_t namps = int64_t(1) << d.n;
+  const int nt = d.n_terms;
+  const uint64_t* pmask = reinterpret_cast<const uint64_t*>(d.terms);
+  const double* coeff = reinterpret_cast<const double*>(d.terms + 8 * (size_t)nt);
+  const int32_t* obs = reinterpret_cast<const int32_t*>(d.terms + 16 * (size_t)nt);
+  const T* w = grad_out + (int64_t)d.row * n_obs;
+  const C* src = states + d.state_off;
+  C* p = psi + d.work_off;
+  C* l = lam + d.work_off;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
+    double sgn = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const double wc = (double)w[obs[k]] * coeff[k];
+      sgn += (__popcll((uint64_t)i & pmask[k]) & 1) ? -wc : wc;
+    }
+    const C a = src[i];
+    p[i] = a;
+    C b;
+    b.x = (T)(sgn * (double)a.x);
+    b.y = (T)(sgn * (double)a.y);
+    l[i] = b;
+  }
+}
+
+template <typename T>
+__global__ void adj_batch_final_kernel(const DevCirc* __restrict__ circs, const int64_t* __restrict__ ppref,
+                                       int count, const double* __restrict__ partial, T* __restrict__ grad) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= ppref[count]) return;
+  const int c = find_circ(ppref, count, gid);
+  const DevCirc& d = circs[c];
+  const int p = (int)(gid - ppref[c]);
+  const int64_t ntiles = d.n_stages > 0 ? (int64_t(1) << (d.n - d.stages[0].t)) : 1;
+  double g = 0.0;
+  if (p < d.n_used) {
+    const double* part = partial + d.part_off;
+    for (int e = d.pslot_ptr[p]; e < d.pslot_ptr[p + 1]; ++e) {
+      double x = 0.0;
+      const double* row = part + (int64_t)d.pslot_idx[e] * ntiles;
+      for (int64_t tl = 0; tl < ntiles; ++tl) x += row[tl];
+      g += 2.0 * d.pslot_scale[e] * x;
+    }
+  }
+  grad[d.param_off + p] = (T)g;
+}
+
+template <typename T, int R>
+static tq_status launch_adj_batch_stages_R(const BatchLaunch& b, const void* mats, void* psi, void* lam,
+                                           double* partial, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  for (size_t L = 0; L + 1 < b.level_begin.size(); ++L) {
+    const int64_t items = b.level_begin[L + 1] - b.level_begin[L];
+    if (items == 0) continue;
+    const int t = b.level_t[L];
+    const unsigned threads = 1u << (t - R);
+    const unsigned waves = (threads + 63) / 64;
+    const size_t lds = 2 * (sizeof(C) << t) + (size_t)std::max(1, b.level_nslot[L]) * waves * sizeof(T);
+    hipLaunchKernelGGL((adj_batch_stage_kernel<T, R>), dim3((unsigned)items), dim3(threads), lds, stream, b.d_circ,
+                       b.d_items + b.level_begin[L], (int)L, (const C*)mats, (C*)psi, (C*)lam, partial);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+tq_status launch_batch_adjoint(const BatchLaunch& b, const void* d_params, void* d_mats, const void* d_states,
+                               void* d_work_psi, void* d_work_lam, double* d_partial, const T* d_grad_out,
+                               int n_obs, T* d_grad, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  if (b.count == 0) return TQ_OK;
+  if (b.total_mats > 0) {
+    hipLaunchKernelGGL(adj_batch_gate_build_kernel<T>, dim3((unsigned)((b.total_mats + 127) / 128)), dim3(128), 0,
+                       stream, b.d_circ, b.d_pref, b.count, (const T*)d_params, (C*)d_mats);
+    TQ_HIP(hipGetLastError());
+  }
+  for (int c0 = 0; c0 < b.count; c0 += 65535) {
+    const int cn = std::min(65535, b.count - c0);
+    int64_t bx = (b.max_amps + 255) / 256;
+    bx = std::min<int64_t>(bx, std::max<int64_t>(1, 8192 / cn));
+    hipLaunchKernelGGL(adj_batch_init_kernel<T>, dim3((unsigned)bx, cn), dim3(256), 0, stream, b.d_circ + c0,
+                       (const C*)d_states, (C*)d_work_psi, (C*)d_work_lam, d_grad_out, n_obs);
+    TQ_HIP(hipGetLastError());
+  }
+  tq_status st;
+  switch (b.R) {
+    case 1: st = launch_adj_batch_stages_R<T, 1>(b, d_mats, d_work_psi, d_work_lam, d_partial, stream); break;
+    case 2: st = launch_adj_batch_stages_R<T, 2>(b, d_mats, d_work_psi, d_work_lam, d_partial, stream); break;
+    case 3: st = launch_adj_batch_stages_R<T, 3>(b, d_mats, d_work_psi, d_work_lam, d_partial, stream); break;
+    case 4: st = launch_adj_batch_stages_R<T, 4>(b, d_mats, d_work_psi, d_work_lam, d_partial, stream); break;
+    default: return fail(TQ_ENOTSUP, "adjoint register bits must be 1..4");
+  }
+  TQ_TRY(st);
+  if (b.total_params > 0) {
+    hipLaunchKernelGGL(adj_batch_final_kernel<T>, dim3((unsigned)((b.total_params + 127) / 128)), dim3(128), 0,
+                       stream, b.d_circ, b.d_ppref, b.count, (const double*)d_partial, d_grad);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+template tq_status launch_batch_adjoint<float>(const BatchLaunch&, const void*, void*, const void*, void*, void*,
+                                               double*, const float*, int, float*, hipStream_t);
+template tq_status launch_batch_adjoint<double>(const BatchLaunch&, const void*, void*, const void*, void*, void*,
+                                                double*, const double*, int, double*, hipStream_t);
 
 template tq_status launch_adjoint<float>(const Schedule&, const void*, BatchMap, const void*, BatchMap, void*, void*,
                                          BatchMap, void*, double*, const uint64_t*, const double*, const int32_t*, int,

@@ -233,10 +233,98 @@ __device__ __forceinline__ DevOp load_op(const DevOp* ops, int o) {
   return d;
 }
 
+// Largest c with pref[c] <= g (pref ascending, pref[0] = 0, pref[count] > g).
+__device__ __forceinline__ int find_circ(const int64_t* __restrict__ pref, int count, int64_t g) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pref[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 __host__ __device__ __forceinline__ int64_t insert_zero(int64_t k, int pos) {
   const int64_t lo = k & ((int64_t(1) << pos) - 1);
   return ((k >> pos) << (pos + 1)) | lo;
 }
+
+// One circuit of a heterogeneous batch: its schedule's device tables and its offsets into
+// the batch buffers. Forward launches use the first group of fields, the reverse sweep the
+// adjoint ones. All fields are 4- or 8-byte aligned at their natural offsets.
+struct DevCirc {
+  const DevStage* stages;
+  const DevPhase* phases;
+  const DevOp* ops;
+  const tq_gate* gates;
+  const int32_t* rec;        // forward: matrix recipes (kind, qa, qb, begin) + sentinel
+  const int32_t* rec_gates;  // forward: constituent gate indices
+  const int32_t* dslot;      // adjoint: per-op slot info
+  const int32_t* pslot_ptr;  // adjoint: parameter -> slot CSR
+  const int32_t* pslot_idx;
+  const double* pslot_scale;
+  const unsigned char* terms;  // adjoint: [masks u64][coeff f64][obs i32] for this n
+  int64_t mats_off;   // matrix table, complex elements
+  int64_t state_off;  // caller state, complex elements
+  int64_t param_off;  // parameters and gradients, reals
+  int64_t work_off;   // adjoint psi / lambda working copies, complex elements
+  int64_t part_off;   // adjoint per-tile partial sums, doubles
+  int32_t n;          // qubits
+  int32_t n_mats;     // forward: matrix-table entries; adjoint: gates
+  int32_t n_stages;
+  int32_t n_slots;    // adjoint gradient slots
+  int32_t n_params;   // gradient entries written
+  int32_t n_used;     // parameters referenced by the gates
+  int32_t row;        // batch index (row of grad_out)
+  int32_t n_terms;
+};
+static_assert(sizeof(DevCirc) == 160, "DevCirc layout");
+
+// A work item of a batched stage launch: one tile of one circuit.
+struct BatchItem {
+  int32_t circ;
+  uint32_t tile;
+};
+
+// Batched launches over a heterogeneous batch (one kernel per stage level).
+struct BatchLaunch {
+  const DevCirc* d_circ = nullptr;
+  const int64_t* d_pref = nullptr;   // per-circuit prefix of matrix (or gate) counts, count+1
+  const int64_t* d_ppref = nullptr;  // adjoint: per-circuit prefix of gradient entries, count+1
+  const BatchItem* d_items = nullptr;
+  std::vector<int64_t> level_begin;  // item ranges per level, levels+1 entries
+  std::vector<int32_t> level_t;      // largest tile bits at each level
+  std::vector<int32_t> level_nslot;  // adjoint: largest per-stage slot count at each level
+  int count = 0;
+  int64_t total_mats = 0;
+  int64_t total_params = 0;
+  int64_t max_amps = 0;
+  int T = 0, R = 0;
+};
+template <typename T>
+tq_status launch_batch_forward(const BatchLaunch& b, const void* d_params, void* d_mats, void* d_states,
+                               hipStream_t stream);
+template <typename T>
+tq_status launch_batch_adjoint(const BatchLaunch& b, const void* d_params, void* d_mats, const void* d_states,
+                               void* d_work_psi, void* d_work_lam, double* d_partial, const T* d_grad_out,
+                               int n_obs, T* d_grad, hipStream_t stream);
+
+// Host helpers shared by the entry points (api.hip).
+// Circuits of a batch grouped by structure (n, gate_off, n_gates), in first-seen order.
+struct Group {
+  int n;
+  int64_t gate_off;
+  int n_gates;
+  int n_params;
+  std::vector<int> members;
+};
+tq_status group_batch(const tq_batch* b, const int32_t* n_params, std::vector<Group>& groups);
+tq_status member_map(tq_ctx* ctx, int slot, const int64_t* all, const std::vector<int>& m, hipStream_t stream,
+                     BatchMap* out);
+tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, int mode, const tq_sv_opts* opts,
+                       Schedule** out);
+tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, const tq_sv_opts* opts,
+                               Schedule** out);
+tq_status term_table(tq_ctx* ctx, int n, const tq_zterm* terms, int n_terms, const unsigned char** dev);
 
 // launchers (sv_kernels.hip)
 template <typename T>
@@ -265,6 +353,6 @@ size_t expval_scratch_doubles(int n, int count, int n_obs);
 template <typename T>
 tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,
                         const uint64_t* d_pmask, const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs,
-                        double* d_scratch, size_t scratch_doubles, T* d_out, hipStream_t stream);
+                        double* d_scratch, size_t scratch_doubles, T* d_out, BatchMap rows, hipStream_t stream);
 
 }  // namespace tq

@@ -13,19 +13,11 @@ namespace tq {
 // double precision from the circuit's parameters and rounded once to the state dtype.
 // ---------------------------------------------------------------------------------
 template <typename T>
-__global__ void gate_build_kernel(const tq_gate* __restrict__ gates, const int32_t* __restrict__ rec,
-                                  const int32_t* __restrict__ rec_gates, int n_mats,
-                                  const T* __restrict__ params, BatchMap pmap,
-                                  typename Cx<T>::type* __restrict__ mats, int count) {
-  using C = typename Cx<T>::type;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)n_mats * count) return;
-  const int m = (int)(gid % n_mats);
-  const int circ = (int)(gid / n_mats);
-  const T* p = params + pmap.at(circ);
+__device__ __forceinline__ void build_mat(const tq_gate* __restrict__ gates, const int32_t* __restrict__ rec,
+                                          const int32_t* __restrict__ rec_gates, int m, const T* __restrict__ p,
+                                          typename Cx<T>::type* __restrict__ out) {
   const int kind = rec[4 * m + 0], qa = rec[4 * m + 1];
   const int b0 = rec[4 * m + 3], b1 = rec[4 * (m + 1) + 3];
-  C* out = mats + ((int64_t)circ * n_mats + m) * 4;
   if (kind == R_MAT2) {
     dmat2 M = dmat2::identity();
     for (int i = b0; i < b1; ++i) {
@@ -50,6 +42,31 @@ __global__ void gate_build_kernel(const tq_gate* __restrict__ gates, const int32
     }
     for (int k = 0; k < 4; ++k) out[k] = to_cx<T>(d[k]);
   }
+}
+
+template <typename T>
+__global__ void gate_build_kernel(const tq_gate* __restrict__ gates, const int32_t* __restrict__ rec,
+                                  const int32_t* __restrict__ rec_gates, int n_mats,
+                                  const T* __restrict__ params, BatchMap pmap,
+                                  typename Cx<T>::type* __restrict__ mats, int count) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_mats * count) return;
+  const int m = (int)(gid % n_mats);
+  const int circ = (int)(gid / n_mats);
+  build_mat<T>(gates, rec, rec_gates, m, params + pmap.at(circ), mats + ((int64_t)circ * n_mats + m) * 4);
+}
+
+// Heterogeneous batch: one thread per (circuit, matrix entry) over the concatenated tables.
+template <typename T>
+__global__ void batch_gate_build_kernel(const DevCirc* __restrict__ circs, const int64_t* __restrict__ pref,
+                                        int count, const T* __restrict__ params,
+                                        typename Cx<T>::type* __restrict__ mats) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= pref[count]) return;
+  const int c = find_circ(pref, count, gid);
+  const DevCirc& d = circs[c];
+  const int m = (int)(gid - pref[c]);
+  build_mat<T>(d.gates, d.rec, d.rec_gates, m, params + d.param_off, mats + d.mats_off + 4 * (int64_t)m);
 }
 
 // ---------------------------------------------------------------------------------
@@ -233,22 +250,18 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
   }
 }
 
+// One stage over one tile. Threads with act == false (past the 2^(t-R) a tile of a smaller
+// circuit needs, in a batched work-group sized for the largest) hold no amplitudes and only
+// take part in the barriers.
 template <typename T, int R>
-__global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restrict__ stg,
-                                                        const DevPhase* __restrict__ phases,
-                                                        const DevOp* __restrict__ ops,
-                                                        const typename Cx<T>::type* __restrict__ mats,
-                                                        int64_t mats_stride, typename Cx<T>::type* __restrict__ state,
-                                                        BatchMap smap) {
+__device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
+                                           const DevOp* __restrict__ ops,
+                                           const typename Cx<T>::type* __restrict__ M,
+                                           typename Cx<T>::type* __restrict__ st, uint32_t tile, uint32_t tid,
+                                           bool act, typename Cx<T>::type* lds) {
   using C = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
   const int t = stg->t;
   const int tb = t - R;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t tile = blockIdx.x;
-  C* st = state + smap.at(blockIdx.y);
-  const C* M = mats + (int64_t)blockIdx.y * mats_stride;
 
   // global offsets of this thread's amplitudes in the load/store layout
   int64_t base = 0;
@@ -262,7 +275,7 @@ __global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restric
     int64_t hi = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
-    v[j] = sb[hi];
+    if (act) v[j] = sb[hi]; else v[j] = C{(T)0, (T)0};
   }
 
   // local indices in the current layout (load layout: registers = top R local bits)
@@ -276,8 +289,9 @@ __global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restric
     if (ph.xchg) {
       if (!first_x) __syncthreads();
       first_x = false;
+      if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
+        for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
       uint32_t tp = 0;
       for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
 #pragma unroll
@@ -288,26 +302,61 @@ __global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restric
         li[j] = tp | rp;
       }
       __syncthreads();
+      if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(li[j])];
+        for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(li[j])];
     }
     apply_phase_ops<T, R>(v, li, ops, ph.op_begin, ph.op_end, M, t, tile);
   }
   if (stg->store_xchg) {
     if (!first_x) __syncthreads();
+    if (act)
 #pragma unroll
-    for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
+      for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
     __syncthreads();
+    if (act)
 #pragma unroll
-    for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(tid | ((uint32_t)j << tb))];
+      for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(tid | ((uint32_t)j << tb))];
   }
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < (1 << R); ++j) {
-    int64_t hi = 0;
+    for (int j = 0; j < (1 << R); ++j) {
+      int64_t hi = 0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
-    sb[hi] = v[j];
+      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+      sb[hi] = v[j];
+    }
   }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restrict__ stg,
+                                                        const DevPhase* __restrict__ phases,
+                                                        const DevOp* __restrict__ ops,
+                                                        const typename Cx<T>::type* __restrict__ mats,
+                                                        int64_t mats_stride, typename Cx<T>::type* __restrict__ state,
+                                                        BatchMap smap) {
+  using C = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  stage_tile<T, R>(stg, phases, ops, mats + (int64_t)blockIdx.y * mats_stride, state + smap.at(blockIdx.y),
+                   blockIdx.x, threadIdx.x, true, reinterpret_cast<C*>(smem_raw));
+}
+
+// Heterogeneous batch, one stage level: work-group i runs items[i] (a tile of one circuit's
+// stage `level`). The work-group is sized for the level's largest tile.
+template <typename T, int R>
+__global__ void __launch_bounds__(512) sv_batch_stage_kernel(const DevCirc* __restrict__ circs,
+                                                              const BatchItem* __restrict__ items, int level,
+                                                              const typename Cx<T>::type* __restrict__ mats,
+                                                              typename Cx<T>::type* __restrict__ states) {
+  using C = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint2 w = reinterpret_cast<const uint2*>(items)[blockIdx.x];
+  const DevCirc& d = circs[(int)w.x];
+  const DevStage* stg = d.stages + level;
+  const bool act = threadIdx.x < (1u << (stg->t - R));
+  stage_tile<T, R>(stg, d.phases, d.ops, mats + d.mats_off, states + d.state_off, w.y, threadIdx.x, act,
+                   reinterpret_cast<C*>(smem_raw));
 }
 
 // Basis-state initialisation |b> (Sec. 3.1 default |0..0> for b = 0): vector stores only.
@@ -448,5 +497,42 @@ template tq_status launch_plain<float>(const Schedule&, void*, BatchMap, const v
 template tq_status launch_plain<double>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
 template tq_status launch_stages<float>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
 template tq_status launch_stages<double>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
+
+// ---- heterogeneous batch ---------------------------------------------------------------
+template <typename T, int R>
+static tq_status launch_batch_stages_R(const BatchLaunch& b, const void* d_mats, void* d_states,
+                                       hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  for (size_t L = 0; L + 1 < b.level_begin.size(); ++L) {
+    const int64_t items = b.level_begin[L + 1] - b.level_begin[L];
+    if (items == 0) continue;
+    const int t = b.level_t[L];
+    hipLaunchKernelGGL((sv_batch_stage_kernel<T, R>), dim3((unsigned)items), dim3(1u << (t - R)), sizeof(C) << t,
+                       stream, b.d_circ, b.d_items + b.level_begin[L], (int)L, (const C*)d_mats, (C*)d_states);
+    TQ_HIP(hipGetLastError());
+  }
+  return TQ_OK;
+}
+
+template <typename T>
+tq_status launch_batch_forward(const BatchLaunch& b, const void* d_params, void* d_mats, void* d_states,
+                               hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  if (b.total_mats > 0) {
+    hipLaunchKernelGGL(batch_gate_build_kernel<T>, dim3((unsigned)((b.total_mats + 127) / 128)), dim3(128), 0,
+                       stream, b.d_circ, b.d_pref, b.count, (const T*)d_params, (C*)d_mats);
+    TQ_HIP(hipGetLastError());
+  }
+  switch (b.R) {
+    case 1: return launch_batch_stages_R<T, 1>(b, d_mats, d_states, stream);
+    case 2: return launch_batch_stages_R<T, 2>(b, d_mats, d_states, stream);
+    case 3: return launch_batch_stages_R<T, 3>(b, d_mats, d_states, stream);
+    case 4: return launch_batch_stages_R<T, 4>(b, d_mats, d_states, stream);
+    case 5: return launch_batch_stages_R<T, 5>(b, d_mats, d_states, stream);
+    default: return fail(TQ_ENOTSUP, "register bits must be 1..5");
+  }
+}
+template tq_status launch_batch_forward<float>(const BatchLaunch&, const void*, void*, void*, hipStream_t);
+template tq_status launch_batch_forward<double>(const BatchLaunch&, const void*, void*, void*, hipStream_t);
 
 }  // namespace tq

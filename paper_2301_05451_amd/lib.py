@@ -262,6 +262,113 @@ def zero_states(spec: BatchSpec, dtype, device="cuda"):
     return init_states(st, spec, 0)
 
 
+# ---- compiled batches (tq_svb_*) ------------------------------------------------------------
+class SvbOpts(ct.Structure):
+    _fields_ = [(k, ct.c_int32) for k in ("tile_bits", "reg_bits", "coal_bits", "adj_tile_bits", "adj_reg_bits",
+                                          "adj_coal_bits", "init", "graph")]
+
+
+_lib.tq_svb_create.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _i32, _i32, ct.POINTER(SvbOpts),
+                               ct.POINTER(_vp)]
+_lib.tq_svb_create.restype = ct.c_int
+_lib.tq_svb_destroy.argtypes = [_vp]
+_lib.tq_svb_destroy.restype = None
+_lib.tq_svb_forward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_svb_forward.restype = ct.c_int
+_lib.tq_svb_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_svb_backward.restype = ct.c_int
+_lib.tq_svb_autotune.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _vp, ct.POINTER(SvbOpts), ct.POINTER(ct.c_double)]
+_lib.tq_svb_autotune.restype = ct.c_int
+_lib.tq_svb_info.argtypes = [_vp, ct.POINTER(ct.c_int64)]
+_lib.tq_svb_info.restype = ct.c_int
+
+SVB_INFO_FIELDS = ("levels", "items", "adj_levels", "adj_items", "graph_captures", "graph_replays", "tile_bits",
+                   "reg_bits")
+
+
+class SVBatch:
+    """A batch of circuits compiled once (tq_svb_create) and run many times: forward
+    (initial |0..0> unless ``init_from_states``, gate application, expectation values) and
+    the adjoint backward, optionally replayed as HIP graphs (``graph=True``)."""
+
+    def __init__(self, spec: BatchSpec, terms, n_obs, c128=False, graph=False, init_from_states=False,
+                 tile_bits=0, reg_bits=0, adj_tile_bits=0, adj_reg_bits=0, ctx=None):
+        self.spec = spec
+        self.terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
+        self.n_obs = int(n_obs)
+        self.c128 = bool(c128)
+        self.ctx = ctx or context()
+        o = SvbOpts(int(tile_bits), int(reg_bits), 0, int(adj_tile_bits), int(adj_reg_bits), 0,
+                    1 if init_from_states else 0, 1 if graph else 0)
+        h = _vp()
+        check(_lib.tq_svb_create(self.ctx.h, TQ_C128 if c128 else TQ_C64, ct.byref(spec.c), spec.gates.ctypes.data,
+                                 spec.n_params.ctypes.data, self.terms.ctypes.data, int(self.terms.shape[0]),
+                                 self.n_obs, ct.byref(o), ct.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.tq_svb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dtypes(self):
+        import torch
+        return (torch.complex128, torch.float64) if self.c128 else (torch.complex64, torch.float32)
+
+    def new_states(self, device="cuda"):
+        import torch
+        return torch.empty(self.spec.total_amps, dtype=self._dtypes()[0], device=device)
+
+    def forward(self, params, states, out=None, with_expval=True):
+        """Runs the batch; returns the [count, n_obs] expectation values (or None)."""
+        import torch
+        cdt, rdt = self._dtypes()
+        if states.dtype != cdt:
+            raise ValueError(f"states must be {cdt}")
+        _check_tensors(states, params, self.spec)
+        if with_expval and out is None:
+            out = torch.empty((self.spec.count, self.n_obs), dtype=rdt, device=states.device)
+        check(_lib.tq_svb_forward(self.ctx.h, self.h, params.data_ptr(), states.data_ptr(),
+                                  out.data_ptr() if with_expval else None, _stream()))
+        return out if with_expval else None
+
+    def backward(self, params, states, grad_out, grad=None):
+        """Adjoint gradients in the layout of params."""
+        import torch
+        _check_tensors(states, params, self.spec)
+        if grad_out.dtype != params.dtype or not grad_out.is_contiguous() or \
+                grad_out.numel() < self.spec.count * self.n_obs:
+            raise ValueError(f"grad_out must be a contiguous {params.dtype} tensor of {self.spec.count} x {self.n_obs}")
+        if grad is None:
+            grad = torch.zeros_like(params)
+        check(_lib.tq_svb_backward(self.ctx.h, self.h, params.data_ptr(), states.data_ptr(), grad_out.data_ptr(),
+                                   grad.data_ptr(), _stream()))
+        return grad
+
+    def autotune(self, params, states, which=0, reps=3):
+        """Times every candidate shape on the device and keeps the fastest; returns
+        (tile_bits, reg_bits, ms)."""
+        best = SvbOpts()
+        ms = ct.c_double()
+        check(_lib.tq_svb_autotune(self.ctx.h, self.h, params.data_ptr(), states.data_ptr(), int(which), int(reps),
+                                   _stream(), ct.byref(best), ct.byref(ms)))
+        if which == 0:
+            return best.tile_bits, best.reg_bits, ms.value
+        return best.adj_tile_bits, best.adj_reg_bits, ms.value
+
+    @property
+    def info(self):
+        out = (ct.c_int64 * 8)()
+        check(_lib.tq_svb_info(self.h, out))
+        return dict(zip(SVB_INFO_FIELDS, [int(v) for v in out]))
+
+
 # ---- tensor-network mode -------------------------------------------------------------------
 class TnDesc(ct.Structure):
     _fields_ = [("n_leaves", ct.c_int32), ("leaf_rank", ct.c_void_p), ("leaf_inds", ct.c_void_p),

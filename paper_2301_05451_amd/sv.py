@@ -1,6 +1,7 @@
 """PyTorch interface of the state-vector path (the quantum-to-classical interface of the
-paper's Sec. 4.3): a ``torch.autograd.Function`` whose forward runs tq_sv_init +
-tq_sv_apply + tq_expval and whose backward runs the adjoint sweep tq_sv_backward.
+paper's Sec. 4.3): ``torch.autograd.Function``s whose forward runs tq_sv_init +
+tq_sv_apply + tq_expval (or a compiled batch's tq_svb_forward) and whose backward runs the
+adjoint sweep tq_sv_backward (tq_svb_backward).
 
 All arithmetic runs in libtq kernels; torch provides device memory, streams and the
 autograd graph around the circuit.
@@ -45,6 +46,34 @@ class SVExpval(torch.autograd.Function):
 def expval(params, spec, terms, n_obs=1, dtype=torch.complex64, fwd_opts=None, bwd_opts=None):
     """Differentiable expectation values of a batch of circuits."""
     return SVExpval.apply(params, spec, terms, n_obs, dtype, fwd_opts or {}, bwd_opts or {})
+
+
+class BatchExpval(torch.autograd.Function):
+    """Differentiable expectation values of a compiled batch (lib.SVBatch): forward is
+    tq_svb_forward, backward tq_svb_backward. The final states stay in ``states`` (no
+    copy), so the backward pass must run before that buffer is reused by another forward."""
+
+    @staticmethod
+    def forward(ctx, params, svb, states):
+        params = params.contiguous()
+        out = svb.forward(params, states)
+        ctx.save_for_backward(params)
+        ctx.svb, ctx.states = svb, states
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (params,) = ctx.saved_tensors
+        g = ctx.svb.backward(params, ctx.states, grad_out.contiguous().to(params.dtype))
+        return g, None, None
+
+
+def batch_expval(params, svb, states=None):
+    """``svb`` = lib.SVBatch. ``states`` (optional) is reused as the state buffer, which
+    lets graph replays see the same pointers every step."""
+    if states is None:
+        states = svb.new_states(params.device)
+    return BatchExpval.apply(params, svb, states)
 
 
 def shifted_param_sets(params, spec):
