@@ -55,6 +55,211 @@ def cpu_baseline(c, seconds_hint=True):
                       f"{dt:.1f} s on {cpu_model()} (numpy tensordot per gate)"}
 
 
+def _timed(fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls after `warmup` calls (HIP events on the
+    current stream, which every libtq call here is launched on)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_qnn(steps):
+    """16-qubit, 8-layer QNN over 512 samples (angle-encoded inputs, shared weights), MSE loss
+    on <Z0>: one training step = compiled-batch forward + loss gradient + adjoint backward,
+    replayed as HIP graphs. Compared with the GPU parameter-shift rule and with a loop of
+    single-circuit calls, on the same device."""
+    import numpy as np
+    import torch
+
+    from paper_2301_05451_amd import lib, sv
+    from paper_2301_05451_amd import workloads as W
+
+    n, B = 16, 512
+    gates, x, theta, y = W.qnn_batch(n=n, layers=8, batch=B, seed=1003)
+    P = n + theta.shape[0]
+    pb = np.concatenate([x, np.broadcast_to(theta, (B, theta.shape[0]))], 1)
+    spec = lib.BatchSpec.uniform(n, gates, B, P)
+    terms = W.zterms([([0], 1.0, 0)])
+    params = torch.tensor(pb.reshape(-1), dtype=torch.float32, device="cuda")
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")[:, None]
+    svb = lib.SVBatch(spec, terms, 1, graph=True)
+    states = svb.new_states()
+    out = torch.empty(B, 1, device="cuda")
+    w = torch.empty(B, 1, device="cuda")
+    grad = torch.zeros_like(params)
+
+    def step():
+        svb.forward(params, states, out)
+        torch.sub(out, yt, out=w).mul_(2.0 / B)  # dL/df of the mean squared error
+        svb.backward(params, states, w, grad)
+
+    ms = _timed(step, steps, 3)
+    # GPU parameter shift on 4 samples (2P shifted circuits each), same weights
+    sel = slice(0, 4)
+    ps_ms = _timed(lambda: sv.param_shift_grad_gpu(params.reshape(B, P)[sel], gates, n, terms, 1, w[sel]), 2, 1)
+    g_ps = sv.param_shift_grad_gpu(params.reshape(B, P)[sel], gates, n, terms, 1, w[sel])
+    err = (grad.reshape(B, P)[sel] - g_ps).abs().max().item()
+    # loop of single-circuit calls (16 samples, one circuit per call)
+    one = lib.BatchSpec.uniform(n, gates, 1, P)
+    psi1 = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+
+    def loop16():
+        for b in range(16):
+            pr = params[b * P:(b + 1) * P]
+            lib.init_states(psi1, one, 0)
+            lib.sv_apply(psi1, pr, one)
+            lib.expval(psi1, one, terms, 1)
+            lib.sv_backward(psi1, pr, one, terms, 1, w[b:b + 1])
+
+    loop_ms = _timed(loop16, 2, 1) / 16
+    gate_amps = gates.shape[0] * (1 << n) * B
+    return {"workload": "16-qubit 8-layer QNN (RY encoding, RY/RZ layers, CNOT chain; 392 gates, 272 params), "
+                        "batch 512, complex64, MSE on <Z0>",
+            "grad_circuits_per_s": B / (ms * 1e-3), "ms_per_step": round(ms, 3),
+            "forward_gate_amps_per_s": gate_amps / (ms * 1e-3),
+            "param_shift_gpu_circuits_per_s": 4 / (ps_ms * 1e-3),
+            "adjoint_speedup_vs_param_shift": round((ps_ms / 4) / (ms / B), 1),
+            "max_abs_grad_diff_vs_param_shift": err,
+            "single_call_loop_circuits_per_s": 1 / (loop_ms * 1e-3),
+            "batched_speedup_vs_single_calls": round(loop_ms / (ms / B), 1),
+            "levels": svb.info["levels"], "graph_replays": svb.info["graph_replays"]}
+
+
+def bench_uneven(steps):
+    """1024 random circuits, n uniform in 8..20, 2n layers of U3 on every qubit + floor(n/2)
+    random CNOT pairs, <Z0> and its full gradient: compiled batch (autotuned, graph-replayed)
+    vs a loop of single-circuit calls."""
+    import numpy as np
+    import torch
+
+    from paper_2301_05451_amd import lib
+    from paper_2301_05451_amd import workloads as W
+
+    circs = W.uneven_batch()
+    spec = lib.BatchSpec.from_circuits(circs)
+    terms = W.zterms([([0], 1.0, 0)])
+    params = torch.tensor(np.concatenate([c.params for c in circs]), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    svb = lib.SVBatch(spec, terms, 1, graph=True)
+    compile_s = time.perf_counter() - t0
+    states = svb.new_states()
+    tf = svb.autotune(params, states, which=0, reps=1)
+    svb.forward(params, states)
+    tb = svb.autotune(params, states, which=1, reps=1)
+    out = torch.empty(len(circs), 1, device="cuda")
+    w = torch.ones(len(circs), 1, device="cuda")
+    grad = torch.zeros_like(params)
+    fwd_ms = _timed(lambda: svb.forward(params, states, out), steps, 3)
+
+    def step():
+        svb.forward(params, states, out)
+        svb.backward(params, states, w, grad)
+
+    ms = _timed(step, steps, 3)
+    gate_amps = int(sum(c.gates.shape[0] << c.n for c in circs))
+    # single-circuit calls, one circuit per call
+    specs1 = [lib.BatchSpec.from_circuits([c]) for c in circs]
+    offs = spec.param_off
+
+    def loop():
+        for i, c in enumerate(circs):
+            one = specs1[i]
+            pr = params[int(offs[i]):int(offs[i]) + c.n_params]
+            psi1 = lib.zero_states(one, torch.complex64)
+            lib.sv_apply(psi1, pr, one)
+            lib.expval(psi1, one, terms, 1)
+            lib.sv_backward(psi1, pr, one, terms, 1, w[i:i + 1])
+
+    loop_ms = _timed(loop, 1, 1)
+    return {"workload": "1024 random circuits, n uniform in 8..20 (seeded), 2n layers of U3 on all qubits + "
+                        "floor(n/2) random CNOT pairs, complex64, <Z0> + full gradient",
+            "grad_circuits_per_s": len(circs) / (ms * 1e-3), "ms_per_step": round(ms, 3),
+            "forward_ms": round(fwd_ms, 3), "forward_gate_amps_per_s": gate_amps / (fwd_ms * 1e-3),
+            "gate_amps": gate_amps, "compile_s": round(compile_s, 2),
+            "autotuned_forward": list(tf[:2]), "autotuned_backward": list(tb[:2]),
+            "single_call_loop_grad_circuits_per_s": len(circs) / (loop_ms * 1e-3),
+            "batched_speedup_vs_single_calls": round(loop_ms / ms, 1),
+            "levels": svb.info["levels"], "items": svb.info["items"]}
+
+
+def bench_tn(steps):
+    """QAOA MaxCut on a seeded random 3-regular graph of 50 nodes (75 edges): one light-cone
+    network per edge for <Z_i Z_j>, value + gradient of (gamma, beta). All 75 networks at
+    p = 3; at p = 4 the edges whose min-fill tree has width <= 26. Plus one dense pairwise
+    step on the FP32-MFMA complex GEMM path."""
+    import numpy as np
+    import torch
+
+    from paper_2301_05451_amd import lib, tn
+    from paper_2301_05451_amd import workloads as W
+
+    res = {}
+    for p in (3, 4):
+        prob = W.qaoa_maxcut(p=p)
+        t0 = time.perf_counter()
+        progs = []
+        for e in prob.edges:
+            net, _ = tn.qaoa_edge_network(prob, e)
+            tree = tn.elimination_tree(net, tn.elimination_order(net, None, "fill")[0])
+            if tree.max_rank > 26:
+                continue
+            progs.append(tn.TNProgram(net, tree))
+        plan_s = time.perf_counter() - t0
+        if not progs:
+            continue
+        pars = [torch.tensor(pg.net.params, dtype=torch.float32, device="cuda") for pg in progs]
+
+        def run():
+            for pg, pt in zip(progs, pars):
+                pg.value(pt)
+                pg.grad(pt)
+
+        ms = _timed(run, max(1, steps // 4), 1)
+        flops = sum(pg.plan.info["flops"] for pg in progs)  # contraction only, 8 real flops per complex MAC
+        res[f"p{p}"] = {"networks": len(progs), "plan_s": round(plan_s, 2), "ms_value_and_grad_all": round(ms, 3),
+                        "grad_networks_per_s": len(progs) / (ms * 1e-3),
+                        "contraction_flops_per_network_sum": flops,
+                        # value + gradient = 3 forward contractions of algorithmic work (the
+                        # reverse pass also recomputes the forward: not counted)
+                        "tn_gflops": 3 * flops / (ms * 1e-3) / 1e9,
+                        "max_width": max(pg.tree.max_rank for pg in progs)}
+    # dense step: C[b,m,n] = sum_k A[b,m,k] B[b,k,n], b = 1 bit, M = N = 2^12, K = 2^10
+    b, m, k, nn = [0], list(range(1, 13)), list(range(13, 23)), list(range(23, 35))
+    plan = lib.TnPlan([b + m + k, b + k + nn], [(0, 1)], out_inds=b + m + nn)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    leaves = torch.randn(plan.leaf_elems, dtype=torch.complex64, device="cuda", generator=g)
+    work = torch.empty(max(plan.workspace_bytes(False), 16), dtype=torch.uint8, device="cuda")
+    ms = _timed(lambda: lib.tn_contract(plan, leaves, work), steps, 2)
+    fl = 8 * 2 * (1 << 12) * (1 << 12) * (1 << 10)
+    # sampled entries against a float64 sum over k
+    C = lib.tn_contract(plan, leaves, work)
+    A = leaves[:plan.leaf_offsets[1]].reshape(2, 1 << 12, 1 << 10)
+    Bm = leaves[plan.leaf_offsets[1]:].reshape(2, 1 << 10, 1 << 12)
+    rs = np.random.default_rng(9)
+    errs = []
+    for _ in range(16):
+        bb, mm, nn_ = int(rs.integers(2)), int(rs.integers(1 << 12)), int(rs.integers(1 << 12))
+        a = A[bb, mm].cpu().numpy().astype(np.complex128)
+        bcol = Bm[bb, :, nn_].cpu().numpy().astype(np.complex128)
+        want = np.dot(a, bcol)
+        got = complex(C.reshape(2, 1 << 12, 1 << 12)[bb, mm, nn_].item())
+        errs.append(abs(got - want) / np.sqrt(np.sum(np.abs(a) ** 2) * np.sum(np.abs(bcol) ** 2)))
+    res["dense_step"] = {"shape": "batch 2, M = N = 4096, K = 1024 complex", "gemm_steps": plan.info["gemm_steps"],
+                         "ms": round(ms, 3), "tflops": fl / (ms * 1e-3) / 1e12,
+                         "mfma_frac_fp32": fl / (ms * 1e-3) / 157.3e12,
+                         "sampled_rel_err": float(max(errs))}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +269,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1, help="steps of the one-sweep-per-gate path")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the QNN batch, uneven batch and tensor-network measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -165,6 +372,10 @@ def main():
         "expval_sum_z": float(f[0, 0]),
         "plain": plain,
     }
+    if not args.no_extras:
+        out["qnn16_batch512"] = bench_qnn(max(5, args.steps // 2))
+        out["uneven1024"] = bench_uneven(max(3, args.steps // 4))
+        out["tn_qaoa50"] = bench_tn(max(4, args.steps // 2))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)
