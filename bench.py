@@ -10,6 +10,7 @@ Prints one JSON line. ``value`` is gates*amps/s = 1670 * 2^24 / seconds per step
 """
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -260,6 +261,56 @@ def bench_tn(steps):
     return res
 
 
+def bench_costmodel():
+    """Learned tree ranking: the cost-model MLP is trained on the GPU from measured times
+    (value + gradient) of candidate trees of QAOA light-cone networks on other seeded graphs
+    (30 nodes, p = 2 and 3), then picks one tree per edge network of the 50-node p = 3
+    workload; its picks are timed against the fewest-FLOPs picks."""
+    import numpy as np
+    import torch
+
+    from paper_2301_05451_amd import costmodel, tn
+    from paper_2301_05451_amd import workloads as W
+
+    t0 = time.perf_counter()
+    feats, ys = [], []
+    for seed in (2001, 2002, 2003):
+        for p in (2, 3):
+            r = np.random.default_rng(seed)
+            edges = W.random_regular_graph(3, 30, r)
+            prob = W.QAOAProblem(30, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
+            for e in edges[:5]:
+                net, _ = tn.qaoa_edge_network(prob, e)
+                pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
+                for tree, prog, f in costmodel.candidates_with_plans(net, n_random=5, seed=seed):
+                    feats.append(f)
+                    ys.append(math.log(costmodel.time_program(prog, pt, reps=2)))
+    collect_s = time.perf_counter() - t0
+    cm = costmodel.CostModel(seed=0)
+    t1 = time.perf_counter()
+    hist = cm.fit(np.array(feats), np.array(ys), epochs=800, lr=3e-3)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t1
+    prob = W.qaoa_maxcut(p=3)
+    t_flop = t_mlp = 0.0
+    same = 0
+    for e in prob.edges:
+        net, _ = tn.qaoa_edge_network(prob, e)
+        pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
+        cands = costmodel.candidates_with_plans(net, n_random=5, seed=7)
+        kf, km = costmodel.pick(cands), costmodel.pick(cands, cm)
+        tf = costmodel.time_program(cands[kf][1], pt, reps=3)
+        tm = tf if km == kf else costmodel.time_program(cands[km][1], pt, reps=3)
+        same += km == kf
+        t_flop += tf
+        t_mlp += tm
+    return {"workload": "75 light-cone networks of QAOA p=3 on the 50-node 3-regular graph, 8 candidate trees each",
+            "train_samples": len(ys), "collect_s": round(collect_s, 1), "fit_s": round(fit_s, 2),
+            "train_mse_first_last": [hist[0], hist[-1]],
+            "ms_flop_ranked": round(t_flop, 2), "ms_mlp_ranked": round(t_mlp, 2),
+            "learned_gain": round(t_flop / t_mlp, 3), "same_pick": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +427,7 @@ def main():
         out["qnn16_batch512"] = bench_qnn(max(5, args.steps // 2))
         out["uneven1024"] = bench_uneven(max(3, args.steps // 4))
         out["tn_qaoa50"] = bench_tn(max(4, args.steps // 2))
+        out["tree_ranking"] = bench_costmodel()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)

@@ -303,6 +303,36 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
                            const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
                            const void* d_grad_leaves, void* d_grad_params, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Cost-model MLP (ranks contraction trees by predicted runtime; Sec. 3.2.2 ranks them by
+ * FLOPs, and Sec. 6.6 notes that small pairwise steps make runtime and FLOPs disagree).
+ * x -> tanh(W_1 x + b_1) -> ... -> tanh(W_{L-1} h + b_{L-1}) -> W_L h + b_L, float32, one
+ * scalar output (sizes[n_layers] must be 1). Parameters are packed layer by layer as
+ * W_l [sizes[l+1]][sizes[l]] row-major followed by b_l [sizes[l+1]]. Inputs are [batch][sizes[0]]
+ * row-major. Reductions over the batch run in a fixed order (repeatable bitwise).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_layers;  /* 1..8 */
+  int32_t sizes[9];  /* sizes[0] = input features, ..., sizes[n_layers] = 1; each 1..4096 */
+} tq_mlp_desc;
+
+/* Number of packed parameters, and workspace bytes for a batch (-1 on a bad descriptor). */
+int64_t tq_mlp_param_count(const tq_mlp_desc* desc);
+int64_t tq_mlp_workspace(const tq_mlp_desc* desc, int32_t batch);
+
+/* d_y[b] = MLP(d_x[b]). Errors: TQ_EINVAL, TQ_EWORKSPACE. */
+tq_status tq_mlp_forward(tq_ctx* ctx, const tq_mlp_desc* desc, const float* d_params, const float* d_x,
+                         int32_t batch, float* d_y, void* d_work, int64_t work_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected; t is the 1-based step count) on the mean
+ * squared error L = mean_b (MLP(x_b) - y_b)^2: d_params, d_m, d_v (first and second moments,
+ * zero before step 1) are updated in place. d_loss (may be NULL) receives L before the
+ * update, d_grad (may be NULL) dL/dparams. */
+tq_status tq_mlp_train_step(tq_ctx* ctx, const tq_mlp_desc* desc, float* d_params, float* d_m, float* d_v,
+                            int32_t t, float lr, float beta1, float beta2, float eps, const float* d_x,
+                            const float* d_y, int32_t batch, float* d_loss, float* d_grad, void* d_work,
+                            int64_t work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -502,3 +502,81 @@ def tn_param_grad(plan: TnPlan, gates, leaf_specs, params, grad_leaves):
                                 params.data_ptr(), int(params.numel()), grad_leaves.contiguous().data_ptr(),
                                 out.data_ptr(), _stream()))
     return out
+
+
+# ---- cost-model MLP (tq_mlp_*) ---------------------------------------------------------------
+class MlpDesc(ct.Structure):
+    _fields_ = [("n_layers", ct.c_int32), ("sizes", ct.c_int32 * 9)]
+
+
+_lib.tq_mlp_param_count.argtypes = [ct.POINTER(MlpDesc)]
+_lib.tq_mlp_param_count.restype = ct.c_int64
+_lib.tq_mlp_workspace.argtypes = [ct.POINTER(MlpDesc), _i32]
+_lib.tq_mlp_workspace.restype = ct.c_int64
+_lib.tq_mlp_forward.argtypes = [_vp, ct.POINTER(MlpDesc), _vp, _vp, _i32, _vp, _vp, ct.c_int64, _vp]
+_lib.tq_mlp_forward.restype = ct.c_int
+_lib.tq_mlp_train_step.argtypes = [_vp, ct.POINTER(MlpDesc), _vp, _vp, _vp, _i32, ct.c_float, ct.c_float, ct.c_float,
+                                   ct.c_float, _vp, _vp, _i32, _vp, _vp, _vp, ct.c_int64, _vp]
+_lib.tq_mlp_train_step.restype = ct.c_int
+
+
+def mlp_desc(sizes):
+    d = MlpDesc()
+    d.n_layers = len(sizes) - 1
+    for i, v in enumerate(sizes):
+        d.sizes[i] = int(v)
+    return d
+
+
+def mlp_param_count(sizes):
+    n = int(_lib.tq_mlp_param_count(ct.byref(mlp_desc(sizes))))
+    if n < 0:
+        raise TQError(1, last_error())
+    return n
+
+
+def _f32(t, name):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA float32 tensor")
+
+
+def mlp_forward(sizes, params, x, ctx=None):
+    """[batch] outputs of the MLP on x [batch, sizes[0]] (tq_mlp_forward)."""
+    import torch
+    _f32(params, "params")
+    _f32(x, "x")
+    d = mlp_desc(sizes)
+    B = int(x.shape[0])
+    if x.numel() != B * sizes[0] or params.numel() != mlp_param_count(sizes):
+        raise ValueError("shape mismatch")
+    ctx = ctx or context(x.device.index)
+    y = torch.empty(B, dtype=torch.float32, device=x.device)
+    need = int(_lib.tq_mlp_workspace(ct.byref(d), B))
+    ws = _ws(need, x.device)
+    check(_lib.tq_mlp_forward(ctx.h, ct.byref(d), params.data_ptr(), x.data_ptr(), B, y.data_ptr(), ws.data_ptr(),
+                              need, _stream()))
+    return y
+
+
+def mlp_train_step(sizes, params, m, v, t, x, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_grad=False,
+                   ctx=None):
+    """One Adam step on the MSE of the MLP (tq_mlp_train_step); returns (loss tensor [1], grad or None)."""
+    import torch
+    for a, nm in ((params, "params"), (m, "m"), (v, "v"), (x, "x"), (y, "y")):
+        _f32(a, nm)
+    d = mlp_desc(sizes)
+    B = int(x.shape[0])
+    P = mlp_param_count(sizes)
+    if params.numel() != P or m.numel() != P or v.numel() != P or y.numel() != B or x.numel() != B * sizes[0]:
+        raise ValueError("shape mismatch")
+    ctx = ctx or context(x.device.index)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(P, dtype=torch.float32, device=x.device) if want_grad else None
+    need = int(_lib.tq_mlp_workspace(ct.byref(d), B))
+    ws = _ws(need, x.device)
+    check(_lib.tq_mlp_train_step(ctx.h, ct.byref(d), params.data_ptr(), m.data_ptr(), v.data_ptr(), int(t),
+                                 float(lr), float(beta1), float(beta2), float(eps), x.data_ptr(), y.data_ptr(), B,
+                                 loss.data_ptr(), grad.data_ptr() if want_grad else None, ws.data_ptr(), need,
+                                 _stream()))
+    return loss, grad
