@@ -89,6 +89,19 @@ struct tq_tn_plan {
   void* d_bperm = nullptr;
   std::vector<int> sliced_leaves;      // leaf tensor ids that depend on a sliced index
   void* d_gather = nullptr;            // per sliced leaf: [keep pos][slice pos][slice bit] x kTnMaxBits
+  // execution segments: runs of small steps (one fused launch each) and single large steps
+  struct Seg {
+    int fused = 0;       // 1: run of small direct steps in tn_fused_kernel
+    int first = 0;       // first step (index into fwd / bwd)
+    int count = 0;
+    int64_t list = 0;    // fused: first entry in the DevFused table
+    int shared = 0;      // forward: outputs do not depend on a sliced index (one copy)
+  };
+  std::vector<Seg> fseg, bseg;
+  void* d_ffused = nullptr;            // DevFused entries of the forward runs
+  void* d_bfused = nullptr;            // ... of the reverse runs
+  void* d_leaf_env = nullptr;          // (leaf offset, environment offset, elements) of unsliced leaves
+  int n_leaf_env = 0;
   ~tq_tn_plan();
 };
 
@@ -104,45 +117,168 @@ __device__ __forceinline__ int64_t deposit_bits(uint64_t v, const uint8_t* pos, 
   return r;
 }
 
-// Z[e] = sum_s X[xoff(e, s)] * Y[yoff(e, s)]; blockIdx.y = slice copy (stride 0 for shared).
+// A pairwise step by bit deposits: Z[e] = sum_s X[xoff(e) + xsum(s)] * Y[yoff(e) + ysum(s)].
+// 2^tb consecutive lanes share one output e: lane l sums the assignments s = l, l + 2^tb, ..
+// of the summed bits, then the group adds its partial sums by a butterfly (and, for groups
+// wider than a wave, through LDS): a fixed order, so results repeat bitwise. The offsets of
+// the low kt summed bits come from LDS tables built by the whole work-group.
+constexpr int kTnTabBits = 9;
+
+template <typename T>
+__device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ st, int64_t* tx, int64_t* ty) {
+  const int kt = st->ks < kTnTabBits ? st->ks : kTnTabBits;
+  for (int i = threadIdx.x; i < (1 << kt); i += blockDim.x) {
+    tx[i] = deposit_bits((uint64_t)i, st->xs, kt);
+    ty[i] = deposit_bits((uint64_t)i, st->ys, kt);
+  }
+}
+
+// Outputs of groups g = g0, g0 + gstride, ... (one group = 2^tb lanes). Every thread of the
+// work-group calls this with the same g0 / gstride trip count (barriers inside when tb > 6).
+template <typename T>
+__device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st, const int64_t* tx,
+                                                const int64_t* ty, const typename Cx<T>::type* __restrict__ x,
+                                                const typename Cx<T>::type* __restrict__ y,
+                                                typename Cx<T>::type* __restrict__ z, int tb, int64_t gfirst,
+                                                int64_t gstride, T* red) {
+  using C = typename Cx<T>::type;
+  const int zr = st->zr, ks = st->ks;
+  const int kt = ks < kTnTabBits ? ks : kTnTabBits;
+  const int nt = 1 << kt;
+  const int G = 1 << tb;
+  const int lane = threadIdx.x & (G - 1);
+  const int gpb = (int)blockDim.x >> tb;  // groups per block
+  const int64_t nz = int64_t(1) << zr;
+  const int64_t nouter = int64_t(1) << (ks - kt);
+  const int64_t ngroups = (nz + gpb - 1) / gpb;  // rounds of the block's group slots
+  for (int64_t r = gfirst; r < ngroups; r += gstride) {
+    const int64_t e = r * gpb + (threadIdx.x >> tb);
+    const bool valid = e < nz;
+    T ar = 0, ai = 0;
+    if (valid) {
+      const int64_t xb = deposit_bits((uint64_t)e, st->xo, zr);
+      const int64_t yb = deposit_bits((uint64_t)e, st->yo, zr);
+      for (int64_t so = 0; so < nouter; ++so) {
+        const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
+        const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
+        for (int sl = lane; sl < nt; sl += G) {
+          const C a = x[xo2 + tx[sl]], b = y[yo2 + ty[sl]];
+          ar += a.x * b.x - a.y * b.y;
+          ai += a.x * b.y + a.y * b.x;
+        }
+      }
+    }
+    const int wl = tb < 6 ? tb : 6;  // butterfly inside the wave
+    for (int off = 1; off < (1 << wl); off <<= 1) {
+      ar += __shfl_xor(ar, off, 64);
+      ai += __shfl_xor(ai, off, 64);
+    }
+    if (tb > 6) {  // groups of 128 or 256 lanes: add the waves' sums in wave order
+      const int wv = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) {
+        red[2 * wv] = ar;
+        red[2 * wv + 1] = ai;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        ar = 0;
+        ai = 0;
+        for (int w = 0; w < (G >> 6); ++w) {
+          ar += red[2 * (wv + w)];
+          ai += red[2 * (wv + w) + 1];
+        }
+      }
+      __syncthreads();
+    }
+    if (valid && lane == 0) {
+      C o;
+      o.x = ar;
+      o.y = ai;
+      z[e] = o;
+    }
+  }
+}
+
+// One step over the whole device; blockIdx.y = slice copy (stride 0 for shared tensors).
 template <typename T>
 __global__ void __launch_bounds__(256)
     tn_direct_kernel(const DevTnStep* __restrict__ st, const typename Cx<T>::type* __restrict__ X, int64_t xs,
                      const typename Cx<T>::type* __restrict__ Y, int64_t ys, typename Cx<T>::type* __restrict__ Z,
-                     int64_t zs) {
-  using C = typename Cx<T>::type;
-  __shared__ int64_t tx[4096], ty[4096];
-  const int zr = st->zr, ks = st->ks;
-  const int kt = ks < 12 ? ks : 12;  // table bits
-  const int nt = 1 << kt;
-  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-    tx[i] = deposit_bits((uint64_t)i, st->xs, kt);
-    ty[i] = deposit_bits((uint64_t)i, st->ys, kt);
-  }
+                     int64_t zs, int tb) {
+  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
+  __shared__ T red[16];
+  tn_build_tables<T>(st, tx, ty);
   __syncthreads();
-  const C* x = X + xs * blockIdx.y;
-  const C* y = Y + ys * blockIdx.y;
-  C* z = Z + zs * blockIdx.y;
-  const int64_t nz = int64_t(1) << zr;
-  const int64_t nouter = int64_t(1) << (ks - kt);
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nz; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t xb = deposit_bits((uint64_t)e, st->xo, zr);
-    const int64_t yb = deposit_bits((uint64_t)e, st->yo, zr);
-    T ar = 0, ai = 0;
-    for (int64_t so = 0; so < nouter; ++so) {
-      const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
-      const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
-      for (int s = 0; s < nt; ++s) {
-        const C a = x[xo2 + tx[s]], b = y[yo2 + ty[s]];
-        ar += a.x * b.x - a.y * b.y;
-        ai += a.x * b.y + a.y * b.x;
-      }
-    }
-    C r;
-    r.x = ar;
-    r.y = ai;
-    z[e] = r;
+  tn_step_outputs<T>(st, tx, ty, X + xs * blockIdx.y, Y + ys * blockIdx.y, Z + zs * blockIdx.y, tb, blockIdx.x,
+                     gridDim.x, red);
+}
+
+// A run of small steps in one launch: one work-group per slice copy executes the steps in
+// order, with a barrier between steps (each step reads tensors the earlier ones wrote).
+struct DevFused {
+  int32_t step;   // index in the plan's step table
+  int32_t flags;  // bit 0: X from the leaf buffer, bit 1: Y from the leaf buffer
+  int64_t xo, xs, yo, ys, zo, zs;  // complex-element offsets and per-copy strides
+};
+static_assert(sizeof(DevFused) == 56, "DevFused layout");
+
+// Steps run inside a fused run when their output has at most 2^12 elements and their work
+// (outputs x summed assignments) at most 2^16 complex products.
+constexpr int kTnFusedMaxOut = 12;
+constexpr int kTnFusedMaxWork = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_fused_kernel(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list, int n,
+                    const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
+  using C = typename Cx<T>::type;
+  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
+  __shared__ T red[16];
+  const int64_t c = blockIdx.x;
+  for (int k = 0; k < n; ++k) {
+    const DevFused f = list[k];
+    const DevTnStep* st = steps + f.step;
+    const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
+    const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
+    C* z = ws + f.zo + f.zs * c;
+    tn_build_tables<T>(st, tx, ty);
+    __syncthreads();
+    // enough lanes per output to give the 256 threads work: 2^tb with tb = 8 - zr, capped
+    // by the summed bits and at 8
+    int tb = 8 - st->zr;
+    tb = tb < 0 ? 0 : tb;
+    tb = tb > st->ks ? st->ks : tb;
+    tn_step_outputs<T>(st, tx, ty, x, y, z, tb, 0, 1, red);
+    __syncthreads();
   }
+}
+
+// Leaf environments -> gradient buffer: row i of the table is (leaf offset, environment
+// offset, elements); out[leaf + j] += sum over the G copies of env[j] (copies in order).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_leaf_env_kernel(const int64_t* __restrict__ tab, const typename Cx<T>::type* __restrict__ ws, int G,
+                       typename Cx<T>::type* __restrict__ grad) {
+  using C = typename Cx<T>::type;
+  const int64_t lo = tab[3 * blockIdx.x], eo = tab[3 * blockIdx.x + 1], n = tab[3 * blockIdx.x + 2];
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+    C v = grad[lo + j];
+    for (int g = 0; g < G; ++g) {
+      const C e = ws[eo + n * g + j];
+      v.x += e.x;
+      v.y += e.y;
+    }
+    grad[lo + j] = v;
+  }
+}
+
+// The upstream value as the result's environment, one copy per slice of the group.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_broadcast_kernel(const typename Cx<T>::type* __restrict__ in, typename Cx<T>::type* __restrict__ out,
+                        int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    out[n * blockIdx.y + j] = in[j];
 }
 
 // Bit permutation: out[j] = in[i(j)], out bit q taken from in bit perm[q].
@@ -457,7 +593,7 @@ static TnExec make_exec(const std::vector<int>& xi, const std::vector<int>& yi, 
 }  // namespace tq
 
 tq_tn_plan::~tq_tn_plan() {
-  void* p[] = {d_fwd, d_bwd, d_perm, d_bperm, d_gather};
+  void* p[] = {d_fwd, d_bwd, d_perm, d_bperm, d_gather, d_ffused, d_bfused, d_leaf_env};
   for (void* x : p)
     if (x) (void)hipFree(x);
 }
@@ -655,6 +791,91 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     }
     gt.insert(gt.end(), row.begin(), row.end());
   }
+  // execution segments (the workspace layout is final here)
+  std::vector<DevFused> ff, bf;
+  {
+    auto small = [](const TnExec& ex) {
+      return ex.method == 0 && ex.dev.zr <= kTnFusedMaxOut && ex.dev.zr + ex.dev.ks <= kTnFusedMaxWork;
+    };
+    auto operand = [&](int id, int64_t* o, int64_t* st, bool* leaf) {
+      const TnTensorInfo& t = p->t[id];
+      if (t.leaf >= 0 && !t.sdep) {
+        *o = p->leaf_off[t.leaf];
+        *st = 0;
+        *leaf = true;
+      } else {
+        *o = t.off;
+        *st = t.sdep ? (int64_t(1) << t.rank) : 0;
+        *leaf = false;
+      }
+    };
+    for (size_t k = 0; k < p->fwd.size(); ++k) {
+      const TnExec& ex = p->fwd[k];
+      const int shared = p->t[ex.z].sdep ? 0 : 1;
+      if (small(ex)) {
+        if (p->fseg.empty() || !p->fseg.back().fused || p->fseg.back().shared != shared) {
+          tq_tn_plan::Seg sg;
+          sg.fused = 1;
+          sg.first = (int)k;
+          sg.list = (int64_t)ff.size();
+          sg.shared = shared;
+          p->fseg.push_back(sg);
+        }
+        p->fseg.back().count++;
+        DevFused f{};
+        bool lx, ly, lz;
+        f.step = (int32_t)k;
+        operand(ex.x, &f.xo, &f.xs, &lx);
+        operand(ex.y, &f.yo, &f.ys, &ly);
+        operand(ex.z, &f.zo, &f.zs, &lz);
+        f.flags = (lx ? 1 : 0) | (ly ? 2 : 0);
+        ff.push_back(f);
+      } else {
+        tq_tn_plan::Seg sg;
+        sg.first = (int)k;
+        sg.count = 1;
+        sg.shared = shared;
+        p->fseg.push_back(sg);
+      }
+    }
+    for (size_t k = 0; k < p->bwd.size(); ++k) {
+      const TnExec& ex = p->bwd[k];
+      if (small(ex)) {
+        if (p->bseg.empty() || !p->bseg.back().fused) {
+          tq_tn_plan::Seg sg;
+          sg.fused = 1;
+          sg.first = (int)k;
+          sg.list = (int64_t)bf.size();
+          p->bseg.push_back(sg);
+        }
+        p->bseg.back().count++;
+        DevFused f{};
+        bool ly;
+        f.step = (int32_t)k;
+        f.xo = p->env_off[ex.x];
+        f.xs = int64_t(1) << p->t[ex.x].rank;
+        operand(ex.y, &f.yo, &f.ys, &ly);
+        f.zo = p->env_off[ex.z];
+        f.zs = int64_t(1) << p->t[ex.z].rank;
+        f.flags = ly ? 2 : 0;
+        bf.push_back(f);
+      } else {
+        tq_tn_plan::Seg sg;
+        sg.first = (int)k;
+        sg.count = 1;
+        p->bseg.push_back(sg);
+      }
+    }
+  }
+  std::vector<int64_t> le;
+  for (int l = 0; l < L; ++l) {
+    const TnTensorInfo& t = p->t[l];
+    if (t.sdep) continue;
+    le.push_back(p->leaf_off[l]);
+    le.push_back(p->env_off[l]);
+    le.push_back(int64_t(1) << t.rank);
+  }
+  p->n_leaf_env = (int)(le.size() / 3);
   // device copies of the step tables
   {
     std::vector<DevTnStep> fs, bs;
@@ -677,6 +898,9 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     TQ_TRY(up(bs.data(), bs.size() * sizeof(DevTnStep), &p->d_bwd));
     TQ_TRY(up(pt.data(), pt.size(), &p->d_perm));
     TQ_TRY(up(gt.data(), gt.size(), &p->d_gather));
+    TQ_TRY(up(ff.data(), ff.size() * sizeof(DevFused), &p->d_ffused));
+    TQ_TRY(up(bf.data(), bf.size() * sizeof(DevFused), &p->d_bfused));
+    TQ_TRY(up(le.data(), le.size() * sizeof(int64_t), &p->d_leaf_env));
   }
   *out = p.release();
   return TQ_OK;
@@ -748,16 +972,32 @@ struct TnRun {
   int64_t esz(int i) const { return int64_t(1) << p->t[i].rank; }
 };
 
+// One large direct step over the device: 2^tb lanes per output, enough lanes in total
+// (about 2^16) to fill the machine, at most 256 per output.
 template <typename T>
-static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const typename Cx<T>::type* x, int64_t xs,
-                           const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs, int zr,
+static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep& h, const typename Cx<T>::type* x,
+                           int64_t xs, const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs,
                            int64_t copies) {
-  const int64_t nz = int64_t(1) << zr;
+  const int zr = h.zr, ks = h.ks;
+  int tb = std::max(0, 16 - zr);
+  tb = std::min(tb, std::min(8, ks));
+  const int64_t gpb = 256 >> tb;
+  const int64_t rounds = ((int64_t(1) << zr) + gpb - 1) / gpb;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
   for (int64_t c0 = 0; c0 < copies; c0 += 65535) {
     const int64_t cn = std::min<int64_t>(65535, copies - c0);
-    hipLaunchKernelGGL(tn_direct_kernel<T>, dim3(grid_for(nz), (unsigned)cn), dim3(256), 0, R.st, dstep, x + xs * c0,
-                       xs, y + ys * c0, ys, z + zs * c0, zs);
+    hipLaunchKernelGGL(tn_direct_kernel<T>, dim3(blocks, (unsigned)cn), dim3(256), 0, R.st, dstep, x + xs * c0, xs,
+                       y + ys * c0, ys, z + zs * c0, zs, tb);
   }
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+// A run of small steps: one work-group per slice copy (grid x; copies <= 2^24).
+template <typename T>
+static tq_status tn_fused(TnRun<T>& R, const DevTnStep* steps, const void* list, int n, int64_t copies) {
+  hipLaunchKernelGGL(tn_fused_kernel<T>, dim3((unsigned)copies), dim3(256), 0, R.st, steps, (const DevFused*)list, n,
+                     R.leaves, R.ws);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -776,7 +1016,13 @@ static tq_status tn_forward_group(TnRun<T>& R) {
                        tab + 2 * kTnMaxBits, (int)t.sliced_pos.size(), R.s0);
     TQ_HIP(hipGetLastError());
   }
-  for (size_t s = 0; s < p->fwd.size(); ++s) {
+  for (const tq_tn_plan::Seg& sg : p->fseg) {
+    if (sg.fused) {
+      TQ_TRY(tn_fused<T>(R, (const DevTnStep*)p->d_fwd, (const DevFused*)p->d_ffused + sg.list, sg.count,
+                         sg.shared ? 1 : R.g));
+      continue;
+    }
+    const size_t s = (size_t)sg.first;
     const TnExec& ex = p->fwd[s];
     int64_t xs, ys, zs;
     const C* x = R.tptr(ex.x, &xs);
@@ -819,7 +1065,7 @@ static tq_status tn_forward_group(TnRun<T>& R) {
         continue;
       }
     }
-    TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_fwd + s, x, xs, y, ys, z, zs, p->t[ex.z].rank, copies));
+    TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_fwd + s, ex.dev, x, xs, y, ys, z, zs, copies));
   }
   return TQ_OK;
 }
@@ -874,31 +1120,34 @@ static tq_status tn_backward_t(tq_ctx* ctx, const tq_tn_plan* p, const void* d_l
     R.g = std::min<int64_t>(p->G, p->n_slices - s0);
     TQ_TRY(tn_forward_group<T>(R));
     // environment of the result: the upstream value, one copy per slice
-    for (int64_t c = 0; c < R.g; ++c) {
-      hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(nout)), dim3(256), 0, stream, (const C*)d_grad_out, 0,
-                         1, R.eptr(p->root) + c * nout, nout, 0);
-    }
+    hipLaunchKernelGGL(tn_broadcast_kernel<T>, dim3(grid_for(nout), (unsigned)R.g), dim3(256), 0, stream,
+                       (const C*)d_grad_out, R.eptr(p->root), nout);
     TQ_HIP(hipGetLastError());
-    for (size_t k = 0; k < p->bwd.size(); ++k) {
+    for (const tq_tn_plan::Seg& sg : p->bseg) {
+      if (sg.fused) {
+        TQ_TRY(tn_fused<T>(R, (const DevTnStep*)p->d_bwd, (const DevFused*)p->d_bfused + sg.list, sg.count, R.g));
+        continue;
+      }
+      const size_t k = (size_t)sg.first;
       const TnExec& ex = p->bwd[k];
       int64_t ys;
       const C* y = R.tptr(ex.y, &ys);
-      TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_bwd + k, R.eptr(ex.x), R.esz(ex.x), y, ys, R.eptr(ex.z),
-                          R.esz(ex.z), p->t[ex.z].rank, R.g));
+      TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_bwd + k, ex.dev, R.eptr(ex.x), R.esz(ex.x), y, ys, R.eptr(ex.z),
+                          R.esz(ex.z), R.g));
     }
     // leaf environments -> gradient buffer (sum over the group's slices, in order)
-    for (int l = 0; l < p->n_leaves; ++l) {
-      const TnTensorInfo& t = p->t[l];
+    if (p->n_leaf_env > 0) {
+      hipLaunchKernelGGL(tn_leaf_env_kernel<T>, dim3((unsigned)p->n_leaf_env), dim3(256), 0, stream,
+                         (const int64_t*)p->d_leaf_env, (const C*)R.ws, (int)R.g, grad);
+      TQ_HIP(hipGetLastError());
+    }
+    for (int li : p->sliced_leaves) {
+      const TnTensorInfo& t = p->t[li];
       const int64_t n = int64_t(1) << t.rank;
-      if (t.sdep) {
-        const uint8_t* tab = (const uint8_t*)p->d_gather + (size_t)t.gather * 3 * kTnMaxBits;
-        hipLaunchKernelGGL(tn_slice_scatter_kernel<T>, dim3(grid_for(n)), dim3(256), 0, stream, R.eptr(l), n,
-                           (int)R.g, grad + p->leaf_off[l], t.rank, tab, tab + kTnMaxBits, tab + 2 * kTnMaxBits,
-                           (int)t.sliced_pos.size(), s0);
-      } else {
-        hipLaunchKernelGGL(tn_sum_copies_kernel<T>, dim3(grid_for(n)), dim3(256), 0, stream, R.eptr(l), n, (int)R.g,
-                           grad + p->leaf_off[l], n, 1);
-      }
+      const uint8_t* tab = (const uint8_t*)p->d_gather + (size_t)t.gather * 3 * kTnMaxBits;
+      hipLaunchKernelGGL(tn_slice_scatter_kernel<T>, dim3(grid_for(n)), dim3(256), 0, stream, R.eptr(li), n,
+                         (int)R.g, grad + p->leaf_off[t.leaf], t.rank, tab, tab + kTnMaxBits, tab + 2 * kTnMaxBits,
+                         (int)t.sliced_pos.size(), s0);
     }
     TQ_HIP(hipGetLastError());
   }

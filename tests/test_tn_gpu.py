@@ -149,3 +149,57 @@ def test_plan_validation():
         lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], sliced=[7])  # sliced index in no leaf
     with pytest.raises(lib.TQError):
         lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], out_inds=[5])  # no tensor carries index 5
+
+
+@pytest.mark.parametrize("c128", [False, True])
+@pytest.mark.parametrize("case", ["scalar18", "out14"])
+def test_wide_direct_steps(case, c128):
+    """Large steps on the generic kernel: a scalar from 18 summed indices (256 lanes per
+    output, reduced through LDS) and a 14-index output with 4 summed indices; values and
+    the reverse pass against einsum."""
+    from paper_2301_05451_amd import lib
+
+    if case == "scalar18":
+        inds, outi = [list(range(18)), list(range(18))], []
+    else:
+        inds, outi = [list(range(16)), list(range(12, 18))], list(range(12)) + [16, 17]
+    rs = np.random.default_rng(8)
+    ra, rb = len(inds[0]), len(inds[1])
+    A = rs.normal(size=2 ** ra) + 1j * rs.normal(size=2 ** ra)
+    B = rs.normal(size=2 ** rb) + 1j * rs.normal(size=2 ** rb)
+    cdt = torch.complex128 if c128 else torch.complex64
+    plan = lib.TnPlan(inds, [(0, 1)], out_inds=outi, c128=c128)
+    assert plan.info["gemm_steps"] == 0
+    leaves = torch.tensor(np.concatenate([A, B]), dtype=cdt, device="cuda")
+    v = lib.tn_contract(plan, leaves).cpu().numpy()
+    want = np.einsum(A.reshape((2,) * ra), inds[0], B.reshape((2,) * rb), inds[1], outi).reshape(-1)
+    tol = 1e-12 if c128 else 1e-5
+    assert np.abs(v - want).max() <= tol * np.abs(want).max()
+    g = np.ones(1) if not outi else rs.normal(size=v.size)
+    env = lib.tn_backward(plan, leaves, torch.tensor(g, dtype=cdt, device="cuda")).cpu().numpy()
+    envA = np.einsum(g.reshape((2,) * len(outi)) if outi else np.array(1.0), outi, B.reshape((2,) * rb), inds[1],
+                     inds[0]).reshape(-1)
+    assert np.abs(env[:2 ** ra] - envA).max() <= tol * np.abs(envA).max()
+
+
+def test_qaoa50_p4_narrowest_edge_sliced_vs_unsliced():
+    """p = 4 on the 50-node graph: the edge whose min-fill tree is narrowest (a 33-qubit
+    light cone, width 20 at this seed; too large for the oracle's state vector): the value
+    unsliced and with the same tree sliced (Sec. 3.2.3: the sum over slices is the value),
+    real to float32 precision and within [-1, 1]."""
+    prob = W.qaoa_maxcut(p=4)
+    best = None
+    for e in prob.edges:
+        net, cone = tn.qaoa_edge_network(prob, e)
+        tr = tn.elimination_tree(net, tn.elimination_order(net, None, "fill")[0])
+        if best is None or tr.max_rank < best[2].max_rank:
+            best = (e, net, tr, cone)
+    e, net, tr, cone = best
+    print(f"p4 edge {e} cone {len(cone)} width {tr.max_rank}", flush=True)
+    p = _params(net, False)
+    v1 = tn.TNProgram(net, tr).value(p).cpu().numpy()[0]
+    tr2 = tn.slice_tree(net, tr, tr.max_rank - 3)
+    assert len(tr2.sliced) >= 1
+    v2 = tn.TNProgram(net, tr2).value(p).cpu().numpy()[0]
+    assert abs(v1.imag) <= 1e-5 and abs(v1 - v2) <= 2e-5
+    assert abs(v1.real) <= 1.0 + 1e-5
