@@ -56,6 +56,27 @@ def cpu_baseline(c, seconds_hint=True):
                       f"{dt:.1f} s on {cpu_model()} (numpy tensordot per gate)"}
 
 
+def measured_traffic():
+    """HBM bytes per stage-kernel launch from the committed rocprofv3 counter summary, if
+    the kernel sources still hash to what was profiled (else None: the counters are stale)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "sv_stage_brickwork24_c64_hbm_counters.txt")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "source_")))
+    srcs = ["paper_2301_05451_amd/csrc/sv_kernels.hip", "paper_2301_05451_amd/csrc/sv_device.h",
+            "paper_2301_05451_amd/csrc/schedule.hip", "paper_2301_05451_amd/csrc/tq_internal.h"]
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def _timed(fn, steps, warmup):
     """Mean milliseconds of fn() over `steps` calls after `warmup` calls (HIP events on the
     current stream, which every libtq call here is launched on)."""
@@ -263,9 +284,9 @@ def bench_tn(steps):
 
 def bench_costmodel():
     """Learned tree ranking: the cost-model MLP is trained on the GPU from measured times
-    (value + gradient) of candidate trees of QAOA light-cone networks on other seeded graphs
-    (30 nodes, p = 2 and 3), then picks one tree per edge network of the 50-node p = 3
-    workload; its picks are timed against the fewest-FLOPs picks."""
+    (value + gradient) of candidate trees of QAOA p = 3 light-cone networks on three other
+    seeded 50-node 3-regular graphs, then picks one tree per edge network of the workload
+    graph; its picks are timed against the fewest-FLOPs picks."""
     import numpy as np
     import torch
 
@@ -273,22 +294,24 @@ def bench_costmodel():
     from paper_2301_05451_amd import workloads as W
 
     t0 = time.perf_counter()
-    feats, ys = [], []
+    groups = []
     for seed in (2001, 2002, 2003):
-        for p in (2, 3):
-            r = np.random.default_rng(seed)
-            edges = W.random_regular_graph(3, 30, r)
-            prob = W.QAOAProblem(30, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
-            for e in edges[:5]:
-                net, _ = tn.qaoa_edge_network(prob, e)
-                pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
-                for tree, prog, f in costmodel.candidates_with_plans(net, n_random=5, seed=seed):
-                    feats.append(f)
-                    ys.append(math.log(costmodel.time_program(prog, pt, reps=2)))
+        p = 3
+        r = np.random.default_rng(seed)
+        edges = W.random_regular_graph(3, 50, r)
+        prob = W.QAOAProblem(50, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
+        for e in edges[:10]:
+            net, _ = tn.qaoa_edge_network(prob, e)
+            pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
+            fs, ts = [], []
+            for tree, prog, f in costmodel.candidates_with_plans(net, n_random=5, seed=seed):
+                fs.append(f)
+                ts.append(math.log(costmodel.time_program(prog, pt, reps=3)))
+            groups.append((np.array(fs), np.array(ts)))
     collect_s = time.perf_counter() - t0
     cm = costmodel.CostModel(seed=0)
     t1 = time.perf_counter()
-    hist = cm.fit(np.array(feats), np.array(ys), epochs=800, lr=3e-3)
+    hist = cm.fit_groups(groups, epochs=800, lr=3e-3)
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t1
     prob = W.qaoa_maxcut(p=3)
@@ -305,7 +328,8 @@ def bench_costmodel():
         t_flop += tf
         t_mlp += tm
     return {"workload": "75 light-cone networks of QAOA p=3 on the 50-node 3-regular graph, 8 candidate trees each",
-            "train_samples": len(ys), "collect_s": round(collect_s, 1), "fit_s": round(fit_s, 2),
+            "train_samples": int(sum(len(t) for _, t in groups)), "collect_s": round(collect_s, 1),
+            "fit_s": round(fit_s, 2),
             "train_mse_first_last": [hist[0], hist[-1]],
             "ms_flop_ranked": round(t_flop, 2), "ms_mlp_ranked": round(t_mlp, 2),
             "learned_gain": round(t_flop / t_mlp, 3), "same_pick": same}
@@ -322,6 +346,9 @@ def main():
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the QNN batch, uneven batch and tensor-network measurements")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="calibration only: 10 device-to-device copies of this many bytes (the known "
+                         "traffic that scales the HBM byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -333,6 +360,15 @@ def main():
 
     from paper_2301_05451_amd import lib
     from paper_2301_05451_amd import workloads as W
+
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 10}), flush=True)
+        return
 
     c = W.brickwork()
     n, G = c.n, c.gates.shape[0]
@@ -381,12 +417,14 @@ def main():
     t_alu = flops_per_stage / (ALU_PEAK_TFLOPS * 1e12)
     if t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
+                "algorithmic_bytes": bytes_per_stage,
                 "peak_published_fp32_vector": ALU_PEAK_PUBLISHED_TFLOPS,
                 "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "algorithmic_bytes": bytes_per_stage}
     roof.update({"kernel": "sv_stage_kernel<float,%d>" % info["reg_bits"], "launches_per_step": stages,
                  "avg_launch_us": round(stage_ms * 1e3, 2)})
 

@@ -16,7 +16,9 @@ Features (16 per tree, all computed on the host):
   5  largest rank (width)
   6  steps on the MFMA GEMM path (plan)
   7  log2(1 + FLOPs on the GEMM path)
-Target: natural log of the measured time in milliseconds.
+Target: natural log of the measured time in milliseconds, centred per network (the model
+ranks the candidates of one network), and only candidates within a small factor of the
+fewest FLOPs are re-ranked.
 """
 from __future__ import annotations
 
@@ -136,6 +138,19 @@ class CostModel:
         y = self.lib.mlp_forward(SIZES, self.params, self._x(feats))
         return y.cpu().numpy().astype(np.float64) + self.y_mu
 
+    def fit_groups(self, groups, epochs=800, lr=3e-3):
+        """Ranking within a network is what matters: ``groups`` is a list of (features [k, F],
+        log ms [k]) per network, and the model learns the differences from each network's
+        mean (features and targets both centred per network)."""
+        F = np.concatenate([np.asarray(f) - np.mean(f, 0) for f, _ in groups])
+        y = np.concatenate([np.asarray(t) - np.mean(t) for _, t in groups])
+        return self.fit(F, y, epochs=epochs, lr=lr)
+
+    def predict_relative(self, feats):
+        """Predicted log-time differences from the mean of these candidates (one network)."""
+        f = np.asarray(feats, dtype=np.float64)
+        return self.predict_log_ms(f - f.mean(0))
+
 
 def candidates_with_plans(net, n_random=5, seed=0, target_rank=26):
     """Candidate trees of a network with their libtq plans and features."""
@@ -146,8 +161,13 @@ def candidates_with_plans(net, n_random=5, seed=0, target_rank=26):
     return out
 
 
-def pick(cands, model=None):
-    """Index of the candidate with the fewest FLOPs (model None) or the lowest predicted time."""
+def pick(cands, model=None, trust=4.0):
+    """Index of the candidate with the fewest FLOPs (model None), or of the lowest predicted
+    time among the candidates within ``trust`` times the fewest FLOPs (the model re-ranks
+    near-optimal trees; it is not asked to extrapolate to far costlier ones)."""
+    fl = np.array([t.flops for t, _, _ in cands], dtype=np.float64)
     if model is None:
-        return int(np.argmin([t.flops for t, _, _ in cands]))
-    return int(np.argmin(model.predict_log_ms([f for _, _, f in cands])))
+        return int(np.argmin(fl))
+    ok = np.nonzero(fl <= trust * fl.min())[0]
+    score = model.predict_relative([cands[i][2] for i in range(len(cands))])
+    return int(ok[np.argmin(score[ok])])
