@@ -344,6 +344,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1, help="steps of the one-sweep-per-gate path")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--reg-bits", type=int, default=0)
+    ap.add_argument("--coal-bits", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the QNN batch, uneven batch and tensor-network measurements")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -375,7 +376,7 @@ def main():
     spec = lib.BatchSpec.uniform(n, c.gates, 1, c.n_params)
     params = torch.tensor(c.params, dtype=torch.float32, device="cuda")
     psi = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
-    opts = dict(tile_bits=args.tile_bits, reg_bits=args.reg_bits)
+    opts = dict(tile_bits=args.tile_bits, reg_bits=args.reg_bits, coal_bits=args.coal_bits)
     info = lib.plan_info(n, c.gates, mode=0, **opts)
 
     def step():
@@ -418,7 +419,7 @@ def main():
     if t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
-                "algorithmic_bytes": bytes_per_stage,
+                "algorithmic_bytes": bytes_per_stage, "algorithmic_flops": flops_per_stage,
                 "peak_published_fp32_vector": ALU_PEAK_PUBLISHED_TFLOPS,
                 "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
@@ -456,7 +457,9 @@ def main():
         "config": {"workload": "24-qubit brickwork state-vector circuit: 20 layers of RX,RY,RZ on all qubits "
                                "+ CZ on alternating neighbour pairs (1670 gates), complex64, sum_i Z_i, batch 1",
                    "qubits": n, "gates": G, "fused_sweeps": stages, "tile_bits": info["tile_bits"],
-                   "reg_bits": info["reg_bits"]},
+                   "reg_bits": info["reg_bits"], "coal_bits": args.coal_bits or None,
+                   "flops_per_amp": info["flops_per_amp"], "phases": info["phases"],
+                   "exchanges": info["exchanges"]},
         "roofline": roof,
         "expval_sum_z": float(f[0, 0]),
         "plain": plain,

@@ -96,9 +96,9 @@ typedef struct {
  *   mode:      0 = fused (gates grouped into LDS-tile stages, one HBM sweep per stage),
  *              1 = plain (one HBM sweep per gate). Batches of circuits of uneven size and
  *              structure run best as a compiled batch (tq_svb_*, below).
- *   tile_bits: local qubits per fused tile (0 = default: 13 for TQ_C64, 12 for TQ_C128), 1..14.
+ *   tile_bits: local qubits per fused tile (0 = default 12), 1..14.
  *   reg_bits:  amplitude-index bits held in registers per thread, 1..5 (0 = default 4).
- *   coal_bits: low index bits always kept local for coalesced HBM access (0 = default). */
+ *   coal_bits: low index bits always kept local for coalesced HBM access (0 = default 4). */
 typedef struct {
   int32_t mode;
   int32_t tile_bits;

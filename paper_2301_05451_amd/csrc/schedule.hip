@@ -254,13 +254,25 @@ void build_stages(Schedule& s) {
         DevOp d{};
         d.kind = (uint8_t)o.kind;
         d.mat = o.mat;
+        // register index of a qubit in this phase, or -1 (thread or tile bit)
+        auto reg_of = [&](int q) {
+          const int lp = loc_of_q[q];
+          if (lp < 0) return -1;
+          const auto it = std::find(rv.begin(), rv.end(), lp);
+          return it == rv.end() ? -1 : (int)(it - rv.begin());
+        };
         if (o.kind == K_MAT1 || o.kind == K_CX) {
-          int lp = loc_of_q[o.qa];
-          d.rbit = (uint8_t)(std::find(rv.begin(), rv.end(), lp) - rv.begin());
-          if (o.kind == K_CX) d.pa = (uint8_t)xpos(o.qb);
+          d.rbit = (uint8_t)reg_of(o.qa);
+          if (o.kind == K_CX) {
+            d.pa = (uint8_t)xpos(o.qb);
+            d.pb = (uint8_t)(reg_of(o.qb) + 1);  // control's register index + 1 (0: not a register bit)
+          }
         } else {
           d.pa = (uint8_t)xpos(o.qa);
           d.pb = o.qb >= 0 ? (uint8_t)xpos(o.qb) : 0;
+          // register indices + 1 of both operands (0: not a register bit), low and high nibble
+          const int ka = reg_of(o.qa), kb = o.qb >= 0 ? reg_of(o.qb) : -1;
+          d.rbit = (uint8_t)((ka + 1) | ((kb + 1) << 4));
         }
         s.dops.push_back(d);
       }

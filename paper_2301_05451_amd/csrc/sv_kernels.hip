@@ -175,67 +175,104 @@ __device__ __forceinline__ void reg_mat(typename Cx<T>::type (&v)[1 << R], typen
   }
 }
 
+// Bit `pos` of the tile-local index of this thread's amplitudes when it is not a register
+// bit: a thread bit (tp holds the thread bits at their local positions) or a tile bit.
+__device__ __forceinline__ uint32_t idx_bit(int pos, uint32_t tp, int t, uint32_t tile) {
+  return pos < t ? ((tp >> pos) & 1u) : ((tile >> (pos - t)) & 1u);
+}
+
+__device__ __forceinline__ float flip_sign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
+__device__ __forceinline__ double flip_sign(double x, uint32_t s) {
+  return __longlong_as_double(__double_as_longlong(x) ^ ((long long)s << 32));
+}
+
+// Masks over the register index j (bit j set when bit k of j is 1), for register bit k.
+__device__ __forceinline__ uint32_t reg_mask(int k) {
+  // a select chain (a table indexed at run time would live in scratch memory)
+  return k == 0 ? 0xAAAAAAAAu
+       : k == 1 ? 0xCCCCCCCCu
+       : k == 2 ? 0xF0F0F0F0u
+       : k == 3 ? 0xFF00FF00u
+       : k == 4 ? 0xFFFF0000u
+                : 0xFFFFFFFFu;
+}
+
+// CX with the target on register bit B: the pairs with (mc >> j) & 1 are swapped where the
+// per-thread flag cb is set. A register control gives a uniform mc and cb = 1; a thread or
+// tile control gives mc = all and a per-thread cb.
 template <typename T, int R, int B>
-__device__ __forceinline__ void reg_cx(typename Cx<T>::type (&v)[1 << R], const uint32_t (&li)[1 << R],
-                                       int pc, int t, uint32_t tile) {
+__device__ __forceinline__ void reg_cx(typename Cx<T>::type (&v)[1 << R], uint32_t mc, uint32_t cb) {
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     if (j & (1 << B)) continue;
     const int j1 = j | (1 << B);
-    const uint32_t cb = pc < t ? ((li[j] >> pc) & 1u) : ((tile >> (pc - t)) & 1u);
-    auto a = v[j], b = v[j1];
-    v[j] = cb ? b : a;
-    v[j1] = cb ? a : b;
+    if ((mc >> j) & 1u) {
+      auto a = v[j], b = v[j1];
+      v[j].x = cb ? b.x : a.x;
+      v[j].y = cb ? b.y : a.y;
+      v[j1].x = cb ? a.x : b.x;
+      v[j1].y = cb ? a.y : b.y;
+    }
   }
 }
 
-template <typename T, int R, typename F>
-__device__ __forceinline__ void dispatch_bit(int b, F&& f) {
-  switch (b) {
-    case 0: if constexpr (R > 0) f(std::integral_constant<int, 0>{}); break;
-    case 1: if constexpr (R > 1) f(std::integral_constant<int, 1>{}); break;
-    case 2: if constexpr (R > 2) f(std::integral_constant<int, 2>{}); break;
-    case 3: if constexpr (R > 3) f(std::integral_constant<int, 3>{}); break;
-    case 4: if constexpr (R > 4) f(std::integral_constant<int, 4>{}); break;
-    case 5: if constexpr (R > 5) f(std::integral_constant<int, 5>{}); break;
-    default: break;
+// CZ: amplitudes with (m >> j) & 1 (register operands both 1) get the per-thread sign s (the
+// product of the non-register operand bits).
+template <typename T, int R>
+__device__ __forceinline__ void reg_cz(typename Cx<T>::type (&v)[1 << R], uint32_t m, uint32_t s) {
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    if ((m >> j) & 1u) {
+      v[j].x = flip_sign(v[j].x, s);
+      v[j].y = flip_sign(v[j].y, s);
+    }
   }
 }
 
 template <typename T, int R>
 __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], const uint32_t (&li)[1 << R],
+                                                uint32_t tp,
                                                 const DevOp* __restrict__ ops, int ob, int oe,
                                                 const typename Cx<T>::type* __restrict__ M, int t,
                                                 uint32_t tile) {
   using C = typename Cx<T>::type;
   for (int o = ob; o < oe; ++o) {
     const DevOp op = load_op(ops, o);
-    if (op.kind == K_MAT1) {
+    C m0{}, m1{}, m2{}, m3{};
+    if (op.mat >= 0) {
       const C* m = M + 4 * (int64_t)op.mat;
-      const C m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+      m0 = m[0]; m1 = m[1]; m2 = m[2]; m3 = m[3];
+    }
+    if (op.kind == K_MAT1) {
+      // every path applies the gate (register bits >= R never occur; they fall to the top
+      // bit), so the tile is updated in place on all branches
 #define TQ_MAT_CASE(B) \
   case B:              \
-    if constexpr (R > B) reg_mat<T, R, (R > B ? B : 0)>(v, m0, m1, m2, m3); \
+    reg_mat<T, R, (R > B ? B : R - 1)>(v, m0, m1, m2, m3); \
     break;
-      switch (op.rbit) { TQ_MAT_CASE(0) TQ_MAT_CASE(1) TQ_MAT_CASE(2) TQ_MAT_CASE(3) TQ_MAT_CASE(4) default: break; }
+      switch (op.rbit) { TQ_MAT_CASE(0) TQ_MAT_CASE(1) TQ_MAT_CASE(2) TQ_MAT_CASE(3)
+        default: reg_mat<T, R, (R > 4 ? 4 : R - 1)>(v, m0, m1, m2, m3); break; }
 #undef TQ_MAT_CASE
     } else if (op.kind == K_CX) {
+      const int kc = (int)op.pb - 1;
+      const uint32_t cb = kc < 0 ? idx_bit(op.pa, tp, t, tile) : 1u;
+      const uint32_t mc = reg_mask(kc);
 #define TQ_CX_CASE(B) \
   case B:             \
-    if constexpr (R > B) reg_cx<T, R, (R > B ? B : 0)>(v, li, op.pa, t, tile); \
+    reg_cx<T, R, (R > B ? B : R - 1)>(v, mc, cb); \
     break;
-      switch (op.rbit) { TQ_CX_CASE(0) TQ_CX_CASE(1) TQ_CX_CASE(2) TQ_CX_CASE(3) TQ_CX_CASE(4) default: break; }
+      switch (op.rbit) { TQ_CX_CASE(0) TQ_CX_CASE(1) TQ_CX_CASE(2) TQ_CX_CASE(3)
+        default: reg_cx<T, R, (R > 4 ? 4 : R - 1)>(v, mc, cb); break; }
 #undef TQ_CX_CASE
     } else if (op.kind == K_CZ) {
-#pragma unroll
-      for (int j = 0; j < (1 << R); ++j) {
-        uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
-        uint32_t bb = op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u);
-        if (ba & bb) { v[j].x = -v[j].x; v[j].y = -v[j].y; }
-      }
+      const int ka = (op.rbit & 15) - 1, kb = (op.rbit >> 4) - 1;
+      uint32_t f = 1u;
+      if (ka < 0) f &= idx_bit(op.pa, tp, t, tile);
+      if (kb < 0) f &= idx_bit(op.pb, tp, t, tile);
+      reg_cz<T, R>(v, reg_mask(ka) & reg_mask(kb), f << 31);
     } else {
-      const C* d = M + 4 * (int64_t)op.mat;
-      const C d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3];
+      // diagonal on one (entries d[bit a]) or two qubits (entries d[2 bit a + bit b])
+      const C d0 = m0, d1 = m1, d2 = m2, d3 = m3;
       const bool two = op.kind == K_DIAG2;
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
@@ -278,10 +315,12 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
     if (act) v[j] = sb[hi]; else v[j] = C{(T)0, (T)0};
   }
 
-  // local indices in the current layout (load layout: registers = top R local bits)
+  // local indices in the current layout (load layout: registers = top R local bits); tp is
+  // the thread's own bits at their local positions
   uint32_t li[1 << R];
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
+  uint32_t tp = tid & ((1u << tb) - 1u);
 
   bool first_x = true;
   for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
@@ -292,7 +331,7 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
       if (act)
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
-      uint32_t tp = 0;
+      tp = 0;
       for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
@@ -306,7 +345,7 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(li[j])];
     }
-    apply_phase_ops<T, R>(v, li, ops, ph.op_begin, ph.op_end, M, t, tile);
+    apply_phase_ops<T, R>(v, li, tp, ops, ph.op_begin, ph.op_end, M, t, tile);
   }
   if (stg->store_xchg) {
     if (!first_x) __syncthreads();

@@ -67,9 +67,10 @@ struct Recipe {
 // Device-side descriptors (plain structs, copied verbatim to device memory).
 struct DevOp {
   uint8_t kind;
-  uint8_t rbit;  // MAT1/CX: target's register-bit index within the phase
+  uint8_t rbit;  // MAT1/CX: target's register-bit index within the phase;
+                 // DIAG/CZ: (register index of qa + 1) | (register index of qb + 1) << 4, 0 = none
   uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX)
-  uint8_t pb;    // x-position of qb (DIAG2/CZ)
+  uint8_t pb;    // x-position of qb (DIAG2/CZ); CX: control's register index + 1 (0 = none)
   int32_t mat;
 };
 static_assert(sizeof(DevOp) == 8, "DevOp layout");
