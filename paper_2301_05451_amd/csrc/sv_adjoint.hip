@@ -94,7 +94,17 @@ __device__ __forceinline__ T wave_sum(T v, int lane, int active) {
   return v;
 }
 
-// One register-resident target bit B: psi <- U^dag psi, gradient terms, lam <- U^dag lam.
+// conj(x) * y accumulated into acc
+template <typename C>
+__device__ __forceinline__ void cconj_fma(C& acc, C x, C y) {
+  acc.x += x.x * y.x + x.y * y.y;
+  acc.y += x.x * y.y - x.y * y.x;
+}
+
+// One register-resident target bit B: psi <- U^dag psi, lam <- U^dag lam, and the gradient
+// terms Re <lam| dU_q psi> for the gate's angles q. Per thread, M[r][c] = sum over its pairs
+// of conj(lam_r) psi_c (psi after U^dag, lam before it) is accumulated once; each angle's term
+// is then Re sum_rc dU_q[r][c] M[r][c] (the derivative matrices never touch the amplitudes).
 template <typename T, int R, int B>
 __device__ __forceinline__ void adj_mat(typename Cx<T>::type (&vp)[1 << R], typename Cx<T>::type (&vl)[1 << R],
                                         const typename Cx<T>::type* __restrict__ m, int na, T (&acc)[3]) {
@@ -102,11 +112,7 @@ __device__ __forceinline__ void adj_mat(typename Cx<T>::type (&vp)[1 << R], type
   const C u00 = m[0], u01 = m[1], u10 = m[2], u11 = m[3];
   // U^dag = [[conj u00, conj u10], [conj u01, conj u11]]
   C h00{u00.x, -u00.y}, h01{u10.x, -u10.y}, h10{u01.x, -u01.y}, h11{u11.x, -u11.y};
-  C d[3][4];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[j][i] = j < na ? m[4 + 4 * j + i] : C{0, 0};
+  C M00{(T)0, (T)0}, M01{(T)0, (T)0}, M10{(T)0, (T)0}, M11{(T)0, (T)0};
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     if (j & (1 << B)) continue;
@@ -116,35 +122,63 @@ __device__ __forceinline__ void adj_mat(typename Cx<T>::type (&vp)[1 << R], type
     vp[j] = a;
     vp[j1] = b;
     const C la = vl[j], lb = vl[j1];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      if (q < na) {
-        const C x0 = cfma2(d[q][0], a, d[q][1], b);
-        const C x1 = cfma2(d[q][2], a, d[q][3], b);
-        acc[q] += re_dot(la, x0) + re_dot(lb, x1);
-      }
+    if (na > 0) {
+      cconj_fma(M00, la, a);
+      cconj_fma(M01, la, b);
+      cconj_fma(M10, lb, a);
+      cconj_fma(M11, lb, b);
     }
     vl[j] = cfma2(h00, la, h01, lb);
     vl[j1] = cfma2(h10, la, h11, lb);
   }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (q < na) {
+      const C* d = m + 4 + 4 * q;
+      acc[q] += re_dot(C{d[0].x, -d[0].y}, M00) + re_dot(C{d[1].x, -d[1].y}, M01) +
+                re_dot(C{d[2].x, -d[2].y}, M10) + re_dot(C{d[3].x, -d[3].y}, M11);
+    }
+  }
 }
 
+// CX with the target on register bit B on both tiles: pairs with (mc >> j) & 1 swap where cb.
 template <typename T, int R, int B>
 __device__ __forceinline__ void adj_cx(typename Cx<T>::type (&vp)[1 << R], typename Cx<T>::type (&vl)[1 << R],
-                                       const uint32_t (&li)[1 << R], int pc, int t, uint32_t tile) {
+                                       uint32_t mc, uint32_t cb) {
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     if (j & (1 << B)) continue;
     const int j1 = j | (1 << B);
-    const uint32_t cb = pc < t ? ((li[j] >> pc) & 1u) : ((tile >> (pc - t)) & 1u);
-    auto a = vp[j], b = vp[j1];
-    vp[j] = cb ? b : a;
-    vp[j1] = cb ? a : b;
-    a = vl[j];
-    b = vl[j1];
-    vl[j] = cb ? b : a;
-    vl[j1] = cb ? a : b;
+    if ((mc >> j) & 1u) {
+      auto a = vp[j], b = vp[j1];
+      vp[j].x = cb ? b.x : a.x;
+      vp[j].y = cb ? b.y : a.y;
+      vp[j1].x = cb ? a.x : b.x;
+      vp[j1].y = cb ? a.y : b.y;
+      a = vl[j];
+      b = vl[j1];
+      vl[j].x = cb ? b.x : a.x;
+      vl[j].y = cb ? b.y : a.y;
+      vl[j1].x = cb ? a.x : b.x;
+      vl[j1].y = cb ? a.y : b.y;
+    }
   }
+}
+
+__device__ __forceinline__ uint32_t adj_reg_mask(int k) {
+  return k == 0 ? 0xAAAAAAAAu
+       : k == 1 ? 0xCCCCCCCCu
+       : k == 2 ? 0xF0F0F0F0u
+       : k == 3 ? 0xFF00FF00u
+       : k == 4 ? 0xFFFF0000u
+                : 0xFFFFFFFFu;
+}
+__device__ __forceinline__ uint32_t adj_idx_bit(int pos, uint32_t tp, int t, uint32_t tile) {
+  return pos < t ? ((tp >> pos) & 1u) : ((tile >> (pos - t)) & 1u);
+}
+__device__ __forceinline__ float adj_flip(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
+__device__ __forceinline__ double adj_flip(double x, uint32_t s) {
+  return __longlong_as_double(__double_as_longlong(x) ^ ((long long)s << 32));
 }
 
 // One reverse stage over one tile of psi and lambda. `nact` threads (a power of two) hold
@@ -189,6 +223,7 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
   uint32_t li[1 << R];
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
+  uint32_t tp = tid & ((1u << tb) - 1u);  // this thread's own bits at their local positions
 
   for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
     const DevPhase& ph = phases[p];
@@ -200,7 +235,7 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
           lds_p[adj_swz<T>(li[j])] = vp[j];
           lds_l[adj_swz<T>(li[j])] = vl[j];
         }
-      uint32_t tp = 0;
+      tp = 0;
       for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
@@ -226,25 +261,33 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
       if (op.kind == K_MAT1) {
 #define TQ_ADJ_CASE(B) \
   case B:              \
-    if constexpr (R > B) adj_mat<T, R, (R > B ? B : 0)>(vp, vl, m, na, acc); \
+    adj_mat<T, R, (R > B ? B : R - 1)>(vp, vl, m, na, acc); \
     break;
-        switch (op.rbit) { TQ_ADJ_CASE(0) TQ_ADJ_CASE(1) TQ_ADJ_CASE(2) TQ_ADJ_CASE(3) TQ_ADJ_CASE(4) default: break; }
+        switch (op.rbit) { TQ_ADJ_CASE(0) TQ_ADJ_CASE(1) TQ_ADJ_CASE(2) TQ_ADJ_CASE(3)
+          default: adj_mat<T, R, (R > 4 ? 4 : R - 1)>(vp, vl, m, na, acc); break; }
 #undef TQ_ADJ_CASE
       } else if (op.kind == K_CX) {
+        const int kc = (int)op.pb - 1;  // control's register index, or -1
+        const uint32_t cb = kc < 0 ? adj_idx_bit(op.pa, tp, t, tile) : 1u;
+        const uint32_t mc = adj_reg_mask(kc);
 #define TQ_ADJX_CASE(B) \
   case B:               \
-    if constexpr (R > B) adj_cx<T, R, (R > B ? B : 0)>(vp, vl, li, op.pa, t, tile); \
+    adj_cx<T, R, (R > B ? B : R - 1)>(vp, vl, mc, cb); \
     break;
-        switch (op.rbit) { TQ_ADJX_CASE(0) TQ_ADJX_CASE(1) TQ_ADJX_CASE(2) TQ_ADJX_CASE(3) TQ_ADJX_CASE(4) default: break; }
+        switch (op.rbit) { TQ_ADJX_CASE(0) TQ_ADJX_CASE(1) TQ_ADJX_CASE(2) TQ_ADJX_CASE(3)
+          default: adj_cx<T, R, (R > 4 ? 4 : R - 1)>(vp, vl, mc, cb); break; }
 #undef TQ_ADJX_CASE
       } else if (op.kind == K_CZ) {
+        const int ka = (op.rbit & 15) - 1, kb = (op.rbit >> 4) - 1;
+        uint32_t f = 1u;
+        if (ka < 0) f &= adj_idx_bit(op.pa, tp, t, tile);
+        if (kb < 0) f &= adj_idx_bit(op.pb, tp, t, tile);
+        const uint32_t msk = adj_reg_mask(ka) & adj_reg_mask(kb), sg = f << 31;
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) {
-          uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
-          uint32_t bb = op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u);
-          if (ba & bb) {
-            vp[j].x = -vp[j].x; vp[j].y = -vp[j].y;
-            vl[j].x = -vl[j].x; vl[j].y = -vl[j].y;
+          if ((msk >> j) & 1u) {
+            vp[j].x = adj_flip(vp[j].x, sg); vp[j].y = adj_flip(vp[j].y, sg);
+            vl[j].x = adj_flip(vl[j].x, sg); vl[j].y = adj_flip(vl[j].y, sg);
           }
         }
       } else {
