@@ -240,15 +240,29 @@ def bench_tn(steps):
             continue
         pars = [torch.tensor(pg.net.params, dtype=torch.float32, device="cuda") for pg in progs]
 
-        def run():
+        def run_single():
             for pg, pt in zip(progs, pars):
                 pg.value(pt)
                 pg.grad(pt)
 
-        ms = _timed(run, max(1, steps // 4), 1)
+        batch = tn.TNBatch(progs)
+
+        def run_batch():
+            batch.values(pars)
+            batch.grads(pars)
+
+        ms1 = _timed(run_single, max(1, steps // 4), 1)
+        ms = _timed(run_batch, steps, 2)
+        vb = torch.stack([v[0] for v in batch.values(pars)]).cpu().numpy()
+        vs = np.array([pg.value(pt).cpu().numpy()[0] for pg, pt in zip(progs, pars)])
         flops = sum(pg.plan.info["flops"] for pg in progs)  # contraction only, 8 real flops per complex MAC
-        res[f"p{p}"] = {"networks": len(progs), "plan_s": round(plan_s, 2), "ms_value_and_grad_all": round(ms, 3),
+        res[f"p{p}"] = {"networks": len(progs), "plan_s": round(plan_s, 2),
+                        "ms_value_and_grad_all": round(ms, 3),
                         "grad_networks_per_s": len(progs) / (ms * 1e-3),
+                        "single_calls_ms": round(ms1, 3),
+                        "batched_speedup_vs_single_calls": round(ms1 / ms, 1),
+                        "batched_equals_single": bool(np.array_equal(vb, vs)),
+                        "maxcut_value": float(np.sum((1.0 - vb.real) / 2.0)),
                         "contraction_flops_per_network_sum": flops,
                         # value + gradient = 3 forward contractions of algorithmic work (the
                         # reverse pass also recomputes the forward: not counted)

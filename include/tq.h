@@ -280,6 +280,20 @@ tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leav
 tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, const void* d_grad_out,
                          void* d_grad_leaves, void* d_work, int64_t work_bytes, void* stream);
 
+/* Many networks at once (e.g. one light-cone network per measured edge). Arrays of length n
+ * hold each network's plan, packed leaves, output (value: 2^n_out complex; backward: the
+ * packed leaf environments), workspace and its size (tq_tn_workspace(plan, 0 or 1)). Plans
+ * without slices whose passes are short runs of small steps execute together in one launch,
+ * one work-group per network; the others run as tq_tn_contract / tq_tn_backward would.
+ * Plans in one launch must share a dtype. The upload of the network table is stream-ordered. */
+tq_status tq_tn_contract_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                               const void* const* d_leaves, void* const* d_out, void* const* d_work,
+                               const int64_t* work_bytes, void* stream);
+tq_status tq_tn_backward_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                               const void* const* d_leaves, const void* const* d_grad_out,
+                               void* const* d_grad_leaves, void* const* d_work,
+                               const int64_t* work_bytes, void* stream);
+
 /* Leaves of a circuit network from the circuit parameters (Sec. 3.2.1: state, gate and
  * observable tensors, with conjugate copies for the bra half). kind per leaf: 0 constant
  * (const_vals[const_off ..], complex128 interleaved), 1 one-qubit gate [out, in],

@@ -68,6 +68,28 @@ tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev) 
   return TQ_OK;
 }
 
+tq_status stage_upload(tq_ctx* ctx, int slot, const void* host, size_t bytes, hipStream_t stream, void** dev) {
+  TQ_TRY(scratch(ctx, slot, bytes, dev));
+  if (ctx->pinned_pending) {  // the previous upload may still read the staging buffer
+    TQ_HIP(hipEventSynchronize(ctx->pinned_done));
+    ctx->pinned_pending = false;
+  }
+  if (ctx->pinned_bytes < bytes) {
+    if (ctx->pinned) TQ_HIP(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    TQ_HIP(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+  }
+  if (!ctx->pinned_done) TQ_HIP(hipEventCreateWithFlags(&ctx->pinned_done, hipEventDisableTiming));
+  std::memcpy(ctx->pinned, host, bytes);
+  TQ_HIP(hipMemcpyAsync(*dev, ctx->pinned, bytes, hipMemcpyHostToDevice, stream));
+  TQ_HIP(hipEventRecord(ctx->pinned_done, stream));
+  ctx->pinned_pending = true;
+  return TQ_OK;
+}
+
 template <typename V>
 static tq_status to_device(const std::vector<V>& v, void** dev) {
   size_t bytes = std::max<size_t>(v.size() * sizeof(V), 16);
@@ -466,8 +488,10 @@ void tq_ctx_destroy(tq_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   ctx->schedules.clear();
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 9; ++i)
     if (ctx->scratch[i]) (void)hipFree(ctx->scratch[i]);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second);
   delete ctx;
 }

@@ -228,13 +228,11 @@ constexpr int kTnFusedMaxOut = 12;
 constexpr int kTnFusedMaxWork = 16;
 
 template <typename T>
-__global__ void __launch_bounds__(256)
-    tn_fused_kernel(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list, int n,
-                    const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
+__device__ __forceinline__ void tn_run_list(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list,
+                                            int n, const typename Cx<T>::type* __restrict__ leaves,
+                                            typename Cx<T>::type* __restrict__ ws, int64_t c, int64_t* tx,
+                                            int64_t* ty, T* red) {
   using C = typename Cx<T>::type;
-  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
-  __shared__ T red[16];
-  const int64_t c = blockIdx.x;
   for (int k = 0; k < n; ++k) {
     const DevFused f = list[k];
     const DevTnStep* st = steps + f.step;
@@ -250,6 +248,71 @@ __global__ void __launch_bounds__(256)
     tb = tb > st->ks ? st->ks : tb;
     tn_step_outputs<T>(st, tx, ty, x, y, z, tb, 0, 1, red);
     __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_fused_kernel(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list, int n,
+                    const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
+  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
+  __shared__ T red[16];
+  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x, tx, ty, red);
+}
+
+// Many networks at once: items of one launch, one work-group each.
+struct DevFusedItem {  // a run of small steps of one network
+  const DevTnStep* steps;
+  const DevFused* list;
+  const void* leaves;
+  void* ws;
+  int32_t n;
+  int32_t pad;
+};
+static_assert(sizeof(DevFusedItem) == 40, "DevFusedItem layout");
+struct DevCopyItem {  // dst[0, n) = src[0, n)
+  const void* src;
+  void* dst;
+  int64_t n;
+};
+static_assert(sizeof(DevCopyItem) == 24, "DevCopyItem layout");
+struct DevEnvItem {  // leaf environments of one unsliced network into its gradient buffer
+  const int64_t* tab;  // rows (leaf offset, environment offset, elements)
+  const void* ws;
+  void* grad;
+  int32_t rows;
+  int32_t pad;
+};
+static_assert(sizeof(DevEnvItem) == 32, "DevEnvItem layout");
+
+template <typename T>
+__global__ void __launch_bounds__(256) tn_fused_multi_kernel(const DevFusedItem* __restrict__ items) {
+  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
+  __shared__ T red[16];
+  const DevFusedItem& d = items[blockIdx.x];
+  tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0, tx,
+                 ty, red);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) tn_copy_multi_kernel(const DevCopyItem* __restrict__ items) {
+  using C = typename Cx<T>::type;
+  const DevCopyItem& d = items[blockIdx.x];
+  const C* src = (const C*)d.src;
+  C* dst = (C*)d.dst;
+  for (int64_t j = threadIdx.x; j < d.n; j += blockDim.x) dst[j] = src[j];
+}
+
+// Unsliced networks: every leaf has one environment, so the gradient is a copy.
+template <typename T>
+__global__ void __launch_bounds__(256) tn_env_multi_kernel(const DevEnvItem* __restrict__ items) {
+  using C = typename Cx<T>::type;
+  const DevEnvItem& d = items[blockIdx.x];
+  const C* ws = (const C*)d.ws;
+  C* grad = (C*)d.grad;
+  for (int r = 0; r < d.rows; ++r) {
+    const int64_t lo = d.tab[3 * r], eo = d.tab[3 * r + 1], n = d.tab[3 * r + 2];
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) grad[lo + j] = ws[eo + j];
   }
 }
 
@@ -1003,6 +1066,9 @@ static tq_status tn_fused(TnRun<T>& R, const DevTnStep* steps, const void* list,
 }
 
 template <typename T>
+static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg);
+
+template <typename T>
 static tq_status tn_forward_group(TnRun<T>& R) {
   using C = typename Cx<T>::type;
   const tq_tn_plan* p = R.p;
@@ -1022,6 +1088,17 @@ static tq_status tn_forward_group(TnRun<T>& R) {
                          sg.shared ? 1 : R.g));
       continue;
     }
+    TQ_TRY(tn_fwd_wide<T>(R, sg));
+  }
+  return TQ_OK;
+}
+
+// One large forward step (a segment that is not a fused run).
+template <typename T>
+static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
+  using C = typename Cx<T>::type;
+  const tq_tn_plan* p = R.p;
+  {
     const size_t s = (size_t)sg.first;
     const TnExec& ex = p->fwd[s];
     int64_t xs, ys, zs;
@@ -1062,7 +1139,7 @@ static tq_status tn_forward_group(TnRun<T>& R) {
                              (int)ex.N, (int)ex.K);
         }
         TQ_HIP(hipGetLastError());
-        continue;
+        return TQ_OK;
       }
     }
     TQ_TRY(tn_direct<T>(R, (const DevTnStep*)p->d_fwd + s, ex.dev, x, xs, y, ys, z, zs, copies));
@@ -1198,6 +1275,172 @@ tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leav
                                 (hipStream_t)stream);
   return tn_backward_t<double>(ctx, plan, d_leaves, d_grad_out, d_grad_leaves, d_work, work_bytes,
                                (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace tq {
+
+// One large reverse step (a segment that is not a fused run).
+template <typename T>
+static tq_status tn_bwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
+  using C = typename Cx<T>::type;
+  const tq_tn_plan* p = R.p;
+  const size_t k = (size_t)sg.first;
+  const TnExec& ex = p->bwd[k];
+  int64_t ys;
+  const C* y = R.tptr(ex.y, &ys);
+  return tn_direct<T>(R, (const DevTnStep*)p->d_bwd + k, ex.dev, R.eptr(ex.x), R.esz(ex.x), y, ys, R.eptr(ex.z),
+                      R.esz(ex.z), R.g);
+}
+
+// Many unsliced networks in rounds: in round r every network runs its r-th segment; the
+// fused runs of a round share one launch (one work-group per network), large steps launch
+// on their own. Item tables of every round are built first and uploaded in one copy.
+template <typename T>
+static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P, const std::vector<const void*>& L,
+                            const std::vector<const void*>& G, const std::vector<void*>& O,
+                            const std::vector<void*>& Wk, int mode, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const size_t n = P.size();
+  std::vector<TnRun<T>> R;
+  for (size_t i = 0; i < n; ++i) R.push_back(TnRun<T>{P[i], (const C*)L[i], (C*)Wk[i], stream});
+  std::vector<unsigned char> blob;
+  auto put = [&](const void* x, size_t bytes) {
+    const size_t off = blob.size();
+    blob.insert(blob.end(), (const unsigned char*)x, (const unsigned char*)x + bytes);
+    return off;
+  };
+  auto rounds = [&](bool fwd, std::vector<std::pair<size_t, int>>& tab) {
+    size_t rmax = 0;
+    for (size_t i = 0; i < n; ++i) rmax = std::max(rmax, (fwd ? P[i]->fseg : P[i]->bseg).size());
+    for (size_t r = 0; r < rmax; ++r) {
+      const size_t off = blob.size();
+      int cnt = 0;
+      for (size_t i = 0; i < n; ++i) {
+        const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;
+        if (r >= segs.size() || !segs[r].fused) continue;
+        DevFusedItem it{};
+        it.steps = (const DevTnStep*)(fwd ? P[i]->d_fwd : P[i]->d_bwd);
+        it.list = (const DevFused*)(fwd ? P[i]->d_ffused : P[i]->d_bfused) + segs[r].list;
+        it.leaves = L[i];
+        it.ws = Wk[i];
+        it.n = segs[r].count;
+        put(&it, sizeof it);
+        ++cnt;
+      }
+      tab.push_back({off, cnt});
+    }
+  };
+  std::vector<std::pair<size_t, int>> ftab, btab;
+  rounds(true, ftab);
+  size_t head_off = 0, tail_off = 0;
+  if (mode == 0) {
+    tail_off = blob.size();
+    for (size_t i = 0; i < n; ++i) {
+      DevCopyItem c{(const C*)Wk[i] + P[i]->t[P[i]->root].off, O[i], int64_t(1) << P[i]->t[P[i]->root].rank};
+      put(&c, sizeof c);
+    }
+  } else {
+    head_off = blob.size();
+    for (size_t i = 0; i < n; ++i) {
+      DevCopyItem c{G[i], (C*)Wk[i] + P[i]->env_off[P[i]->root], int64_t(1) << P[i]->t[P[i]->root].rank};
+      put(&c, sizeof c);
+    }
+    rounds(false, btab);
+    tail_off = blob.size();
+    for (size_t i = 0; i < n; ++i) {
+      DevEnvItem e{(const int64_t*)P[i]->d_leaf_env, Wk[i], O[i], P[i]->n_leaf_env, 0};
+      put(&e, sizeof e);
+    }
+  }
+  void* dev;
+  TQ_TRY(stage_upload(ctx, S_TNB, blob.data(), blob.size(), stream, &dev));
+  const unsigned char* db = (const unsigned char*)dev;
+  auto run_rounds = [&](bool fwd, const std::vector<std::pair<size_t, int>>& tab) -> tq_status {
+    for (size_t r = 0; r < tab.size(); ++r) {
+      if (tab[r].second > 0) {
+        hipLaunchKernelGGL(tn_fused_multi_kernel<T>, dim3((unsigned)tab[r].second), dim3(256), 0, stream,
+                           (const DevFusedItem*)(db + tab[r].first));
+        TQ_HIP(hipGetLastError());
+      }
+      for (size_t i = 0; i < n; ++i) {
+        const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;
+        if (r < segs.size() && !segs[r].fused)
+          TQ_TRY(fwd ? tn_fwd_wide<T>(R[i], segs[r]) : tn_bwd_wide<T>(R[i], segs[r]));
+      }
+    }
+    return TQ_OK;
+  };
+  TQ_TRY(run_rounds(true, ftab));
+  if (mode == 0) {
+    hipLaunchKernelGGL(tn_copy_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
+                       (const DevCopyItem*)(db + tail_off));
+    TQ_HIP(hipGetLastError());
+    return TQ_OK;
+  }
+  hipLaunchKernelGGL(tn_copy_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
+                     (const DevCopyItem*)(db + head_off));
+  TQ_HIP(hipGetLastError());
+  TQ_TRY(run_rounds(false, btab));
+  hipLaunchKernelGGL(tn_env_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
+                     (const DevEnvItem*)(db + tail_off));
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+// Shared driver of the batched calls: unsliced plans in rounds, the rest one by one.
+static tq_status tn_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans, const void* const* d_leaves,
+                          const void* const* d_gout, void* const* d_out, void* const* d_work,
+                          const int64_t* work_bytes, int mode, hipStream_t stream) {
+  if (!ctx || n < 0 || (n > 0 && (!plans || !d_leaves || !d_out || !d_work || !work_bytes)))
+    return fail(TQ_EINVAL, "null argument");
+  if (mode == 1 && n > 0 && !d_gout) return fail(TQ_EINVAL, "null upstream values");
+  std::vector<const tq_tn_plan*> P[2];
+  std::vector<const void*> L[2], G[2];
+  std::vector<void*> O[2], Wk[2];
+  std::vector<int> rest;
+  for (int i = 0; i < n; ++i) {
+    const tq_tn_plan* p = plans[i];
+    if (!p || !d_leaves[i] || !d_out[i] || !d_work[i] || (mode == 1 && !d_gout[i]))
+      return fail(TQ_EINVAL, "null plan or buffer for network " + std::to_string(i));
+    if (work_bytes[i] < tq_tn_workspace(p, mode))
+      return fail(TQ_EWORKSPACE, "workspace too small for network " + std::to_string(i));
+    if (p->n_slices != 1 || p->fwd.empty()) {
+      rest.push_back(i);
+      continue;
+    }
+    const int k = p->dtype == TQ_C64 ? 0 : 1;
+    P[k].push_back(p);
+    L[k].push_back(d_leaves[i]);
+    G[k].push_back(mode == 1 ? d_gout[i] : nullptr);
+    O[k].push_back(d_out[i]);
+    Wk[k].push_back(d_work[i]);
+  }
+  if (!P[0].empty()) TQ_TRY(tn_batch_t<float>(ctx, P[0], L[0], G[0], O[0], Wk[0], mode, stream));
+  if (!P[1].empty()) TQ_TRY(tn_batch_t<double>(ctx, P[1], L[1], G[1], O[1], Wk[1], mode, stream));
+  for (int i : rest) {
+    if (mode == 0)
+      TQ_TRY(tq_tn_contract(ctx, plans[i], d_leaves[i], d_out[i], d_work[i], work_bytes[i], stream));
+    else
+      TQ_TRY(tq_tn_backward(ctx, plans[i], d_leaves[i], d_gout[i], d_out[i], d_work[i], work_bytes[i], stream));
+  }
+  return TQ_OK;
+}
+
+}  // namespace tq
+
+extern "C" {
+
+tq_status tq_tn_contract_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans, const void* const* d_leaves,
+                               void* const* d_out, void* const* d_work, const int64_t* work_bytes, void* stream) {
+  return tn_batch(ctx, n, plans, d_leaves, nullptr, d_out, d_work, work_bytes, 0, (hipStream_t)stream);
+}
+
+tq_status tq_tn_backward_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans, const void* const* d_leaves,
+                               const void* const* d_grad_out, void* const* d_grad_leaves, void* const* d_work,
+                               const int64_t* work_bytes, void* stream) {
+  return tn_batch(ctx, n, plans, d_leaves, d_grad_out, d_grad_leaves, d_work, work_bytes, 1, (hipStream_t)stream);
 }
 
 tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,

@@ -158,8 +158,13 @@ struct tq_ctx {
   size_t lds_max = 160 * 1024;
   std::unordered_map<std::string, std::unique_ptr<tq::Schedule>> schedules;
   // grow-only device scratch buffers
-  void* scratch[8] = {nullptr};
-  size_t scratch_bytes[8] = {0};
+  void* scratch[9] = {nullptr};
+  size_t scratch_bytes[9] = {0};
+  // pinned staging buffer for per-call tables (reused once the previous upload finished)
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_done = nullptr;
+  bool pinned_pending = false;
   // immutable small device tables cached by content hash
   std::unordered_map<std::string, void*> tables;
   // autotune results: key -> (t, R)
@@ -168,8 +173,11 @@ struct tq_ctx {
 
 namespace tq {
 // scratch slots
-enum { S_MATS = 0, S_PARTIAL = 1, S_OFFS = 2, S_LAMBDA = 3, S_PSI = 4, S_GRADP = 5, S_TERMS = 6, S_MISC = 7 };
+enum { S_MATS = 0, S_PARTIAL = 1, S_OFFS = 2, S_LAMBDA = 3, S_PSI = 4, S_GRADP = 5, S_TERMS = 6, S_MISC = 7,
+       S_TNB = 8 };
 tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out);
 // Immutable device copy of a small host table, cached by content (no per-call upload).
 tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev);
+// Stream-ordered upload of a per-call table into scratch slot `slot` (via pinned memory).
+tq_status stage_upload(tq_ctx* ctx, int slot, const void* host, size_t bytes, hipStream_t stream, void** dev);
 }  // namespace tq

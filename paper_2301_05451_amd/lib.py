@@ -478,6 +478,55 @@ def tn_backward(plan: TnPlan, leaves, grad_out, work=None):
     return grad
 
 
+_lib.tq_tn_contract_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_tn_contract_batch.restype = ct.c_int
+_lib.tq_tn_backward_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_tn_backward_batch.restype = ct.c_int
+
+
+def _ptrs(xs):
+    return (ct.c_void_p * max(1, len(xs)))(*[ct.c_void_p(x) for x in xs])
+
+
+def tn_contract_batch(plans, leaves, works=None):
+    """Values of many networks (tq_tn_contract_batch); returns one output tensor per plan."""
+    import torch
+    outs, ws = [], []
+    for k, (pl, lv) in enumerate(zip(plans, leaves)):
+        cdt = torch.complex128 if pl.c128 else torch.complex64
+        if lv.dtype != cdt or not lv.is_cuda or not lv.is_contiguous() or lv.numel() < pl.leaf_elems:
+            raise ValueError(f"leaves of network {k} do not fit its plan")
+        outs.append(torch.empty(1 << pl.n_out, dtype=cdt, device=lv.device))
+        need = pl.workspace_bytes(False)
+        ws.append(works[k] if works is not None and works[k].numel() >= need else _ws(need, lv.device))
+    need = (ct.c_int64 * max(1, len(plans)))(*[pl.workspace_bytes(False) for pl in plans])
+    check(_lib.tq_tn_contract_batch(plans[0].ctx.h if plans else context().h, len(plans),
+                                    _ptrs([pl.h.value for pl in plans]), _ptrs([x.data_ptr() for x in leaves]),
+                                    _ptrs([o.data_ptr() for o in outs]), _ptrs([w.data_ptr() for w in ws]), need,
+                                    _stream()))
+    return outs
+
+
+def tn_backward_batch(plans, leaves, grad_outs, works=None):
+    """Leaf environments of many networks (tq_tn_backward_batch), one packed tensor per plan."""
+    import torch
+    envs, ws, gs = [], [], []
+    for k, (pl, lv, g) in enumerate(zip(plans, leaves, grad_outs)):
+        cdt = torch.complex128 if pl.c128 else torch.complex64
+        if lv.dtype != cdt or not lv.is_cuda or not lv.is_contiguous() or lv.numel() < pl.leaf_elems:
+            raise ValueError(f"leaves of network {k} do not fit its plan")
+        gs.append(g.to(device=lv.device, dtype=cdt).contiguous())
+        envs.append(torch.empty(pl.leaf_elems, dtype=cdt, device=lv.device))
+        need = pl.workspace_bytes(True)
+        ws.append(works[k] if works is not None and works[k].numel() >= need else _ws(need, lv.device))
+    need = (ct.c_int64 * max(1, len(plans)))(*[pl.workspace_bytes(True) for pl in plans])
+    check(_lib.tq_tn_backward_batch(plans[0].ctx.h if plans else context().h, len(plans),
+                                    _ptrs([pl.h.value for pl in plans]), _ptrs([x.data_ptr() for x in leaves]),
+                                    _ptrs([g.data_ptr() for g in gs]), _ptrs([e.data_ptr() for e in envs]),
+                                    _ptrs([w.data_ptr() for w in ws]), need, _stream()))
+    return envs
+
+
 def tn_build_leaves(plan: TnPlan, gates, leaf_specs, const_vals, params):
     """Packed leaf buffer of a circuit network from its parameters (tq_tn_build_leaves)."""
     import torch

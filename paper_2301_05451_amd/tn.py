@@ -428,6 +428,33 @@ class TNProgram:
         return lib.tn_param_grad(self.plan, self.net.gates, self.specs, params, env)
 
 
+class TNBatch:
+    """Many planned networks evaluated together (tq_tn_contract_batch / tq_tn_backward_batch):
+    the 75 light-cone networks of a QAOA graph run as one launch, one work-group each."""
+
+    def __init__(self, programs):
+        self.programs = list(programs)
+        self.plans = [p.plan for p in self.programs]
+
+    def values(self, params_list):
+        from . import lib
+        leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
+        return lib.tn_contract_batch(self.plans, leaves)
+
+    def grads(self, params_list, grad_outs=None):
+        """d Re(T_k) / d params_k (times grad_outs[k]) for every network k."""
+        import torch
+        from . import lib
+
+        leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
+        if grad_outs is None:
+            grad_outs = [torch.ones(1 << p.plan.n_out, dtype=L.dtype, device=L.device)
+                         for p, L in zip(self.programs, leaves)]
+        envs = lib.tn_backward_batch(self.plans, leaves, grad_outs)
+        return [lib.tn_param_grad(p.plan, p.net.gates, p.specs, q, e)
+                for p, q, e in zip(self.programs, params_list, envs)]
+
+
 def tn_expval(program: TNProgram, params):
     """Differentiable Re(T) of a scalar network (torch.autograd.Function)."""
     import torch

@@ -162,3 +162,39 @@ def test_expval_sum_z_24_terms_matches_popcount_identity():
     f = lib.expval(psi, spec, terms, 1).cpu().numpy()[0, 0]
     pc = np.array([bin(x).count("1") for x in range(1 << n)])
     assert abs(f - float(np.dot(np.abs(v) ** 2, n - 2 * pc))) < 1e-12
+
+
+def test_brickwork24_full_size_in_bench_configuration():
+    """The 24-qubit brickwork circuit at full size, fused with the default shape (the launch
+    configuration the benchmark times): its first two layers (168 gates) against the oracle
+    amplitude by amplitude; the whole 1670-gate circuit against the one-sweep-per-gate path
+    element by element, unit norm, and sum_i <Z_i> against the popcount identity on the
+    final state."""
+    from paper_2301_05451_amd import lib
+
+    c = W.brickwork()
+    n = c.n
+    head = c.gates[:168]
+    print("brickwork24: two layers vs oracle", flush=True)
+    spec_h = lib.BatchSpec.uniform(n, head, 1, c.n_params)
+    params = torch.tensor(c.params, dtype=torch.float32, device="cuda")
+    psi = lib.zero_states(spec_h, torch.complex64)
+    lib.sv_apply(psi, params, spec_h)
+    want = osv.run(n, head, c.params)
+    assert np.abs(psi.cpu().numpy() - want).max() <= 1e-5
+    del want
+    print("brickwork24: full circuit fused vs plain", flush=True)
+    spec = lib.BatchSpec.uniform(n, c.gates, 1, c.n_params)
+    fused = lib.zero_states(spec, torch.complex64)
+    lib.sv_apply(fused, params, spec)
+    plain = lib.zero_states(spec, torch.complex64)
+    lib.sv_apply(plain, params, spec, mode=1)
+    assert (fused - plain).abs().max().item() <= 1e-5
+    p = (fused.real.double() ** 2 + fused.imag.double() ** 2)
+    assert abs(p.sum().item() - 1.0) <= 1e-5
+    f = lib.expval(fused, spec, c.terms, 1)[0, 0].item()
+    pc = torch.zeros(1 << n, dtype=torch.float64, device="cuda")
+    idx = torch.arange(1 << n, device="cuda")
+    for q in range(n):
+        pc += ((idx >> q) & 1).double()
+    assert abs(f - (p * (n - 2 * pc)).sum().item()) <= 1e-4
