@@ -80,6 +80,7 @@ struct tq_tn_plan {
   int64_t perm_off = 0;                // workspace offset of the permute scratch
   int64_t env_off0 = 0;                // reverse pass: environment offsets per tensor
   std::vector<int64_t> env_off;
+  int64_t split_off = 0, split_elems = 0;  // partial sums of steps split over the summed range
   int64_t flops = 0, gemm_flops = 0, max_elems = 0;
   int n_direct = 0, n_gemm = 0;
   // device copies
@@ -135,12 +136,15 @@ __device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ st
 
 // Outputs of groups g = g0, g0 + gstride, ... (one group = 2^tb lanes). Every thread of the
 // work-group calls this with the same g0 / gstride trip count (barriers inside when tb > 6).
+// Summed assignments are walked as outer chunks so0 .. so1 of the table (all of them by
+// default); output e goes to z[e * zstride] (zstride > 1: partial sums of one chunk range).
 template <typename T>
 __device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st, const int64_t* tx,
                                                 const int64_t* ty, const typename Cx<T>::type* __restrict__ x,
                                                 const typename Cx<T>::type* __restrict__ y,
                                                 typename Cx<T>::type* __restrict__ z, int tb, int64_t gfirst,
-                                                int64_t gstride, T* red) {
+                                                int64_t gstride, T* red, int64_t so0 = 0, int64_t so1 = -1,
+                                                int64_t zstride = 1) {
   using C = typename Cx<T>::type;
   const int zr = st->zr, ks = st->ks;
   const int kt = ks < kTnTabBits ? ks : kTnTabBits;
@@ -149,7 +153,7 @@ __device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st
   const int lane = threadIdx.x & (G - 1);
   const int gpb = (int)blockDim.x >> tb;  // groups per block
   const int64_t nz = int64_t(1) << zr;
-  const int64_t nouter = int64_t(1) << (ks - kt);
+  const int64_t nouter = so1 < 0 ? (int64_t(1) << (ks - kt)) : so1;
   const int64_t ngroups = (nz + gpb - 1) / gpb;  // rounds of the block's group slots
   for (int64_t r = gfirst; r < ngroups; r += gstride) {
     const int64_t e = r * gpb + (threadIdx.x >> tb);
@@ -158,7 +162,7 @@ __device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st
     if (valid) {
       const int64_t xb = deposit_bits((uint64_t)e, st->xo, zr);
       const int64_t yb = deposit_bits((uint64_t)e, st->yo, zr);
-      for (int64_t so = 0; so < nouter; ++so) {
+      for (int64_t so = so0; so < nouter; ++so) {
         const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
         const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
         for (int sl = lane; sl < nt; sl += G) {
@@ -194,23 +198,54 @@ __device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st
       C o;
       o.x = ar;
       o.y = ai;
-      z[e] = o;
+      z[e * zstride] = o;
     }
   }
 }
 
 // One step over the whole device; blockIdx.y = slice copy (stride 0 for shared tensors).
+// With kb > 0 the summed range is also split over 2^kb chunks of work-groups: block x runs
+// output rounds (x mod rb) for chunk (x / rb) and writes partial sums P[e][chunk]; the
+// chunks are added afterwards in order by tn_chunk_sum_kernel.
 template <typename T>
 __global__ void __launch_bounds__(256)
     tn_direct_kernel(const DevTnStep* __restrict__ st, const typename Cx<T>::type* __restrict__ X, int64_t xs,
                      const typename Cx<T>::type* __restrict__ Y, int64_t ys, typename Cx<T>::type* __restrict__ Z,
-                     int64_t zs, int tb) {
+                     int64_t zs, int tb, int kb, int rb, typename Cx<T>::type* __restrict__ P, int64_t ps) {
   __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
   __shared__ T red[16];
   tn_build_tables<T>(st, tx, ty);
   __syncthreads();
-  tn_step_outputs<T>(st, tx, ty, X + xs * blockIdx.y, Y + ys * blockIdx.y, Z + zs * blockIdx.y, tb, blockIdx.x,
-                     gridDim.x, red);
+  const typename Cx<T>::type* x = X + xs * blockIdx.y;
+  const typename Cx<T>::type* y = Y + ys * blockIdx.y;
+  if (kb == 0) {
+    tn_step_outputs<T>(st, tx, ty, x, y, Z + zs * blockIdx.y, tb, blockIdx.x, gridDim.x, red);
+    return;
+  }
+  const int kt = st->ks < kTnTabBits ? st->ks : kTnTabBits;
+  const int64_t per = (int64_t(1) << (st->ks - kt)) >> kb;  // outer chunks per split
+  const int64_t c = blockIdx.x / rb;
+  tn_step_outputs<T>(st, tx, ty, x, y, P + ps * blockIdx.y + c, tb, blockIdx.x % rb, rb, red, c * per,
+                     (c + 1) * per, int64_t(1) << kb);
+}
+
+// z[e] = sum over chunks c in order of P[e][c]; blockIdx.y = slice copy.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_chunk_sum_kernel(const typename Cx<T>::type* __restrict__ P, int64_t ps, typename Cx<T>::type* __restrict__ Z,
+                        int64_t zs, int64_t nz, int nchunks) {
+  using C = typename Cx<T>::type;
+  const C* p = P + ps * blockIdx.y;
+  C* z = Z + zs * blockIdx.y;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nz; e += (int64_t)gridDim.x * blockDim.x) {
+    C v{(T)0, (T)0};
+    for (int c = 0; c < nchunks; ++c) {
+      const C q = p[e * nchunks + c];
+      v.x += q.x;
+      v.y += q.y;
+    }
+    z[e] = v;
+  }
 }
 
 // A run of small steps in one launch: one work-group per slice copy executes the steps in
@@ -807,6 +842,9 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
   }
   p->perm_off = w;
   w += p->G * p->perm_elems;
+  p->split_off = w;  // shared by every direct step (they run one after another)
+  p->split_elems = int64_t(1) << 18;
+  w += p->split_elems;
   w += p->G;  // root per-slice values (if the root is shared, copies are still G)
   p->ws_fwd = w + (int64_t(1) << p->t[p->root].rank) * p->G;
   // reverse pass: environments of every tensor, G copies each
@@ -1041,16 +1079,30 @@ template <typename T>
 static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep& h, const typename Cx<T>::type* x,
                            int64_t xs, const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs,
                            int64_t copies) {
+  using C = typename Cx<T>::type;
   const int zr = h.zr, ks = h.ks;
   int tb = std::max(0, 16 - zr);
   tb = std::min(tb, std::min(8, ks));
+  const int64_t nz = int64_t(1) << zr;
   const int64_t gpb = 256 >> tb;
-  const int64_t rounds = ((int64_t(1) << zr) + gpb - 1) / gpb;
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
+  const int64_t rounds = (nz + gpb - 1) / gpb;
+  // few outputs with many summed assignments: split the summed range over work-groups too,
+  // up to about 2^17 lanes, within the plan's partial-sum region
+  const int kt = std::min(ks, kTnTabBits);
+  int kb = 0;
+  while (kb < ks - kt && (nz << (tb + kb)) * copies < (int64_t(1) << 17) &&
+         (nz << (kb + 1)) * copies <= R.p->split_elems)
+    ++kb;
+  const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
+  C* P = R.ws + R.p->split_off;
+  const int64_t ps = nz << kb;
   for (int64_t c0 = 0; c0 < copies; c0 += 65535) {
     const int64_t cn = std::min<int64_t>(65535, copies - c0);
-    hipLaunchKernelGGL(tn_direct_kernel<T>, dim3(blocks, (unsigned)cn), dim3(256), 0, R.st, dstep, x + xs * c0, xs,
-                       y + ys * c0, ys, z + zs * c0, zs, tb);
+    hipLaunchKernelGGL(tn_direct_kernel<T>, dim3(rb << kb, (unsigned)cn), dim3(256), 0, R.st, dstep, x + xs * c0, xs,
+                       y + ys * c0, ys, z + zs * c0, zs, tb, kb, (int)rb, P, ps);
+    if (kb > 0)
+      hipLaunchKernelGGL(tn_chunk_sum_kernel<T>, dim3(grid_for(nz), (unsigned)cn), dim3(256), 0, R.st, P, ps,
+                         z + zs * c0, zs, nz, 1 << kb);
   }
   TQ_HIP(hipGetLastError());
   return TQ_OK;
