@@ -192,69 +192,74 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
                                          uint32_t tile, uint32_t tid, int nact, int slot0, int nslot, int64_t ntiles,
                                          double* __restrict__ part, unsigned char* smem_raw) {
   using C = typename Cx<T>::type;
-  const int t = stg->t;
+  constexpr uint32_t E = sizeof(C);
+  const gword* const sw = reinterpret_cast<const gword*>(gptr(stg));
+  const int t = (int)sw[0];
   const int tb = t - R;
-  C* lds_p = reinterpret_cast<C*>(smem_raw);
-  C* lds_l = lds_p + (1u << t);
-  T* red = reinterpret_cast<T*>(lds_l + (1u << t));  // [nslot][waves]
+  // LDS: psi tile, lambda tile, then the per-wave partial sums. Amplitude j of a thread sits
+  // at local index tp | rp_j; the swizzle is linear over XOR, so its byte offset is
+  // swz(tp) ^ swz(rp_j) (a per-thread term and a uniform one per register index).
+  unsigned char* const lbp = smem_raw;
+  unsigned char* const lbl = smem_raw + ((size_t)E << t);
+  T* red = reinterpret_cast<T*>(smem_raw + 2 * ((size_t)E << t));  // [nslot][waves]
   const int nwaves = (nact + 63) >> 6;
   const int lane = tid & 63, wv = tid >> 6;
   const int active = nact < 64 ? nact : 64;
   const bool act = (int)tid < nact;
 
-  int64_t base = 0;
-  for (int k = 0; k < stg->n_nonlocal; ++k) base |= (int64_t)((tile >> k) & 1u) << stg->npos[k];
-  int64_t thr = 0;
-  for (int k = 0; k < tb; ++k) thr |= (int64_t)((tid >> k) & 1u) << stg->lpos[k];
+  const int64_t off = stage_tile_base(sw, tile) | stage_thread_offset(sw, tb, tid);
   C vp[1 << R], vl[1 << R];
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     int64_t hi = 0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << word_byte(sw, kStageLposWord, tb + k);
     if (act) {
-      vp[j] = sp[(base | thr) + hi];
-      vl[j] = sl[(base | thr) + hi];
+      vp[j] = sp[off + hi];
+      vl[j] = sl[off + hi];
     } else {
       vp[j] = C{(T)0, (T)0};
       vl[j] = C{(T)0, (T)0};
     }
   }
-  uint32_t li[1 << R];
-#pragma unroll
-  for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
   uint32_t tp = tid & ((1u << tb) - 1u);  // this thread's own bits at their local positions
+  uint32_t ta = adj_swz<T>(tp) * E;
+  uint32_t ra[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) ra[j] = adj_swz<T>((uint32_t)j << tb) * E;
 
-  for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
-    const DevPhase& ph = phases[p];
-    if (ph.xchg) {
+  const int p_end = (int)sw[2];
+  for (int p = (int)sw[1]; p < p_end; ++p) {
+    const gword* const pw = reinterpret_cast<const gword*>(gptr(phases)) + (int64_t)p * kPhaseWords;
+    if (pw[2]) {
       __syncthreads();
       if (act)
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) {
-          lds_p[adj_swz<T>(li[j])] = vp[j];
-          lds_l[adj_swz<T>(li[j])] = vl[j];
+          *reinterpret_cast<C*>(lbp + (ta ^ ra[j])) = vp[j];
+          *reinterpret_cast<C*>(lbl + (ta ^ ra[j])) = vl[j];
         }
-      tp = 0;
-      for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
+      tp = phase_thread_bits(pw, tb, tid);
+      ta = adj_swz<T>(tp) * E;
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
         uint32_t rp = 0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << ph.rpos[k];
-        li[j] = tp | rp;
+        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << word_byte(pw, kPhaseRposWord, k);
+        ra[j] = adj_swz<T>(rp) * E;
       }
       __syncthreads();
       if (act)
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) {
-          vp[j] = lds_p[adj_swz<T>(li[j])];
-          vl[j] = lds_l[adj_swz<T>(li[j])];
+          vp[j] = *reinterpret_cast<const C*>(lbp + (ta ^ ra[j]));
+          vl[j] = *reinterpret_cast<const C*>(lbl + (ta ^ ra[j]));
         }
     }
-    for (int o = ph.op_begin; o < ph.op_end; ++o) {
+    const int o_end = (int)pw[1];
+    for (int o = (int)pw[0]; o < o_end; ++o) {
       const DevOp op = load_op(ops, o);
-      const int sl_info = dslot[o];
+      const int sl_info = gptr(dslot)[o];
       const int na = sl_info & 3, s0 = sl_info >> 2;
       const C* m = M + (int64_t)op.mat * kAdjMatStride;
       T acc[3] = {(T)0, (T)0, (T)0};
@@ -294,10 +299,14 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
         const bool two = op.kind == K_DIAG2;
         const C d0 = m[0], d1 = m[1], d2 = m[2], d3 = m[3];
         const C e0 = m[4], e1 = m[5], e2 = m[6], e3 = m[7];
+        // an operand is a register bit (index ka / kb) or a thread or tile bit
+        const int ka = (op.rbit & 15) - 1, kb = (op.rbit >> 4) - 1;
+        const uint32_t xa = ka < 0 ? adj_idx_bit(op.pa, tp, t, tile) : 0u;
+        const uint32_t xb = (two && kb < 0) ? adj_idx_bit(op.pb, tp, t, tile) : 0u;
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) {
-          const uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
-          const uint32_t bb = !two ? ba : (op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u));
+          const uint32_t ba = ka >= 0 ? (((uint32_t)j >> ka) & 1u) : xa;
+          const uint32_t bb = !two ? ba : (kb >= 0 ? (((uint32_t)j >> kb) & 1u) : xb);
           C f, g;
           f.x = ba ? (two ? (bb ? d3.x : d2.x) : d1.x) : (two ? (bb ? d1.x : d0.x) : d0.x);
           f.y = ba ? (two ? (bb ? d3.y : d2.y) : d1.y) : (two ? (bb ? d1.y : d0.y) : d0.y);
@@ -319,21 +328,22 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
     }
   }
   // store both tiles in the load layout
-  if (stg->store_xchg) {
+  if (sw[4]) {
     __syncthreads();
     if (act)
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
-        lds_p[adj_swz<T>(li[j])] = vp[j];
-        lds_l[adj_swz<T>(li[j])] = vl[j];
+        *reinterpret_cast<C*>(lbp + (ta ^ ra[j])) = vp[j];
+        *reinterpret_cast<C*>(lbl + (ta ^ ra[j])) = vl[j];
       }
     __syncthreads();
+    const uint32_t ts = adj_swz<T>(tid & ((1u << tb) - 1u)) * E;
     if (act)
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
-        const uint32_t l0 = tid | ((uint32_t)j << tb);
-        vp[j] = lds_p[adj_swz<T>(l0)];
-        vl[j] = lds_l[adj_swz<T>(l0)];
+        const uint32_t a0 = ts ^ (adj_swz<T>((uint32_t)j << tb) * E);
+        vp[j] = *reinterpret_cast<const C*>(lbp + a0);
+        vl[j] = *reinterpret_cast<const C*>(lbl + a0);
       }
   }
   if (act)
@@ -341,9 +351,9 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
     for (int j = 0; j < (1 << R); ++j) {
       int64_t hi = 0;
 #pragma unroll
-      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
-      sp[(base | thr) + hi] = vp[j];
-      sl[(base | thr) + hi] = vl[j];
+      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << word_byte(sw, kStageLposWord, tb + k);
+      sp[off + hi] = vp[j];
+      sl[off + hi] = vl[j];
     }
   __syncthreads();
   if (act)
@@ -379,10 +389,11 @@ __global__ void __launch_bounds__(512)
   const uint2 w = reinterpret_cast<const uint2*>(items)[blockIdx.x];
   const DevCirc& d = circs[(int)w.x];
   const DevStage* stg = d.stages + level;
-  const int2 sl = reinterpret_cast<const int2*>(d.rec)[level];
-  const int t = stg->t;
+  const gword* const rw = reinterpret_cast<const gword*>(gptr(d.rec)) + 2 * level;
+  const int slot0 = (int)rw[0], nslot = (int)rw[1];
+  const int t = (int)reinterpret_cast<const gword*>(gptr(stg))[0];
   adj_tile<T, R>(stg, d.phases, d.ops, d.dslot, mats + d.mats_off, psi + d.work_off, lam + d.work_off, w.y,
-                 threadIdx.x, 1 << (t - R), sl.x, sl.y, int64_t(1) << (d.n - t), partial + d.part_off, smem_raw);
+                 threadIdx.x, 1 << (t - R), slot0, nslot, int64_t(1) << (d.n - t), partial + d.part_off, smem_raw);
 }
 
 // grad[p] = sum over occurrences s of p: pscale_s * 2 * sum_tiles partial[s][tile] (fixed order)

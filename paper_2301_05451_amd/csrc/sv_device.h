@@ -2,6 +2,7 @@
 // from angles in double precision, batch offset maps.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "tq_internal.h"
@@ -217,13 +218,29 @@ __device__ inline void gate_and_derivs(int op, const double* a, dcx (&out)[kAdjM
 }
 
 
+// Schedule records, op lists and slot tables live in device (global) memory. Their
+// pointers are often read from device memory themselves (the per-circuit records of a
+// batch), and the compiler then only knows them as generic pointers: loads through them
+// become flat loads, vector loads whose results land in vector registers even when every
+// lane reads the same word. Reading through global-address-space pointers lets such
+// uniform reads go through scalar loads.
+#define TQ_GLOBAL __attribute__((address_space(1)))
+using gword = TQ_GLOBAL const uint32_t;
+template <typename P>
+__device__ __forceinline__ const TQ_GLOBAL P* gptr(const P* p) {
+  return (const TQ_GLOBAL P*)p;
+}
+
 // Read one 8-byte op descriptor as a single aligned 64-bit word and unpack its byte
 // fields. Reading the fields one by one let the compiler split a field's address into a
 // misaligned scalar base plus a misaligned immediate offset; the scalar unit does not
 // add those before dropping the low address bits, so the matrix index came back as the
 // op header and the matrix load left its buffer.
 __device__ __forceinline__ DevOp load_op(const DevOp* ops, int o) {
-  const uint2 w = reinterpret_cast<const uint2*>(ops)[o];
+  const gword* const q = reinterpret_cast<const gword*>(gptr(ops)) + 2 * (int64_t)o;
+  uint2 w;
+  w.x = q[0];
+  w.y = q[1];
   DevOp d;
   d.kind = (uint8_t)(w.x & 0xffu);
   d.rbit = (uint8_t)((w.x >> 8) & 0xffu);
@@ -231,6 +248,60 @@ __device__ __forceinline__ DevOp load_op(const DevOp* ops, int o) {
   d.pb = (uint8_t)(w.x >> 24);
   d.mat = (int32_t)w.y;
   return d;
+}
+
+// Schedule records (DevStage, DevPhase) are read as aligned 32-bit words with the byte
+// fields unpacked in registers. A byte field read on its own is a vector load (the scalar
+// unit loads whole words), a full memory round trip the wave waits for; reading words that
+// every lane shares lets them come through the scalar cache, several per instruction.
+constexpr int kStageWords = (int)(sizeof(DevStage) / 4);
+constexpr int kPhaseWords = (int)(sizeof(DevPhase) / 4);
+constexpr int kStageLposWord = (int)(offsetof(DevStage, lpos) / 4);
+constexpr int kStageNposWord = (int)(offsetof(DevStage, npos) / 4);
+constexpr int kPhaseRposWord = (int)(offsetof(DevPhase, rpos) / 4);
+constexpr int kPhaseTposWord = (int)(offsetof(DevPhase, tpos) / 4);
+static_assert(sizeof(DevStage) % 4 == 0 && sizeof(DevPhase) % 4 == 0, "word-readable records");
+static_assert(offsetof(DevStage, lpos) % 4 == 0 && offsetof(DevStage, npos) % 4 == 0, "word-aligned");
+static_assert(offsetof(DevPhase, rpos) % 4 == 0 && offsetof(DevPhase, tpos) % 4 == 0, "word-aligned");
+static_assert(offsetof(DevStage, t) == 0 && offsetof(DevStage, phase_begin) == 4 &&
+              offsetof(DevStage, phase_end) == 8 && offsetof(DevStage, n_nonlocal) == 12 &&
+              offsetof(DevStage, store_xchg) == 16, "DevStage header words");
+static_assert(offsetof(DevPhase, op_begin) == 0 && offsetof(DevPhase, op_end) == 4 &&
+              offsetof(DevPhase, xchg) == 8, "DevPhase header words");
+
+__device__ __forceinline__ uint32_t word_byte(const gword* w, int first_word, int k) {
+  return (w[first_word + (k >> 2)] >> (8 * (k & 3))) & 0xffu;
+}
+
+// Most thread bits a stage tile has: launches use at most 512 threads.
+constexpr int kMaxThreadBits = 9;
+
+// Global offset of a tile's fixed (non-local) index bits: uniform, scalar work only. The
+// tile id has no bits at or above the stage's non-local count, so every position byte may
+// be visited (no branch per bit).
+__device__ __forceinline__ int64_t stage_tile_base(const gword* sw, uint32_t tile) {
+  int64_t base = 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) base |= (int64_t)((tile >> k) & 1u) << word_byte(sw, kStageNposWord, k);
+  return base;
+}
+
+// Global offset of a thread's own index bits (the low tb local bits in the load layout).
+__device__ __forceinline__ int64_t stage_thread_offset(const gword* sw, int tb, uint32_t tid) {
+  const uint32_t tl = tid & ((1u << tb) - 1u);
+  int64_t thr = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxThreadBits; ++k) thr |= (int64_t)((tl >> k) & 1u) << word_byte(sw, kStageLposWord, k);
+  return thr;
+}
+
+// Tile-local positions of a thread's bits in a phase's layout.
+__device__ __forceinline__ uint32_t phase_thread_bits(const gword* pw, int tb, uint32_t tid) {
+  const uint32_t tl = tid & ((1u << tb) - 1u);
+  uint32_t tp = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxThreadBits; ++k) tp |= ((tl >> k) & 1u) << word_byte(pw, kPhaseTposWord, k);
+  return tp;
 }
 
 // Largest c with pref[c] <= g (pref ascending, pref[0] = 0, pref[count] > g).

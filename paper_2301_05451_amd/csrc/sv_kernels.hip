@@ -230,8 +230,7 @@ __device__ __forceinline__ void reg_cz(typename Cx<T>::type (&v)[1 << R], uint32
 }
 
 template <typename T, int R>
-__device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], const uint32_t (&li)[1 << R],
-                                                uint32_t tp,
+__device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], uint32_t tp,
                                                 const DevOp* __restrict__ ops, int ob, int oe,
                                                 const typename Cx<T>::type* __restrict__ M, int t,
                                                 uint32_t tile) {
@@ -271,13 +270,17 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
       if (kb < 0) f &= idx_bit(op.pb, tp, t, tile);
       reg_cz<T, R>(v, reg_mask(ka) & reg_mask(kb), f << 31);
     } else {
-      // diagonal on one (entries d[bit a]) or two qubits (entries d[2 bit a + bit b])
+      // diagonal on one (entries d[bit a]) or two qubits (entries d[2 bit a + bit b]); an
+      // operand is a register bit (index ka / kb) or a thread or tile bit
       const C d0 = m0, d1 = m1, d2 = m2, d3 = m3;
       const bool two = op.kind == K_DIAG2;
+      const int ka = (op.rbit & 15) - 1, kb = (op.rbit >> 4) - 1;
+      const uint32_t xa = ka < 0 ? idx_bit(op.pa, tp, t, tile) : 0u;
+      const uint32_t xb = (two && kb < 0) ? idx_bit(op.pb, tp, t, tile) : 0u;
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
-        const uint32_t ba = op.pa < t ? ((li[j] >> op.pa) & 1u) : ((tile >> (op.pa - t)) & 1u);
-        const uint32_t bb = !two ? ba : (op.pb < t ? ((li[j] >> op.pb) & 1u) : ((tile >> (op.pb - t)) & 1u));
+        const uint32_t ba = ka >= 0 ? (((uint32_t)j >> ka) & 1u) : xa;
+        const uint32_t bb = !two ? ba : (kb >= 0 ? (((uint32_t)j >> kb) & 1u) : xb);
         C f;
         f.x = ba ? (two ? (bb ? d3.x : d2.x) : d1.x) : (two ? (bb ? d1.x : d0.x) : d0.x);
         f.y = ba ? (two ? (bb ? d3.y : d2.y) : d1.y) : (two ? (bb ? d1.y : d0.y) : d0.y);
@@ -290,6 +293,11 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
 // One stage over one tile. Threads with act == false (past the 2^(t-R) a tile of a smaller
 // circuit needs, in a batched work-group sized for the largest) hold no amplitudes and only
 // take part in the barriers.
+//
+// LDS addresses: amplitude j of a thread sits at local index tp | rp_j (thread bits and
+// register bits occupy disjoint positions). The swizzle is linear over XOR, so its byte
+// address is swz(tp) ^ swz(rp_j): one per-thread term and one uniform term per register
+// index, kept in scalar registers.
 template <typename T, int R>
 __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, const DevPhase* __restrict__ phases,
                                            const DevOp* __restrict__ ops,
@@ -297,72 +305,74 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
                                            typename Cx<T>::type* __restrict__ st, uint32_t tile, uint32_t tid,
                                            bool act, typename Cx<T>::type* lds) {
   using C = typename Cx<T>::type;
-  const int t = stg->t;
+  constexpr uint32_t E = sizeof(C);
+  const gword* const sw = reinterpret_cast<const gword*>(gptr(stg));
+  const int t = (int)sw[0];
   const int tb = t - R;
+  unsigned char* const lb = reinterpret_cast<unsigned char*>(lds);
 
   // global offsets of this thread's amplitudes in the load/store layout
-  int64_t base = 0;
-  for (int k = 0; k < stg->n_nonlocal; ++k) base |= (int64_t)((tile >> k) & 1u) << stg->npos[k];
-  int64_t thr = 0;
-  for (int k = 0; k < tb; ++k) thr |= (int64_t)((tid >> k) & 1u) << stg->lpos[k];
-  C* const sb = st + (base | thr);
+  C* const sb = st + (stage_tile_base(sw, tile) | stage_thread_offset(sw, tb, tid));
   C v[1 << R];
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     int64_t hi = 0;
 #pragma unroll
-    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+    for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << word_byte(sw, kStageLposWord, tb + k);
     if (act) v[j] = sb[hi]; else v[j] = C{(T)0, (T)0};
   }
 
-  // local indices in the current layout (load layout: registers = top R local bits); tp is
-  // the thread's own bits at their local positions
-  uint32_t li[1 << R];
-#pragma unroll
-  for (int j = 0; j < (1 << R); ++j) li[j] = tid | ((uint32_t)j << tb);
+  // load layout: thread bits are the low tb local bits, registers the top R
   uint32_t tp = tid & ((1u << tb) - 1u);
+  uint32_t ta = lds_swz<T>(tp) * E;
+  uint32_t ra[1 << R];
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) ra[j] = lds_swz<T>((uint32_t)j << tb) * E;
 
   bool first_x = true;
-  for (int p = stg->phase_begin; p < stg->phase_end; ++p) {
-    const DevPhase& ph = phases[p];
-    if (ph.xchg) {
+  const int p_end = (int)sw[2];
+  for (int p = (int)sw[1]; p < p_end; ++p) {
+    const gword* const pw = reinterpret_cast<const gword*>(gptr(phases)) + (int64_t)p * kPhaseWords;
+    if (pw[2]) {
       if (!first_x) __syncthreads();
       first_x = false;
       if (act)
 #pragma unroll
-        for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
-      tp = 0;
-      for (int k = 0; k < tb; ++k) tp |= ((tid >> k) & 1u) << ph.tpos[k];
+        for (int j = 0; j < (1 << R); ++j) *reinterpret_cast<C*>(lb + (ta ^ ra[j])) = v[j];
+      tp = phase_thread_bits(pw, tb, tid);
+      ta = lds_swz<T>(tp) * E;
 #pragma unroll
       for (int j = 0; j < (1 << R); ++j) {
         uint32_t rp = 0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << ph.rpos[k];
-        li[j] = tp | rp;
+        for (int k = 0; k < R; ++k) rp |= (uint32_t)((j >> k) & 1) << word_byte(pw, kPhaseRposWord, k);
+        ra[j] = lds_swz<T>(rp) * E;
       }
       __syncthreads();
       if (act)
 #pragma unroll
-        for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(li[j])];
+        for (int j = 0; j < (1 << R); ++j) v[j] = *reinterpret_cast<const C*>(lb + (ta ^ ra[j]));
     }
-    apply_phase_ops<T, R>(v, li, tp, ops, ph.op_begin, ph.op_end, M, t, tile);
+    apply_phase_ops<T, R>(v, tp, ops, (int)pw[0], (int)pw[1], M, t, tile);
   }
-  if (stg->store_xchg) {
+  if (sw[4]) {
     if (!first_x) __syncthreads();
     if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) lds[lds_swz<T>(li[j])] = v[j];
+      for (int j = 0; j < (1 << R); ++j) *reinterpret_cast<C*>(lb + (ta ^ ra[j])) = v[j];
     __syncthreads();
+    const uint32_t ts = lds_swz<T>(tid & ((1u << tb) - 1u)) * E;
     if (act)
 #pragma unroll
-      for (int j = 0; j < (1 << R); ++j) v[j] = lds[lds_swz<T>(tid | ((uint32_t)j << tb))];
+      for (int j = 0; j < (1 << R); ++j)
+        v[j] = *reinterpret_cast<const C*>(lb + (ts ^ (lds_swz<T>((uint32_t)j << tb) * E)));
   }
   if (act) {
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
       int64_t hi = 0;
 #pragma unroll
-      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << stg->lpos[tb + k];
+      for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << word_byte(sw, kStageLposWord, tb + k);
       sb[hi] = v[j];
     }
   }
@@ -393,7 +403,7 @@ __global__ void __launch_bounds__(512) sv_batch_stage_kernel(const DevCirc* __re
   const uint2 w = reinterpret_cast<const uint2*>(items)[blockIdx.x];
   const DevCirc& d = circs[(int)w.x];
   const DevStage* stg = d.stages + level;
-  const bool act = threadIdx.x < (1u << (stg->t - R));
+  const bool act = threadIdx.x < (1u << ((int)reinterpret_cast<const gword*>(gptr(stg))[0] - R));
   stage_tile<T, R>(stg, d.phases, d.ops, mats + d.mats_off, states + d.state_off, w.y, threadIdx.x, act,
                    reinterpret_cast<C*>(smem_raw));
 }
