@@ -170,6 +170,125 @@ static void greedy_take(const std::vector<HostOp>& all, std::vector<int>& remain
   remaining.swap(rest);
 }
 
+// Register bits an op reads or changes, and whether it is diagonal (diagonal ops commute
+// with each other).
+static uint32_t op_reg_bits(const DevOp& d, bool* diag) {
+  *diag = false;
+  if (d.kind == K_MAT1) return 1u << d.rbit;
+  if (d.kind == K_CX) return (1u << d.rbit) | (d.pb ? 1u << (d.pb - 1) : 0u);
+  *diag = true;
+  const int ka = (d.rbit & 15) - 1, kb = (d.rbit >> 4) - 1;
+  return (ka >= 0 ? 1u << ka : 0u) | (kb >= 0 ? 1u << kb : 0u);
+}
+
+// Forward stages: order one phase's ops by layers and merge each layer's one-qubit matrices
+// and CZs. Ops in one layer touch disjoint register bits (thread and tile bits are never
+// changed inside a phase), so they commute; a layer is the earliest one after every op
+// that must precede. One-qubit matrices of a layer become one MATG op (their matrices get
+// consecutive table indices through `remap`); register-register CZs become the uniform
+// flip mask of a ZG op, which also takes up to two CZs with one register operand. This
+// cuts the per-op loop overhead of the stage kernel; the arithmetic is the same.
+static void emit_layered(const std::vector<DevOp>& pd, int R, std::vector<int>& remap, int& n_mapped,
+                         std::vector<DevOp>& out) {
+  const int n = (int)pd.size();
+  std::vector<int> lay(n);
+  int last_any[8] = {0}, last_nd[8] = {0}, top = 0;
+  for (int i = 0; i < n; ++i) {
+    bool diag;
+    const uint32_t b = op_reg_bits(pd[i], &diag);
+    int l = 1;
+    for (int k = 0; k < R; ++k)
+      if ((b >> k) & 1u) l = std::max(l, 1 + (diag ? last_nd[k] : last_any[k]));
+    lay[i] = l;
+    top = std::max(top, l);
+    for (int k = 0; k < R; ++k)
+      if ((b >> k) & 1u) {
+        last_any[k] = std::max(last_any[k], l);
+        if (!diag) last_nd[k] = l;
+      }
+  }
+  auto new_mat = [&](int old) {
+    if (remap[old] < 0) remap[old] = n_mapped++;
+    return remap[old];
+  };
+  for (int l = 1; l <= top; ++l) {
+    // one-qubit matrices, ascending register bit (a bit holds at most one per layer)
+    int mat_of_bit[8];
+    uint32_t mask = 0;
+    for (int i = 0; i < n; ++i)
+      if (lay[i] == l && pd[i].kind == K_MAT1) {
+        mask |= 1u << pd[i].rbit;
+        mat_of_bit[pd[i].rbit] = pd[i].mat;
+      }
+    bool fresh = true;  // the group's matrices can take consecutive new indices
+    for (int k = 0; k < R; ++k)
+      if (((mask >> k) & 1u) && remap[mat_of_bit[k]] >= 0) fresh = false;
+    if (mask && !fresh) {
+      for (int i = 0; i < n; ++i)
+        if (lay[i] == l && pd[i].kind == K_MAT1) {
+          DevOp d = pd[i];
+          d.mat = new_mat(d.mat);
+          out.push_back(d);
+        }
+    } else if (mask) {
+      DevOp g{};
+      g.kind = K_MATG;
+      g.rbit = (uint8_t)mask;
+      g.mat = -1;
+      for (int k = 0; k < R; ++k)
+        if ((mask >> k) & 1u) {
+          const int m = new_mat(mat_of_bit[k]);
+          if (g.mat < 0) g.mat = m;
+        }
+      out.push_back(g);
+    }
+    // CZs: register-register ones as a flip mask, up to two register-other ones per op
+    uint32_t flips = 0;
+    std::vector<std::pair<int, int>> half;  // (register index, partner x-position)
+    for (int i = 0; i < n; ++i) {
+      if (lay[i] != l || pd[i].kind != K_CZ) continue;
+      const int ka = (pd[i].rbit & 15) - 1, kb = (pd[i].rbit >> 4) - 1;
+      if (ka >= 0 && kb >= 0) {
+        for (int j = 0; j < (1 << R); ++j)
+          if (((j >> ka) & 1) && ((j >> kb) & 1)) flips ^= 1u << j;
+      } else if (ka >= 0) {
+        half.push_back({ka, pd[i].pb});
+      } else if (kb >= 0) {
+        half.push_back({kb, pd[i].pa});
+      } else {
+        out.push_back(pd[i]);  // no register operand: stays a plain CZ
+      }
+    }
+    size_t h = 0;
+    bool any = flips != 0 || !half.empty();
+    while (any) {
+      DevOp z{};
+      z.kind = K_ZG;
+      z.mat = (int32_t)flips;
+      flips = 0;
+      if (h < half.size()) {
+        z.rbit = (uint8_t)(half[h].first + 1);
+        z.pa = (uint8_t)half[h].second;
+        ++h;
+      }
+      if (h < half.size()) {
+        z.rbit |= (uint8_t)((half[h].first + 1) << 4);
+        z.pb = (uint8_t)half[h].second;
+        ++h;
+      }
+      out.push_back(z);
+      any = h < half.size();
+    }
+    // everything else of the layer in program order
+    for (int i = 0; i < n; ++i) {
+      if (lay[i] != l || pd[i].kind == K_MAT1 || pd[i].kind == K_CZ) continue;
+      DevOp d = pd[i];
+      if (d.mat >= 0) d.mat = new_mat(d.mat);
+      out.push_back(d);
+    }
+  }
+}
+
 void build_stages(Schedule& s) {
   const int n = s.n;
   s.stages.clear();
@@ -178,6 +297,10 @@ void build_stages(Schedule& s) {
   s.dstages.clear();
   const int t = std::min(s.t, n);
   const int R = std::min(s.R, t);
+  // layered grouping: forward schedules whose register index fits a 16-way mask
+  const bool group = !s.adjoint && R <= 4;
+  std::vector<int> remap(group ? s.recipes.size() : 0, -1);
+  int n_mapped = 0;
   const int c = std::min(s.c, std::max(0, t - 1));
   std::vector<int> remaining(s.ops.size());
   for (size_t i = 0; i < s.ops.size(); ++i) remaining[i] = (int)i;
@@ -249,6 +372,7 @@ void build_stages(Schedule& s) {
       cur_t = nt;
       for (int k = 0; k < R; ++k) ph.rpos[k] = nr[k];
       for (int k = 0; k < t - R; ++k) ph.tpos[k] = nt[k];
+      std::vector<DevOp> pd;  // this phase's ops in program order
       for (int oi : ptaken) {
         const HostOp& o = s.ops[oi];
         DevOp d{};
@@ -274,8 +398,10 @@ void build_stages(Schedule& s) {
           const int ka = reg_of(o.qa), kb = o.qb >= 0 ? reg_of(o.qb) : -1;
           d.rbit = (uint8_t)((ka + 1) | ((kb + 1) << 4));
         }
-        s.dops.push_back(d);
+        pd.push_back(d);
       }
+      if (group) emit_layered(pd, R, remap, n_mapped, s.dops);
+      else s.dops.insert(s.dops.end(), pd.begin(), pd.end());
       ph.op_end = (int)s.dops.size();
       s.phases.push_back(ph);
       st.n_ops += (int)ptaken.size();
@@ -295,6 +421,17 @@ void build_stages(Schedule& s) {
     for (int i = 0; i < n - t; ++i) ds.npos[i] = (uint8_t)st.npos[i];
     s.dstages.push_back(ds);
     s.stages.push_back(std::move(st));
+  }
+  if (group) {
+    // renumber the matrix table in first-use order (recipes no op uses go last)
+    int next = n_mapped;
+    for (int& r : remap)
+      if (r < 0) r = next++;
+    std::vector<Recipe> rec(s.recipes.size());
+    for (size_t i = 0; i < s.recipes.size(); ++i) rec[remap[i]] = std::move(s.recipes[i]);
+    s.recipes = std::move(rec);
+    for (HostOp& o : s.ops)
+      if (o.mat >= 0) o.mat = remap[o.mat];
   }
 }
 

@@ -229,6 +229,24 @@ __device__ __forceinline__ void reg_cz(typename Cx<T>::type (&v)[1 << R], uint32
   }
 }
 
+// A layer of one-qubit matrices on the register bits in MASK, ascending bit order; the
+// matrices are consecutive in the table (m, then m + 4, ...). Straight-line code: one loop
+// iteration of the op list covers the whole layer.
+template <typename T, int R, int MASK, int B = 0, int RANK = 0>
+__device__ __forceinline__ void reg_mat_group(typename Cx<T>::type (&v)[1 << R],
+                                              const typename Cx<T>::type* __restrict__ m) {
+  if constexpr (B < R) {
+    if constexpr (((MASK >> B) & 1) != 0) {
+      reg_mat<T, R, B>(v, m[4 * RANK], m[4 * RANK + 1], m[4 * RANK + 2], m[4 * RANK + 3]);
+      // keep the matrices' passes apart (interleaving them only raises register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      reg_mat_group<T, R, MASK, B + 1, RANK + 1>(v, m);
+    } else {
+      reg_mat_group<T, R, MASK, B + 1, RANK>(v, m);
+    }
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], uint32_t tp,
                                                 const DevOp* __restrict__ ops, int ob, int oe,
@@ -237,8 +255,51 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
   using C = typename Cx<T>::type;
   for (int o = ob; o < oe; ++o) {
     const DevOp op = load_op(ops, o);
+    if constexpr (R <= 4) {
+      if (op.kind == K_MATG) {
+        const C* m = M + 4 * (int64_t)op.mat;
+#define TQ_MATG_CASE(K) \
+  case K:               \
+    reg_mat_group<T, R, K>(v, m); \
+    break;
+        switch (op.rbit) {
+          TQ_MATG_CASE(1) TQ_MATG_CASE(2) TQ_MATG_CASE(3) TQ_MATG_CASE(4) TQ_MATG_CASE(5)
+          TQ_MATG_CASE(6) TQ_MATG_CASE(7) TQ_MATG_CASE(8) TQ_MATG_CASE(9) TQ_MATG_CASE(10)
+          TQ_MATG_CASE(11) TQ_MATG_CASE(12) TQ_MATG_CASE(13) TQ_MATG_CASE(14)
+          default: reg_mat_group<T, R, 15>(v, m); break;
+        }
+#undef TQ_MATG_CASE
+        continue;
+      }
+      if (op.kind == K_ZG) {
+        // sign flips: uniform ones from the register-register CZs, per-thread ones from up
+        // to two CZs whose partner is a thread or tile bit
+        const uint32_t uni = (uint32_t)op.mat;
+        const int k1 = (op.rbit & 15) - 1, k2 = (op.rbit >> 4) - 1;
+        if (k1 < 0) {
+#pragma unroll
+          for (int j = 0; j < (1 << R); ++j)
+            if ((uni >> j) & 1u) {
+              v[j].x = flip_sign(v[j].x, 0x80000000u);
+              v[j].y = flip_sign(v[j].y, 0x80000000u);
+            }
+        } else {
+          const uint32_t s1 = idx_bit(op.pa, tp, t, tile) << 31;
+          const uint32_t s2 = k2 >= 0 ? idx_bit(op.pb, tp, t, tile) << 31 : 0u;
+#pragma unroll
+          for (int j = 0; j < (1 << R); ++j) {
+            uint32_t sg = ((uni >> j) & 1u) << 31;
+            if ((j >> k1) & 1) sg ^= s1;
+            if (k2 >= 0 && ((j >> k2) & 1)) sg ^= s2;
+            v[j].x = flip_sign(v[j].x, sg);
+            v[j].y = flip_sign(v[j].y, sg);
+          }
+        }
+        continue;
+      }
+    }
     C m0{}, m1{}, m2{}, m3{};
-    if (op.mat >= 0) {
+    if (op.kind == K_MAT1 || op.kind == K_DIAG1 || op.kind == K_DIAG2) {
       const C* m = M + 4 * (int64_t)op.mat;
       m0 = m[0]; m1 = m[1]; m2 = m[2]; m3 = m[3];
     }
@@ -378,8 +439,16 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
   }
 }
 
+// Waves per SIMD the stage kernel is compiled for. A complex64 tile of 2^12 amplitudes takes
+// 32 KiB of LDS, so five work-groups fit a CU; with R = 4 that needs at most 96 registers,
+// which the code meets without spilling. Other shapes leave the choice to the compiler.
 template <typename T, int R>
-__global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restrict__ stg,
+constexpr int stage_waves() {
+  return (sizeof(T) == 4 && R == 4) ? 5 : 1;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<T, R>()))) sv_stage_kernel(const DevStage* __restrict__ stg,
                                                         const DevPhase* __restrict__ phases,
                                                         const DevOp* __restrict__ ops,
                                                         const typename Cx<T>::type* __restrict__ mats,
@@ -394,7 +463,7 @@ __global__ void __launch_bounds__(512) sv_stage_kernel(const DevStage* __restric
 // Heterogeneous batch, one stage level: work-group i runs items[i] (a tile of one circuit's
 // stage `level`). The work-group is sized for the level's largest tile.
 template <typename T, int R>
-__global__ void __launch_bounds__(512) sv_batch_stage_kernel(const DevCirc* __restrict__ circs,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<T, R>()))) sv_batch_stage_kernel(const DevCirc* __restrict__ circs,
                                                               const BatchItem* __restrict__ items, int level,
                                                               const typename Cx<T>::type* __restrict__ mats,
                                                               typename Cx<T>::type* __restrict__ states) {

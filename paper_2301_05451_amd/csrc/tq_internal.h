@@ -44,6 +44,8 @@ enum OpKind : uint8_t {
   K_DIAG1 = 2,  // diagonal on one qubit (2 entries)
   K_DIAG2 = 3,  // diagonal on two qubits (4 entries, index 2*bit(qa)+bit(qb))
   K_CZ = 4,     // sign flip where both qubits are 1
+  K_MATG = 5,   // forward stages: 2x2 matrices on several register bits of one layer
+  K_ZG = 6,     // forward stages: several CZs of one layer as sign flips
 };
 
 // A matrix-table entry: how the gate-build kernel forms it from the original gates.
@@ -69,9 +71,15 @@ struct DevOp {
   uint8_t kind;
   uint8_t rbit;  // MAT1/CX: target's register-bit index within the phase;
                  // DIAG/CZ: (register index of qa + 1) | (register index of qb + 1) << 4, 0 = none
-  uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX)
-  uint8_t pb;    // x-position of qb (DIAG2/CZ); CX: control's register index + 1 (0 = none)
-  int32_t mat;
+                 // MATG: mask of the register bits, one matrix each, ascending
+                 // ZG: register indices + 1 of up to two CZs whose partner is a thread or
+                 //     tile bit (low and high nibble, 0 = none)
+  uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX); ZG: first CZ's partner
+  uint8_t pb;    // x-position of qb (DIAG2/CZ); CX: control's register index + 1 (0 = none);
+                 // ZG: second CZ's partner
+  int32_t mat;   // matrix index (MATG: of the lowest bit's matrix, the rest follow);
+                 // ZG: mask over register indices j of the sign flips of the
+                 // register-register CZs
 };
 static_assert(sizeof(DevOp) == 8, "DevOp layout");
 
