@@ -94,6 +94,26 @@ __device__ __forceinline__ T wave_sum(T v, int lane, int active) {
   return v;
 }
 
+// v + (v moved across lanes by the data-parallel-primitive control CTRL); rows outside
+// ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+
+// Sum over all 64 lanes of a full wave without the LDS crossbar: pair sums within quads,
+// mirrors within half-rows and rows, then row broadcasts; lane 63 holds the total, which
+// is returned to every lane.
+__device__ __forceinline__ float wave_sum_full(float v) {
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // conj(x) * y accumulated into acc
 template <typename C>
 __device__ __forceinline__ void cconj_fma(C& acc, C x, C y) {
@@ -321,7 +341,9 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         if (q < na) {
-          const T s = wave_sum<T>(acc[q], lane, active);
+          T s;
+          if constexpr (sizeof(T) == 4) s = active == 64 ? wave_sum_full(acc[q]) : wave_sum<T>(acc[q], lane, active);
+          else s = wave_sum<T>(acc[q], lane, active);
           if (lane == 0 && wv < nwaves) red[(s0 + q) * nwaves + wv] = s;
         }
       }
