@@ -19,7 +19,8 @@ tq_status fail(tq_status st, const std::string& msg) {
 
 Schedule::~Schedule() {
   void* ptrs[] = {d_gates,  d_rec,       d_rec_gates,   d_ops,         d_phases,
-                  d_stages, d_dslot,     d_pslot_ptr,   d_pslot_idx,   d_pslot_scale, d_stage_slot0};
+                  d_stages, d_dslot,     d_pslot_ptr,   d_pslot_idx,   d_pslot_scale, d_stage_slot0,
+                  d_adj_runs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -217,11 +218,12 @@ tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gate
   s->R = R;
   s->c = c;
   s->n_gates = n_gates;
-  lower_adjoint_ops(g, n_gates, s->ops);
+  lower_adjoint_ops(g, n_gates, s->ops, s->adj_runs);
   build_stages(*s);
   build_adjoint_slots(*s, g, n_gates);
   TQ_TRY(upload_schedule(*s, g, n_gates));
   TQ_TRY(to_device(s->dslot, &s->d_dslot));
+  TQ_TRY(to_device(s->adj_runs, &s->d_adj_runs));
   std::vector<int32_t> slot_pairs;  // per stage: (first slot, slot count), read by batched launches
   for (size_t k = 0; k < s->stage_slot0.size(); ++k) {
     slot_pairs.push_back(s->stage_slot0[k]);

@@ -244,6 +244,7 @@ tq_status build_adjoint(tq_svb* b, int T, int R, int c) {
     d.ops = (const DevOp*)s->d_ops;
     d.gates = (const tq_gate*)s->d_gates;
     d.rec = (const int32_t*)s->d_stage_slot0;
+    d.rec_gates = (const int32_t*)s->d_adj_runs;
     d.dslot = (const int32_t*)s->d_dslot;
     d.pslot_ptr = (const int32_t*)s->d_pslot_ptr;
     d.pslot_idx = (const int32_t*)s->d_pslot_idx;

@@ -191,6 +191,7 @@ static uint32_t op_reg_bits(const DevOp& d, bool* diag) {
 static void emit_layered(const std::vector<DevOp>& pd, int R, std::vector<int>& remap, int& n_mapped,
                          std::vector<DevOp>& out) {
   const int n = (int)pd.size();
+  const size_t first = out.size();  // ops of earlier phases are not touched
   std::vector<int> lay(n);
   int last_any[8] = {0}, last_nd[8] = {0}, top = 0;
   for (int i = 0; i < n; ++i) {
@@ -258,6 +259,14 @@ static void emit_layered(const std::vector<DevOp>& pd, int R, std::vector<int>& 
       } else {
         out.push_back(pd[i]);  // no register operand: stays a plain CZ
       }
+    }
+    // with only register-register CZs, the flips ride on the matrix op emitted just before
+    // (pa | pb << 8) if it belongs to this phase: it is this layer's (disjoint bits) or the
+    // previous layer's last op, so nothing lies between it and the flips
+    if (half.empty() && flips != 0 && out.size() > first && out.back().kind == K_MATG && R <= 4) {
+      out.back().pa ^= (uint8_t)(flips & 0xffu);
+      out.back().pb ^= (uint8_t)(flips >> 8);
+      flips = 0;
     }
     size_t h = 0;
     bool any = flips != 0 || !half.empty();
@@ -439,21 +448,66 @@ void build_stages(Schedule& s) {
 
 namespace tq {
 
-// Reverse-sweep op list: every original gate in reverse order as its own op (parameterised
-// gates keep their own matrices so that each angle's derivative is available). mat holds
-// the gate index; nang its angle count.
-void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops) {
+// Reverse-sweep op list. A run of one-qubit gates on one qubit with no other gate on that
+// qubit in between (at most three angles, at most kAdjMaxRun gates) is reversed as one op:
+// the gates between its members act on other qubits and commute with it, so it sits at the
+// position of its last gate. Every other gate is its own op. mat holds the gate index of
+// the op's last gate (its matrix-table entry); nang the op's angle count.
+constexpr int kAdjMaxRun = 8;
+static bool adj_one_qubit(int op) { return op != TQ_CNOT && op != TQ_CZ && op != TQ_RZZ; }
+
+void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops, std::vector<int32_t>& runs) {
   ops.clear();
-  for (int k = n_gates - 1; k >= 0; --k) {
+  // group runs in forward order
+  std::vector<std::vector<int>> run_of_last(n_gates);  // run gates, stored at the last one
+  std::vector<char> is_member(n_gates, 0);            // inside a run that ends later
+  std::vector<std::vector<int>> open(kMaxQ + 1);
+  std::vector<int> open_ang(kMaxQ + 1, 0);
+  auto close = [&](int q) {
+    if (open[q].empty()) return;
+    const int last = open[q].back();
+    for (size_t i = 0; i + 1 < open[q].size(); ++i) is_member[open[q][i]] = 1;
+    run_of_last[last] = open[q];
+    open[q].clear();
+    open_ang[q] = 0;
+  };
+  for (int k = 0; k < n_gates; ++k) {
     const tq_gate& x = g[k];
+    const int na = gate_n_angles(x.op);
+    if (adj_one_qubit(x.op)) {
+      const int q = x.q[0];
+      if (!open[q].empty() && (open_ang[q] + na > 3 || (int)open[q].size() >= kAdjMaxRun)) close(q);
+      open[q].push_back(k);
+      open_ang[q] += na;
+    } else {
+      close(x.q[0]);
+      close(x.q[1]);
+      run_of_last[k] = {k};
+    }
+  }
+  for (int q = 0; q <= kMaxQ; ++q) close(q);
+  runs.assign(n_gates + 1, 0);
+  std::vector<int32_t> list;
+  for (int k = 0; k < n_gates; ++k) {
+    runs[k] = (int32_t)list.size();
+    if (!is_member[k]) list.insert(list.end(), run_of_last[k].begin(), run_of_last[k].end());
+  }
+  runs[n_gates] = (int32_t)list.size();
+  runs.insert(runs.end(), list.begin(), list.end());
+
+  for (int k = n_gates - 1; k >= 0; --k) {
+    if (is_member[k]) continue;
+    const tq_gate& x = g[k];
+    const std::vector<int>& rg = run_of_last[k];
     HostOp o{};
     o.mat = k;
     o.src = k;
-    o.nang = gate_n_angles(x.op);
+    o.nang = 0;
+    for (int m : rg) o.nang += gate_n_angles(g[m].op);
     if (x.op == TQ_CNOT) { o.kind = K_CX; o.qa = x.q[1]; o.qb = x.q[0]; }
     else if (x.op == TQ_CZ) { o.kind = K_CZ; o.qa = x.q[0]; o.qb = x.q[1]; }
     else if (x.op == TQ_RZZ) { o.kind = K_DIAG2; o.qa = x.q[0]; o.qb = x.q[1]; }
-    else if (diag1(x.op)) { o.kind = K_DIAG1; o.qa = x.q[0]; o.qb = -1; }
+    else if (rg.size() == 1 && diag1(x.op)) { o.kind = K_DIAG1; o.qa = x.q[0]; o.qb = -1; }
     else { o.kind = K_MAT1; o.qa = x.q[0]; o.qb = -1; }
     ops.push_back(o);
   }
@@ -473,13 +527,19 @@ void build_adjoint_slots(Schedule& s, const tq_gate* g, int n_gates) {
     int local = 0;
     for (int p = s.dstages[st].phase_begin; p < s.dstages[st].phase_end; ++p)
       for (int o = s.phases[p].op_begin; o < s.phases[p].op_end; ++o) {
+        // the op's angles: its run's gates in forward order, each gate's angles in order
         const int k = s.dops[o].mat;
-        const int na = gate_n_angles(g[k].op);
-        s.dslot[o] = (local << 2) | na;
-        for (int j = 0; j < na; ++j) {
-          s.slot_gate.push_back(k);
-          s.slot_angle.push_back(j);
+        const int base = n_gates + 1;
+        int na = 0;
+        for (int r = s.adj_runs[k]; r < s.adj_runs[k + 1]; ++r) {
+          const int m = s.adj_runs[base + r];
+          for (int j = 0; j < gate_n_angles(g[m].op); ++j) {
+            s.slot_gate.push_back(m);
+            s.slot_angle.push_back(j);
+            ++na;
+          }
         }
+        s.dslot[o] = (local << 2) | na;
         local += na;
       }
     s.stage_nslot.push_back(local);

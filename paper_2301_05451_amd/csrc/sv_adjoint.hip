@@ -18,17 +18,15 @@
 namespace tq {
 
 template <typename T>
-__global__ void adj_gate_build_kernel(const tq_gate* __restrict__ gates, int n_gates, const T* __restrict__ params,
-                                      BatchMap pmap, typename Cx<T>::type* __restrict__ mats, int count) {
+__global__ void adj_gate_build_kernel(const tq_gate* __restrict__ gates, int n_gates, const int32_t* __restrict__ runs,
+                                      const T* __restrict__ params, BatchMap pmap,
+                                      typename Cx<T>::type* __restrict__ mats, int count) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)n_gates * count) return;
   const int k = (int)(gid % n_gates);
   const int circ = (int)(gid / n_gates);
-  const tq_gate& g = gates[k];
-  double a[3];
-  gate_angles(g, params + pmap.at(circ), a);
   dcx m[kAdjMatStride];
-  gate_and_derivs(g.op, a, m);
+  if (!adj_entry(gates, n_gates, runs, k, params + pmap.at(circ), m)) return;
   typename Cx<T>::type* out = mats + ((int64_t)circ * n_gates + k) * kAdjMatStride;
   for (int i = 0; i < kAdjMatStride; ++i) out[i] = to_cx<T>(m[i]);
 }
@@ -478,7 +476,8 @@ tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap,
   if (s.n_gates > 0) {
     const int64_t total = (int64_t)s.n_gates * count;
     hipLaunchKernelGGL(adj_gate_build_kernel<T>, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, stream,
-                       (const tq_gate*)s.d_gates, s.n_gates, (const T*)d_params, pmap, (C*)mats, count);
+                       (const tq_gate*)s.d_gates, s.n_gates, (const int32_t*)s.d_adj_runs, (const T*)d_params, pmap,
+                       (C*)mats, count);
     TQ_HIP(hipGetLastError());
   }
   for (int c0 = 0; c0 < count; c0 += 65535) {
@@ -522,10 +521,8 @@ __global__ void adj_batch_gate_build_kernel(const DevCirc* __restrict__ circs, c
   const int c = find_circ(pref, count, gid);
   const DevCirc& d = circs[c];
   const int k = (int)(gid - pref[c]);
-  double a[3];
-  gate_angles(d.gates[k], params + d.param_off, a);
   dcx m[kAdjMatStride];
-  gate_and_derivs(d.gates[k].op, a, m);
+  if (!adj_entry(d.gates, d.n_mats, d.rec_gates, k, params + d.param_off, m)) return;
   typename Cx<T>::type* out = mats + d.mats_off + (int64_t)k * kAdjMatStride;
   for (int i = 0; i < kAdjMatStride; ++i) out[i] = to_cx<T>(m[i]);
 }

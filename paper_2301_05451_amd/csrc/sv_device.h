@@ -218,6 +218,72 @@ __device__ inline void gate_and_derivs(int op, const double* a, dcx (&out)[kAdjM
 }
 
 
+// Full 2x2 forms of a one-qubit gate and of its angle derivatives; returns the angle count.
+__device__ inline int gate_full2(int op, const double* a, dmat2& U, dmat2 (&D)[3]) {
+  dcx m[kAdjMatStride];
+  gate_and_derivs(op, a, m);
+  const int na = gate_n_angles_dev(op);
+  const dcx z{0, 0};
+  if (op == TQ_RZ || op == TQ_Z) {  // stored as the diagonal
+    U = dmat2{{m[0], z, z, m[1]}};
+    if (na > 0) D[0] = dmat2{{m[4], z, z, m[5]}};
+  } else {
+    U = dmat2{{m[0], m[1], m[2], m[3]}};
+    for (int j = 0; j < na; ++j) D[j] = dmat2{{m[4 + 4 * j], m[5 + 4 * j], m[6 + 4 * j], m[7 + 4 * j]}};
+  }
+  return na;
+}
+
+constexpr int kAdjRunMax = 8;  // gates in one reversed run (the schedule's limit)
+
+// Matrix-table entry of the reverse-sweep op at gate k (runs as in the adjoint schedule: n
+// offsets + 1, then the gate lists). A gate on its own keeps its own U and dU/da_j. A run
+// G_L ... G_1 on one qubit gets U = G_L ... G_1 and, for angle j of gate i, the matrix
+// (G_L ... G_{i+1}) dG_i/da_j (G_{i-1} ... G_1): the gradient term of that angle is then
+// Re <lam| X |psi> with psi taken before the run and lam after it, the same form as for a
+// single gate. Returns false for a gate inside another gate's run (no entry).
+template <typename P>
+__device__ inline bool adj_entry(const tq_gate* gates, int n_gates, const int32_t* runs, int k, const P* params,
+                                 dcx (&out)[kAdjMatStride]) {
+  const int b = runs[k], e = runs[k + 1];
+  if (b == e) return false;
+  if (e - b == 1) {
+    double a[3];
+    gate_angles(gates[k], params, a);
+    gate_and_derivs(gates[k].op, a, out);
+    return true;
+  }
+  const int32_t* lst = runs + n_gates + 1;
+  const int L = e - b < kAdjRunMax ? e - b : kAdjRunMax;
+  dmat2 G[kAdjRunMax];
+  for (int i = 0; i < L; ++i) {
+    double a[3];
+    gate_angles(gates[lst[b + i]], params, a);
+    dmat2 D[3];
+    gate_full2(gates[lst[b + i]].op, a, G[i], D);
+  }
+  for (int i = 0; i < kAdjMatStride; ++i) out[i] = dcx{0, 0};
+  dmat2 U = dmat2::identity();
+  for (int i = 0; i < L; ++i) U = mat_mul(G[i], U);
+  for (int r = 0; r < 4; ++r) out[r] = U.m[r];
+  int slot = 1;
+  dmat2 B = dmat2::identity();  // G_{i-1} ... G_1
+  for (int i = 0; i < L; ++i) {
+    double a[3];
+    gate_angles(gates[lst[b + i]], params, a);
+    dmat2 Gi, D[3];
+    const int na = gate_full2(gates[lst[b + i]].op, a, Gi, D);
+    dmat2 A = dmat2::identity();  // G_L ... G_{i+1}
+    for (int m = i + 1; m < L; ++m) A = mat_mul(G[m], A);
+    for (int j = 0; j < na && slot < 4; ++j, ++slot) {
+      const dmat2 X = mat_mul(A, mat_mul(D[j], B));
+      for (int r = 0; r < 4; ++r) out[4 * slot + r] = X.m[r];
+    }
+    B = mat_mul(Gi, B);
+  }
+  return true;
+}
+
 // Schedule records, op lists and slot tables live in device (global) memory. Their
 // pointers are often read from device memory themselves (the per-circuit records of a
 // batch), and the compiler then only knows them as generic pointers: loads through them
@@ -328,7 +394,7 @@ struct DevCirc {
   const DevOp* ops;
   const tq_gate* gates;
   const int32_t* rec;        // forward: matrix recipes (kind, qa, qb, begin) + sentinel
-  const int32_t* rec_gates;  // forward: constituent gate indices
+  const int32_t* rec_gates;  // forward: constituent gate indices; adjoint: run table
   const int32_t* dslot;      // adjoint: per-op slot info
   const int32_t* pslot_ptr;  // adjoint: parameter -> slot CSR
   const int32_t* pslot_idx;

@@ -269,6 +269,16 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
           default: reg_mat_group<T, R, 15>(v, m); break;
         }
 #undef TQ_MATG_CASE
+        // the layer's register-register CZs as uniform sign flips
+        const uint32_t fl = (uint32_t)op.pa | ((uint32_t)op.pb << 8);
+        if (fl) {
+#pragma unroll
+          for (int j = 0; j < (1 << R); ++j)
+            if ((fl >> j) & 1u) {
+              v[j].x = flip_sign(v[j].x, 0x80000000u);
+              v[j].y = flip_sign(v[j].y, 0x80000000u);
+            }
+        }
         continue;
       }
       if (op.kind == K_ZG) {

@@ -74,9 +74,10 @@ struct DevOp {
                  // MATG: mask of the register bits, one matrix each, ascending
                  // ZG: register indices + 1 of up to two CZs whose partner is a thread or
                  //     tile bit (low and high nibble, 0 = none)
-  uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX); ZG: first CZ's partner
+  uint8_t pa;    // x-position of qa (DIAG/CZ) or of the control (CX); ZG: first CZ's partner;
+                 // MATG: sign flips after the matrices, mask over j, low byte
   uint8_t pb;    // x-position of qb (DIAG2/CZ); CX: control's register index + 1 (0 = none);
-                 // ZG: second CZ's partner
+                 // ZG: second CZ's partner; MATG: flip mask, high byte
   int32_t mat;   // matrix index (MATG: of the lowest bit's matrix, the rest follow);
                  // ZG: mask over register indices j of the sign flips of the
                  // register-register CZs
@@ -131,6 +132,12 @@ struct Schedule {
   std::vector<int32_t> pslot_ptr;     // CSR: parameter -> global slots (with pscale)
   std::vector<int32_t> pslot_idx;
   std::vector<double> pslot_scale;
+  // adjoint: runs of one-qubit gates on one qubit reversed as one op. Entries 0..n_gates are
+  // offsets into the list that follows them: [adj_runs[k], adj_runs[k+1]) are the gates
+  // (forward order) whose product the op at gate k applies; empty for a gate inside
+  // another gate's run, {k} for a gate on its own.
+  std::vector<int32_t> adj_runs;
+  void* d_adj_runs = nullptr;
   void* d_dslot = nullptr;
   void* d_pslot_ptr = nullptr;
   void* d_pslot_idx = nullptr;
@@ -151,7 +158,7 @@ struct Schedule {
 void lower_ops(const tq_gate* g, int n_gates, int n, bool fuse, std::vector<Recipe>& recipes,
                std::vector<HostOp>& ops);
 void build_stages(Schedule& s);
-void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops);
+void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops, std::vector<int32_t>& runs);
 void build_adjoint_slots(Schedule& s, const tq_gate* g, int n_gates);
 tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params);
 int gate_n_angles(int op);
