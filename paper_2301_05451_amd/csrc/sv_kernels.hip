@@ -294,13 +294,13 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
               v[j].y = flip_sign(v[j].y, 0x80000000u);
             }
         } else {
-          const uint32_t s1 = idx_bit(op.pa, tp, t, tile) << 31;
-          const uint32_t s2 = k2 >= 0 ? idx_bit(op.pb, tp, t, tile) << 31 : 0u;
+          // this thread's flip mask over j, then bit j moved to the sign position
+          uint32_t f = uni;
+          if (idx_bit(op.pa, tp, t, tile)) f ^= reg_mask(k1);
+          if (k2 >= 0 && idx_bit(op.pb, tp, t, tile)) f ^= reg_mask(k2);
 #pragma unroll
           for (int j = 0; j < (1 << R); ++j) {
-            uint32_t sg = ((uni >> j) & 1u) << 31;
-            if ((j >> k1) & 1) sg ^= s1;
-            if (k2 >= 0 && ((j >> k2) & 1)) sg ^= s2;
+            const uint32_t sg = (f << (31 - j)) & 0x80000000u;
             v[j].x = flip_sign(v[j].x, sg);
             v[j].y = flip_sign(v[j].y, sg);
           }
