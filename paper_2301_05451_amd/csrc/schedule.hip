@@ -409,8 +409,18 @@ void build_stages(Schedule& s) {
         }
         pd.push_back(d);
       }
-      if (group) emit_layered(pd, R, remap, n_mapped, s.dops);
-      else s.dops.insert(s.dops.end(), pd.begin(), pd.end());
+      if (group) {
+        emit_layered(pd, R, remap, n_mapped, s.dops);
+        // the stage kernel takes grouped phases' ops two at a time: pad to an even count
+        // with a sign group that flips nothing
+        if ((s.dops.size() - (size_t)ph.op_begin) % 2 != 0) {
+          DevOp z{};
+          z.kind = K_ZG;
+          s.dops.push_back(z);
+        }
+      } else {
+        s.dops.insert(s.dops.end(), pd.begin(), pd.end());
+      }
       ph.op_end = (int)s.dops.size();
       s.phases.push_back(ph);
       st.n_ops += (int)ptaken.size();

@@ -248,13 +248,10 @@ __device__ __forceinline__ void reg_mat_group(typename Cx<T>::type (&v)[1 << R],
 }
 
 template <typename T, int R>
-__device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], uint32_t tp,
-                                                const DevOp* __restrict__ ops, int ob, int oe,
-                                                const typename Cx<T>::type* __restrict__ M, int t,
-                                                uint32_t tile) {
+__device__ __forceinline__ void apply_op(typename Cx<T>::type (&v)[1 << R], const DevOp op, uint32_t tp,
+                                         const typename Cx<T>::type* __restrict__ M, int t, uint32_t tile) {
   using C = typename Cx<T>::type;
-  for (int o = ob; o < oe; ++o) {
-    const DevOp op = load_op(ops, o);
+  {
     if constexpr (R <= 4) {
       if (op.kind == K_MATG) {
         const C* m = M + 4 * (int64_t)op.mat;
@@ -279,7 +276,7 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
               v[j].y = flip_sign(v[j].y, 0x80000000u);
             }
         }
-        continue;
+        return;
       }
       if (op.kind == K_ZG) {
         // sign flips: uniform ones from the register-register CZs, per-thread ones from up
@@ -305,7 +302,7 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
             v[j].y = flip_sign(v[j].y, sg);
           }
         }
-        continue;
+        return;
       }
     }
     C m0{}, m1{}, m2{}, m3{};
@@ -358,6 +355,25 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
         v[j] = cmul(f, v[j]);
       }
     }
+  }
+}
+
+// A phase's ops in order. Forward schedules with grouped layers (R <= 4) pad every phase
+// to an even op count, and the loop takes two ops per trip: the first op's results can then
+// live in other registers than the loop-carried ones and the second op's results land back
+// in them, instead of every trip ending with a copy of all amplitudes.
+template <typename T, int R>
+__device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R], uint32_t tp,
+                                                const DevOp* __restrict__ ops, int ob, int oe,
+                                                const typename Cx<T>::type* __restrict__ M, int t,
+                                                uint32_t tile) {
+  if constexpr (R <= 4) {
+    for (int o = ob; o < oe; o += 2) {
+      apply_op<T, R>(v, load_op(ops, o), tp, M, t, tile);
+      apply_op<T, R>(v, load_op(ops, o + 1), tp, M, t, tile);
+    }
+  } else {
+    for (int o = ob; o < oe; ++o) apply_op<T, R>(v, load_op(ops, o), tp, M, t, tile);
   }
 }
 

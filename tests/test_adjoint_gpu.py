@@ -149,3 +149,34 @@ def test_backward_validation():
         lib.sv_backward(psi, params, spec, W.zterms([([0], 1.0, 3)]), 1, torch.ones(1, 1, device="cuda"))
     with pytest.raises(lib.TQError):
         lib.sv_backward(psi, params, spec, c.terms, 1, torch.ones(1, 1, device="cuda"), reg_bits=7)
+
+
+@pytest.mark.parametrize("name", ["c64", "c128"])
+def test_one_qubit_runs_vs_param_shift(name):
+    """Long runs of one-qubit gates on each qubit (diagonal, fixed and parameterised gates,
+    one to three angles each) separated by two-qubit gates: the reverse sweep takes up to
+    three angles' worth of a run as one op, so runs are split at every angle count."""
+    rng = np.random.default_rng(77)
+    one_q = [W.H, W.X, W.Y, W.Z, W.RX, W.RY, W.RZ, W.U3, W.ROT]
+    terms = W.zterms([([0], 1.0, 0), ([1, 2], 0.6, 0)])
+    for n in [3, 6, 9]:
+        g = W.GateList()
+        n_params = 10
+        for layer in range(4):
+            for q in range(n):
+                for _ in range(int(rng.integers(1, 9))):
+                    op = int(rng.choice(one_q))
+                    na = W.N_ANGLES[op]
+                    g.add(op, [q], [int(rng.integers(n_params)) for _ in range(na)],
+                          [float(rng.choice([1.0, -0.5, 2.0])) for _ in range(na)])
+            for q in range(layer % 2, n - 1, 2):
+                op2 = int(rng.choice([W.CNOT, W.CZ, W.RZZ]))
+                na2 = W.N_ANGLES[op2]
+                g.add(op2, [q, q + 1], [int(rng.integers(n_params))] * na2, [1.0] * na2)
+        c = W.Circuit(n, g.array(), W.f32_angles(rng, n_params, 0.0, 2 * math.pi), 1, terms)
+        print(f"adjoint runs n={n} {name} gates={len(c.gates)}", flush=True)
+        _, got = _adjoint([c], name, terms, 1, [[1.0]])
+        want = osv.param_shift_grad(c)
+        err = np.abs(got - want).max()
+        print(f"  max|d grad| = {err:.2e}", flush=True)
+        assert err <= 4 * TOL[name], (n, err)
