@@ -12,6 +12,19 @@ namespace tq {
 
 constexpr int kExpThreads = 256;
 
+// +1 or -1 built from the parity bit with integer operations (a wave-uniform parity stays in
+// scalar registers, so the multiply-add takes it as a scalar operand)
+template <typename T>
+__device__ __forceinline__ T unit_sign(uint32_t parity);
+template <>
+__device__ __forceinline__ float unit_sign<float>(uint32_t parity) {
+  return __uint_as_float(0x3f800000u | (parity << 31));
+}
+template <>
+__device__ __forceinline__ double unit_sign<double>(uint32_t parity) {
+  return __longlong_as_double((long long)(0x3ff0000000000000ull | ((unsigned long long)parity << 63)));
+}
+
 template <typename T, int KT>
 __global__ void __launch_bounds__(kExpThreads)
     expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int pb,
@@ -27,13 +40,22 @@ __global__ void __launch_bounds__(kExpThreads)
     mlo[k] = k < nk ? (uint32_t)(pmask[k] & lo_mask) : 0u;
     acc[k] = (T)0;
   }
+  // loc = tid + kExpThreads * i: the low bits (the thread id) give one sign per term and
+  // thread, applied at the end; the high bits (i) give a sign per term that every lane
+  // shares, so each amplitude costs one multiply-add per term
   const uint32_t namp = 1u << pb;
-  for (uint32_t loc = threadIdx.x; loc < namp; loc += kExpThreads) {
-    const C a = s[base + loc];
-    const T p = a.x * a.x + a.y * a.y;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t hi = 0; hi < namp; hi += kExpThreads) {
+    if (tid < namp) {
+      const C a = s[base + hi + tid];
+      const T p = a.x * a.x + a.y * a.y;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) acc[k] += (__popc(loc & mlo[k]) & 1) ? -p : p;
+      for (int k = 0; k < KT; ++k) acc[k] = fma(unit_sign<T>(__popc(hi & mlo[k]) & 1u), p, acc[k]);
+    }
   }
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if (__popc(tid & mlo[k]) & 1) acc[k] = -acc[k];
   __shared__ double red[kExpThreads / 64][KT];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -65,6 +87,7 @@ __global__ void __launch_bounds__(kExpThreads)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int k = wv; k < nk; k += kExpThreads / 64) {
     double x = 0.0;
+#pragma unroll 8
     for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * nblocks + b) * KT + k];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0) sk[k] = x;
