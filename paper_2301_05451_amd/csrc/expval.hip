@@ -45,6 +45,7 @@ __global__ void __launch_bounds__(kExpThreads)
   // shares, so each amplitude costs one multiply-add per term
   const uint32_t namp = 1u << pb;
   const uint32_t tid = threadIdx.x;
+#pragma unroll 8
   for (uint32_t hi = 0; hi < namp; hi += kExpThreads) {
     if (tid < namp) {
       const C a = s[base + hi + tid];
@@ -60,9 +61,11 @@ __global__ void __launch_bounds__(kExpThreads)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    double x = (double)acc[k];
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) red[wv][k] = x;
+    if (k < nk) {  // terms past nk (the template's padding) are not reduced
+      double x = (double)acc[k];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) red[wv][k] = x;
+    }
   }
   __syncthreads();
   if (threadIdx.x < nk && threadIdx.x < KT) {
@@ -70,12 +73,13 @@ __global__ void __launch_bounds__(kExpThreads)
     double x = 0.0;
     for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][k];
     const bool hi_odd = __popcll(base & pmask[k]) & 1;
-    partial[((int64_t)blockIdx.y * nblocks + blockIdx.x) * KT + k] = hi_odd ? -x : x;
+    partial[((int64_t)blockIdx.y * KT + k) * nblocks + blockIdx.x] = hi_odd ? -x : x;
   }
 }
 
 // One work-group per circuit. Each wave sums the block partials of one term at a time
-// (lane-strided, then a butterfly: a fixed order), and thread 0 accumulates coeff * S_k into
+// (stored term-major, so a wave's loads are contiguous; lane-strided, then a butterfly: a
+// fixed order), and thread 0 accumulates coeff * S_k into
 // its observable in term order. Circuit i of the launch writes output row rows.at(i).
 template <typename T, int KT>
 __global__ void __launch_bounds__(kExpThreads)
@@ -88,7 +92,7 @@ __global__ void __launch_bounds__(kExpThreads)
   for (int k = wv; k < nk; k += kExpThreads / 64) {
     double x = 0.0;
 #pragma unroll 8
-    for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * nblocks + b) * KT + k];
+    for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * KT + k) * nblocks + b];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0) sk[k] = x;
   }
