@@ -275,7 +275,9 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
         }
     }
     const int o_end = (int)pw[1];
-    for (int o = (int)pw[0]; o < o_end; ++o) {
+    // one op of the phase; two per loop trip, so that the loop-carried amplitudes need no
+    // register copies at the end of every trip
+    auto do_op = [&](int o) {
       const DevOp op = load_op(ops, o);
       const int sl_info = gptr(dslot)[o];
       const int na = sl_info & 3, s0 = sl_info >> 2;
@@ -345,6 +347,10 @@ __device__ __forceinline__ void adj_tile(const DevStage* __restrict__ stg, const
           if (lane == 0 && wv < nwaves) red[(s0 + q) * nwaves + wv] = s;
         }
       }
+    };
+    for (int o = (int)pw[0]; o < o_end; o += 2) {
+      do_op(o);
+      if (o + 1 < o_end) do_op(o + 1);
     }
   }
   // store both tiles in the load layout
