@@ -125,12 +125,37 @@ __device__ __forceinline__ int64_t deposit_bits(uint64_t v, const uint8_t* pos, 
 // the low kt summed bits come from LDS tables built by the whole work-group.
 constexpr int kTnTabBits = 9;
 
+// Per-step LDS state of a work-group: the step record itself (its position bytes would
+// otherwise be re-read from device memory one byte per bit, each a memory round trip) and
+// offset tables of the low 16 output bits in X and Y, 8 bits per table.
+struct TnStepLds {
+  DevTnStep st;
+  int64_t ox[2][256], oy[2][256];
+};
+static_assert(sizeof(DevTnStep) % 4 == 0, "word copy of the step record");
+
+// Work-group-wide: stage the step, then build the summed-bit tables (tx, ty) and the
+// output-bit tables. The caller synchronises before using them.
 template <typename T>
-__device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ st, int64_t* tx, int64_t* ty) {
+__device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ gst, TnStepLds* L, int64_t* tx,
+                                                int64_t* ty) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(gst);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&L->st);
+  for (int i = threadIdx.x; i < (int)(sizeof(DevTnStep) / 4); i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  const DevTnStep* st = &L->st;
   const int kt = st->ks < kTnTabBits ? st->ks : kTnTabBits;
   for (int i = threadIdx.x; i < (1 << kt); i += blockDim.x) {
     tx[i] = deposit_bits((uint64_t)i, st->xs, kt);
     ty[i] = deposit_bits((uint64_t)i, st->ys, kt);
+  }
+  const int z0 = st->zr < 8 ? st->zr : 8;
+  const int z1 = st->zr < 8 ? 0 : (st->zr < 16 ? st->zr - 8 : 8);
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+    L->ox[0][i] = deposit_bits((uint64_t)i, st->xo, z0);
+    L->oy[0][i] = deposit_bits((uint64_t)i, st->yo, z0);
+    L->ox[1][i] = deposit_bits((uint64_t)i, st->xo + 8, z1);
+    L->oy[1][i] = deposit_bits((uint64_t)i, st->yo + 8, z1);
   }
 }
 
@@ -139,13 +164,14 @@ __device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ st
 // Summed assignments are walked as outer chunks so0 .. so1 of the table (all of them by
 // default); output e goes to z[e * zstride] (zstride > 1: partial sums of one chunk range).
 template <typename T>
-__device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st, const int64_t* tx,
+__device__ __forceinline__ void tn_step_outputs(const TnStepLds* L, const int64_t* tx,
                                                 const int64_t* ty, const typename Cx<T>::type* __restrict__ x,
                                                 const typename Cx<T>::type* __restrict__ y,
                                                 typename Cx<T>::type* __restrict__ z, int tb, int64_t gfirst,
                                                 int64_t gstride, T* red, int64_t so0 = 0, int64_t so1 = -1,
                                                 int64_t zstride = 1) {
   using C = typename Cx<T>::type;
+  const DevTnStep* st = &L->st;
   const int zr = st->zr, ks = st->ks;
   const int kt = ks < kTnTabBits ? ks : kTnTabBits;
   const int nt = 1 << kt;
@@ -160,8 +186,12 @@ __device__ __forceinline__ void tn_step_outputs(const DevTnStep* __restrict__ st
     const bool valid = e < nz;
     T ar = 0, ai = 0;
     if (valid) {
-      const int64_t xb = deposit_bits((uint64_t)e, st->xo, zr);
-      const int64_t yb = deposit_bits((uint64_t)e, st->yo, zr);
+      int64_t xb = L->ox[0][e & 255] + L->ox[1][(e >> 8) & 255];
+      int64_t yb = L->oy[0][e & 255] + L->oy[1][(e >> 8) & 255];
+      if (zr > 16) {
+        xb |= deposit_bits((uint64_t)e >> 16, st->xo + 16, zr - 16);
+        yb |= deposit_bits((uint64_t)e >> 16, st->yo + 16, zr - 16);
+      }
       for (int64_t so = so0; so < nouter; ++so) {
         const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
         const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
@@ -214,18 +244,19 @@ __global__ void __launch_bounds__(256)
                      int64_t zs, int tb, int kb, int rb, typename Cx<T>::type* __restrict__ P, int64_t ps) {
   __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
   __shared__ T red[16];
-  tn_build_tables<T>(st, tx, ty);
+  __shared__ TnStepLds L;
+  tn_build_tables<T>(st, &L, tx, ty);
   __syncthreads();
   const typename Cx<T>::type* x = X + xs * blockIdx.y;
   const typename Cx<T>::type* y = Y + ys * blockIdx.y;
   if (kb == 0) {
-    tn_step_outputs<T>(st, tx, ty, x, y, Z + zs * blockIdx.y, tb, blockIdx.x, gridDim.x, red);
+    tn_step_outputs<T>(&L, tx, ty, x, y, Z + zs * blockIdx.y, tb, blockIdx.x, gridDim.x, red);
     return;
   }
-  const int kt = st->ks < kTnTabBits ? st->ks : kTnTabBits;
-  const int64_t per = (int64_t(1) << (st->ks - kt)) >> kb;  // outer chunks per split
+  const int kt = L.st.ks < kTnTabBits ? L.st.ks : kTnTabBits;
+  const int64_t per = (int64_t(1) << (L.st.ks - kt)) >> kb;  // outer chunks per split
   const int64_t c = blockIdx.x / rb;
-  tn_step_outputs<T>(st, tx, ty, x, y, P + ps * blockIdx.y + c, tb, blockIdx.x % rb, rb, red, c * per,
+  tn_step_outputs<T>(&L, tx, ty, x, y, P + ps * blockIdx.y + c, tb, blockIdx.x % rb, rb, red, c * per,
                      (c + 1) * per, int64_t(1) << kb);
 }
 
@@ -266,22 +297,21 @@ template <typename T>
 __device__ __forceinline__ void tn_run_list(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list,
                                             int n, const typename Cx<T>::type* __restrict__ leaves,
                                             typename Cx<T>::type* __restrict__ ws, int64_t c, int64_t* tx,
-                                            int64_t* ty, T* red) {
+                                            int64_t* ty, T* red, TnStepLds* L) {
   using C = typename Cx<T>::type;
   for (int k = 0; k < n; ++k) {
     const DevFused f = list[k];
-    const DevTnStep* st = steps + f.step;
     const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
     const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
     C* z = ws + f.zo + f.zs * c;
-    tn_build_tables<T>(st, tx, ty);
+    tn_build_tables<T>(steps + f.step, L, tx, ty);
     __syncthreads();
     // enough lanes per output to give the 256 threads work: 2^tb with tb = 8 - zr, capped
     // by the summed bits and at 8
-    int tb = 8 - st->zr;
+    int tb = 8 - L->st.zr;
     tb = tb < 0 ? 0 : tb;
-    tb = tb > st->ks ? st->ks : tb;
-    tn_step_outputs<T>(st, tx, ty, x, y, z, tb, 0, 1, red);
+    tb = tb > L->st.ks ? L->st.ks : tb;
+    tn_step_outputs<T>(L, tx, ty, x, y, z, tb, 0, 1, red);
     __syncthreads();
   }
 }
@@ -292,7 +322,8 @@ __global__ void __launch_bounds__(256)
                     const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
   __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
   __shared__ T red[16];
-  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x, tx, ty, red);
+  __shared__ TnStepLds L;
+  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x, tx, ty, red, &L);
 }
 
 // Many networks at once: items of one launch, one work-group each.
@@ -324,9 +355,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) tn_fused_multi_kernel(const DevFusedItem* __restrict__ items) {
   __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
   __shared__ T red[16];
+  __shared__ TnStepLds L;
   const DevFusedItem& d = items[blockIdx.x];
   tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0, tx,
-                 ty, red);
+                 ty, red, &L);
 }
 
 template <typename T>
