@@ -463,7 +463,6 @@ namespace tq {
 // the gates between its members act on other qubits and commute with it, so it sits at the
 // position of its last gate. Every other gate is its own op. mat holds the gate index of
 // the op's last gate (its matrix-table entry); nang the op's angle count.
-constexpr int kAdjMaxRun = 8;
 static bool adj_one_qubit(int op) { return op != TQ_CNOT && op != TQ_CZ && op != TQ_RZZ; }
 
 void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops, std::vector<int32_t>& runs) {

@@ -234,7 +234,6 @@ __device__ inline int gate_full2(int op, const double* a, dmat2& U, dmat2 (&D)[3
   return na;
 }
 
-constexpr int kAdjRunMax = 8;  // gates in one reversed run (the schedule's limit)
 
 // Matrix-table entry of the reverse-sweep op at gate k (runs as in the adjoint schedule: n
 // offsets + 1, then the gate lists). A gate on its own keeps its own U and dU/da_j. A run
@@ -254,8 +253,8 @@ __device__ inline bool adj_entry(const tq_gate* gates, int n_gates, const int32_
     return true;
   }
   const int32_t* lst = runs + n_gates + 1;
-  const int L = e - b < kAdjRunMax ? e - b : kAdjRunMax;
-  dmat2 G[kAdjRunMax];
+  const int L = e - b < kAdjMaxRun ? e - b : kAdjMaxRun;
+  dmat2 G[kAdjMaxRun];
   for (int i = 0; i < L; ++i) {
     double a[3];
     gate_angles(gates[lst[b + i]], params, a);

@@ -85,6 +85,8 @@ struct DevOp {
 static_assert(sizeof(DevOp) == 8, "DevOp layout");
 
 constexpr int kMaxReg = 6;
+// Reverse sweep: most one-qubit gates reversed as one op (a run on one qubit).
+constexpr int kAdjMaxRun = 8;
 struct DevPhase {
   int32_t op_begin, op_end;
   int32_t xchg;      // 1: the register layout differs from the previous one (LDS exchange)
