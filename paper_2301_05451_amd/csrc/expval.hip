@@ -2,10 +2,11 @@
 // <O_o> = sum over terms k with obs_k = o of coeff_k * sum_x |psi_x|^2 (-1)^popcount(x & m_k).
 //
 // A work-group owns 2^pb contiguous amplitudes, so the index bits at and above pb are fixed
-// per group: their parity is one uniform sign per term, and each amplitude only needs a
-// 32-bit popcount of its low bits. Per-thread sums run in the state's precision over a
-// few dozen amplitudes; everything above (waves, the group, the groups of a circuit) is a
-// fixed-order double tree, so repeated runs are bitwise equal.
+// per group: their parity is one uniform sign per term. Below pb, a thread holds up to 32
+// amplitudes (index = it * 256 + thread id); the sums of all terms over them are read off
+// one Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's precision.
+// Everything above (waves, the group, the groups of a circuit) is a fixed-order double
+// tree, so repeated runs are bitwise equal.
 #include "sv_device.h"
 
 namespace tq {
@@ -40,23 +41,52 @@ __global__ void __launch_bounds__(kExpThreads)
     mlo[k] = k < nk ? (uint32_t)(pmask[k] & lo_mask) : 0u;
     acc[k] = (T)0;
   }
-  // loc = tid + kExpThreads * i: the low bits (the thread id) give one sign per term and
-  // thread, applied at the end; the high bits (i) give a sign per term that every lane
-  // shares, so each amplitude costs one multiply-add per term
+  // loc = it * 256 + tid. The thread id (low 8 bits) gives one sign per term and thread,
+  // applied at the end. Over the iteration bits, a term's sum is one coefficient of the
+  // Walsh-Hadamard transform of the thread's |psi|^2 values: W[u] = sum_it (-1)^{|it & u|}
+  // p[it], with u the term's mask bits at 8 and above. So each thread loads its values,
+  // transforms them in registers (it has at most 2^(13-8) = 32 of them) and reads one
+  // coefficient per term.
+  constexpr int kMaxIt = 32;
   const uint32_t namp = 1u << pb;
   const uint32_t tid = threadIdx.x;
-#pragma unroll 8
-  for (uint32_t hi = 0; hi < namp; hi += kExpThreads) {
-    if (tid < namp) {
-      const C a = s[base + hi + tid];
-      const T p = a.x * a.x + a.y * a.y;
+  const int lg = pb > 8 ? pb - 8 : 0;
+  const int nit = 1 << lg;
+  // straight-line: out-of-range slots load a valid (clamped) address and count as zero, and
+  // the full 32-point transform of the zero-padded values gives the same coefficients
+  const uint32_t tcl = tid & (namp - 1);
+  T pv[kMaxIt];
 #pragma unroll
-      for (int k = 0; k < KT; ++k) acc[k] = fma(unit_sign<T>(__popc(hi & mlo[k]) & 1u), p, acc[k]);
-    }
+  for (int it = 0; it < kMaxIt; ++it) {
+    const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
+    const C a = s[base + (itc << 8) + tcl];
+    const T p = a.x * a.x + a.y * a.y;
+    pv[it] = (it < nit && tid < namp) ? p : (T)0;
   }
 #pragma unroll
-  for (int k = 0; k < KT; ++k)
-    if (__popc(tid & mlo[k]) & 1) acc[k] = -acc[k];
+  for (int h = 1; h < kMaxIt; h <<= 1) {
+#pragma unroll
+    for (int i = 0; i < kMaxIt; ++i)
+      if ((i & h) == 0) {
+        const T a = pv[i], b = pv[i | h];
+        pv[i] = a + b;
+        pv[i | h] = a - b;
+      }
+  }
+  // coefficient u of this thread at wsh[u][tid] (a term's index u is the same for every
+  // lane, so the lanes read consecutive words)
+  __shared__ T wsh[kMaxIt][kExpThreads];
+#pragma unroll
+  for (int it = 0; it < kMaxIt; ++it)
+    if (it < nit) wsh[it][tid] = pv[it];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    if (k < nk) {
+      const uint32_t u = (mlo[k] >> 8) & (uint32_t)(nit - 1);
+      const T w = wsh[u][tid];
+      acc[k] = (__popc(tid & mlo[k] & 0xffu) & 1) ? -w : w;
+    }
+  }
   __shared__ double red[kExpThreads / 64][KT];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -117,6 +147,8 @@ static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, in
                      n_obs, outacc, first, last, out, rows);
 }
 
+// A work-group sums 2^13 amplitudes at most: 256 threads x 32 values per thread, the size of
+// the per-thread transform in expval_partial_kernel.
 int expval_block_bits(int n) { return n < 13 ? n : 13; }
 
 size_t expval_scratch_doubles(int n, int count, int n_obs) {
