@@ -26,6 +26,31 @@ __device__ __forceinline__ double unit_sign<double>(uint32_t parity) {
   return __longlong_as_double((long long)(0x3ff0000000000000ull | ((unsigned long long)parity << 63)));
 }
 
+// v + (v moved across lanes by the data-parallel-primitive control CTRL), in double: both
+// 32-bit halves move with the same control; rows outside ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffull), CTRL, ROWS, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return v + __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a full wave in a fixed order (pairs in quads, half-row and row
+// mirrors, then row broadcasts); every lane gets the total of lane 63.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v = dpp_add_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add_f64<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add_f64<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffull), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <typename T, int KT>
 __global__ void __launch_bounds__(kExpThreads)
     expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int pb,
@@ -92,8 +117,7 @@ __global__ void __launch_bounds__(kExpThreads)
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     if (k < nk) {  // terms past nk (the template's padding) are not reduced
-      double x = (double)acc[k];
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      const double x = wave_sum_f64((double)acc[k]);  // the work-group is four full waves
       if (lane == 0) red[wv][k] = x;
     }
   }
