@@ -12,6 +12,7 @@
 namespace tq {
 
 constexpr int kExpThreads = 256;
+constexpr int kExpFinalThreads = 1024;  // final sums: one wave per term for up to 16 terms at once
 
 // +1 or -1 built from the parity bit with integer operations (a wave-uniform parity stays in
 // scalar registers, so the multiply-add takes it as a scalar operand)
@@ -136,14 +137,14 @@ __global__ void __launch_bounds__(kExpThreads)
 // fixed order), and thread 0 accumulates coeff * S_k into
 // its observable in term order. Circuit i of the launch writes output row rows.at(i).
 template <typename T, int KT>
-__global__ void __launch_bounds__(kExpThreads)
+__global__ void __launch_bounds__(kExpFinalThreads)
     expval_final_kernel(const double* __restrict__ partial, int nblocks, int nk, const double* __restrict__ coeff,
                         const int32_t* __restrict__ obs, int n_obs, double* __restrict__ outacc, int first,
                         int last, T* __restrict__ out, BatchMap rows) {
   __shared__ double sk[KT];
   const int circ = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < nk; k += kExpThreads / 64) {
+  for (int k = wv; k < nk; k += kExpFinalThreads / 64) {
     double x = 0.0;
 #pragma unroll 8
     for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * KT + k) * nblocks + b];
@@ -167,7 +168,7 @@ static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, in
                          double* outacc, int first, int last, T* out, BatchMap rows, hipStream_t stream) {
   hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
                      d_states, smap, pb, pm, nk, partial, nblocks);
-  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3(cn), dim3(kExpThreads), 0, stream, partial, nblocks, nk, cf, ob,
+  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3(cn), dim3(kExpFinalThreads), 0, stream, partial, nblocks, nk, cf, ob,
                      n_obs, outacc, first, last, out, rows);
 }
 
