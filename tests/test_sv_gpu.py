@@ -198,3 +198,27 @@ def test_brickwork24_full_size_in_bench_configuration():
     for q in range(n):
         pc += ((idx >> q) & 1).double()
     assert abs(f - (p * (n - 2 * pc)).sum().item()) <= 1e-4
+
+
+@pytest.mark.parametrize("name,n", [("c64", 14), ("c64", 20), ("c128", 17)])
+def test_expval_random_z_strings_many_blocks(name, n):
+    """Random multi-qubit Z-strings (qubits anywhere in the index, so every block and every
+    per-thread bit group of the reduction contributes signs) on a random state, several
+    observables, against the oracle's expectation values of the same amplitudes."""
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(100 + n)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    v /= np.linalg.norm(v)
+    cdt = torch.complex64 if name == "c64" else torch.complex128
+    psi = torch.tensor(v, dtype=cdt, device="cuda")
+    spec = lib.BatchSpec.uniform(n, W.GateList().array(), 1, 1)
+    spec_terms = []
+    for k in range(27):
+        qs = sorted(int(q) for q in rng.choice(n, size=int(rng.integers(1, min(n, 6) + 1)), replace=False))
+        spec_terms.append((qs, float(rng.normal()), k % 3))
+    terms = W.zterms(spec_terms)
+    got = lib.expval(psi, spec, terms, 3).cpu().numpy()[0]
+    want = osv.expvals(psi.cpu().numpy().astype(np.complex128), n, terms, 3)
+    tol = 1e-5 if name == "c64" else 1e-12
+    assert np.abs(got - want).max() <= tol * max(1.0, np.abs(want).max()), (got, want)
