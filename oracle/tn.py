@@ -147,23 +147,101 @@ def circuit_zexp_tn(c: W.Circuit, zqubits, sliced=(), init=None):
 
 
 # ---- QAOA --------------------------------------------------------------------------
+#
+# The value <Z_i Z_j> only depends on the gates in the reverse causal cone of {i, j}: walking
+# the circuit backwards, a gate belongs to the cone iff it touches a qubit already in it, and
+# then its qubits join. Every other gate commutes past the observable and meets its own
+# inverse in <psi| ... |psi> (the light-cone reduction the paper lists as the first step of
+# its tensor-network mode, Sec. 3.2). For a QAOA circuit this cone holds the graph nodes
+# within distance p of the edge (each cost layer widens it by one graph step).
+
+
+def _is_diagonal(g):
+    """Whether a gate's matrix (the oracle's own, at a generic angle) is diagonal."""
+    U = sv.gate_matrix(int(g["op"]), [0.731, 1.913, 2.377])
+    return bool(np.all(U[~np.eye(U.shape[0], dtype=bool)] == 0))
+
+
+def cone_circuit(c: W.Circuit, qubits):
+    """Sub-circuit of the reverse causal cone of ``qubits``, relabelled onto the cone's
+    qubits in increasing order. Returns (circuit, cone qubit list).
+
+    Walking backwards, a gate is kept iff it touches the cone, and its qubits join the
+    cone. Diagonal gates commute with each other and with a Z-string observable, so a
+    maximal run of consecutive diagonal gates is one commuting block: each gate of the
+    block is tested against the cone as it stood after the block, and the qubits of the
+    kept ones join afterwards (a gate that misses that cone can be moved past the whole
+    block and then cancels against its conjugate)."""
+    cone = set(int(q) for q in qubits)
+    keep = []
+    k = len(c.gates) - 1
+    while k >= 0:
+        if not _is_diagonal(c.gates[k]):
+            qs = sv.gate_qubits(c.gates[k])
+            if cone.intersection(qs):
+                keep.append(k)
+                cone.update(qs)
+            k -= 1
+            continue
+        block = []
+        while k >= 0 and _is_diagonal(c.gates[k]):
+            block.append(k)
+            k -= 1
+        joined = set()
+        for b in block:
+            qs = sv.gate_qubits(c.gates[b])
+            if cone.intersection(qs):
+                keep.append(b)
+                joined.update(qs)
+        cone |= joined
+    order = sorted(cone)
+    pos = {q: i for i, q in enumerate(order)}
+    keep.sort()
+    gates = c.gates[np.array(keep, dtype=np.int64)].copy() if keep else c.gates[:0].copy()
+    for k in range(len(gates)):
+        nq = W.N_QUBITS[int(gates[k]["op"])]
+        gates["q"][k, :nq] = [pos[int(q)] for q in gates["q"][k, :nq]]
+    return W.Circuit(len(order), gates, c.params.copy()), order
+
+
+def graph_ball(n, edges, centre, radius):
+    """Graph nodes within ``radius`` steps of any node of ``centre`` (breadth-first)."""
+    nbr = [[] for _ in range(n)]
+    for a, b in edges:
+        nbr[a].append(b)
+        nbr[b].append(a)
+    dist = {int(v): 0 for v in centre}
+    frontier = list(dist)
+    for d in range(1, radius + 1):
+        nxt = []
+        for v in frontier:
+            for w in nbr[v]:
+                if w not in dist:
+                    dist[w] = d
+                    nxt.append(w)
+        frontier = nxt
+    return sorted(dist)
+
+
+def qaoa_cone(prob: W.QAOAProblem, edge, gammas=None, betas=None):
+    """(cone circuit, position of edge[0], position of edge[1], cone qubits)."""
+    pr = prob if gammas is None else W.QAOAProblem(prob.n, prob.edges, prob.p, np.asarray(gammas),
+                                                    np.asarray(betas))
+    c, order = cone_circuit(W.qaoa_circuit(pr), edge)
+    return c, order.index(edge[0]), order.index(edge[1]), order
+
 
 def qaoa_edge_zz_sv(prob: W.QAOAProblem, edge, gammas=None, betas=None):
     """<Z_i Z_j> for one edge by state-vector evolution of its light-cone qubits."""
-    cone = W.light_cone_nodes(prob, edge)
-    pr = prob if gammas is None else W.QAOAProblem(prob.n, prob.edges, prob.p, np.asarray(gammas), np.asarray(betas))
-    c = W.qaoa_circuit(pr, cone)
+    c, i, j, _ = qaoa_cone(prob, edge, gammas, betas)
     psi = sv.run(c.n, c.gates, c.params)
-    i, j = cone.index(edge[0]), cone.index(edge[1])
     return float(np.dot(np.abs(psi) ** 2, sv.zstring_diag(c.n, [i, j])))
 
 
 def qaoa_edge_zz_tn(prob: W.QAOAProblem, edge, sliced_count=0):
     """<Z_i Z_j> for one edge by contracting the light-cone doubled network; optionally
     slicing the first ``sliced_count`` labels of the initial ket legs."""
-    cone = W.light_cone_nodes(prob, edge)
-    c = W.qaoa_circuit(prob, cone)
-    i, j = cone.index(edge[0]), cone.index(edge[1])
+    c, i, j, _ = qaoa_cone(prob, edge)
     net = expectation_network(c.n, c.gates, c.params, [i, j])
     sliced = list(range(sliced_count))
     return contract(net.tensors, sliced)

@@ -51,22 +51,39 @@ class Network:
     output: List[int]
     gates: np.ndarray      # the circuit's gate records (the leaves refer to them)
     params: np.ndarray     # parameter vector
-
-
-def light_cone(gates, qubits):
-    """Indices of the gates in the reverse causal cone of ``qubits`` (program order)."""
-    cone = set(qubits)
-    keep = []
-    for k in range(len(gates) - 1, -1, -1):
-        g = gates[k]
-        qs = [int(q) for q in g["q"][: W.N_QUBITS[int(g["op"])]]]
-        if cone & set(qs):
-            keep.append(k)
-            cone |= set(qs)
-    return keep[::-1], cone
+    qubits: List[int] = dataclasses.field(default_factory=list)  # register qubits the network keeps
 
 
 _DIAG = {W.Z, W.RZ, W.CZ, W.RZZ}
+
+
+def light_cone(gates, qubits):
+    """Indices of the gates in the reverse causal cone of ``qubits`` (program order), and
+    the cone's qubits. Diagonal gates commute with one another and with the Z observable:
+    within a run of consecutive diagonal gates, membership is decided against the cone as
+    it stands after the run, so a cost layer of RZZ gates widens a QAOA cone by one graph
+    step (nodes within distance p of the measured edge)."""
+    cone = set(qubits)
+    keep = []
+    pending, grow = False, set()
+    for k in range(len(gates) - 1, -1, -1):
+        g = gates[k]
+        op = int(g["op"])
+        qs = [int(q) for q in g["q"][: W.N_QUBITS[op]]]
+        if op in _DIAG:
+            pending = True
+            if cone & set(qs):
+                keep.append(k)
+                grow |= set(qs)
+            continue
+        if pending:
+            cone |= grow
+            pending, grow = False, set()
+        if cone & set(qs):
+            keep.append(k)
+            cone |= set(qs)
+    cone |= grow
+    return keep[::-1], cone
 
 
 def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
@@ -125,15 +142,15 @@ def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
                 ren[i] = len(ren)
     for lf in leaves:
         lf.inds = [ren[i] for i in lf.inds]
-    return Network(leaves, len(ren), [], gates, c.params)
+    return Network(leaves, len(ren), [], gates, c.params, used)
 
 
 def qaoa_edge_network(prob: W.QAOAProblem, edge):
-    """<Z_i Z_j> network of one edge: the light-cone circuit, then the doubled network."""
-    cone = W.light_cone_nodes(prob, edge)
-    c = W.qaoa_circuit(prob, cone)
-    i, j = cone.index(edge[0]), cone.index(edge[1])
-    return circuit_network(c, [i, j], use_light_cone=True), cone
+    """<Z_i Z_j> network of one edge of a QAOA graph: the whole-register circuit reduced to
+    the reverse light cone of the edge's two qubits, then doubled. The cone's qubits are
+    the graph nodes within distance p of the edge. Returns (network, cone qubits)."""
+    net = circuit_network(W.qaoa_circuit(prob), list(edge), use_light_cone=True)
+    return net, list(net.qubits)
 
 
 # ---- contraction trees -----------------------------------------------------------------

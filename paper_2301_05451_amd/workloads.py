@@ -222,42 +222,20 @@ def qaoa_maxcut(n=50, p=4, seed=1005):
     return QAOAProblem(n, edges, p, gam, bet)
 
 
-def qaoa_circuit(prob: QAOAProblem, qubits=None):
-    """QAOA circuit on ``qubits`` (default all): H on every qubit, then for each layer l
-    RZZ(gamma_l) on every edge inside ``qubits`` and RX(2 beta_l) on every qubit.
-    Parameter vector: [gamma_0..gamma_{p-1}, beta_0..beta_{p-1}]. Qubit labels are the
-    positions in ``qubits``."""
-    if qubits is None:
-        qubits = list(range(prob.n))
-    pos = {v: i for i, v in enumerate(qubits)}
+def qaoa_circuit(prob: QAOAProblem):
+    """QAOA circuit on the whole register: H on every qubit, then for each layer l
+    RZZ(gamma_l) on every edge and RX(2 beta_l) on every qubit. Parameter vector:
+    [gamma_0..gamma_{p-1}, beta_0..beta_{p-1}]."""
     g = GateList()
-    for v in qubits:
-        g.const(H, [pos[v]])
+    for v in range(prob.n):
+        g.const(H, [v])
     for l in range(prob.p):
         for (a, b) in prob.edges:
-            if a in pos and b in pos:
-                g.add(RZZ, [pos[a], pos[b]], [l])
-        for v in qubits:
-            g.add(RX, [pos[v]], [prob.p + l], [2.0])
+            g.add(RZZ, [a, b], [l])
+        for v in range(prob.n):
+            g.add(RX, [v], [prob.p + l], [2.0])
     params = np.concatenate([prob.gammas, prob.betas])
-    return Circuit(len(qubits), g.array(), params)
-
-
-def light_cone_nodes(prob: QAOAProblem, edge):
-    """Graph nodes within distance <= p of either end of ``edge`` (sorted)."""
-    adj = {v: set() for v in range(prob.n)}
-    for a, b in prob.edges:
-        adj[a].add(b)
-        adj[b].add(a)
-    front = set(edge)
-    seen = set(edge)
-    for _ in range(prob.p):
-        nxt = set()
-        for v in front:
-            nxt |= adj[v]
-        front = nxt - seen
-        seen |= nxt
-    return sorted(seen)
+    return Circuit(prob.n, g.array(), params)
 
 
 def random_circuit(n, n_gates, rng, ops=None, n_params=None):

@@ -164,3 +164,44 @@ def test_hermitian_expval_matches_z_string():
     psi = sv.run(3, c.gates, c.params)
     O = np.diag(sv.zstring_diag(3, [0, 2]))
     assert abs(sv.expval_hermitian(psi, O) - sv.expvals(psi, 3, W.zterms([([0, 2], 1.0, 0)]), 1)[0]) < 1e-14
+
+
+# ---- identities that pin the matrices the paper does not print ------------------------
+
+def _kron_h_on(U4, which):
+    H = sv.gate_matrix(W.H, [])
+    I = np.eye(2)
+    K = np.kron(H, I) if which == 0 else np.kron(I, H)
+    return K @ U4 @ K
+
+
+def test_cz_is_cnot_between_hadamards():
+    # H on the target turns CZ into CNOT (CNOT is pinned by the printed block tensor and H by
+    # the Bell state); CZ is symmetric, so H on the other qubit gives the reversed CNOT.
+    cz = sv.gate_matrix(W.CZ, [])
+    cnot = sv.gate_matrix(W.CNOT, [])
+    assert np.allclose(_kron_h_on(cz, 1), cnot, atol=1e-15)
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    assert np.allclose(_kron_h_on(cz, 0), swap @ cnot @ swap, atol=1e-15)
+
+
+def test_y_and_z_from_x_and_h():
+    X = sv.gate_matrix(W.X, [])
+    Z = sv.gate_matrix(W.Z, [])
+    H = sv.gate_matrix(W.H, [])
+    assert np.allclose(H @ X @ H, Z, atol=1e-15)              # Z = H X H
+    assert np.allclose(sv.gate_matrix(W.Y, []), 1j * X @ Z, atol=1e-15)  # Y = i X Z
+
+
+@pytest.mark.parametrize("op,pauli", [(W.RX, W.X), (W.RY, W.Y), (W.RZ, W.Z)])
+def test_rotation_at_pi_is_minus_i_pauli(op, pauli):
+    # R_P(pi) = exp(-i pi P / 2) = -i P
+    assert np.allclose(sv.gate_matrix(op, [math.pi]), -1j * sv.gate_matrix(pauli, []), atol=1e-15)
+
+
+@pytest.mark.parametrize("gam", [0.4, 2.6])
+def test_rzz_is_cnot_rz_cnot(gam):
+    # exp(-i g Z Z / 2) = CNOT (I x RZ(g)) CNOT: the parity of the two bits goes through RZ
+    cnot = sv.gate_matrix(W.CNOT, [])
+    mid = np.kron(np.eye(2), sv.gate_matrix(W.RZ, [gam]))
+    assert np.allclose(cnot @ mid @ cnot, sv.gate_matrix(W.RZZ, [gam]), atol=1e-15)

@@ -101,3 +101,38 @@ def test_qaoa_p1_closed_form():
             want = (0.5 * math.sin(4 * b) * math.sin(g) * (math.cos(g) ** du + math.cos(g) ** dv)
                     + 0.5 * math.sin(2 * b) ** 2 * math.cos(g) ** (du + dv - 2 * t) * (1 - math.cos(2 * g) ** t))
             assert abs(tn.qaoa_edge_zz_sv(prob, (u, v)) - want) < 1e-12, (u, v)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_qaoa_cone_is_graph_ball(p):
+    # the reverse causal cone of an edge holds exactly the nodes within distance p
+    prob = W.qaoa_maxcut(p=p)
+    for e in prob.edges[::7]:
+        _, i, j, order = tn.qaoa_cone(prob, e)
+        assert order == tn.graph_ball(prob.n, prob.edges, e, p)
+        assert (order[i], order[j]) == tuple(e)
+
+
+def test_qaoa_p3_cone_equals_full_register():
+    rng = np.random.default_rng(31)
+    n = 12
+    edges = W.random_regular_graph(3, n, rng)
+    prob = W.QAOAProblem(n, edges, 3, W.f32_angles(rng, 3, 0, math.pi), W.f32_angles(rng, 3, 0, math.pi))
+    for e in edges[:6]:
+        assert abs(tn.qaoa_full_zz_sv(prob, e) - tn.qaoa_edge_zz_sv(prob, e)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_cone_circuit_keeps_value_random(seed):
+    # random circuits over all gate types (with runs of diagonal gates): the value of a
+    # Z-string on one or two qubits is the same from the cone and from the whole register
+    rng = np.random.default_rng(400 + seed)
+    n = 7
+    c = W.random_circuit(n, 12, rng)
+    for zq in ([0], [2, 5], [6]):
+        full = sv.run(n, c.gates, c.params)
+        want = float(np.dot(np.abs(full) ** 2, sv.zstring_diag(n, zq)))
+        cc, order = tn.cone_circuit(c, zq)
+        psi = sv.run(cc.n, cc.gates, cc.params)
+        got = float(np.dot(np.abs(psi) ** 2, sv.zstring_diag(cc.n, [order.index(q) for q in zq])))
+        assert abs(got - want) < 1e-12

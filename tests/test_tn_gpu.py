@@ -63,8 +63,7 @@ def test_qaoa_sliced_unsliced_groups_and_grad():
         t0 = tn.elimination_tree(net, tn.elimination_order(net)[0])
         ts = tn.slice_tree(net, t0, max(2, t0.max_rank - 3))
         want = otn.qaoa_edge_zz_sv(prob, e)
-        c = W.qaoa_circuit(prob, cone)
-        i, j = cone.index(e[0]), cone.index(e[1])
+        c, i, j, _ = otn.qaoa_cone(prob, e)
         c.terms, c.n_obs = W.zterms([([i, j], 1.0, 0)]), 1
         gw = osv.param_shift_grad(c)
         for tree, G in ((t0, 0), (ts, 0), (ts, 2), (ts, 1)):
@@ -84,8 +83,7 @@ def test_autograd_tn_expval():
     p = _params(net, False).requires_grad_(True)
     f = tn.tn_expval(prog, p)
     (3.0 * f).backward()
-    c = W.qaoa_circuit(prob, cone)
-    i, j = cone.index(e[0]), cone.index(e[1])
+    c, i, j, _ = otn.qaoa_cone(prob, e)
     c.terms, c.n_obs = W.zterms([([i, j], 1.0, 0)]), 1
     assert abs(f.item() - otn.qaoa_edge_zz_sv(prob, e)) <= 1e-5
     assert np.abs(p.grad.cpu().numpy() - 3.0 * osv.param_shift_grad(c)).max() <= 3e-5
@@ -97,10 +95,9 @@ def test_qaoa50_p3_edges_vs_cone_state_vector():
     prob = W.qaoa_maxcut(p=3)
     done = 0
     for e in prob.edges:
-        cone = W.light_cone_nodes(prob, e)
+        net, cone = tn.qaoa_edge_network(prob, e)
         if len(cone) > 20:
             continue
-        net, _ = tn.qaoa_edge_network(prob, e)
         prog = tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]))
         v = prog.value(_params(net, False)).cpu().numpy()[0]
         assert abs(v.real - otn.qaoa_edge_zz_sv(prob, e)) <= 1e-5, e
