@@ -1,6 +1,8 @@
 """GPU parity of the adjoint backward (tq_sv_backward, SVExpval.backward) against the
 oracle's parameter-shift gradients (exact) and central finite differences.
-Tolerances: complex64 |d grad| <= 1e-5, complex128 <= 1e-12 (times the weight scale)."""
+Tolerances: complex64 |d grad| <= 1e-5, complex128 <= 1e-12, times the weight scale
+sum_o |w_o| sum_{terms of o} |coeff| of the differentiated sum (1 for a unit weight on one
+unit-coefficient Z-string)."""
 import math
 
 import numpy as np
@@ -17,6 +19,11 @@ TOL = {"c64": 1e-5, "c128": 1e-12}
 
 def _types(name):
     return (torch.complex64, torch.float32) if name == "c64" else (torch.complex128, torch.float64)
+
+
+def _wscale(terms, weights):
+    w = np.abs(np.asarray(weights, dtype=np.float64)).reshape(-1)
+    return float(sum(abs(float(t["coeff"])) * w[int(t["obs"])] for t in terms))
 
 
 def _adjoint(circs, name, terms, n_obs, weights, **kw):
@@ -46,7 +53,7 @@ def test_random_circuits_vs_param_shift(name):
         want = osv.param_shift_grad(c, weights=np.array(w[0]))
         err = np.abs(g - want).max()
         print(f"  max|d grad| = {err:.2e}", flush=True)
-        assert err <= 2 * TOL[name], (n, err)
+        assert err <= TOL[name] * _wscale(terms, w), (n, err)
 
 
 @pytest.mark.parametrize("tile", [(5, 2), (6, 3), (8, 4), (10, 4)])
@@ -60,7 +67,9 @@ def test_adjoint_tile_shapes_multi_stage(tile):
         _, g = _adjoint([c], "c64", terms, 1, [[1.0]], tile_bits=t, reg_bits=R)
         c.terms, c.n_obs = terms, 1
         want = osv.param_shift_grad(c)
-        assert np.abs(g - want).max() <= 2e-5
+        err = np.abs(g - want).max()
+        print(f"  max|d grad| = {err:.2e}", flush=True)
+        assert err <= 1e-5
 
 
 def test_hea_ring_adjoint_matches_param_shift_and_fd():
@@ -179,4 +188,4 @@ def test_one_qubit_runs_vs_param_shift(name):
         want = osv.param_shift_grad(c)
         err = np.abs(got - want).max()
         print(f"  max|d grad| = {err:.2e}", flush=True)
-        assert err <= 4 * TOL[name], (n, err)
+        assert err <= TOL[name] * _wscale(terms, [1.0]), (n, err)

@@ -2,7 +2,8 @@
 expectation values, parameter-shift gradients), HIP-graph replays against eager runs, the
 autotuner, the 512-sample 16-qubit QNN batch against the single-structure path, and the
 1024-circuit uneven batch (n = 8..20) at full size on sampled outputs and invariants.
-Tolerances: complex64 1e-5, complex128 1e-12 (gradients 2x, weights of order 1)."""
+Tolerances: complex64 1e-5, complex128 1e-12; gradients times the weight scale
+sum_o |w_o| sum_{terms of o} |coeff| of the differentiated sum."""
 import math
 
 import numpy as np
@@ -76,7 +77,8 @@ def test_uneven_batch_vs_oracle(c128, shape):
         assert np.abs(out[i] - _oracle_expvals(c, psi, TERMS, 2)).max() <= tol, i
         gw = osv.param_shift_grad(_weighted(c, TERMS, w[i]))
         p = int(spec.param_off[i])
-        assert np.abs(grad[p:p + c.n_params] - gw).max() <= 2 * tol, i
+        ws = sum(abs(float(t["coeff"]) * w[i][int(t["obs"])]) for t in TERMS)
+        assert np.abs(grad[p:p + c.n_params] - gw).max() <= tol * max(1.0, ws), i
 
 
 def test_caller_initial_state_and_no_expval():
@@ -157,7 +159,7 @@ def test_autotune_keeps_results():
     r_grad = ref.backward(params, r_states, gw)
     torch.cuda.synchronize()
     assert (out - r_out).abs().max().item() <= 1e-5
-    assert (grad - r_grad).abs().max().item() <= 2e-5
+    assert (grad - r_grad).abs().max().item() <= 1e-5 * 1.75  # weight scale of TERMS with unit weights
     assert (states - r_states).abs().max().item() <= 1e-5
     # a new compiled batch of the same structure starts from the tuned shape
     again = lib.SVBatch(spec, TERMS, 2)
@@ -187,7 +189,7 @@ def test_qnn512_batch_matches_single_structure_path_and_oracle():
     g_ref = lib.sv_backward(psi, params, spec, terms, 1, w)
     torch.cuda.synchronize()
     assert (f - f_ref).abs().max().item() <= 1e-5
-    assert (g - g_ref).abs().max().item() <= 2e-5
+    assert (g - g_ref).abs().max().item() <= 1e-5 * max(1.0, w.abs().max().item())
     for b in (0, 311):
         fo = osv.circuit_f(W.Circuit(n, gates, pb[b], 1, terms))[0]
         assert abs(f[b, 0].item() - fo) <= 1e-5
@@ -206,12 +208,13 @@ def test_qnn512_batch_matches_single_structure_path_and_oracle():
     assert (th.grad - th2.grad).abs().max().item() <= 1e-5
 
 
+@pytest.mark.timeout(900)
 def test_uneven1024_full_size_sampled():
     """The 1024-circuit uneven batch (n uniform in 8..20, 2n layers of U3 + random CNOT
-    pairs) at full size: norms of every final state, the oracle's values for sampled
-    circuits up to 12 qubits, and adjoint gradients of sampled circuits against the
-    single-circuit adjoint path and (three parameters of a 20-qubit circuit) against the
-    parameter-shift rule evaluated with the single-circuit forward path."""
+    pairs) at full size, in the benchmark's launch configuration (HIP graphs): norms of every
+    final state; states and <Z0> of sampled circuits up to 12 qubits and of two 20-qubit
+    circuits against the oracle; adjoint gradients of one 20-qubit circuit against the
+    oracle's parameter-shift rule on three parameters (each used once, unit weight)."""
     from paper_2301_05451_amd import lib
 
     circs = W.uneven_batch()
@@ -237,36 +240,42 @@ def test_uneven1024_full_size_sampled():
     assert np.abs(norms - 1.0).max() <= 1e-5
     fc, gc = f.cpu().numpy()[:, 0], g.cpu().numpy()
     small = [i for i in range(len(circs)) if ns[i] <= 12][:6]
-    for i in small:
+    big = [i for i in range(len(circs)) if ns[i] == 20][:2]
+    for i in small + big:
         c = circs[i]
+        print(f"uneven1024: oracle circuit {i} (n = {c.n}, {len(c.gates)} gates)", flush=True)
         psi = osv.run(c.n, c.gates, c.params)
         o = int(so[i])
-        assert np.abs(states[o:o + (1 << c.n)].cpu().numpy() - psi).max() <= 1e-5, i
+        err = np.abs(states[o:o + (1 << c.n)].cpu().numpy() - psi).max()
+        print(f"  max|d amp| = {err:.2e}", flush=True)
+        assert err <= 1e-5, i
         assert abs(fc[i] - float(np.dot(np.abs(psi) ** 2, osv.zstring_diag(c.n, [0])))) <= 1e-5, i
-    big = [i for i in range(len(circs)) if ns[i] == 20][:2] + [i for i in range(len(circs)) if ns[i] == 15][:1]
-    for i in big:
-        c = circs[i]
-        one = lib.BatchSpec.from_circuits([c])
-        p1 = torch.tensor(c.params, dtype=torch.float32, device="cuda")
-        psi = lib.zero_states(one, torch.complex64)
-        lib.sv_apply(psi, p1, one)
-        g1 = lib.sv_backward(psi, p1, one, terms, 1, torch.ones(1, 1, device="cuda")).cpu().numpy()
-        p = int(spec.param_off[i])
-        assert np.abs(gc[p:p + c.n_params] - g1).max() <= 2e-5, i
+    # oracle parameter shift on the theta angle of every U3 of the fourth-last layer of a
+    # 20-qubit circuit (each used once, unit weight): the state before that layer is computed
+    # once and the last four layers are rerun per shift; at least three of them must carry a
+    # gradient of size, so the comparison is not one of zeros
     i = big[0]
     c = circs[i]
-    one = lib.BatchSpec.from_circuits([c])
     p = int(spec.param_off[i])
-    for k in (0, c.n_params // 2 + 1, c.n_params - 1):
+    zd = osv.zstring_diag(c.n, [0])
+    per_layer = c.n + c.n // 2
+    g0 = (2 * c.n - 4) * per_layer
+    pre = osv.run(c.n, c.gates[:g0], c.params)
+    big_grads = 0
+    for q in range(c.n):
+        gk = g0 + q
+        assert int(c.gates[gk]["op"]) == W.U3
+        k = int(c.gates[gk]["pidx"][0])
         vals = []
         for s in (+1, -1):
-            pk = c.params.copy()
-            pk[k] += s * math.pi / 2
-            pt = torch.tensor(pk, dtype=torch.float64, device="cuda")
-            psi = lib.zero_states(one, torch.complex128)
-            lib.sv_apply(psi, pt, one)
-            vals.append(lib.expval(psi, one, terms, 1)[0, 0].item())
-        assert abs(gc[p + k] - 0.5 * (vals[0] - vals[1])) <= 2e-5, k
+            post = osv.run(c.n, c.gates[gk:], c.params, init=osv.run(c.n, c.gates[g0:gk], c.params, init=pre),
+                           shift=(0, 0, s * math.pi / 2))
+            vals.append(float(np.dot(np.abs(post) ** 2, zd)))
+        want = 0.5 * (vals[0] - vals[1])
+        print(f"  qubit {q} param {k}: adjoint {gc[p + k]:+.8f} oracle shift {want:+.8f}", flush=True)
+        assert abs(gc[p + k] - want) <= 1e-5, k
+        big_grads += abs(want) > 1e-3
+    assert big_grads >= 3
 
 
 def test_create_validation():

@@ -101,10 +101,13 @@ def test_mixed_batch_and_user_states(name):
         s0 = int(spec.state_off[i])
         v = init[s0:s0 + (1 << c.n)]
         want = osv.run(c.n, c.gates, c.params, init=v)
-        scale = max(1.0, np.abs(want).max())
-        assert np.abs(got[s0:s0 + (1 << c.n)] - want).max() <= TOL[name] * scale * 4
+        # the user state is not normalised: amplitudes are compared relative to its largest
+        # entry, expectation values relative to its squared norm times the coefficients
+        amax = np.abs(v).max()
+        assert np.abs(got[s0:s0 + (1 << c.n)] - want).max() <= TOL[name] * amax
         fw = osv.expvals(want, c.n, terms, 3)
-        assert np.abs(f[i] - fw).max() <= TOL[name] * (1 << c.n) * scale ** 2
+        coef = np.array([sum(abs(float(t["coeff"])) for t in terms if int(t["obs"]) == o) for o in range(3)])
+        assert np.all(np.abs(f[i] - fw) <= TOL[name] * np.linalg.norm(v) ** 2 * coef), (i, f[i], fw)
 
 
 def test_uniform_batch_many_parameter_sets():
@@ -164,40 +167,33 @@ def test_expval_sum_z_24_terms_matches_popcount_identity():
     assert abs(f - float(np.dot(np.abs(v) ** 2, n - 2 * pc))) < 1e-12
 
 
+@pytest.mark.timeout(900)
 def test_brickwork24_full_size_in_bench_configuration():
-    """The 24-qubit brickwork circuit at full size, fused with the default shape (the launch
-    configuration the benchmark times): its first two layers (168 gates) against the oracle
-    amplitude by amplitude; the whole 1670-gate circuit against the one-sweep-per-gate path
-    element by element, unit norm, and sum_i <Z_i> against the popcount identity on the
-    final state."""
+    """The 24-qubit brickwork circuit (all 1670 gates) at full size, fused with the default
+    shape (the launch configuration the benchmark times), against the oracle amplitude by
+    amplitude; sum_i <Z_i> against the oracle's value; the plain one-sweep-per-gate path
+    against the oracle too."""
     from paper_2301_05451_amd import lib
 
     c = W.brickwork()
     n = c.n
-    head = c.gates[:168]
-    print("brickwork24: two layers vs oracle", flush=True)
-    spec_h = lib.BatchSpec.uniform(n, head, 1, c.n_params)
-    params = torch.tensor(c.params, dtype=torch.float32, device="cuda")
-    psi = lib.zero_states(spec_h, torch.complex64)
-    lib.sv_apply(psi, params, spec_h)
-    want = osv.run(n, head, c.params)
-    assert np.abs(psi.cpu().numpy() - want).max() <= 1e-5
-    del want
-    print("brickwork24: full circuit fused vs plain", flush=True)
+    print("brickwork24: oracle state (1670 gates, complex128)", flush=True)
+    want = osv.run(n, c.gates, c.params)
+    f_want = osv.expvals(want, n, c.terms, 1)[0]
     spec = lib.BatchSpec.uniform(n, c.gates, 1, c.n_params)
-    fused = lib.zero_states(spec, torch.complex64)
-    lib.sv_apply(fused, params, spec)
-    plain = lib.zero_states(spec, torch.complex64)
-    lib.sv_apply(plain, params, spec, mode=1)
-    assert (fused - plain).abs().max().item() <= 1e-5
-    p = (fused.real.double() ** 2 + fused.imag.double() ** 2)
-    assert abs(p.sum().item() - 1.0) <= 1e-5
-    f = lib.expval(fused, spec, c.terms, 1)[0, 0].item()
-    pc = torch.zeros(1 << n, dtype=torch.float64, device="cuda")
-    idx = torch.arange(1 << n, device="cuda")
-    for q in range(n):
-        pc += ((idx >> q) & 1).double()
-    assert abs(f - (p * (n - 2 * pc)).sum().item()) <= 1e-4
+    params = torch.tensor(c.params, dtype=torch.float32, device="cuda")
+    for mode in (0, 1):
+        psi = lib.zero_states(spec, torch.complex64)
+        lib.sv_apply(psi, params, spec, mode=mode)
+        f = lib.expval(psi, spec, c.terms, 1)[0, 0].item()
+        got = psi.cpu().numpy()
+        d = got.astype(np.complex128) - want
+        err, l2 = np.abs(d).max(), np.linalg.norm(d)
+        print(f"brickwork24 mode={mode}: max|d amp| = {err:.3e}, ||d psi||_2 = {l2:.3e}, "
+              f"|d sum Z| = {abs(f - f_want):.3e}", flush=True)
+        assert err <= 1e-5, (mode, err)
+        assert abs(f - f_want) <= 1e-5, (mode, f, f_want)
+        del psi, got, d
 
 
 @pytest.mark.parametrize("name,n", [("c64", 14), ("c64", 20), ("c128", 17)])
@@ -222,3 +218,30 @@ def test_expval_random_z_strings_many_blocks(name, n):
     want = osv.expvals(psi.cpu().numpy().astype(np.complex128), n, terms, 3)
     tol = 1e-5 if name == "c64" else 1e-12
     assert np.abs(got - want).max() <= tol * max(1.0, np.abs(want).max()), (got, want)
+
+
+@pytest.mark.parametrize("name", ["c64", "c128"])
+def test_expval_more_than_32_terms(name):
+    """70 random Z-strings over 5 observables: the term table is processed in chunks of 32,
+    the first chunk writing and later chunks accumulating into every output."""
+    from paper_2301_05451_amd import lib
+
+    n = 15
+    rng = np.random.default_rng(222)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    v /= np.linalg.norm(v)
+    cdt = torch.complex64 if name == "c64" else torch.complex128
+    psi = torch.tensor(np.concatenate([v, v[::-1]]), dtype=cdt, device="cuda")
+    spec = lib.BatchSpec.uniform(n, W.GateList().array(), 2, 1)
+    spec_terms = []
+    for k in range(70):
+        qs = sorted(int(q) for q in rng.choice(n, size=int(rng.integers(1, 5)), replace=False))
+        spec_terms.append((qs, float(rng.uniform(-1, 1)), int(rng.integers(5))))
+    terms = W.zterms(spec_terms)
+    got = lib.expval(psi, spec, terms, 5).cpu().numpy()
+    host = psi.cpu().numpy().astype(np.complex128)
+    coef = np.array([sum(abs(c) for _, c, o in spec_terms if o == k) for k in range(5)])
+    for b in range(2):
+        want = osv.expvals(host[b << n:(b + 1) << n], n, terms, 5)
+        tol = 1e-5 if name == "c64" else 1e-12
+        assert np.all(np.abs(got[b] - want) <= tol * coef), (b, got[b], want)

@@ -47,7 +47,7 @@ def test_random_circuits_value_and_grad(c128):
         assert abs(v.real - want) <= tol and abs(v.imag) <= tol
         g = prog.grad(p).cpu().numpy()
         c.terms, c.n_obs = W.zterms([(zq, 1.0, 0)]), 1
-        assert np.abs(g - osv.param_shift_grad(c)).max() <= 2 * tol
+        assert np.abs(g - osv.param_shift_grad(c)).max() <= tol
 
 
 def _qaoa10():
@@ -224,8 +224,66 @@ def test_batched_networks_match_single_calls_and_oracle(c128):
     tol = 1e-12 if c128 else 1e-5
     for k, (pg, pt) in enumerate(zip(progs, pars)):
         assert np.abs(vals[k] - pg.value(pt).cpu().numpy()).max() <= tol, k
-        assert np.abs(grads[k] - pg.grad(pt).cpu().numpy()).max() <= 2 * tol, k
+        assert np.abs(grads[k] - pg.grad(pt).cpu().numpy()).max() <= tol, k
     for k in (0, 17, 41, 74):
         want = otn.qaoa_edge_zz_sv(prob, prob.edges[k])
         assert abs(vals[k][0].real - want) <= max(tol, 1e-5), k
     assert abs(vals[-1][0] - vals[0][0]) <= 2 * tol
+
+
+def _p4_graph(n=16, seed=41):
+    r = np.random.default_rng(seed)
+    edges = W.random_regular_graph(3, n, r)
+    return W.QAOAProblem(n, edges, 4, W.f32_angles(r, 4, 0, math.pi), W.f32_angles(r, 4, 0, math.pi))
+
+
+@pytest.mark.timeout(600)
+def test_qaoa_p4_small_graph_vs_oracle_full_register():
+    """QAOA p = 4 on a 16-node 3-regular graph (every light cone is the whole register):
+    the tensor-network value of every edge against the oracle's whole-register state vector,
+    and the gamma/beta gradients of four edges against the oracle's central differences on
+    the cone circuit (8 parameters, each shared by every edge or node of its layer)."""
+    prob = _p4_graph()
+    psi = osv.run(prob.n, W.qaoa_circuit(prob).gates, np.concatenate([prob.gammas, prob.betas]))
+    prob_sq = np.abs(psi) ** 2
+    for k, e in enumerate(prob.edges):
+        net, cone = tn.qaoa_edge_network(prob, e)
+        tr = tn.elimination_tree(net, tn.elimination_order(net)[0])
+        prog = tn.TNProgram(net, tr)
+        p = _params(net, False)
+        v = prog.value(p).cpu().numpy()[0]
+        want = float(np.dot(prob_sq, osv.zstring_diag(prob.n, list(e))))
+        assert abs(v.real - want) <= 1e-5 and abs(v.imag) <= 1e-5, (e, v, want)
+        if k % 6 == 0:
+            c, i, j, _ = otn.qaoa_cone(prob, e)
+            c.terms, c.n_obs = W.zterms([([i, j], 1.0, 0)]), 1
+            gw = osv.fd_grad(c)
+            got = prog.grad(p).cpu().numpy()
+            print(f"p4 edge {e}: width {tr.max_rank}, max|d grad| = {np.abs(got - gw).max():.2e}", flush=True)
+            assert np.abs(got - gw).max() <= 1e-5, (e, got, gw)
+
+
+def test_qaoa50_p1_closed_form_all_edges():
+    """p = 1 on the 50-node graph: all 75 light-cone networks in one batched launch against
+    the analytic p = 1 value (in this build's RZZ(g) = exp(-i g ZZ/2), RX(2b) convention):
+    <Z_u Z_v> = 1/2 sin(4b) sin(g) (cos^du g + cos^dv g)
+              + 1/2 sin^2(2b) cos^(du+dv-2t) g (1 - cos^t 2g),
+    du, dv the other neighbours of u and v, t the triangles through (u, v)."""
+    prob = W.qaoa_maxcut(p=1)
+    adj = {v: set() for v in range(prob.n)}
+    for a, b in prob.edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    g, b = float(prob.gammas[0]), float(prob.betas[0])
+    progs, pars = [], []
+    for e in prob.edges:
+        net, _ = tn.qaoa_edge_network(prob, e)
+        progs.append(tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0])))
+        pars.append(_params(net, False))
+    vals = [v.cpu().numpy()[0] for v in tn.TNBatch(progs).values(pars)]
+    for (u, v), val in zip(prob.edges, vals):
+        du, dv = len(adj[u]) - 1, len(adj[v]) - 1
+        t = len(adj[u] & adj[v])
+        want = (0.5 * math.sin(4 * b) * math.sin(g) * (math.cos(g) ** du + math.cos(g) ** dv)
+                + 0.5 * math.sin(2 * b) ** 2 * math.cos(g) ** (du + dv - 2 * t) * (1 - math.cos(2 * g) ** t))
+        assert abs(val.real - want) <= 1e-5 and abs(val.imag) <= 1e-5, ((u, v), val, want)
