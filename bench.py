@@ -232,8 +232,6 @@ def bench_tn(steps):
         for e in prob.edges:
             net, _ = tn.qaoa_edge_network(prob, e)
             tree = tn.elimination_tree(net, tn.elimination_order(net, None, "fill")[0])
-            if tree.max_rank > 26:
-                continue
             progs.append(tn.TNProgram(net, tree))
         plan_s = time.perf_counter() - t0
         if not progs:
