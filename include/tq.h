@@ -146,25 +146,39 @@ tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_g
                           int32_t n_gates, const tq_sv_opts* opts, int64_t out[8]);
 
 /* Sec. 4 cost: d_out[i * n_obs + o] = sum over terms with obs == o of
- * coeff * <psi_i| Z-string |psi_i> (real; accumulated in double with a fixed reduction
- * order, written in the dtype's real precision). Terms name qubits (bit q = qubit q). */
+ * coeff * <psi_i| Z-string |psi_i> (real, written in the dtype's real precision). Each
+ * thread sums |psi|^2 with the terms' signs over its own amplitudes (32 per 2^13-amplitude
+ * chunk) in the state's precision; all further accumulation (over threads, work-groups and
+ * terms) is in double with a fixed order, so repeated calls are bitwise equal. Terms name
+ * qubits (bit q = qubit q). */
 tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states,
                     const tq_zterm* terms, int32_t n_terms, int32_t n_obs, void* d_out,
                     void* stream);
 
 /* Gradient of L = sum_i sum_o d_grad_out[i*n_obs+o] * <O_o>_i with respect to every
- * circuit's parameters, by one reverse (adjoint) sweep per circuit. d_states holds the
- * final states as left by tq_sv_apply (read only). Internally psi is copied to context
- * scratch, lambda = sum_o w_o O_o psi, then for each gate in reverse psi <- U^dag psi,
- * g += 2 Re<lambda| dU psi>, lambda <- U^dag lambda. The values equal the parameter-shift
- * gradients of Sec. 4.2. d_grad[param_off[i] + k] receives dL/d params_i[k] (overwritten,
+ * circuit's parameters, by one reverse (adjoint) sweep per circuit (Sec. 4: the values equal
+ * the parameter-shift gradients of Sec. 4.2; the paper's backpropagation of Sec. 4.1 keeps
+ * every intermediate state, the sweep keeps two). d_states holds the final states as left by
+ * tq_sv_apply (read only). In the caller's workspace psi is copied, lambda = sum_o w_o O_o
+ * psi, then for each gate in reverse psi <- U^dag psi, g += 2 Re<lambda| dU psi>,
+ * lambda <- U^dag lambda. d_grad[param_off[i] + k] receives dL/d params_i[k] (overwritten,
  * dtype's real precision); gradients of all occurrences of a parameter are summed with
- * their pscale factors. d_grad_out is [count][n_obs] in the dtype's real precision. */
+ * their pscale factors. d_grad_out is [count][n_obs] in the dtype's real precision.
+ * d_work (device, work_bytes bytes, owned by the caller, contents need not be initialised)
+ * must hold at least tq_sv_backward_workspace(...) bytes for the same arguments: psi and
+ * lambda copies of the largest run of circuits sharing a gate list, their gate matrices and
+ * gradient partial sums. Errors as tq_sv_apply / tq_expval, and TQ_EWORKSPACE (d_work NULL
+ * or too small). The call neither allocates nor synchronises once the size query has been
+ * made for the same gate lists, terms and batch offsets (the query builds and caches the
+ * schedules and device tables the call uses). */
+int64_t tq_sv_backward_workspace(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                                 const int32_t* n_params, const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
+                                 const tq_sv_opts* opts); /* bytes, or -1 on error (tq_last_error) */
 tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
                          const int32_t* n_params, const void* d_params, const void* d_states,
                          const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
                          const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
-                         void* stream);
+                         void* d_work, int64_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Compiled batches. The paper compiles a circuit once and evaluates it many times with new
@@ -247,7 +261,21 @@ typedef struct {
   int32_t dtype;             /* tq_dtype */
   int64_t slice_group;       /* slices contracted together per launch sequence (0 = auto) */
   int64_t mem_budget;        /* bytes of workspace the auto slice group may use (0 = 4 GiB) */
+  int32_t store_policy;      /* TQ_TN_RECOMPUTE, TQ_TN_STORE or TQ_TN_AUTO, below */
+  int32_t _pad;
 } tq_tn_desc;
+
+/* What the reverse pass does for the forward's intermediate tensors. The paper's
+ * backpropagation (Sec. 4.1) stores them; recomputing them trades one extra forward pass for
+ * memory when the slices cannot all be held at once.
+ *   TQ_TN_RECOMPUTE: tq_tn_backward recomputes the forward inside the call (any slice group).
+ *   TQ_TN_STORE: tq_tn_backward reuses the intermediates that the immediately preceding
+ *     tq_tn_contract of the same plan and leaves left in the same workspace (which must then
+ *     have the backward size, tq_tn_workspace(plan, 1)); the plan must run all slices as one
+ *     group within mem_budget, else tq_tn_plan_create fails with TQ_ENOTSUP.
+ *   TQ_TN_AUTO: store when all slices fit mem_budget as one group, else recompute.
+ * The batched calls (tq_tn_*_batch) always recompute. */
+enum { TQ_TN_RECOMPUTE = 0, TQ_TN_STORE = 1, TQ_TN_AUTO = 2 };
 
 /* Host-only: classifies every step (batch / contracted / kept / summed-out indices), picks
  * its kernel (direct bit-indexed contraction, or bit-permute + FP32-MFMA complex GEMM when
@@ -256,6 +284,9 @@ typedef struct {
  * from out_inds as a set. */
 tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* desc, tq_tn_plan** out);
 void tq_tn_plan_destroy(tq_tn_plan* plan);
+/* 1 if tq_tn_backward of this plan reuses the forward's stored intermediates (the store
+ * policy is in effect), 0 if it recomputes them, -1 for a NULL plan. */
+int32_t tq_tn_plan_stores(const tq_tn_plan* plan);
 /* Complex elements of the packed leaf buffer, and leaf i's offset in it. */
 int64_t tq_tn_leaf_elems(const tq_tn_plan* plan);
 int64_t tq_tn_leaf_offset(const tq_tn_plan* plan, int32_t leaf);
@@ -271,12 +302,14 @@ tq_status tq_tn_plan_info(const tq_tn_plan* plan, int64_t out[8]);
 tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, void* d_out, void* d_work,
                          int64_t work_bytes, void* stream);
 
-/* Reverse pass over the tree: d_grad_leaves (packed like the leaves) receives, for every
- * leaf, its environment scaled by the upstream value: sum over the output entries o of
- * d_grad_out[o] * dT[o]/dL (holomorphic derivative of the multilinear value T). For a
- * real loss l = Re sum_o conj(g_o) T_o pass d_grad_out = g; dl/dtheta is then
- * Re sum_leaf sum_x d_grad_leaves[x] * dL[x]/dtheta. Intermediates are recomputed from
- * the leaves inside the call (nothing is kept between calls). */
+/* Reverse pass over the tree (Sec. 4.1, backpropagation through the contraction):
+ * d_grad_leaves (packed like the leaves) receives, for every leaf, its environment scaled
+ * by the upstream value: sum over the output entries o of d_grad_out[o] * dT[o]/dL
+ * (holomorphic derivative of the multilinear value T). For a real loss
+ * l = Re sum_o conj(g_o) T_o pass d_grad_out = g; dl/dtheta is then
+ * Re sum_leaf sum_x d_grad_leaves[x] * dL[x]/dtheta. The forward's intermediates are
+ * recomputed inside the call, or reused from the workspace under the store policy
+ * (tq_tn_desc.store_policy). Errors: TQ_EWORKSPACE if work_bytes < tq_tn_workspace(plan, 1). */
 tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, const void* d_grad_out,
                          void* d_grad_leaves, void* d_work, int64_t work_bytes, void* stream);
 

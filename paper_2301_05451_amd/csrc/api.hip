@@ -25,46 +25,58 @@ Schedule::~Schedule() {
     if (p) (void)hipFree(p);
 }
 
-tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out) {
+tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out, bool zero) {
   if (bytes == 0) bytes = 256;
   if (ctx->scratch_bytes[slot] < bytes) {
-    if (ctx->scratch[slot]) {
-      TQ_HIP(hipDeviceSynchronize());
-      TQ_HIP(hipFree(ctx->scratch[slot]));
-      ctx->scratch[slot] = nullptr;
-      ctx->scratch_bytes[slot] = 0;
-    }
-    size_t want = std::max(bytes, (size_t)4096);
+    // Grow without waiting for the device: work already queued may still use the old
+    // buffer, so it is retired (freed when the context is destroyed) rather than freed.
+    // Sizes at least double, so retired buffers add up to less than the live one.
+    if (ctx->scratch[slot]) ctx->retired.push_back(ctx->scratch[slot]);
+    ctx->scratch[slot] = nullptr;
+    size_t want = std::max(bytes, std::max((size_t)4096, 2 * ctx->scratch_bytes[slot]));
+    ctx->scratch_bytes[slot] = 0;
     if (hipMalloc(&ctx->scratch[slot], want) != hipSuccess)
       return fail(TQ_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes of context scratch failed");
     ctx->scratch_bytes[slot] = want;
+    if (zero) TQ_HIP(hipMemset(ctx->scratch[slot], 0, want));
   }
   *out = ctx->scratch[slot];
   return TQ_OK;
 }
 
 // Immutable small host tables (offset maps, observable terms) live in device memory cached
-// by content, so repeated calls neither re-upload nor synchronise (and can be captured in a
-// hipGraph once warmed up).
+// by their full content (the key is the bytes themselves, so equal keys mean equal tables),
+// so repeated calls neither re-upload nor synchronise (and can be captured in a hipGraph once
+// warmed up). The cache is bounded (kTableCacheBytes / kTableCacheEntries): when a new
+// table would exceed it, the device is synchronised once and the least recently used
+// tables are freed.
 tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev) {
-  const unsigned char* b = (const unsigned char*)host;
-  uint64_t h1 = 0xCBF29CE484222325ull, h2 = 0x84222325CBF29CE4ull;
-  for (size_t i = 0; i < bytes; ++i) {
-    h1 = (h1 ^ b[i]) * 0x100000001B3ull;
-    h2 = (h2 + b[i]) * 0xFF51AFD7ED558CCDull;
-    h2 ^= h2 >> 29;
-  }
-  char key[64];
-  snprintf(key, sizeof key, "%016llx%016llx:%zu", (unsigned long long)h1, (unsigned long long)h2, bytes);
+  std::string key((const char*)host, bytes);
   auto it = ctx->tables.find(key);
+  ++ctx->table_clock;
   if (it != ctx->tables.end()) {
-    *dev = it->second;
+    it->second.last_use = ctx->table_clock;
+    *dev = it->second.dev;
     return TQ_OK;
+  }
+  if (ctx->table_bytes + bytes > kTableCacheBytes || ctx->tables.size() + 1 > kTableCacheEntries) {
+    TQ_HIP(hipDeviceSynchronize());
+    std::vector<std::pair<uint64_t, const std::string*>> age;
+    for (auto& kv : ctx->tables) age.push_back({kv.second.last_use, &kv.first});
+    std::sort(age.begin(), age.end());
+    for (auto& a : age) {
+      if (ctx->table_bytes + bytes <= kTableCacheBytes / 2 && ctx->tables.size() + 1 <= kTableCacheEntries / 2) break;
+      auto jt = ctx->tables.find(*a.second);
+      (void)hipFree(jt->second.dev);
+      ctx->table_bytes -= jt->second.bytes;
+      ctx->tables.erase(jt);
+    }
   }
   void* d = nullptr;
   TQ_HIP(hipMalloc(&d, std::max<size_t>(bytes, 16)));
   if (bytes) TQ_HIP(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
-  ctx->tables.emplace(key, d);
+  ctx->tables.emplace(std::move(key), TableEntry{d, bytes, ctx->table_clock});
+  ctx->table_bytes += bytes;
   *dev = d;
   return TQ_OK;
 }
@@ -99,22 +111,13 @@ static tq_status to_device(const std::vector<V>& v, void** dev) {
   return TQ_OK;
 }
 
-// 128-bit content hash of a gate list (two 64-bit multiply-xorshift lanes over 8-byte words).
+// Cache key of a schedule: the gate records themselves plus the shape (an exact key: two
+// structures share a schedule only if their bytes are equal).
 static std::string schedule_key(const tq_gate* g, int n_gates, int n, int mode, int t, int R, int c) {
-  const uint64_t* w = reinterpret_cast<const uint64_t*>(g);
-  const size_t nw = (size_t)n_gates * sizeof(tq_gate) / 8;
-  uint64_t h1 = 0x9E3779B97F4A7C15ull ^ (uint64_t)n_gates, h2 = 0xC2B2AE3D27D4EB4Full + (uint64_t)n;
-  for (size_t i = 0; i < nw; ++i) {
-    uint64_t x = w[i];
-    h1 = (h1 ^ x) * 0x100000001B3ull;
-    h1 ^= h1 >> 29;
-    h2 = (h2 + x) * 0xFF51AFD7ED558CCDull;
-    h2 ^= h2 >> 31;
-  }
-  char buf[128];
-  snprintf(buf, sizeof buf, "%016llx%016llx:%d:%d:%d:%d:%d:%d", (unsigned long long)h1, (unsigned long long)h2, n,
-           n_gates, mode, t, R, c);
-  return buf;
+  const int32_t head[7] = {n, n_gates, mode, t, R, c, (int32_t)sizeof(tq_gate)};
+  std::string k((const char*)head, sizeof head);
+  k.append((const char*)g, (size_t)n_gates * sizeof(tq_gate));
+  return k;
 }
 
 static tq_status upload_schedule(Schedule& s, const tq_gate* g, int n_gates) {
@@ -391,22 +394,15 @@ static tq_status expval_t(tq_ctx* ctx, const tq_batch* batch, const void* d_stat
   return TQ_OK;
 }
 
-template <typename T>
-static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
-                               const void* d_params, const void* d_states, const tq_zterm* terms, int n_terms,
-                               int n_obs, const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
-                               hipStream_t stream) {
-  using C = typename Cx<T>::type;
-  const int dt = sizeof(T) == 4 ? TQ_C64 : TQ_C128;
+// Validation shared by the adjoint size query and the call itself.
+static tq_status sv_backward_check(const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                                   const tq_zterm* terms, int n_terms, int n_obs, std::vector<Group>& groups) {
   if (!n_params) return fail(TQ_EINVAL, "n_params is required for the backward pass");
-  std::vector<Group> groups;
   TQ_TRY(group_batch(batch, n_params, groups));
   if (n_obs < 1) return fail(TQ_EINVAL, "n_obs must be >= 1");
   if (n_terms < 0 || (n_terms > 0 && !terms)) return fail(TQ_EINVAL, "bad terms");
   for (int k = 0; k < n_terms; ++k)
     if (terms[k].obs < 0 || terms[k].obs >= n_obs) return fail(TQ_EINVAL, "term obs index out of range");
-  if (!groups.empty() && (!d_params || !d_states || !d_grad_out || !d_grad))
-    return fail(TQ_EINVAL, "null device pointer");
   for (const Group& gr : groups) {
     TQ_TRY(validate_gates(gates + gr.gate_off, gr.n_gates, gr.n, gr.n_params));
     for (int i : gr.members)
@@ -415,37 +411,82 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
     for (int k = 0; k < n_terms; ++k)
       if (gr.n < 64 && (terms[k].mask >> gr.n) != 0) return fail(TQ_EINVAL, "term names a qubit >= n");
   }
+  return TQ_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// The adjoint sweep. Circuits sharing a gate list run together in runs of consecutive batch
+// indices; the runs execute one after another on the stream and reuse one workspace region:
+// psi and lambda copies (one state each per circuit), the adjoint gate matrices and the
+// per-tile gradient partial sums. With d_work == nullptr only the schedules and tables are
+// prepared (cached in the context) and *need receives the workspace bytes.
+template <typename T>
+static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                               const void* d_params, const void* d_states, const tq_zterm* terms, int n_terms,
+                               int n_obs, const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
+                               void* d_work, int64_t work_bytes, int64_t* need, hipStream_t stream) {
+  using C = typename Cx<T>::type;
+  const int dt = sizeof(T) == 4 ? TQ_C64 : TQ_C128;
+  const bool exec = d_work != nullptr || need == nullptr;
+  std::vector<Group> groups;
+  TQ_TRY(sv_backward_check(batch, gates, n_params, terms, n_terms, n_obs, groups));
+  if (exec && !groups.empty() && (!d_params || !d_states || !d_grad_out || !d_grad))
+    return fail(TQ_EINVAL, "null device pointer");
+  // first pass: schedules, tables and the workspace size
+  struct Run {
+    Schedule* s;
+    const unsigned char* tt;
+    std::vector<int> mem;
+    size_t psi, lam, mats, part;
+    int n, n_params;
+  };
+  std::vector<Run> runs;
+  size_t ws = 256;
   for (const Group& gr : groups) {
     const tq_gate* g = gates + gr.gate_off;
     Schedule* s;
     TQ_TRY(get_adjoint_schedule(ctx, dt, g, gr.n_gates, gr.n, opts, &s));
     const unsigned char* tt;
     TQ_TRY(term_table(ctx, gr.n, terms, n_terms, &tt));
-    // members in runs of consecutive batch indices share one launch sequence
     size_t i0 = 0;
     while (i0 < gr.members.size()) {
       size_t i1 = i0 + 1;
       while (i1 < gr.members.size() && gr.members[i1] == gr.members[i1 - 1] + 1) ++i1;
-      std::vector<int> mem(gr.members.begin() + i0, gr.members.begin() + i1);
-      const int count = (int)mem.size();
-      BatchMap pmap, smap;
-      TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, mem, stream, &pmap));
-      TQ_TRY(member_map(ctx, S_MISC, batch->state_off, mem, stream, &smap));
+      Run r{s, tt, std::vector<int>(gr.members.begin() + i0, gr.members.begin() + i1), 0, 0, 0, 0, gr.n,
+            gr.n_params};
+      const size_t count = r.mem.size();
       const int64_t namps = int64_t(1) << gr.n;
       const int64_t ntiles = s->stages.empty() ? 1 : (int64_t(1) << (gr.n - s->stages[0].t));
-      void *psi, *lam, *mats, *partial;
-      TQ_TRY(scratch(ctx, S_PSI, (size_t)count * namps * sizeof(C), &psi));
-      TQ_TRY(scratch(ctx, S_LAMBDA, (size_t)count * namps * sizeof(C), &lam));
-      TQ_TRY(scratch(ctx, S_MATS, (size_t)count * std::max(gr.n_gates, 1) * kAdjMatEntries * sizeof(C), &mats));
-      TQ_TRY(scratch(ctx, S_GRADP, (size_t)count * std::max(s->n_slots, 1) * ntiles * sizeof(double), &partial));
-      BatchMap wmap{nullptr, 0, namps};
-      TQ_TRY(launch_adjoint<T>(*s, d_params, pmap, d_states, smap, psi, lam, wmap, mats, (double*)partial,
-                               (const uint64_t*)tt, (const double*)(tt + n_terms * 8),
-                               (const int32_t*)(tt + n_terms * 16), n_terms,
-                               (const T*)d_grad_out + (int64_t)mem[0] * n_obs, n_obs, (T*)d_grad, gr.n_params,
-                               count, stream));
+      r.psi = 0;
+      r.lam = align256(count * namps * sizeof(C));
+      r.mats = r.lam + align256(count * namps * sizeof(C));
+      r.part = r.mats + align256(count * std::max(gr.n_gates, 1) * kAdjMatEntries * sizeof(C));
+      ws = std::max(ws, r.part + align256(count * std::max(s->n_slots, 1) * ntiles * sizeof(double)));
+      BatchMap pmap, smap;  // warm the offset tables
+      TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, r.mem, stream, &pmap));
+      TQ_TRY(member_map(ctx, S_MISC, batch->state_off, r.mem, stream, &smap));
+      runs.push_back(std::move(r));
       i0 = i1;
     }
+  }
+  if (need) *need = (int64_t)ws;
+  if (!exec) return TQ_OK;
+  if (!d_work || work_bytes < (int64_t)ws)
+    return fail(TQ_EWORKSPACE, "adjoint workspace of " + std::to_string(work_bytes) + " bytes is smaller than the " +
+                                   std::to_string(ws) + " bytes tq_sv_backward_workspace reports");
+  unsigned char* w = (unsigned char*)d_work;
+  for (const Run& r : runs) {
+    BatchMap pmap, smap;
+    TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, r.mem, stream, &pmap));
+    TQ_TRY(member_map(ctx, S_MISC, batch->state_off, r.mem, stream, &smap));
+    const int64_t namps = int64_t(1) << r.n;
+    BatchMap wmap{nullptr, 0, namps};
+    TQ_TRY(launch_adjoint<T>(*r.s, d_params, pmap, d_states, smap, w + r.psi, w + r.lam, wmap, w + r.mats,
+                             (double*)(w + r.part), (const uint64_t*)r.tt, (const double*)(r.tt + n_terms * 8),
+                             (const int32_t*)(r.tt + n_terms * 16), n_terms,
+                             (const T*)d_grad_out + (int64_t)r.mem[0] * n_obs, n_obs, (T*)d_grad, r.n_params,
+                             (int)r.mem.size(), stream));
   }
   return TQ_OK;
 }
@@ -494,7 +535,8 @@ void tq_ctx_destroy(tq_ctx* ctx) {
     if (ctx->scratch[i]) (void)hipFree(ctx->scratch[i]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
-  for (auto& kv : ctx->tables) (void)hipFree(kv.second);
+  for (auto& kv : ctx->tables) (void)hipFree(kv.second.dev);
+  for (void* p : ctx->retired) (void)hipFree(p);
   delete ctx;
 }
 
@@ -572,16 +614,38 @@ tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void*
 
 }  // extern "C"
 
+extern "C" int64_t tq_sv_backward_workspace(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                                           const int32_t* n_params, const tq_zterm* terms, int32_t n_terms,
+                                           int32_t n_obs, const tq_sv_opts* opts) {
+  if (!ctx) {
+    fail(TQ_EINVAL, "null context");
+    return -1;
+  }
+  int64_t need = -1;
+  tq_status st;
+  if (dt == TQ_C64)
+    st = sv_backward_t<float>(ctx, batch, gates, n_params, nullptr, nullptr, terms, n_terms, n_obs, nullptr, nullptr,
+                              opts, nullptr, 0, &need, nullptr);
+  else if (dt == TQ_C128)
+    st = sv_backward_t<double>(ctx, batch, gates, n_params, nullptr, nullptr, terms, n_terms, n_obs, nullptr, nullptr,
+                               opts, nullptr, 0, &need, nullptr);
+  else
+    st = fail(TQ_EINVAL, "unknown dtype");
+  return st == TQ_OK ? need : -1;
+}
+
 extern "C" tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
                                     const int32_t* n_params, const void* d_params, const void* d_states,
                                     const tq_zterm* terms, int32_t n_terms, int32_t n_obs, const void* d_grad_out,
-                                    void* d_grad, const tq_sv_opts* opts, void* stream) {
+                                    void* d_grad, const tq_sv_opts* opts, void* d_work, int64_t work_bytes,
+                                    void* stream) {
   if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (!d_work) return fail(TQ_EWORKSPACE, "tq_sv_backward needs a workspace (size from tq_sv_backward_workspace)");
   if (dt == TQ_C64)
     return sv_backward_t<float>(ctx, batch, gates, n_params, d_params, d_states, terms, n_terms, n_obs, d_grad_out,
-                                d_grad, opts, (hipStream_t)stream);
+                                d_grad, opts, d_work, work_bytes, nullptr, (hipStream_t)stream);
   if (dt == TQ_C128)
     return sv_backward_t<double>(ctx, batch, gates, n_params, d_params, d_states, terms, n_terms, n_obs, d_grad_out,
-                                 d_grad, opts, (hipStream_t)stream);
+                                 d_grad, opts, d_work, work_bytes, nullptr, (hipStream_t)stream);
   return fail(TQ_EINVAL, "unknown dtype");
 }

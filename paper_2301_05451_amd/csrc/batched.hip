@@ -71,11 +71,6 @@ struct LevelBufs {
   DevBuf circ, pref, ppref, items;
 };
 
-uint64_t mix(uint64_t h, uint64_t w) {
-  h ^= w + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
-  return h * 0xFF51AFD7ED558CCDull;
-}
-
 }  // namespace
 }  // namespace tq
 
@@ -409,19 +404,18 @@ tq_status run_graphed(tq_svb* b, int which, std::array<const void*, 4> ptrs, hip
   return TQ_OK;
 }
 
+// Exact key of a batch structure (dtype, sizes and gate records): autotuned shapes are
+// shared only between byte-identical structures.
 std::string structure_key(const tq_svb* b) {
-  uint64_t h1 = 0x243F6A8885A308D3ull, h2 = 0x13198A2E03707344ull;
-  h1 = mix(h1, (uint64_t)b->dt);
-  h1 = mix(h1, (uint64_t)b->count);
+  std::string k = "svb:";
+  const int32_t head[2] = {(int32_t)b->dt, (int32_t)b->count};
+  k.append((const char*)head, sizeof head);
   for (int i = 0; i < b->count; ++i) {
-    h1 = mix(h1, (uint64_t)b->n[i] << 32 | (uint32_t)b->n_gates[i]);
-    const uint64_t* w = reinterpret_cast<const uint64_t*>(b->gates.data() + b->gate_off[i]);
-    const size_t nw = (size_t)b->n_gates[i] * sizeof(tq_gate) / 8;
-    for (size_t k = 0; k < nw; ++k) h2 = mix(h2, w[k]);
+    const int32_t sz[2] = {(int32_t)b->n[i], (int32_t)b->n_gates[i]};
+    k.append((const char*)sz, sizeof sz);
+    k.append((const char*)(b->gates.data() + b->gate_off[i]), (size_t)b->n_gates[i] * sizeof(tq_gate));
   }
-  char key[64];
-  snprintf(key, sizeof key, "svb:%016llx%016llx", (unsigned long long)h1, (unsigned long long)h2);
-  return key;
+  return k;
 }
 
 }  // namespace

@@ -1,18 +1,18 @@
 // Expectation values of sums of Pauli-Z strings (the VQC cost of Sec. 4):
 // <O_o> = sum over terms k with obs_k = o of coeff_k * sum_x |psi_x|^2 (-1)^popcount(x & m_k).
 //
-// A work-group owns 2^pb contiguous amplitudes, so the index bits at and above pb are fixed
-// per group: their parity is one uniform sign per term. Below pb, a thread holds up to 32
-// amplitudes (index = it * 256 + thread id); the sums of all terms over them are read off
-// one Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's precision.
-// Everything above (waves, the group, the groups of a circuit) is a fixed-order double
-// tree, so repeated runs are bitwise equal.
+// The state is read in chunks of 2^13 contiguous amplitudes, so the index bits at and above
+// 13 are fixed per chunk: their parity is one uniform sign per term. Within a chunk, a
+// thread holds 32 amplitudes (index = it * 256 + thread id); the sums of all terms over them
+// are read off one Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's
+// precision, as is the thread's running sum over its chunks. Everything above (waves, the
+// group, the groups of a circuit) is a fixed-order double tree, so repeated runs are
+// bitwise equal.
 #include "sv_device.h"
 
 namespace tq {
 
 constexpr int kExpThreads = 256;
-constexpr int kExpFinalThreads = 1024;  // final sums: one wave per term for up to 16 terms at once
 
 // +1 or -1 built from the parity bit with integer operations (a wave-uniform parity stays in
 // scalar registers, so the multiply-add takes it as a scalar operand)
@@ -52,14 +52,36 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Work-groups per circuit of the partial-sum kernel: about kExpGroups over the launch, at
+// most one per 2^13-amplitude chunk.
+constexpr int kExpGroups = 512;
+constexpr bool kExpPrefetch = true;
+
+int expval_groups(int n, int cn) {
+  const int cb = n < 13 ? n : 13;
+  const int64_t chunks = int64_t(1) << (n - cb);
+  const int64_t want = std::max<int64_t>(1, kExpGroups / std::max(cn, 1));
+  return (int)std::min<int64_t>(chunks, want);
+}
+
+// One work-group walks the 2^13-amplitude chunks j = blockIdx.x, blockIdx.x + gridDim.x, ...
+// of its circuit (a fixed sequence, so the sums repeat bitwise), loading the next chunk
+// while it transforms the current one, and writes one partial sum per term.
 template <typename T, int KT>
 __global__ void __launch_bounds__(kExpThreads)
-    expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int pb,
-                          const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial, int nblocks) {
+    expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int n,
+                          const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial) {
   using C = typename Cx<T>::type;
+  constexpr int kMaxIt = 32;
   const C* s = st + smap.at(blockIdx.y);
-  const uint64_t base = (uint64_t)blockIdx.x << pb;
-  const uint32_t lo_mask = (uint32_t)((uint64_t(1) << pb) - 1);
+  const int cb = n < 13 ? n : 13;
+  const uint32_t namp = 1u << cb;
+  const uint32_t lo_mask = namp - 1;
+  const int64_t nchunk = int64_t(1) << (n - cb);
+  const uint32_t tid = threadIdx.x;
+  const int lg = cb > 8 ? cb - 8 : 0;
+  const int nit = 1 << lg;
+  const uint32_t tcl = tid & (namp - 1);
   uint32_t mlo[KT];
   T acc[KT];
 #pragma unroll
@@ -67,50 +89,65 @@ __global__ void __launch_bounds__(kExpThreads)
     mlo[k] = k < nk ? (uint32_t)(pmask[k] & lo_mask) : 0u;
     acc[k] = (T)0;
   }
-  // loc = it * 256 + tid. The thread id (low 8 bits) gives one sign per term and thread,
-  // applied at the end. Over the iteration bits, a term's sum is one coefficient of the
-  // Walsh-Hadamard transform of the thread's |psi|^2 values: W[u] = sum_it (-1)^{|it & u|}
-  // p[it], with u the term's mask bits at 8 and above. So each thread loads its values,
-  // transforms them in registers (it has at most 2^(13-8) = 32 of them) and reads one
-  // coefficient per term.
-  constexpr int kMaxIt = 32;
-  const uint32_t namp = 1u << pb;
-  const uint32_t tid = threadIdx.x;
-  const int lg = pb > 8 ? pb - 8 : 0;
-  const int nit = 1 << lg;
-  // straight-line: out-of-range slots load a valid (clamped) address and count as zero, and
-  // the full 32-point transform of the zero-padded values gives the same coefficients
-  const uint32_t tcl = tid & (namp - 1);
-  T pv[kMaxIt];
+  // loc = it * 256 + tid within a chunk. The thread id (low 8 bits) gives one sign per term
+  // and thread; over the iteration bits a term's sum is one coefficient of the Walsh-Hadamard
+  // transform of the thread's |psi|^2 values, W[u] = sum_it (-1)^{|it & u|} p[it], with u the
+  // term's mask bits 8..12. The transform and a thread's sum over its chunks run in the
+  // state's precision; everything after that (waves, the group, the circuit) is in double.
+  __shared__ T wsh[kMaxIt][kExpThreads];  // per-thread column: indexable storage for W[u]
+  C nxt[kMaxIt];
+  int64_t j = blockIdx.x;
+  if (kExpPrefetch && j < nchunk) {
 #pragma unroll
-  for (int it = 0; it < kMaxIt; ++it) {
-    const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
-    const C a = s[base + (itc << 8) + tcl];
-    const T p = a.x * a.x + a.y * a.y;
-    pv[it] = (it < nit && tid < namp) ? p : (T)0;
+    for (int it = 0; it < kMaxIt; ++it) {
+      const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
+      nxt[it] = s[((uint64_t)j << cb) + (itc << 8) + tcl];
+    }
   }
+  for (; j < nchunk; j += gridDim.x) {
+    if (!kExpPrefetch) {
 #pragma unroll
-  for (int h = 1; h < kMaxIt; h <<= 1) {
-#pragma unroll
-    for (int i = 0; i < kMaxIt; ++i)
-      if ((i & h) == 0) {
-        const T a = pv[i], b = pv[i | h];
-        pv[i] = a + b;
-        pv[i | h] = a - b;
+      for (int it = 0; it < kMaxIt; ++it) {
+        const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
+        nxt[it] = s[((uint64_t)j << cb) + (itc << 8) + tcl];
       }
-  }
-  // coefficient u of this thread at wsh[u][tid] (a term's index u is the same for every
-  // lane, so the lanes read consecutive words)
-  __shared__ T wsh[kMaxIt][kExpThreads];
+    }
+    T pv[kMaxIt];
 #pragma unroll
-  for (int it = 0; it < kMaxIt; ++it)
-    if (it < nit) wsh[it][tid] = pv[it];
+    for (int it = 0; it < kMaxIt; ++it) {
+      const T p = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
+      pv[it] = (it < nit && tid < namp) ? p : (T)0;
+    }
+    const int64_t jn = j + gridDim.x;
+    if (kExpPrefetch && jn < nchunk) {  // next chunk in flight while this one is transformed
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < nk) {
-      const uint32_t u = (mlo[k] >> 8) & (uint32_t)(nit - 1);
-      const T w = wsh[u][tid];
-      acc[k] = (__popc(tid & mlo[k] & 0xffu) & 1) ? -w : w;
+      for (int it = 0; it < kMaxIt; ++it) {
+        const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
+        nxt[it] = s[((uint64_t)jn << cb) + (itc << 8) + tcl];
+      }
+    }
+#pragma unroll
+    for (int h = 1; h < kMaxIt; h <<= 1) {
+#pragma unroll
+      for (int i = 0; i < kMaxIt; ++i)
+        if ((i & h) == 0) {
+          const T a = pv[i], b = pv[i | h];
+          pv[i] = a + b;
+          pv[i | h] = a - b;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kMaxIt; ++it)
+      if (it < nit) wsh[it][tid] = pv[it];
+    const uint64_t hi = (uint64_t)j << cb;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < nk) {
+        const uint32_t u = (mlo[k] >> 8) & (uint32_t)(nit - 1);
+        const T w = wsh[u][tid];
+        const uint32_t par = (uint32_t)(__popc(tid & mlo[k] & 0xffu) + __popcll(hi & pmask[k])) & 1u;
+        acc[k] += par ? -w : w;
+      }
     }
   }
   __shared__ double red[kExpThreads / 64][KT];
@@ -127,27 +164,34 @@ __global__ void __launch_bounds__(kExpThreads)
     const int k = threadIdx.x;
     double x = 0.0;
     for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][k];
-    const bool hi_odd = __popcll(base & pmask[k]) & 1;
-    partial[((int64_t)blockIdx.y * KT + k) * nblocks + blockIdx.x] = hi_odd ? -x : x;
+    partial[((int64_t)blockIdx.y * KT + k) * gridDim.x + blockIdx.x] = x;
   }
 }
 
-// One work-group per circuit. Each wave sums the block partials of one term at a time
-// (stored term-major, so a wave's loads are contiguous; lane-strided, then a butterfly: a
-// fixed order), and thread 0 accumulates coeff * S_k into
-// its observable in term order. Circuit i of the launch writes output row rows.at(i).
+// One work-group per circuit: each wave sums the partials of one term at a time (lane l adds
+// groups l, l + 64, ... in four interleaved chains, then chains and lanes are combined in a
+// fixed order), and thread 0 accumulates coeff * S_k into its observable in term order.
+// Circuit i of the launch writes output row rows.at(i).
 template <typename T, int KT>
-__global__ void __launch_bounds__(kExpFinalThreads)
-    expval_final_kernel(const double* __restrict__ partial, int nblocks, int nk, const double* __restrict__ coeff,
+__global__ void __launch_bounds__(kExpThreads)
+    expval_final_kernel(const double* __restrict__ partial, int nb, int nk, const double* __restrict__ coeff,
                         const int32_t* __restrict__ obs, int n_obs, double* __restrict__ outacc, int first,
                         int last, T* __restrict__ out, BatchMap rows) {
   __shared__ double sk[KT];
   const int circ = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < nk; k += kExpFinalThreads / 64) {
-    double x = 0.0;
-#pragma unroll 8
-    for (int b = lane; b < nblocks; b += 64) x += partial[((int64_t)circ * KT + k) * nblocks + b];
+  for (int k = wv; k < nk; k += kExpThreads / 64) {
+    const double* pk = partial + ((int64_t)circ * KT + k) * nb;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+    int b = lane;
+    for (; b + 192 < nb; b += 256) {
+      x0 += pk[b];
+      x1 += pk[b + 64];
+      x2 += pk[b + 128];
+      x3 += pk[b + 192];
+    }
+    for (; b < nb; b += 64) x0 += pk[b];
+    double x = (x0 + x1) + (x2 + x3);
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0) sk[k] = x;
   }
@@ -163,52 +207,44 @@ __global__ void __launch_bounds__(kExpFinalThreads)
 }
 
 template <typename T, int KT>
-static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, int pb, int nblocks, int cn,
+static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, int n, int nb, int cn,
                          const uint64_t* pm, const double* cf, const int32_t* ob, int nk, int n_obs, double* partial,
                          double* outacc, int first, int last, T* out, BatchMap rows, hipStream_t stream) {
-  hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nblocks, cn), dim3(kExpThreads), 0, stream,
-                     d_states, smap, pb, pm, nk, partial, nblocks);
-  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3(cn), dim3(kExpFinalThreads), 0, stream, partial, nblocks, nk, cf, ob,
-                     n_obs, outacc, first, last, out, rows);
+  hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nb, (unsigned)cn), dim3(kExpThreads), 0, stream,
+                     d_states, smap, n, pm, nk, partial);
+  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3((unsigned)cn), dim3(kExpThreads), 0, stream, partial, nb, nk,
+                     cf, ob, n_obs, outacc, first, last, out, rows);
 }
 
-// A work-group sums 2^13 amplitudes at most: 256 threads x 32 values per thread, the size of
-// the per-thread transform in expval_partial_kernel.
-int expval_block_bits(int n) { return n < 13 ? n : 13; }
-
 size_t expval_scratch_doubles(int n, int count, int n_obs) {
-  const int pb = expval_block_bits(n);
-  const int64_t nblocks = int64_t(1) << (n - pb);
   const int cn = std::min(count, 65535);
-  return (size_t)cn * nblocks * 32 + (size_t)cn * n_obs + 64;
+  const int nb = expval_groups(n, cn);
+  return (size_t)cn * n_obs + (size_t)cn * nb * 32 + 64;
 }
 
 template <typename T>
 tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,
                         const uint64_t* d_pmask, const double* d_coeff, const int32_t* d_obs, int n_terms, int n_obs,
                         double* d_scratch, size_t scratch_doubles, T* d_out, BatchMap rows, hipStream_t stream) {
-  const int pb = expval_block_bits(n);
-  const int64_t nblocks = int64_t(1) << (n - pb);
   if (expval_scratch_doubles(n, count, n_obs) > scratch_doubles) return fail(TQ_ENOMEM, "expval scratch too small");
   for (int c0 = 0; c0 < count; c0 += 65535) {
     const int cn = std::min(65535, count - c0);
-    double* partial = d_scratch;
-    double* outacc = d_scratch + (size_t)cn * nblocks * 32;
-    T* out = d_out;
-    const BatchMap rm = rows.shifted(c0);
-    if (n_terms == 0) {
-      launch_chunk<T, 1>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask, d_coeff, d_obs, 0, n_obs, partial,
-                         outacc, 1, 1, out, rm, stream);
-    }
+    const int nb = expval_groups(n, cn);
+    double* outacc = d_scratch;
+    double* partial = d_scratch + (size_t)cn * n_obs;
+    const BatchMap sm = smap.shifted(c0), rm = rows.shifted(c0);
+    if (n_terms == 0)
+      launch_chunk<T, 1>(d_states, sm, n, nb, cn, d_pmask, d_coeff, d_obs, 0, n_obs, partial, outacc, 1, 1, d_out, rm,
+                         stream);
     for (int k0 = 0; k0 < n_terms; k0 += 32) {
       const int nk = std::min(32, n_terms - k0);
       const int first = k0 == 0, last = k0 + 32 >= n_terms;
       if (nk <= 4)
-        launch_chunk<T, 4>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
-                           nk, n_obs, partial, outacc, first, last, out, rm, stream);
+        launch_chunk<T, 4>(d_states, sm, n, nb, cn, d_pmask + k0, d_coeff + k0, d_obs + k0, nk, n_obs, partial, outacc,
+                           first, last, d_out, rm, stream);
       else
-        launch_chunk<T, 32>(d_states, smap.shifted(c0), pb, (int)nblocks, cn, d_pmask + k0, d_coeff + k0, d_obs + k0,
-                            nk, n_obs, partial, outacc, first, last, out, rm, stream);
+        launch_chunk<T, 32>(d_states, sm, n, nb, cn, d_pmask + k0, d_coeff + k0, d_obs + k0, nk, n_obs, partial,
+                            outacc, first, last, d_out, rm, stream);
     }
     TQ_HIP(hipGetLastError());
   }

@@ -484,7 +484,7 @@ tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap,
                          int n_obs, T* grad, int n_params, int count, hipStream_t stream);
 
 // expval.hip
-int expval_block_bits(int n);
+int expval_groups(int n, int cn);
 size_t expval_scratch_doubles(int n, int count, int n_obs);
 template <typename T>
 tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int n, int count,

@@ -103,6 +103,7 @@ struct tq_tn_plan {
   void* d_bfused = nullptr;            // ... of the reverse runs
   void* d_leaf_env = nullptr;          // (leaf offset, environment offset, elements) of unsliced leaves
   int n_leaf_env = 0;
+  bool store = false;                  // the reverse pass reuses the forward's intermediates
   ~tq_tn_plan();
 };
 
@@ -865,6 +866,15 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
   G = std::min(G, p->n_slices);
   while (G > 1 && (shared + G * (per_slice + p->perm_elems)) * 2 * csz > budget) G >>= 1;
   p->G = std::max<int64_t>(G, 1);
+  // store policy (Sec. 4.1 keeps the forward's intermediates for the backward pass): the
+  // reverse pass can reuse what tq_tn_contract left in the workspace only when every slice's
+  // intermediates are there at once, i.e. all slices run as one group within the budget
+  if (d->store_policy < 0 || d->store_policy > 2) return fail(TQ_EINVAL, "store_policy must be 0, 1 or 2");
+  const bool one_group = p->G >= p->n_slices;
+  if (d->store_policy == TQ_TN_STORE && !one_group)
+    return fail(TQ_ENOTSUP, "store policy: the memory budget cannot hold the intermediates of all " +
+                                std::to_string(p->n_slices) + " slices at once (use recompute or auto)");
+  p->store = d->store_policy != TQ_TN_RECOMPUTE && one_group;
   // workspace offsets (complex elements): shared tensors once, slice tensors G copies
   int64_t w = 0;
   for (auto& t : p->t) {
@@ -1047,6 +1057,8 @@ int64_t tq_tn_leaf_offset(const tq_tn_plan* p, int32_t leaf) {
   if (!p || leaf < 0 || leaf >= p->n_leaves) return -1;
   return p->leaf_off[leaf];
 }
+
+int32_t tq_tn_plan_stores(const tq_tn_plan* p) { return p ? (p->store ? 1 : 0) : -1; }
 
 int64_t tq_tn_workspace(const tq_tn_plan* p, int32_t backward) {
   if (!p) return -1;
@@ -1279,7 +1291,9 @@ static tq_status tn_backward_t(tq_ctx* ctx, const tq_tn_plan* p, const void* d_l
   for (int64_t s0 = 0; s0 < p->n_slices; s0 += p->G) {
     R.s0 = s0;
     R.g = std::min<int64_t>(p->G, p->n_slices - s0);
-    TQ_TRY(tn_forward_group<T>(R));
+    // store policy: the intermediates of the preceding tq_tn_contract are still in the
+    // workspace (one group holds every slice); recompute policy: rebuild them here
+    if (!p->store) TQ_TRY(tn_forward_group<T>(R));
     // environment of the result: the upstream value, one copy per slice
     hipLaunchKernelGGL(tn_broadcast_kernel<T>, dim3(grid_for(nout), (unsigned)R.g), dim3(256), 0, stream,
                        (const C*)d_grad_out, R.eptr(p->root), nout);

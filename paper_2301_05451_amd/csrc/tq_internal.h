@@ -166,6 +166,15 @@ tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params);
 int gate_n_angles(int op);
 constexpr int kAdjMaxSlotsPerStage = 256;
 
+// A cached device table (see cached_table).
+struct TableEntry {
+  void* dev = nullptr;
+  size_t bytes = 0;
+  uint64_t last_use = 0;
+};
+constexpr size_t kTableCacheBytes = size_t(256) << 20;
+constexpr size_t kTableCacheEntries = 4096;
+
 }  // namespace tq
 
 // The context (opaque in the public header).
@@ -182,8 +191,12 @@ struct tq_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t pinned_done = nullptr;
   bool pinned_pending = false;
-  // immutable small device tables cached by content hash
-  std::unordered_map<std::string, void*> tables;
+  // immutable small device tables cached by content (the key is the table's bytes)
+  std::unordered_map<std::string, tq::TableEntry> tables;
+  size_t table_bytes = 0;
+  uint64_t table_clock = 0;
+  // scratch buffers replaced by larger ones (freed with the context)
+  std::vector<void*> retired;
   // autotune results: key -> (t, R)
   std::unordered_map<std::string, std::pair<int, int>> tuned;
 };
@@ -192,7 +205,8 @@ namespace tq {
 // scratch slots
 enum { S_MATS = 0, S_PARTIAL = 1, S_OFFS = 2, S_LAMBDA = 3, S_PSI = 4, S_GRADP = 5, S_TERMS = 6, S_MISC = 7,
        S_TNB = 8 };
-tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out);
+// Grow-only context scratch; `zero` clears a newly allocated buffer (once, synchronously).
+tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out, bool zero = false);
 // Immutable device copy of a small host table, cached by content (no per-call upload).
 tq_status cached_table(tq_ctx* ctx, const void* host, size_t bytes, void** dev);
 // Stream-ordered upload of a per-call table into scratch slot `slot` (via pinned memory).

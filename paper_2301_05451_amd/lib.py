@@ -66,10 +66,12 @@ _lib.tq_sv_init.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), ct.c_int64, _vp, _
 _lib.tq_sv_init.restype = ct.c_int
 _lib.tq_sv_plan_info.argtypes = [_vp, ct.c_int, _i32, _vp, _i32, ct.POINTER(SvOpts), ct.POINTER(ct.c_int64)]
 _lib.tq_sv_plan_info.restype = ct.c_int
-if hasattr(_lib, "tq_sv_backward"):
-    _lib.tq_sv_backward.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
-                                    _vp, ct.POINTER(SvOpts), _vp]
-    _lib.tq_sv_backward.restype = ct.c_int
+_lib.tq_sv_backward_workspace.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _i32, _i32,
+                                          ct.POINTER(SvOpts)]
+_lib.tq_sv_backward_workspace.restype = ct.c_int64
+_lib.tq_sv_backward.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
+                                _vp, ct.POINTER(SvOpts), _vp, ct.c_int64, _vp]
+_lib.tq_sv_backward.restype = ct.c_int
 
 
 def raw():
@@ -228,8 +230,11 @@ def expval(states, spec: BatchSpec, terms, n_obs, ctx=None):
     return out
 
 
-def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0, tile_bits=0, reg_bits=0, ctx=None):
-    """Adjoint gradients d(sum grad_out * <O>)/d params, same layout as params (tq_sv_backward)."""
+def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0, tile_bits=0, reg_bits=0, ctx=None,
+                work=None):
+    """Adjoint gradients d(sum grad_out * <O>)/d params, same layout as params (tq_sv_backward).
+    ``work`` (optional uint8 CUDA tensor) is the caller workspace; a new one is taken from the
+    torch allocator when it is missing or too small."""
     import torch
     _check_tensors(states, params, spec)
     ctx = ctx or context(states.device.index)
@@ -239,11 +244,27 @@ def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0,
         raise ValueError(f"grad_out needs {spec.count} x {n_obs} entries")
     grad = torch.empty_like(params)
     o = _opts(mode, tile_bits, reg_bits, 0)
+    need = sv_backward_workspace(states, spec, terms, n_obs, mode, tile_bits, reg_bits, ctx)
+    if work is None or work.numel() < need:
+        work = torch.empty(need, dtype=torch.uint8, device=states.device)
     check(_lib.tq_sv_backward(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data,
                               spec.n_params.ctypes.data, params.data_ptr(), states.data_ptr(), terms.ctypes.data,
                               int(terms.shape[0]), int(n_obs), grad_out.data_ptr(), grad.data_ptr(), ct.byref(o),
-                              _stream()))
+                              work.data_ptr(), ct.c_int64(work.numel()), _stream()))
     return grad
+
+
+def sv_backward_workspace(states, spec: BatchSpec, terms, n_obs, mode=0, tile_bits=0, reg_bits=0, ctx=None):
+    """Workspace bytes tq_sv_backward needs for this batch (tq_sv_backward_workspace)."""
+    ctx = ctx or context(states.device.index)
+    terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
+    o = _opts(mode, tile_bits, reg_bits, 0)
+    need = _lib.tq_sv_backward_workspace(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data,
+                                         spec.n_params.ctypes.data, terms.ctypes.data, int(terms.shape[0]),
+                                         int(n_obs), ct.byref(o))
+    if need < 0:
+        raise TQError(1, last_error())
+    return int(need)
 
 
 def init_states(states, spec: BatchSpec, basis=0, ctx=None):
@@ -374,7 +395,10 @@ class TnDesc(ct.Structure):
     _fields_ = [("n_leaves", ct.c_int32), ("leaf_rank", ct.c_void_p), ("leaf_inds", ct.c_void_p),
                 ("pairs", ct.c_void_p), ("n_sliced", ct.c_int32), ("sliced", ct.c_void_p), ("n_out", ct.c_int32),
                 ("out_inds", ct.c_void_p), ("dtype", ct.c_int32), ("slice_group", ct.c_int64),
-                ("mem_budget", ct.c_int64)]
+                ("mem_budget", ct.c_int64), ("store_policy", ct.c_int32), ("_pad", ct.c_int32)]
+
+
+TN_RECOMPUTE, TN_STORE, TN_AUTO = 0, 1, 2
 
 
 TN_LEAF_DTYPE = np.dtype([("kind", "<i4"), ("gate", "<i4"), ("conj", "<i4"), ("const_off", "<i4")])
@@ -387,6 +411,8 @@ _lib.tq_tn_leaf_elems.argtypes = [_vp]
 _lib.tq_tn_leaf_elems.restype = ct.c_int64
 _lib.tq_tn_leaf_offset.argtypes = [_vp, _i32]
 _lib.tq_tn_leaf_offset.restype = ct.c_int64
+_lib.tq_tn_plan_stores.argtypes = [_vp]
+_lib.tq_tn_plan_stores.restype = ct.c_int32
 _lib.tq_tn_workspace.argtypes = [_vp, _i32]
 _lib.tq_tn_workspace.restype = ct.c_int64
 _lib.tq_tn_plan_info.argtypes = [_vp, ct.POINTER(ct.c_int64)]
@@ -408,7 +434,7 @@ class TnPlan:
     """Owns a tq_tn_plan built from leaf index lists, an SSA tree and sliced indices."""
 
     def __init__(self, leaf_inds, pairs, sliced=(), out_inds=(), c128=False, slice_group=0, mem_budget=0,
-                 ctx=None):
+                 ctx=None, store_policy=TN_RECOMPUTE):
         self.ctx = ctx or context()
         self.c128 = bool(c128)
         ranks = np.array([len(x) for x in leaf_inds], dtype=np.int32)
@@ -418,7 +444,8 @@ class TnPlan:
         oi = np.array(list(out_inds) or [0], dtype=np.int32)
         self._keep = (ranks, flat, pr, sl, oi)
         d = TnDesc(len(leaf_inds), ranks.ctypes.data, flat.ctypes.data, pr.ctypes.data, len(sliced), sl.ctypes.data,
-                   len(out_inds), oi.ctypes.data, TQ_C128 if c128 else TQ_C64, int(slice_group), int(mem_budget))
+                   len(out_inds), oi.ctypes.data, TQ_C128 if c128 else TQ_C64, int(slice_group), int(mem_budget),
+                   int(store_policy), 0)
         h = _vp()
         check(_lib.tq_tn_plan_create(self.ctx.h, ct.byref(d), ct.byref(h)))
         self.h = h
@@ -429,6 +456,7 @@ class TnPlan:
         out = (ct.c_int64 * 8)()
         check(_lib.tq_tn_plan_info(h, out))
         self.info = dict(zip(TN_INFO_FIELDS, [int(v) for v in out]))
+        self.stores = bool(_lib.tq_tn_plan_stores(h))
 
     def workspace_bytes(self, backward=False):
         return int(_lib.tq_tn_workspace(self.h, 1 if backward else 0))

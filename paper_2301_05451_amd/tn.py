@@ -417,12 +417,12 @@ def leaf_specs(net: Network):
 class TNProgram:
     """A planned circuit network: builds leaves from parameters, contracts, differentiates."""
 
-    def __init__(self, net: Network, tree: Tree, c128=False, slice_group=0, mem_budget=0):
+    def __init__(self, net: Network, tree: Tree, c128=False, slice_group=0, mem_budget=0, store_policy=0):
         from . import lib
 
         self.net, self.tree = net, tree
         self.plan = lib.TnPlan([lf.inds for lf in net.leaves], tree.pairs, tree.sliced, net.output, c128,
-                               slice_group, mem_budget)
+                               slice_group, mem_budget, store_policy=store_policy)
         self.specs, self.consts = leaf_specs(net)
         self.c128 = c128
 
@@ -443,6 +443,21 @@ class TNProgram:
         g = torch.ones(1 << self.plan.n_out, dtype=L.dtype, device=L.device) if grad_out is None else grad_out
         env = lib.tn_backward(self.plan, L, g)
         return lib.tn_param_grad(self.plan, self.net.gates, self.specs, params, env)
+
+    def value_and_grad(self, params, grad_out=None, work=None):
+        """Value and d Re(T)/d params in one pass pair: tq_tn_contract then tq_tn_backward on
+        one workspace (under the store policy the reverse pass reuses the intermediates)."""
+        import torch
+        from . import lib
+
+        L = self.leaves(params)
+        need = self.plan.workspace_bytes(True)
+        if work is None or work.numel() < need:
+            work = torch.empty(max(need, 16), dtype=torch.uint8, device=L.device)
+        v = lib.tn_contract(self.plan, L, work)
+        g = torch.ones(1 << self.plan.n_out, dtype=L.dtype, device=L.device) if grad_out is None else grad_out
+        env = lib.tn_backward(self.plan, L, g, work)
+        return v, lib.tn_param_grad(self.plan, self.net.gates, self.specs, params, env)
 
 
 class TNBatch:

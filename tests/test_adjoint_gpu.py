@@ -189,3 +189,39 @@ def test_one_qubit_runs_vs_param_shift(name):
         err = np.abs(got - want).max()
         print(f"  max|d grad| = {err:.2e}", flush=True)
         assert err <= TOL[name] * _wscale(terms, [1.0]), (n, err)
+
+
+def test_backward_workspace_query_and_errors():
+    """tq_sv_backward runs in the caller's workspace: the size query's bytes suffice, a NULL or
+    smaller workspace is TQ_EWORKSPACE, and a reused larger workspace gives the same result."""
+    import ctypes as ct
+
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(90)
+    circs = [W.random_circuit(n, 30, rng, n_params=8) for n in (5, 9, 5)]
+    spec = lib.BatchSpec.from_circuits(circs)
+    params = torch.tensor(np.concatenate([c.params for c in circs]), dtype=torch.float32, device="cuda")
+    terms = W.zterms([([0], 1.0, 0)])
+    psi = lib.zero_states(spec, torch.complex64)
+    lib.sv_apply(psi, params, spec)
+    need = lib.sv_backward_workspace(psi, spec, terms, 1)
+    assert need > 2 * (1 << 9) * 8
+    w = torch.ones(3, 1, device="cuda")
+    big = torch.empty(need + 4096, dtype=torch.uint8, device="cuda")
+    g1 = lib.sv_backward(psi, params, spec, terms, 1, w, work=big)
+    g2 = lib.sv_backward(psi, params, spec, terms, 1, w)
+    assert torch.equal(g1, g2)
+    for i, c in enumerate(circs):
+        c.terms, c.n_obs = terms, 1
+        p0 = int(spec.param_off[i])
+        assert np.abs(g1[p0:p0 + c.n_params].cpu().numpy() - osv.param_shift_grad(c)).max() <= 1e-5
+    grad = torch.empty_like(params)
+    tt = np.ascontiguousarray(terms)
+    o = lib.SvOpts(0, 0, 0, 0)
+    for buf, nbytes in ((None, 0), (big, need - 1)):
+        st = lib.raw().tq_sv_backward(lib.context().h, 0, ct.byref(spec.c), spec.gates.ctypes.data,
+                                      spec.n_params.ctypes.data, params.data_ptr(), psi.data_ptr(), tt.ctypes.data, 1,
+                                      1, w.data_ptr(), grad.data_ptr(), ct.byref(o),
+                                      None if buf is None else buf.data_ptr(), nbytes, None)
+        assert st == 5, lib.last_error()  # TQ_EWORKSPACE

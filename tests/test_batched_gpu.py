@@ -252,8 +252,9 @@ def test_uneven1024_full_size_sampled():
         assert abs(fc[i] - float(np.dot(np.abs(psi) ** 2, osv.zstring_diag(c.n, [0])))) <= 1e-5, i
     # oracle parameter shift on the theta angle of every U3 of the fourth-last layer of a
     # 20-qubit circuit (each used once, unit weight): the state before that layer is computed
-    # once and the last four layers are rerun per shift; at least three of them must carry a
-    # gradient of size, so the comparison is not one of zeros
+    # once and the last four layers are rerun per shift. Gradients of such a deep random circuit
+    # are small (about 1e-4), so besides the absolute bar, those above 2e-5 (at least three)
+    # must agree to 1e-3 relative: the comparison is not one of zeros
     i = big[0]
     c = circs[i]
     p = int(spec.param_off[i])
@@ -274,7 +275,9 @@ def test_uneven1024_full_size_sampled():
         want = 0.5 * (vals[0] - vals[1])
         print(f"  qubit {q} param {k}: adjoint {gc[p + k]:+.8f} oracle shift {want:+.8f}", flush=True)
         assert abs(gc[p + k] - want) <= 1e-5, k
-        big_grads += abs(want) > 1e-3
+        if abs(want) > 2e-5:
+            assert abs(gc[p + k] - want) <= 1e-3 * abs(want), k
+            big_grads += 1
     assert big_grads >= 3
 
 

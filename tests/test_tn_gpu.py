@@ -287,3 +287,40 @@ def test_qaoa50_p1_closed_form_all_edges():
         want = (0.5 * math.sin(4 * b) * math.sin(g) * (math.cos(g) ** du + math.cos(g) ** dv)
                 + 0.5 * math.sin(2 * b) ** 2 * math.cos(g) ** (du + dv - 2 * t) * (1 - math.cos(2 * g) ** t))
         assert abs(val.real - want) <= 1e-5 and abs(val.imag) <= 1e-5, ((u, v), val, want)
+
+
+def test_store_and_recompute_policies():
+    """Store policy (the forward's intermediates kept in the workspace, Sec. 4.1) and
+    recompute policy give the same environments and gradients; auto picks store when every
+    slice fits the budget at once and recompute otherwise; store under a budget too small for
+    all slices is refused; a too-small workspace is TQ_EWORKSPACE."""
+    from paper_2301_05451_amd import lib
+
+    prob = _qaoa10()
+    e = prob.edges[2]
+    net, _ = tn.qaoa_edge_network(prob, e)
+    t0 = tn.elimination_tree(net, tn.elimination_order(net)[0])
+    ts = tn.slice_tree(net, t0, max(2, t0.max_rank - 3))
+    p = _params(net, False)
+    want = otn.qaoa_edge_zz_sv(prob, e)
+    rec = tn.TNProgram(net, ts, store_policy=lib.TN_RECOMPUTE)
+    sto = tn.TNProgram(net, ts, store_policy=lib.TN_STORE)
+    assert not rec.plan.stores and sto.plan.stores
+    v1, g1 = rec.value_and_grad(p)
+    v2, g2 = sto.value_and_grad(p)
+    assert abs(v2.cpu().numpy()[0].real - want) <= 1e-5
+    assert torch.equal(v1, v2) and torch.equal(g1, g2)
+    auto_small = tn.TNProgram(net, ts, slice_group=1, store_policy=lib.TN_AUTO)
+    assert not auto_small.plan.stores and auto_small.plan.info["slice_group"] == 1
+    v3, g3 = auto_small.value_and_grad(p)
+    assert abs(v3.cpu().numpy()[0] - v1.cpu().numpy()[0]) <= 1e-6
+    assert (g3 - g1).abs().max().item() <= 1e-6
+    with pytest.raises(lib.TQError) as ei:
+        tn.TNProgram(net, ts, slice_group=1, store_policy=lib.TN_STORE)
+    assert ei.value.status == 3  # TQ_ENOTSUP
+    L = sto.leaves(p)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    g = torch.ones(1, dtype=torch.complex64, device="cuda")
+    st = lib.raw().tq_tn_backward(sto.plan.ctx.h, sto.plan.h, L.data_ptr(), g.data_ptr(), L.data_ptr(),
+                                  small.data_ptr(), 16, None)
+    assert st == 5  # TQ_EWORKSPACE
