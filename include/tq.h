@@ -155,6 +155,18 @@ tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void*
                     const tq_zterm* terms, int32_t n_terms, int32_t n_obs, void* d_out,
                     void* stream);
 
+/* tq_expval for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): no context, no allocation, no synchronisation.
+ * `count` circuits of n_qubits qubits whose states start at d_states + i * state_stride
+ * (amplitudes; state_stride >= 2^n_qubits); at most 64 terms; d_out as tq_expval. The term
+ * table and reduction partials live in a static 8 MiB device array per GPU (held until the
+ * process ends); requests needing more (very many circuits) fail with TQ_EWORKSPACE. Every
+ * call on a GPU shares that array, so calls that overlap on one GPU (other streams or host
+ * threads at the same time) race; calls ordered on one stream do not. */
+tq_status tq_expval_noalloc(tq_dtype dt, int32_t n_qubits, int32_t count, int64_t state_stride,
+                            const void* d_states, const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
+                            void* d_out, void* stream);
+
 /* Gradient of L = sum_i sum_o d_grad_out[i*n_obs+o] * <O_o>_i with respect to every
  * circuit's parameters, by one reverse (adjoint) sweep per circuit (Sec. 4: the values equal
  * the parameter-shift gradients of Sec. 4.2; the paper's backpropagation of Sec. 4.1 keeps

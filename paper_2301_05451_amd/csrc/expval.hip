@@ -8,6 +8,8 @@
 // precision, as is the thread's running sum over its chunks. Everything above (waves, the
 // group, the groups of a circuit) is a fixed-order double tree, so repeated runs are
 // bitwise equal.
+#include <mutex>
+
 #include "sv_device.h"
 
 namespace tq {
@@ -257,3 +259,115 @@ template tq_status launch_expval<double>(const double2*, BatchMap, int, int, con
                                          const int32_t*, int, int, double*, size_t, double*, BatchMap, hipStream_t);
 
 }  // namespace tq
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free expectation values, for callers that cannot allocate (code under HIP graph
+// capture, tight serving loops). The term table, the accumulators and the partial sums
+// live in one static device array per GPU, whose device address is looked up once per device
+// (hipGetSymbolAddress with that device current); host code only ever passes that address.
+// Every call on a GPU shares the array and it keeps the last call's contents, so calls that
+// overlap on one GPU (several streams or host threads at once) race.
+// ---------------------------------------------------------------------------------------
+namespace tq {
+namespace {
+
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+constexpr int kStaticMaxTerms = 64;
+constexpr size_t kStaticTableBytes = 2048;  // 64 masks + 64 coefficients + 64 observables
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char expval_static_scratch[kStaticScratchBytes];
+
+struct StaticTerms {
+  uint64_t pm[kStaticMaxTerms];
+  double cf[kStaticMaxTerms];
+  int32_t ob[kStaticMaxTerms];
+};
+
+// Writes the term table at the start of the array.
+__global__ void expval_static_setup_kernel(StaticTerms terms, int n_terms, unsigned char* base) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t* pm = (uint64_t*)base;
+  double* cf = (double*)(base + 8 * kStaticMaxTerms);
+  int32_t* ob = (int32_t*)(base + 16 * kStaticMaxTerms);
+  if (i < n_terms) {
+    pm[i] = terms.pm[i];
+    cf[i] = terms.cf[i];
+    ob[i] = terms.ob[i];
+  }
+}
+
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {nullptr};
+
+tq_status static_scratch_address(void** out) {
+  int dev = -1;
+  TQ_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TQ_ENOTSUP, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(expval_static_scratch));
+    if (e != hipSuccess || !p)
+      return fail(TQ_EHIP, std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e));
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return TQ_OK;
+}
+
+template <typename T>
+tq_status expval_noalloc_t(int n, int count, int64_t stride, const void* d_states, const StaticTerms& st,
+                           int n_terms, int n_obs, void* d_out, hipStream_t stream) {
+  void* base;
+  TQ_TRY(static_scratch_address(&base));
+  const size_t avail = (kStaticScratchBytes - kStaticTableBytes) / sizeof(double);
+  const size_t need = expval_scratch_doubles(n, count, n_obs);
+  if (need > avail)
+    return fail(TQ_EWORKSPACE, "tq_expval_noalloc: " + std::to_string(count) + " circuits of " + std::to_string(n) +
+                                   " qubits with " + std::to_string(n_obs) + " outputs need " +
+                                   std::to_string(need * sizeof(double)) + " bytes of scratch, above the " +
+                                   std::to_string(avail * sizeof(double)) + "-byte static limit");
+  unsigned char* b = (unsigned char*)base;
+  hipLaunchKernelGGL(expval_static_setup_kernel, dim3(1), dim3(kStaticMaxTerms), 0, stream, st, n_terms, b);
+  TQ_HIP(hipGetLastError());
+  BatchMap smap{nullptr, 0, stride};
+  BatchMap rows{nullptr, 0, 1};
+  return launch_expval<T>((const typename Cx<T>::type*)d_states, smap, n, count, (const uint64_t*)b,
+                          (const double*)(b + 8 * kStaticMaxTerms), (const int32_t*)(b + 16 * kStaticMaxTerms), n_terms,
+                          n_obs, (double*)(b + kStaticTableBytes), avail, (T*)d_out, rows, stream);
+}
+
+}  // namespace
+}  // namespace tq
+
+extern "C" tq_status tq_expval_noalloc(tq_dtype dt, int32_t n_qubits, int32_t count, int64_t state_stride,
+                                       const void* d_states, const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
+                                       void* d_out, void* stream) {
+  using namespace tq;
+  if (dt != TQ_C64 && dt != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
+  if (n_qubits < 1 || n_qubits > 34) return fail(TQ_ENOTSUP, "n_qubits must be in 1..34");
+  if (count < 0) return fail(TQ_EINVAL, "negative count");
+  if (count == 0) return TQ_OK;
+  if (state_stride < (int64_t(1) << n_qubits)) return fail(TQ_EINVAL, "state_stride is smaller than 2^n_qubits");
+  if (n_obs < 1) return fail(TQ_EINVAL, "n_obs must be >= 1");
+  if (n_terms < 0 || n_terms > kStaticMaxTerms || (n_terms > 0 && !terms))
+    return fail(TQ_EINVAL, "tq_expval_noalloc takes 0.." + std::to_string(kStaticMaxTerms) + " terms");
+  if (!d_states || !d_out) return fail(TQ_EINVAL, "null device pointer");
+  StaticTerms st{};
+  for (int k = 0; k < n_terms; ++k) {
+    if (terms[k].obs < 0 || terms[k].obs >= n_obs) return fail(TQ_EINVAL, "term obs index out of range");
+    if (n_qubits < 64 && (terms[k].mask >> n_qubits) != 0) return fail(TQ_EINVAL, "term names a qubit >= n");
+    uint64_t m = 0;
+    for (int q = 0; q < n_qubits; ++q)
+      if ((terms[k].mask >> q) & 1ull) m |= 1ull << (n_qubits - 1 - q);
+    st.pm[k] = m;
+    st.cf[k] = terms[k].coeff;
+    st.ob[k] = terms[k].obs;
+  }
+  if (dt == TQ_C64)
+    return expval_noalloc_t<float>(n_qubits, count, state_stride, d_states, st, n_terms, n_obs, d_out,
+                                   (hipStream_t)stream);
+  return expval_noalloc_t<double>(n_qubits, count, state_stride, d_states, st, n_terms, n_obs, d_out,
+                                  (hipStream_t)stream);
+}

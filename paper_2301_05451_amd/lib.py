@@ -230,6 +230,19 @@ def expval(states, spec: BatchSpec, terms, n_obs, ctx=None):
     return out
 
 
+_lib.tq_expval_noalloc.argtypes = [ct.c_int, _i32, _i32, ct.c_int64, _vp, _vp, _i32, _i32, _vp, _vp]
+_lib.tq_expval_noalloc.restype = ct.c_int
+
+
+def expval_noalloc(states, n, count, terms, n_obs, out, stride=None):
+    """tq_expval_noalloc into the caller's ``out`` [count, n_obs] (the call allocates nothing)."""
+    terms = np.ascontiguousarray(terms, dtype=W.ZTERM_DTYPE)
+    stride = (1 << n) if stride is None else int(stride)
+    check(_lib.tq_expval_noalloc(_dt(states), int(n), int(count), ct.c_int64(stride), states.data_ptr(),
+                                 terms.ctypes.data, int(terms.shape[0]), int(n_obs), out.data_ptr(), _stream()))
+    return out
+
+
 def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0, tile_bits=0, reg_bits=0, ctx=None,
                 work=None):
     """Adjoint gradients d(sum grad_out * <O>)/d params, same layout as params (tq_sv_backward).
