@@ -10,14 +10,19 @@
 * Expectation values are the exact quadratic form of the VQC cost in Sec. 4
   (f = <0|U^dag O U|0>), evaluated for sums of Pauli-Z strings.
 * Gradients: the parameter-shift rule of Sec. 4.2 (its equation for k[f(mu+s)-f(mu-s)])
-  with s = pi/2, k = 1/2 for every gate here (generators with eigenvalues +-1/2), applied
-  to each parameter occurrence and summed with its scale factor; central finite
-  differences as an independent cross-check (the paper's difference quotient, taken
-  centrally).
+  with s = pi/2, k = 1/2 for gates whose generator has the two eigenvalues +-1/2, and the
+  four-term rule Sec. 4.2 cites for generators with four eigenvalues (the controlled
+  rotations: eigenvalues 0, 0, +-1/2), applied to each parameter occurrence and summed with
+  its scale factor; central finite differences as an independent cross-check (the paper's
+  difference quotient, taken centrally).
+* Measurements (Sec. 5.1.1): expectation values of Pauli strings with X, Y and Z factors,
+  of general Hermitian matrices, and marginal probabilities of chosen qubits.
 
 Gate matrices are the textbook ones. RY is the matrix the paper prints in Sec. 3.2.1;
 CNOT has the block form printed there (identity block for control 0, X block for
-control 1). U3 follows OpenQASM 2; Rot(phi, theta, omega) = RZ(omega) RY(theta) RZ(phi).
+control 1), and the controlled rotations CRX, CRY, CRZ have the same block form with the
+rotation in place of X. U3 follows OpenQASM 2; Rot(phi, theta, omega) =
+RZ(omega) RY(theta) RZ(phi).
 """
 from __future__ import annotations
 
@@ -86,7 +91,26 @@ def gate_matrix(op, angles):
         g = angles[0]
         e, f = np.exp(-0.5j * g), np.exp(0.5j * g)
         return np.diag([e, f, f, e]).astype(np.complex128)
+    if op in (W.CRX, W.CRY, W.CRZ):
+        m = np.eye(4, dtype=np.complex128)
+        m[2:, 2:] = {W.CRX: rx, W.CRY: ry, W.CRZ: rz}[op](angles[0])
+        return m
     raise ValueError(f"unknown op {op}")
+
+
+# Four-term shift rule for a gate exp(-i a G) whose generator has the eigenvalues 0, 0, +-1/2
+# (the controlled rotations): f(a) is a sum of frequencies 1/2 and 1, and
+# df/da = c1 [f(a + pi/2) - f(a - pi/2)] - c2 [f(a + 3 pi/2) - f(a - 3 pi/2)]
+# with c1 = (sqrt2 + 1) / (4 sqrt2), c2 = (sqrt2 - 1) / (4 sqrt2) (solving the two conditions
+# 2 c1 sin(w pi/2) - 2 c2 sin(3 w pi/2) = w for w = 1/2 and w = 1).
+FOUR_TERM = ((math.pi / 2, (math.sqrt(2) + 1) / (4 * math.sqrt(2))),
+             (3 * math.pi / 2, -(math.sqrt(2) - 1) / (4 * math.sqrt(2))))
+TWO_TERM = ((math.pi / 2, 0.5),)
+
+
+def shift_rule(op):
+    """(shift, coefficient) pairs of the parameter-shift rule for the gate's angles."""
+    return FOUR_TERM if op in (W.CRX, W.CRY, W.CRZ) else TWO_TERM
 
 
 def gate_angles(gate, params, shift=None):
@@ -164,6 +188,47 @@ def expval_hermitian(psi, O):
     return float(np.real(np.vdot(psi, O @ psi)))
 
 
+_PAULI = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
+          "Z": np.array([[1, 0], [0, -1]])}
+
+
+def pauli_letters(term, n):
+    """The term's factor on each qubit ('I', 'X', 'Y' or 'Z')."""
+    x, z = int(term["x"]), int(term["z"])
+    out = []
+    for q in range(n):
+        xb, zb = (x >> q) & 1, (z >> q) & 1
+        out.append("Y" if xb and zb else "X" if xb else "Z" if zb else "I")
+    return out
+
+
+def apply_pauli(psi, n, term):
+    """P psi for a Pauli string, by applying each single-qubit factor to its qubit axis."""
+    v = np.asarray(psi, dtype=np.complex128).reshape((2,) * n)
+    for q, letter in enumerate(pauli_letters(term, n)):
+        if letter != "I":
+            v = apply_matrix(v, _PAULI[letter].astype(np.complex128), [q])
+    return v.reshape(-1)
+
+
+def pauli_expvals(psi, n, terms, n_obs):
+    """<O_o> = sum over terms of coeff * Re <psi| P |psi> (P Hermitian, so the value is real)."""
+    out = np.zeros(n_obs)
+    for t in terms:
+        out[int(t["obs"])] += float(t["coeff"]) * float(np.real(np.vdot(psi, apply_pauli(psi, n, t))))
+    return out
+
+
+def marginal_probs(psi, n, qubits):
+    """Probabilities of the outcomes of the listed qubits (first listed = most significant bit
+    of the outcome index): the squared moduli summed over every other qubit."""
+    p = (np.abs(np.asarray(psi)) ** 2).reshape((2,) * n)
+    rest = tuple(q for q in range(n) if q not in qubits)
+    m = p.sum(axis=rest) if rest else p
+    kept = [q for q in range(n) if q in qubits]  # axis order of m
+    return np.transpose(m, [kept.index(q) for q in qubits]).reshape(-1)
+
+
 def circuit_f(c: W.Circuit, params=None, shift=None, init=None):
     p = c.params if params is None else params
     return expvals(run(c.n, c.gates, p, init, shift), c.n, c.terms, c.n_obs)
@@ -208,7 +273,8 @@ def full_unitary(n, gates, params):
 # ---- gradients ---------------------------------------------------------------------
 
 def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None):
-    """d(sum_o w_o <O_o>)/d params by the two-term shift rule, per parameter occurrence."""
+    """d(sum_o w_o <O_o>)/d params by the shift rule of each gate (two-term, or four-term for
+    the controlled rotations), per parameter occurrence."""
     p = c.params if params is None else np.asarray(params, dtype=np.float64)
     w = np.ones(c.n_obs) if weights is None else np.asarray(weights, dtype=np.float64)
     grad = np.zeros(p.shape[0])
@@ -217,9 +283,12 @@ def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None):
             pi = int(g["pidx"][j])
             if pi < 0:
                 continue
-            fp = circuit_f(c, p, (k, j, math.pi / 2), init)
-            fm = circuit_f(c, p, (k, j, -math.pi / 2), init)
-            grad[pi] += float(g["pscale"][j]) * 0.5 * float(np.dot(w, fp - fm))
+            d = 0.0
+            for s, coef in shift_rule(int(g["op"])):
+                fp = circuit_f(c, p, (k, j, s), init)
+                fm = circuit_f(c, p, (k, j, -s), init)
+                d += coef * float(np.dot(w, fp - fm))
+            grad[pi] += float(g["pscale"][j]) * d
     return grad
 
 

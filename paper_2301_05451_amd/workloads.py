@@ -12,7 +12,8 @@ qubit 0 on the left):
 * a gate's rotation angle in slot ``j`` is ``pscale[j] * params[pidx[j]]`` when
   ``pidx[j] >= 0``, otherwise the constant ``pscale[j]``; parameters are listed in
   gate order (Sec. 2, circuit compilation);
-* two-qubit gates list ``[control, target]`` (CNOT) or an unordered pair (CZ, RZZ).
+* two-qubit gates list ``[control, target]`` (CNOT, CRX, CRY, CRZ) or an unordered pair
+  (CZ, RZZ).
 
 Angles are drawn in float64 and rounded to float32, so that the complex64 GPU path
 and the complex128 oracle see the very same parameter values.
@@ -25,10 +26,12 @@ import math
 import numpy as np
 
 # ---- gate codes (must match include/tq.h) ------------------------------------------
-H, X, Y, Z, RX, RY, RZ, U3, ROT, CNOT, CZ, RZZ = range(12)
-OP_NAMES = ["H", "X", "Y", "Z", "RX", "RY", "RZ", "U3", "ROT", "CNOT", "CZ", "RZZ"]
-N_ANGLES = {H: 0, X: 0, Y: 0, Z: 0, RX: 1, RY: 1, RZ: 1, U3: 3, ROT: 3, CNOT: 0, CZ: 0, RZZ: 1}
-N_QUBITS = {H: 1, X: 1, Y: 1, Z: 1, RX: 1, RY: 1, RZ: 1, U3: 1, ROT: 1, CNOT: 2, CZ: 2, RZZ: 2}
+H, X, Y, Z, RX, RY, RZ, U3, ROT, CNOT, CZ, RZZ, CRX, CRY, CRZ = range(15)
+OP_NAMES = ["H", "X", "Y", "Z", "RX", "RY", "RZ", "U3", "ROT", "CNOT", "CZ", "RZZ", "CRX", "CRY", "CRZ"]
+N_ANGLES = {H: 0, X: 0, Y: 0, Z: 0, RX: 1, RY: 1, RZ: 1, U3: 3, ROT: 3, CNOT: 0, CZ: 0, RZZ: 1,
+            CRX: 1, CRY: 1, CRZ: 1}
+N_QUBITS = {H: 1, X: 1, Y: 1, Z: 1, RX: 1, RY: 1, RZ: 1, U3: 1, ROT: 1, CNOT: 2, CZ: 2, RZZ: 2,
+            CRX: 2, CRY: 2, CRZ: 2}
 
 # C layout of ``tq_gate``: int32 op, int32 q[2], int32 pidx[3], double pscale[3]  (48 bytes)
 GATE_DTYPE = np.dtype(
@@ -87,6 +90,27 @@ class GateList:
             a[i]["pidx"] = pi
             a[i]["pscale"] = ps
         return a
+
+
+# C layout of ``tq_pauli_term``: uint64 x_mask, uint64 z_mask (bit q: qubit q carries X when
+# only x is set, Z when only z is set, Y when both are), double coeff, int32 obs, pad
+PAULI_DTYPE = np.dtype([("x", "<u8"), ("z", "<u8"), ("coeff", "<f8"), ("obs", "<i4"), ("_pad", "<i4")],
+                       align=True)
+assert PAULI_DTYPE.itemsize == 32
+
+
+def pauli_terms(rows):
+    """``rows`` = list of (Pauli string over qubits as {qubit: 'X'|'Y'|'Z'}, coeff, obs)."""
+    a = np.zeros(len(rows), dtype=PAULI_DTYPE)
+    for i, (ps, c, o) in enumerate(rows):
+        x = z = 0
+        for q, p in ps.items():
+            if p in ("X", "Y"):
+                x |= 1 << int(q)
+            if p in ("Z", "Y"):
+                z |= 1 << int(q)
+        a[i]["x"], a[i]["z"], a[i]["coeff"], a[i]["obs"] = x, z, c, o
+    return a
 
 
 def zterms(pairs):
@@ -243,6 +267,7 @@ def random_circuit(n, n_gates, rng, ops=None, n_params=None):
     draws a parameter index (parameters may be shared) and a scale in {1, 2, -0.5}."""
     if ops is None:
         ops = list(range(12)) if n >= 2 else [H, X, Y, Z, RX, RY, RZ, U3, ROT]
+    # (the controlled rotations CRX, CRY, CRZ are drawn only when ``ops`` lists them)
     if n_params is None:
         n_params = max(1, n_gates)
     g = GateList()

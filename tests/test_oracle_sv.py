@@ -111,7 +111,7 @@ def test_rot_decomposition_against_euler():
     assert np.allclose(sv.rot(p, t, o), np.exp(-0.5j * (p + o)) * sv.u3(t, o, p), atol=1e-15)
 
 
-@pytest.mark.parametrize("op", range(12))
+@pytest.mark.parametrize("op", range(15))
 def test_every_gate_unitary(op):
     rng = np.random.default_rng(op)
     ang = rng.uniform(0, 2 * math.pi, size=3)
@@ -205,3 +205,102 @@ def test_rzz_is_cnot_rz_cnot(gam):
     cnot = sv.gate_matrix(W.CNOT, [])
     mid = np.kron(np.eye(2), sv.gate_matrix(W.RZ, [gam]))
     assert np.allclose(cnot @ mid @ cnot, sv.gate_matrix(W.RZZ, [gam]), atol=1e-15)
+
+
+# ---- controlled rotations and the four-term shift rule (Sec. 4.2) ----------------------
+
+@pytest.mark.parametrize("op,r1q", [(W.CRX, W.RX), (W.CRY, W.RY), (W.CRZ, W.RZ)])
+@pytest.mark.parametrize("theta", [0.4, 2.9])
+def test_controlled_rotation_acts_on_control_one_only(op, r1q, theta):
+    # control |1>: the target gets the (pinned) one-qubit rotation; control |0>: nothing happens
+    rng = np.random.default_rng(int(theta * 10) + op)
+    v = rng.normal(size=2) + 1j * rng.normal(size=2)
+    for cbit in (0, 1):
+        init = np.kron(np.eye(2)[cbit], v)
+        got = sv.run(2, W.GateList().const(op, [0, 1], [theta]).array(), np.zeros(1), init=init)
+        want = np.kron(np.eye(2)[cbit], sv.gate_matrix(r1q, [theta]) @ v if cbit else v)
+        assert np.allclose(got, want, atol=1e-15)
+
+
+def test_controlled_rotations_at_pi():
+    # CRX(pi) = (diag(1,-i) x I) CNOT, CRY(pi) = CNOT CZ, CRZ(pi) = (diag(1,-i) x I) CZ
+    S = np.kron(np.diag([1, -1j]), np.eye(2))
+    cnot, cz = sv.gate_matrix(W.CNOT, []), sv.gate_matrix(W.CZ, [])
+    assert np.allclose(sv.gate_matrix(W.CRX, [math.pi]), S @ cnot, atol=1e-15)
+    assert np.allclose(sv.gate_matrix(W.CRY, [math.pi]), cnot @ cz, atol=1e-15)
+    assert np.allclose(sv.gate_matrix(W.CRZ, [math.pi]), S @ cz, atol=1e-15)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.2, 2.5, 4.0])
+def test_four_term_rule_closed_form(theta):
+    # H on the control, CRY(theta), H on the control: <Z_c> = cos(theta/2) (a frequency-1/2
+    # term, where the two-term rule fails), d/dtheta = -sin(theta/2)/2
+    g = W.GateList().const(W.H, [0]).add(W.CRY, [0, 1], [0]).const(W.H, [0])
+    c = W.Circuit(2, g.array(), np.array([theta]), 1, W.zterms([([0], 1.0, 0)]))
+    assert abs(sv.circuit_f(c)[0] - math.cos(theta / 2)) < 1e-14
+    g4 = sv.param_shift_grad(c)[0]
+    assert abs(g4 + math.sin(theta / 2) / 2) < 1e-14
+    two = 0.5 * (sv.circuit_f(c, shift=(1, 0, math.pi / 2))[0] - sv.circuit_f(c, shift=(1, 0, -math.pi / 2))[0])
+    assert abs(two - g4) > 1e-3 * abs(math.sin(theta / 2))  # the two-term rule would be wrong here
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_four_term_rule_vs_central_fd(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 5))
+    c = W.random_circuit(n, 16, rng, ops=[W.H, W.RX, W.RY, W.U3, W.CNOT, W.CRX, W.CRY, W.CRZ, W.RZZ], n_params=5)
+    c.terms = W.zterms([([0], 1.0, 0), ([n - 1], -0.7, 0), ([0, 1], 0.4, 1)])
+    c.n_obs = 2
+    w = np.array([1.1, -0.6])
+    assert np.allclose(sv.param_shift_grad(c, weights=w), sv.fd_grad(c, weights=w), atol=1e-8)
+
+
+# ---- Pauli-string expectations and probabilities (Sec. 5.1.1) --------------------------
+
+@pytest.mark.parametrize("theta", [0.5, 2.2])
+def test_pauli_closed_forms(theta):
+    one = lambda op: sv.run(1, W.GateList().const(op, [0], [theta]).array(), np.zeros(1))  # noqa: E731
+    X = W.pauli_terms([({0: "X"}, 1.0, 0)])
+    Y = W.pauli_terms([({0: "Y"}, 1.0, 0)])
+    assert abs(sv.pauli_expvals(one(W.RY), 1, X, 1)[0] - math.sin(theta)) < 1e-14
+    assert abs(sv.pauli_expvals(one(W.RX), 1, Y, 1)[0] + math.sin(theta)) < 1e-14
+    assert abs(sv.pauli_expvals(one(W.RX), 1, X, 1)[0]) < 1e-14
+    bell = sv.run(2, W.GateList().const(W.H, [0]).add(W.CNOT, [0, 1]).array(), np.zeros(1))
+    t = W.pauli_terms([({0: "X", 1: "X"}, 1.0, 0), ({0: "Y", 1: "Y"}, 1.0, 1), ({0: "Z", 1: "Z"}, 1.0, 2),
+                       ({0: "X", 1: "Y"}, 1.0, 3)])
+    assert np.allclose(sv.pauli_expvals(bell, 2, t, 4), [1, -1, 1, 0], atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pauli_strings_vs_kron_matrix(seed):
+    rng = np.random.default_rng(600 + seed)
+    n = 4
+    c = W.random_circuit(n, 20, rng)
+    psi = sv.run(n, c.gates, c.params)
+    mats = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
+            "Z": np.diag([1, -1])}
+    for _ in range(6):
+        letters = [str(rng.choice(list("IXYZ"))) for _ in range(n)]
+        M = mats[letters[0]]
+        for L in letters[1:]:
+            M = np.kron(M, mats[L])
+        t = W.pauli_terms([({q: L for q, L in enumerate(letters) if L != "I"}, 1.0, 0)])
+        assert abs(sv.pauli_expvals(psi, n, t, 1)[0] - sv.expval_hermitian(psi, M)) < 1e-14
+
+
+def test_marginal_probabilities():
+    rng = np.random.default_rng(7)
+    n = 5
+    c = W.random_circuit(n, 25, rng)
+    psi = sv.run(n, c.gates, c.params)
+    full = sv.marginal_probs(psi, n, list(range(n)))
+    assert np.allclose(full, np.abs(psi) ** 2, atol=1e-16)
+    for q in range(n):
+        p = sv.marginal_probs(psi, n, [q])
+        z = sv.expvals(psi, n, W.zterms([([q], 1.0, 0)]), 1)[0]
+        assert abs(p.sum() - 1) < 1e-14 and abs(p[1] - (1 - z) / 2) < 1e-14
+    # order of the listed qubits sets the bit order of the outcome index
+    p02, p20 = sv.marginal_probs(psi, n, [0, 2]), sv.marginal_probs(psi, n, [2, 0])
+    assert np.allclose(p02.reshape(2, 2), p20.reshape(2, 2).T, atol=1e-16)
+    ghz = np.zeros(2 ** n); ghz[0] = ghz[-1] = 1 / math.sqrt(2)
+    assert np.allclose(sv.marginal_probs(ghz, n, [1, 3]), [0.5, 0, 0, 0.5], atol=1e-16)
