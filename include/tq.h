@@ -53,11 +53,16 @@ typedef enum { TQ_C64 = 0, TQ_C128 = 1 } tq_dtype;
  *   Sec. 3.2.1); RZ(a) = diag(e^{-ia/2}, e^{ia/2}); U3(th,ph,la) = [[c,-e^{i la}s],
  *   [e^{i ph}s, e^{i(ph+la)}c]] (c,s of th); ROT(ph,th,om) = RZ(om) RY(th) RZ(ph);
  *   CNOT(control, target) = |0><0| x I + |1><1| x X (the block form of Sec. 3.2.1);
- *   CZ = diag(1,1,1,-1); RZZ(a) = exp(-i a Z Z / 2). */
+ *   CZ = diag(1,1,1,-1); RZZ(a) = exp(-i a Z Z / 2);
+ *   CRX(a), CRY(a), CRZ(a) on (control, target) = |0><0| x I + |1><1| x R(a), the controlled
+ *   rotations whose generators have four eigenvalues (Sec. 4.2, four-term shift rule); the
+ *   library applies them through exact identities with H, RZ and RZZ (tq_lower_gates). */
 enum {
   TQ_H = 0, TQ_X, TQ_Y, TQ_Z, TQ_RX, TQ_RY, TQ_RZ, TQ_U3, TQ_ROT, TQ_CNOT, TQ_CZ, TQ_RZZ,
+  TQ_CRX, TQ_CRY, TQ_CRZ,
   TQ_NUM_OPS
 };
+
 
 /* One gate. Angle slot j (j < number of angles of op) is pscale[j] * params[pidx[j]] when
  * pidx[j] >= 0 (index into this circuit's parameter vector), else the constant pscale[j].
@@ -68,6 +73,15 @@ typedef struct {
   int32_t pidx[3];
   double pscale[3];
 } tq_gate;
+
+/* Host only: writes to `out` (capacity `cap` records; may be NULL to query the count) the
+ * gate list as the kernels apply it: controlled rotations replaced by H / RZ / RZZ pieces
+ * (CRZ(a) = RZ_t(a/2) RZZ(-a/2); CRX(a) = H_t CRZ(a) H_t; CRY(a) = RZ_t(pi/2) CRX(a)
+ * RZ_t(-pi/2)), each piece keeping the parameter with its scale halved (so gradients
+ * summed over the pieces are the gate's own), other gates copied. Returns the number of
+ * gates, or -1 (tq_last_error) on a NULL input with n_in > 0, a negative n_in, or cap too
+ * small. */
+int32_t tq_lower_gates(const tq_gate* in, int32_t n_in, tq_gate* out, int32_t cap);
 
 /* One term of an observable: coeff * prod_{q: bit q of mask set} Z_q, added to output
  * `obs`. 24 bytes. */
@@ -154,6 +168,34 @@ tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_g
 tq_status tq_expval(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states,
                     const tq_zterm* terms, int32_t n_terms, int32_t n_obs, void* d_out,
                     void* stream);
+
+/* One Pauli string of an observable: coeff * prod_q P_q added to output `obs`, with P_q = X
+ * where only bit q of x_mask is set, Z where only bit q of z_mask is set, Y where both are,
+ * I elsewhere (bit q = qubit q). 32 bytes. */
+typedef struct {
+  uint64_t x_mask;
+  uint64_t z_mask;
+  double coeff;
+  int32_t obs;
+  int32_t _pad;
+} tq_pauli_term;
+
+/* Sec. 4 cost and Sec. 5.1.1 expectation values for Pauli strings with X, Y and Z factors:
+ * d_out[i * n_obs + o] = sum over terms with obs == o of coeff * <psi_i| P |psi_i> (real for
+ * the Hermitian P; written in the dtype's real precision). Each amplitude is read once per
+ * distinct x_mask among the terms; sums are fixed-order double trees (bitwise repeatable).
+ * A general Hermitian observable on a few qubits is a real combination of such strings
+ * (its Pauli decomposition). Errors as tq_expval. */
+tq_status tq_expval_pauli(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states,
+                          const tq_pauli_term* terms, int32_t n_terms, int32_t n_obs, void* d_out, void* stream);
+
+/* Sec. 5.1.1 probability measurement: d_out[i * 2^n_sel + y] = probability that the listed
+ * qubits read y (qubits[0] is the most significant bit of y), i.e. the sum of |psi_i|^2 over
+ * every other qubit (the state is used as given, not normalised). 1 <= n_sel <= 24, at most
+ * 32 other qubits; dtype's real precision, summed in double in a fixed order. Errors:
+ * TQ_EINVAL (qubit outside the register or listed twice), TQ_ENOTSUP. */
+tq_status tq_probs(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states, const int32_t* qubits,
+                   int32_t n_sel, void* d_out, void* stream);
 
 /* tq_expval for callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): no context, no allocation, no synchronisation.

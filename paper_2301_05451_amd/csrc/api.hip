@@ -318,9 +318,9 @@ static tq_status sv_apply_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* g
     TQ_TRY(validate_gates(g, gr.n_gates, gr.n, gr.n_params));
   }
   for (const Group& gr : groups) {
-    const tq_gate* g = gates + gr.gate_off;
+    const GateView gv(gates + gr.gate_off, gr.n_gates);  // controlled rotations lowered
     Schedule* s;
-    TQ_TRY(get_schedule(ctx, sizeof(T) == 4 ? TQ_C64 : TQ_C128, g, gr.n_gates, gr.n, mode, opts, &s));
+    TQ_TRY(get_schedule(ctx, sizeof(T) == 4 ? TQ_C64 : TQ_C128, gv.g, gv.n, gr.n, mode, opts, &s));
     const int count = (int)gr.members.size();
     BatchMap pmap, smap;
     TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, gr.members, stream, &pmap));
@@ -444,9 +444,9 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
   std::vector<Run> runs;
   size_t ws = 256;
   for (const Group& gr : groups) {
-    const tq_gate* g = gates + gr.gate_off;
+    const GateView gv(gates + gr.gate_off, gr.n_gates);  // controlled rotations lowered
     Schedule* s;
-    TQ_TRY(get_adjoint_schedule(ctx, dt, g, gr.n_gates, gr.n, opts, &s));
+    TQ_TRY(get_adjoint_schedule(ctx, dt, gv.g, gv.n, gr.n, opts, &s));
     const unsigned char* tt;
     TQ_TRY(term_table(ctx, gr.n, terms, n_terms, &tt));
     size_t i0 = 0;
@@ -461,7 +461,7 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
       r.psi = 0;
       r.lam = align256(count * namps * sizeof(C));
       r.mats = r.lam + align256(count * namps * sizeof(C));
-      r.part = r.mats + align256(count * std::max(gr.n_gates, 1) * kAdjMatEntries * sizeof(C));
+      r.part = r.mats + align256(count * std::max(gv.n, 1) * kAdjMatEntries * sizeof(C));
       ws = std::max(ws, r.part + align256(count * std::max(s->n_slots, 1) * ntiles * sizeof(double)));
       BatchMap pmap, smap;  // warm the offset tables
       TQ_TRY(member_map(ctx, S_OFFS, batch->param_off, r.mem, stream, &pmap));
@@ -498,6 +498,23 @@ using namespace tq;
 extern "C" {
 
 const char* tq_last_error(void) { return g_last_error.c_str(); }
+
+int32_t tq_lower_gates(const tq_gate* in, int32_t n_in, tq_gate* out, int32_t cap) {
+  if (n_in < 0 || (n_in > 0 && !in)) {
+    fail(TQ_EINVAL, "tq_lower_gates: bad input");
+    return -1;
+  }
+  std::vector<tq_gate> low;
+  lower_controlled(in, n_in, low);
+  if (out) {
+    if ((int64_t)low.size() > cap) {
+      fail(TQ_ESIZE, "tq_lower_gates: capacity " + std::to_string(cap) + " < " + std::to_string(low.size()));
+      return -1;
+    }
+    std::copy(low.begin(), low.end(), out);
+  }
+  return (int32_t)low.size();
+}
 
 int tq_version(void) { return 100; }
 
@@ -583,8 +600,9 @@ tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_g
   TQ_TRY(validate_gates(gates, n_gates, n_qubits, 0x7fffffff));
   const int mode = opts ? opts->mode : 0;
   if (mode != 0 && mode != 1) return fail(TQ_ENOTSUP, "sv mode must be 0 (fused) or 1 (plain)");
+  const GateView gv(gates, n_gates);
   Schedule* s;
-  TQ_TRY(get_schedule(ctx, dt, gates, n_gates, n_qubits, mode, opts, &s));
+  TQ_TRY(get_schedule(ctx, dt, gv.g, gv.n, n_qubits, mode, opts, &s));
   int64_t flops = 0, mats = 0;
   for (const HostOp& o : s->ops) {
     if (o.kind == K_MAT1) flops += 14, ++mats;

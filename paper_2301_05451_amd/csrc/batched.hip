@@ -455,6 +455,24 @@ tq_status tq_svb_create(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const t
   b->param_off.assign(batch->param_off, batch->param_off + batch->count);
   b->state_off.assign(batch->state_off, batch->state_off + batch->count);
   b->gates.assign(gates, gates + gate_end);
+  if (has_controlled(gates, gate_end)) {
+    // lower the controlled rotations of every distinct gate segment once (circuits sharing a
+    // segment keep sharing its lowered copy)
+    std::vector<tq_gate> low;
+    std::map<std::pair<int64_t, int>, std::pair<int64_t, int>> seg;
+    for (int i = 0; i < b->count; ++i) {
+      const auto key = std::make_pair(b->gate_off[i], b->n_gates[i]);
+      auto it = seg.find(key);
+      if (it == seg.end()) {
+        const int64_t off = (int64_t)low.size();
+        lower_controlled(gates + key.first, key.second, low);
+        it = seg.emplace(key, std::make_pair(off, (int)((int64_t)low.size() - off))).first;
+      }
+      b->gate_off[i] = it->second.first;
+      b->n_gates[i] = it->second.second;
+    }
+    b->gates.swap(low);
+  }
   if (n_terms > 0) b->terms.assign(terms, terms + n_terms);
   b->n_obs = n_obs;
   if (opts) b->opts = *opts;

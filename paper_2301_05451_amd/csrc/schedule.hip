@@ -23,12 +23,60 @@ namespace tq {
 
 int gate_n_angles(int op) {
   switch (op) {
-    case TQ_RX: case TQ_RY: case TQ_RZ: case TQ_RZZ: return 1;
+    case TQ_RX: case TQ_RY: case TQ_RZ: case TQ_RZZ: case TQ_CRX: case TQ_CRY: case TQ_CRZ: return 1;
     case TQ_U3: case TQ_ROT: return 3;
     default: return 0;
   }
 }
-static int n_qubits_of(int op) { return (op == TQ_CNOT || op == TQ_CZ || op == TQ_RZZ) ? 2 : 1; }
+static bool is_controlled_rotation(int op) { return op == TQ_CRX || op == TQ_CRY || op == TQ_CRZ; }
+static int n_qubits_of(int op) {
+  return (op == TQ_CNOT || op == TQ_CZ || op == TQ_RZZ || is_controlled_rotation(op)) ? 2 : 1;
+}
+
+bool has_controlled(const tq_gate* g, int64_t n_gates) {
+  for (int64_t k = 0; k < n_gates; ++k)
+    if (is_controlled_rotation(g[k].op)) return true;
+  return false;
+}
+
+// Controlled rotations become gates the kernels apply directly, by exact identities (no
+// global phase is introduced, so amplitudes are unchanged), on (control c, target t):
+//   CRZ(a) = RZ_t(a/2) RZZ_ct(-a/2)    (both diagonal: diag(1, 1, e^{-ia/2}, e^{ia/2}))
+//   CRX(a) = H_t CRZ(a) H_t            (H Z H = X)
+//   CRY(a) = RZ_t(pi/2) CRX(a) RZ_t(-pi/2)   (RZ(pi/2) X RZ(-pi/2) = Y)
+// An angle a = pscale * params[pidx] keeps its parameter with half (or minus half) the scale,
+// so gradients summed over the pieces are those of the original gate.
+void lower_controlled(const tq_gate* g, int n_gates, std::vector<tq_gate>& out) {
+  const double half_pi = 1.5707963267948966;
+  auto one = [](int op, int q, int32_t pidx, double scale) {
+    tq_gate x{};
+    x.op = op;
+    x.q[0] = q;
+    x.q[1] = -1;
+    x.pidx[0] = pidx;
+    x.pidx[1] = x.pidx[2] = -1;
+    x.pscale[0] = scale;
+    return x;
+  };
+  for (int k = 0; k < n_gates; ++k) {
+    const tq_gate& x = g[k];
+    if (!is_controlled_rotation(x.op)) {
+      out.push_back(x);
+      continue;
+    }
+    const int c = x.q[0], t = x.q[1];
+    const int32_t pi = x.pidx[0];
+    const double sc = x.pscale[0];  // the angle's scale, or the constant angle when pi < 0
+    if (x.op == TQ_CRY) out.push_back(one(TQ_RZ, t, -1, -half_pi));
+    if (x.op != TQ_CRZ) out.push_back(one(TQ_H, t, -1, 0.0));
+    out.push_back(one(TQ_RZ, t, pi, 0.5 * sc));
+    tq_gate zz = one(TQ_RZZ, c, pi, -0.5 * sc);
+    zz.q[1] = t;
+    out.push_back(zz);
+    if (x.op != TQ_CRZ) out.push_back(one(TQ_H, t, -1, 0.0));
+    if (x.op == TQ_CRY) out.push_back(one(TQ_RZ, t, -1, half_pi));
+  }
+}
 static bool diag1(int op) { return op == TQ_Z || op == TQ_RZ; }
 
 tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params) {

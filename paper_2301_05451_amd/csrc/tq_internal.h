@@ -163,6 +163,22 @@ void build_stages(Schedule& s);
 void lower_adjoint_ops(const tq_gate* g, int n_gates, std::vector<HostOp>& ops, std::vector<int32_t>& runs);
 void build_adjoint_slots(Schedule& s, const tq_gate* g, int n_gates);
 tq_status validate_gates(const tq_gate* g, int n_gates, int n, int n_params);
+// Controlled rotations (CRX, CRY, CRZ) lowered to the gates the kernels apply (schedule.hip).
+bool has_controlled(const tq_gate* g, int64_t n_gates);
+void lower_controlled(const tq_gate* g, int n_gates, std::vector<tq_gate>& out);
+// A gate list as the kernels see it: the caller's array, or its lowered copy.
+struct GateView {
+  const tq_gate* g = nullptr;
+  int n = 0;
+  std::vector<tq_gate> own;
+  GateView(const tq_gate* src, int count) : g(src), n(count) {
+    if (has_controlled(src, count)) {
+      lower_controlled(src, count, own);
+      g = own.data();
+      n = (int)own.size();
+    }
+  }
+};
 int gate_n_angles(int op);
 constexpr int kAdjMaxSlotsPerStage = 256;
 

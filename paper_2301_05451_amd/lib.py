@@ -230,6 +230,51 @@ def expval(states, spec: BatchSpec, terms, n_obs, ctx=None):
     return out
 
 
+_lib.tq_expval_pauli.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _i32, _i32, _vp, _vp]
+_lib.tq_expval_pauli.restype = ct.c_int
+_lib.tq_probs.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _i32, _vp, _vp]
+_lib.tq_probs.restype = ct.c_int
+_lib.tq_lower_gates.argtypes = [_vp, _i32, _vp, _i32]
+_lib.tq_lower_gates.restype = ct.c_int32
+
+
+def expval_pauli(states, spec: BatchSpec, terms, n_obs, ctx=None):
+    """[count, n_obs] expectation values of Pauli-string sums (tq_expval_pauli)."""
+    import torch
+    _check_tensors(states, None, spec)
+    ctx = ctx or context(states.device.index)
+    terms = np.ascontiguousarray(terms, dtype=W.PAULI_DTYPE)
+    rdt = torch.float32 if states.dtype == torch.complex64 else torch.float64
+    out = torch.empty((spec.count, n_obs), dtype=rdt, device=states.device)
+    check(_lib.tq_expval_pauli(ctx.h, _dt(states), ct.byref(spec.c), states.data_ptr(), terms.ctypes.data,
+                               int(terms.shape[0]), int(n_obs), out.data_ptr(), _stream()))
+    return out
+
+
+def probs(states, spec: BatchSpec, qubits, ctx=None):
+    """[count, 2^len(qubits)] marginal probabilities of the listed qubits (tq_probs)."""
+    import torch
+    _check_tensors(states, None, spec)
+    ctx = ctx or context(states.device.index)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    rdt = torch.float32 if states.dtype == torch.complex64 else torch.float64
+    out = torch.empty((spec.count, 1 << len(q)), dtype=rdt, device=states.device)
+    check(_lib.tq_probs(ctx.h, _dt(states), ct.byref(spec.c), states.data_ptr(), q.ctypes.data, int(q.shape[0]),
+                        out.data_ptr(), _stream()))
+    return out
+
+
+def lower_gates(gates):
+    """The gate list as the kernels apply it (tq_lower_gates: controlled rotations lowered)."""
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    n = _lib.tq_lower_gates(g.ctypes.data, int(g.shape[0]), None, 0)
+    if n < 0:
+        raise TQError(1, last_error())
+    out = np.zeros(n, dtype=W.GATE_DTYPE)
+    check(0 if _lib.tq_lower_gates(g.ctypes.data, int(g.shape[0]), out.ctypes.data, n) == n else 1)
+    return out
+
+
 _lib.tq_expval_noalloc.argtypes = [ct.c_int, _i32, _i32, ct.c_int64, _vp, _vp, _i32, _i32, _vp, _vp]
 _lib.tq_expval_noalloc.restype = ct.c_int
 

@@ -88,8 +88,12 @@ def light_cone(gates, qubits):
 
 def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
     """Doubled network of <psi| prod Z |psi> for psi = U|0..0>, with diagonal gates as
-    hyperedge tensors. Returns a Network whose leaves reference c.gates."""
+    hyperedge tensors. Controlled rotations are first lowered to the gates the kernels build
+    (tq_lower_gates). Returns a Network whose leaves reference its ``gates``."""
     gates = c.gates
+    if np.isin(gates["op"], [W.CRX, W.CRY, W.CRZ]).any():
+        from . import lib
+        gates = lib.lower_gates(gates)
     if use_light_cone:
         keep, used = light_cone(gates, zqubits)
     else:

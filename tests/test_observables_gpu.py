@@ -1,0 +1,156 @@
+"""GPU parity of the wider gate and measurement set against the oracle: controlled
+rotations (CRX, CRY, CRZ; lowered by the library) in fused, plain and compiled-batch
+forward passes and in the adjoint gradient against the oracle's four-term shift rule;
+Pauli-string expectation values with X, Y and Z factors; marginal probabilities; the
+tensor-network path with controlled rotations.
+Tolerances: complex64 1e-5, complex128 1e-12 (gradients times the weight scale)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sv as osv
+from paper_2301_05451_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {False: 1e-5, True: 1e-12}
+OPS = [W.H, W.X, W.RX, W.RY, W.RZ, W.U3, W.CNOT, W.CZ, W.RZZ, W.CRX, W.CRY, W.CRZ]
+
+
+def _types(c128):
+    return (torch.complex128, torch.float64) if c128 else (torch.complex64, torch.float32)
+
+
+def test_lower_gates_keeps_the_circuit():
+    # the lowered list applied by the oracle gives the same state as the original (exact
+    # identities, no global phase)
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(801)
+    c = W.random_circuit(4, 30, rng, ops=OPS, n_params=6)
+    low = lib.lower_gates(c.gates)
+    assert not np.isin(low["op"], [W.CRX, W.CRY, W.CRZ]).any()
+    assert np.allclose(osv.run(4, low, c.params), osv.run(4, c.gates, c.params), atol=1e-14)
+
+
+@pytest.mark.parametrize("c128", [False, True])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_controlled_rotations_forward_and_adjoint(c128, mode):
+    from paper_2301_05451_amd import lib
+
+    cdt, rdt = _types(c128)
+    rng = np.random.default_rng(810 + mode)
+    terms = W.zterms([([0], 1.0, 0), ([1, 2], -0.6, 0)])
+    for n in (2, 5, 9, 13):
+        c = W.random_circuit(n, 50, rng, ops=OPS if n > 2 else [W.RY, W.CRX, W.CRY, W.CRZ, W.H], n_params=10)
+        if n == 2:
+            terms_n = W.zterms([([0], 1.0, 0), ([1], -0.6, 0)])
+        else:
+            terms_n = terms
+        print(f"controlled n={n} mode={mode} c128={c128}", flush=True)
+        spec = lib.BatchSpec.from_circuits([c])
+        p = torch.tensor(c.params, dtype=rdt, device="cuda")
+        psi = lib.zero_states(spec, cdt)
+        lib.sv_apply(psi, p, spec, mode=mode)
+        want = osv.run(n, c.gates, c.params)
+        assert np.abs(psi.cpu().numpy() - want).max() <= TOL[c128]
+        if mode == 0:
+            g = lib.sv_backward(psi, p, spec, terms_n, 1, torch.ones(1, 1, dtype=rdt, device="cuda")).cpu().numpy()
+            c.terms, c.n_obs = terms_n, 1
+            gw = osv.param_shift_grad(c)  # four-term rule for the controlled rotations
+            print(f"  max|d grad| = {np.abs(g - gw).max():.2e}", flush=True)
+            assert np.abs(g - gw).max() <= TOL[c128] * 1.6
+
+
+def test_controlled_rotations_in_compiled_batch():
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(820)
+    circs = [W.random_circuit(n, 40, rng, ops=OPS, n_params=8) for n in (3, 7, 5, 7)]
+    circs[3] = W.Circuit(7, circs[1].gates, W.f32_angles(rng, 8, 0, 2 * math.pi))  # shares a gate list
+    spec = lib.BatchSpec.from_circuits(circs)
+    terms = W.zterms([([0], 1.0, 0)])
+    svb = lib.SVBatch(spec, terms, 1)
+    params = torch.tensor(np.concatenate([c.params for c in circs]), dtype=torch.float32, device="cuda")
+    states = svb.new_states()
+    f = svb.forward(params, states).cpu().numpy()
+    g = svb.backward(params, states, torch.ones(len(circs), 1, device="cuda")).cpu().numpy()
+    st = states.cpu().numpy()
+    for i, c in enumerate(circs):
+        psi = osv.run(c.n, c.gates, c.params)
+        o = int(spec.state_off[i])
+        assert np.abs(st[o:o + (1 << c.n)] - psi).max() <= 1e-5, i
+        c.terms, c.n_obs = terms, 1
+        assert abs(f[i, 0] - osv.expvals(psi, c.n, terms, 1)[0]) <= 1e-5, i
+        p0 = int(spec.param_off[i])
+        assert np.abs(g[p0:p0 + c.n_params] - osv.param_shift_grad(c)).max() <= 1e-5, i
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_pauli_strings_vs_oracle(c128):
+    from paper_2301_05451_amd import lib
+
+    cdt, _ = _types(c128)
+    rng = np.random.default_rng(830)
+    for n in (1, 3, 8, 14):
+        circs = [W.random_circuit(n, 40, rng) for _ in range(3)]
+        spec = lib.BatchSpec.from_circuits(circs)
+        psi = lib.zero_states(spec, cdt)
+        lib.sv_apply(psi, torch.tensor(np.concatenate([c.params for c in circs]),
+                                       dtype=torch.float64 if c128 else torch.float32, device="cuda"), spec)
+        rows = []
+        for k in range(19):
+            letters = {q: str(rng.choice(list("XYZ"))) for q in range(n) if rng.random() < 0.5}
+            rows.append((letters, float(rng.uniform(-1, 1)), k % 4))
+        rows.append(({0: "X"}, 0.5, 0))
+        rows.append(({0: "X"}, -0.25, 3))  # same flip mask as the previous term
+        terms = W.pauli_terms(rows)
+        got = lib.expval_pauli(psi, spec, terms, 4).cpu().numpy()
+        host = psi.cpu().numpy().astype(np.complex128)
+        coef = np.array([sum(abs(c) for _, c, o in rows if o == k) for k in range(4)])
+        for i, c in enumerate(circs):
+            o = int(spec.state_off[i])
+            want = osv.pauli_expvals(host[o:o + (1 << n)], n, terms, 4)
+            assert np.all(np.abs(got[i] - want) <= TOL[c128] * np.maximum(coef, 1e-300)), (n, i, got[i], want)
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_marginal_probabilities_vs_oracle(c128):
+    from paper_2301_05451_amd import lib
+
+    cdt, rdt = _types(c128)
+    rng = np.random.default_rng(840)
+    for n, sel in ((1, [0]), (5, [3, 0]), (12, [0]), (12, [11, 2, 7]), (16, list(range(16))[::-1][:10]),
+                   (18, [17])):
+        circs = [W.random_circuit(n, 30, rng) for _ in range(2)]
+        spec = lib.BatchSpec.from_circuits(circs)
+        psi = lib.zero_states(spec, cdt)
+        lib.sv_apply(psi, torch.tensor(np.concatenate([c.params for c in circs]), dtype=rdt, device="cuda"), spec)
+        got = lib.probs(psi, spec, sel).cpu().numpy()
+        host = psi.cpu().numpy().astype(np.complex128)
+        for i in range(2):
+            o = int(spec.state_off[i])
+            want = osv.marginal_probs(host[o:o + (1 << n)], n, sel)
+            assert np.abs(got[i] - want).max() <= TOL[c128], (n, sel, i)
+    with pytest.raises(lib.TQError):
+        lib.probs(psi, spec, [0, 0])
+
+
+def test_tn_with_controlled_rotations():
+    from paper_2301_05451_amd import tn
+
+    rng = np.random.default_rng(850)
+    for n in (3, 5):
+        c = W.random_circuit(n, 24, rng, ops=OPS, n_params=6)
+        zq = [0, n - 1]
+        net = tn.circuit_network(c, zq)
+        prog = tn.TNProgram(net, tn.greedy_tree(net), c128=True)
+        p = torch.tensor(net.params, dtype=torch.float64, device="cuda")
+        v = prog.value(p).cpu().numpy()[0]
+        psi = osv.run(n, c.gates, c.params)
+        want = float(np.dot(np.abs(psi) ** 2, osv.zstring_diag(n, zq)))
+        assert abs(v.real - want) <= 1e-12 and abs(v.imag) <= 1e-12
+        c.terms, c.n_obs = W.zterms([(zq, 1.0, 0)]), 1
+        assert np.abs(prog.grad(p).cpu().numpy() - osv.param_shift_grad(c)).max() <= 1e-12
