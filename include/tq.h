@@ -234,6 +234,14 @@ tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const 
                          const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
                          void* d_work, int64_t work_bytes, void* stream);
 
+/* One parameter update of a training loop (Sec. 4: the cost f is minimised by gradient
+ * steps on the circuit parameters), on the device: kind 0 = gradient descent
+ * p -= lr * g; kind 1 = Adam (Kingma and Ba) with bias correction for the 1-based step t,
+ * moments d_m, d_v (zero before step 1) updated in place. Arrays of n reals of the dtype's
+ * precision; arithmetic in double. Errors: TQ_EINVAL. */
+tq_status tq_optimizer_step(tq_dtype dt, int32_t kind, void* d_params, const void* d_grad, void* d_m, void* d_v,
+                            int32_t t, double lr, double beta1, double beta2, double eps, int64_t n, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Compiled batches. The paper compiles a circuit once and evaluates it many times with new
  * parameters (Sec. 2, reusable objects), and runs one circuit over a batch of inputs with

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtq.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["api.hip", "schedule.hip", "sv_kernels.hip", "expval.hip", "sv_adjoint.hip", "tn.hip", "mlp.hip", "batched.hip", "observables.hip"]
+SOURCES = ["api.hip", "schedule.hip", "sv_kernels.hip", "expval.hip", "sv_adjoint.hip", "tn.hip", "mlp.hip", "batched.hip", "observables.hip", "optim.hip"]
 
 # Packed FP32 instructions are disabled for device code (the host pass warns that it does
 # not know the feature; that is harmless).

@@ -264,6 +264,22 @@ def probs(states, spec: BatchSpec, qubits, ctx=None):
     return out
 
 
+_lib.tq_optimizer_step.argtypes = [ct.c_int, _i32, _vp, _vp, _vp, _vp, _i32, ct.c_double, ct.c_double, ct.c_double,
+                                   ct.c_double, ct.c_int64, _vp]
+_lib.tq_optimizer_step.restype = ct.c_int
+
+
+def optimizer_step(params, grad, lr, step=1, m=None, v=None, adam=False, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place update of params (tq_optimizer_step): gradient descent, or Adam with moments m, v."""
+    import torch
+    dt = TQ_C128 if params.dtype == torch.float64 else TQ_C64
+    check(_lib.tq_optimizer_step(dt, 1 if adam else 0, params.data_ptr(), grad.data_ptr(),
+                                 m.data_ptr() if m is not None else None, v.data_ptr() if v is not None else None,
+                                 int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                 ct.c_int64(params.numel()), _stream()))
+    return params
+
+
 def lower_gates(gates):
     """The gate list as the kernels apply it (tq_lower_gates: controlled rotations lowered)."""
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
