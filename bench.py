@@ -213,11 +213,17 @@ def bench_uneven(steps):
             "levels": svb.info["levels"], "items": svb.info["items"]}
 
 
+def _workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def bench_tn(steps):
     """QAOA MaxCut on a seeded random 3-regular graph of 50 nodes (75 edges): one light-cone
-    network per edge for <Z_i Z_j>, value + gradient of (gamma, beta). All 75 networks at
-    p = 3; at p = 4 the edges whose min-fill tree has width <= 26. Plus one dense pairwise
-    step on the FP32-MFMA complex GEMM path."""
+    network per edge for <Z_i Z_j>, value + gradient of (gamma, beta), all 75 networks in
+    one batched call. Trees: the fewest-FLOP tree of the path search's pool (min-fill,
+    min-degree, greedy, recursive bisection). p = 3, p = 4, and p = 4 sliced so that no
+    intermediate exceeds 2^20 elements. Plus one dense pairwise step on the FP32-MFMA
+    complex GEMM path."""
     import numpy as np
     import torch
 
@@ -225,17 +231,13 @@ def bench_tn(steps):
     from paper_2301_05451_amd import workloads as W
 
     res = {}
-    for p in (3, 4):
+    for name, p, target in (("p3", 3, None), ("p4", 4, None), ("p4_sliced20", 4, 20)):
         prob = W.qaoa_maxcut(p=p)
         t0 = time.perf_counter()
-        progs = []
-        for e in prob.edges:
-            net, _ = tn.qaoa_edge_network(prob, e)
-            tree = tn.elimination_tree(net, tn.elimination_order(net, None, "fill")[0])
-            progs.append(tn.TNProgram(net, tree))
+        planned = tn.plan_qaoa(prob, target_rank=target, workers=_workers())
+        progs = [tn.TNProgram(net, tree) for net, tree in planned]
         plan_s = time.perf_counter() - t0
-        if not progs:
-            continue
+        print(f"bench: TN {name} planned in {plan_s:.1f} s", file=sys.stderr, flush=True)
         pars = [torch.tensor(pg.net.params, dtype=torch.float32, device="cuda") for pg in progs]
 
         def run_single():
@@ -249,23 +251,34 @@ def bench_tn(steps):
             batch.values(pars)
             batch.grads(pars)
 
-        ms1 = _timed(run_single, max(1, steps // 4), 1)
-        ms = _timed(run_batch, steps, 2)
+        ms1 = _timed(run_single, 1, 1)
+        ms = _timed(run_batch, max(2, steps // 2), 1)
         vb = torch.stack([v[0] for v in batch.values(pars)]).cpu().numpy()
         vs = np.array([pg.value(pt).cpu().numpy()[0] for pg, pt in zip(progs, pars)])
         flops = sum(pg.plan.info["flops"] for pg in progs)  # contraction only, 8 real flops per complex MAC
-        res[f"p{p}"] = {"networks": len(progs), "plan_s": round(plan_s, 2),
-                        "ms_value_and_grad_all": round(ms, 3),
-                        "grad_networks_per_s": len(progs) / (ms * 1e-3),
-                        "single_calls_ms": round(ms1, 3),
-                        "batched_speedup_vs_single_calls": round(ms1 / ms, 1),
-                        "batched_equals_single": bool(np.array_equal(vb, vs)),
-                        "maxcut_value": float(np.sum((1.0 - vb.real) / 2.0)),
-                        "contraction_flops_per_network_sum": flops,
-                        # value + gradient = 3 forward contractions of algorithmic work (the
-                        # reverse pass also recomputes the forward: not counted)
-                        "tn_gflops": 3 * flops / (ms * 1e-3) / 1e9,
-                        "max_width": max(pg.tree.max_rank for pg in progs)}
+        gemm = sum(pg.plan.info["gemm_flops"] for pg in progs)
+        byts = 0.0  # algorithmic bytes of the forward steps: read both operands, write the result
+        for pg in progs:
+            S = 2 ** len(pg.tree.sliced)
+            for a, b, o in tn.tree_steps(pg.net, pg.tree):
+                byts += (2.0 ** len(a) + 2.0 ** len(b) + 2.0 ** len(o)) * 8 * S
+        res[name] = {"networks": len(progs), "plan_s": round(plan_s, 2),
+                     "ms_value_and_grad_all": round(ms, 3),
+                     "grad_networks_per_s": len(progs) / (ms * 1e-3),
+                     "single_calls_ms": round(ms1, 3),
+                     "batched_speedup_vs_single_calls": round(ms1 / ms, 2),
+                     "batched_equals_single": bool(np.array_equal(vb, vs)),
+                     "maxcut_value": float(np.sum((1.0 - vb.real) / 2.0)),
+                     "contraction_flops_per_pass": flops,
+                     "gemm_flop_share": gemm / max(flops, 1),
+                     # value + gradient = about 3 forward passes of algorithmic work (the
+                     # reverse pass recomputes the forward: not counted)
+                     "tn_gflops": 3 * flops / (ms * 1e-3) / 1e9,
+                     "step_bytes_per_pass": byts,
+                     "hbm_GBs_of_step_bytes": 3 * byts / (ms * 1e-3) / 1e9,
+                     "max_width": max(pg.tree.max_rank for pg in progs),
+                     "sliced_networks": sum(1 for pg in progs if pg.tree.sliced),
+                     "slices_total": sum(2 ** len(pg.tree.sliced) for pg in progs)}
     # dense step: C[b,m,n] = sum_k A[b,m,k] B[b,k,n], b = 1 bit, M = N = 2^12, K = 2^10
     b, m, k, nn = [0], list(range(1, 13)), list(range(13, 23)), list(range(23, 35))
     plan = lib.TnPlan([b + m + k, b + k + nn], [(0, 1)], out_inds=b + m + nn)
@@ -294,57 +307,109 @@ def bench_tn(steps):
     return res
 
 
+def bench_mqr():
+    """Multiple-qubit rotation (the paper's Sec. 6.1 benchmark): 500 training iterations of a
+    4-layer hardware-efficient network minimising sum_i <Z_i> from |0..0>, each iteration a
+    compiled forward + adjoint backward + on-device gradient-descent update (lr 0.1)."""
+    import torch
+
+    from paper_2301_05451_amd import mqr
+
+    out = {"workload": "MQR: 4 layers of RY, RZ on all qubits + CNOT chain, cost sum_i <Z_i>, "
+                       "500 gradient-descent iterations (lr 0.1), complex64", "runs": []}
+    for n in (4, 8, 12, 16, 20):
+        tr = mqr.MQRTrainer(mqr.mqr_circuit(n, layers=4), lr=0.1)
+        tr.run(3)  # warm-up: compiles the graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = tr.run(500)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        out["runs"].append({"qubits": n, "params": int(tr.params.numel()), "s_per_500_iters": round(dt, 4),
+                            "iters_per_s": round(500 / dt, 1), "cost_first": float(h[0]),
+                            "cost_last": float(h[-1])})
+    return out
+
+
 def bench_costmodel():
-    """Learned tree ranking: the cost-model MLP is trained on the GPU from measured times
-    (value + gradient) of candidate trees of QAOA p = 3 light-cone networks on three other
-    seeded 50-node 3-regular graphs, then picks one tree per edge network of the workload
-    graph; its picks are timed against the fewest-FLOPs picks."""
+    """Learned ranking of contraction trees and slicings (QAOA p = 4): the cost-model MLP is
+    trained on the GPU from measured times (value + gradient) of the candidates (path-search
+    trees x slicings to width, width - 2, width - 4) of 8 light-cone networks on each of two
+    other seeded 50-node graphs, then picks one candidate for each of 25 networks of the
+    workload graph (held out); its picks are timed against the fewest-FLOP picks and against
+    the fastest measured candidate (the most any ranking could gain)."""
     import numpy as np
     import torch
 
     from paper_2301_05451_amd import costmodel, tn
     from paper_2301_05451_amd import workloads as W
 
-    t0 = time.perf_counter()
-    groups = []
-    for seed in (2001, 2002, 2003):
-        p = 3
+    def graph(seed, p=4):
         r = np.random.default_rng(seed)
         edges = W.random_regular_graph(3, 50, r)
-        prob = W.QAOAProblem(50, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
-        for e in edges[:10]:
-            net, _ = tn.qaoa_edge_network(prob, e)
-            pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
-            fs, ts = [], []
-            for tree, prog, f in costmodel.candidates_with_plans(net, n_random=5, seed=seed):
-                fs.append(f)
-                ts.append(math.log(costmodel.time_program(prog, pt, reps=3)))
-            groups.append((np.array(fs), np.array(ts)))
-    collect_s = time.perf_counter() - t0
-    cm = costmodel.CostModel(seed=0)
+        return W.QAOAProblem(50, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
+
+    t0 = time.perf_counter()
+    train = []
+    for seed in (2001, 2002):
+        g = graph(seed)
+        train += costmodel.plan_candidates(g, g.edges[::9][:8], workers=_workers())
+    prob = W.qaoa_maxcut(p=4)
+    test = costmodel.plan_candidates(prob, prob.edges[::3], workers=_workers())
+    plan_s = time.perf_counter() - t0
+    print(f"bench: ranking candidates planned in {plan_s:.1f} s", file=sys.stderr, flush=True)
+
+    def measure(net, trees):
+        pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
+        rows = []
+        for t in trees:
+            prog = tn.TNProgram(net, t)
+            rows.append((t, costmodel.tree_features(net, t, prog.plan.info), costmodel.time_program(prog, pt, reps=3),
+                         prog.value(pt).cpu().numpy()[0]))
+            del prog
+        return rows
+
     t1 = time.perf_counter()
+    groups = []
+    for net, trees in train:
+        rows = measure(net, trees)
+        groups.append((np.array([r[1] for r in rows]), np.log(np.array([r[2] for r in rows]))))
+    collect_s = time.perf_counter() - t1
+    cm = costmodel.CostModel(seed=0)
+    t2 = time.perf_counter()
     hist = cm.fit_groups(groups, epochs=800, lr=3e-3)
     torch.cuda.synchronize()
-    fit_s = time.perf_counter() - t1
-    prob = W.qaoa_maxcut(p=3)
-    t_flop = t_mlp = 0.0
+    fit_s = time.perf_counter() - t2
+    t_flop = t_mlp = t_best = 0.0
     same = 0
-    for e in prob.edges:
-        net, _ = tn.qaoa_edge_network(prob, e)
-        pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
-        cands = costmodel.candidates_with_plans(net, n_random=5, seed=7)
-        kf, km = costmodel.pick(cands), costmodel.pick(cands, cm)
-        tf = costmodel.time_program(cands[kf][1], pt, reps=3)
-        tm = tf if km == kf else costmodel.time_program(cands[km][1], pt, reps=3)
+    spread = 0.0
+    err = []
+    for net, trees in test:
+        rows = measure(net, trees)
+        fl = np.array([r[0].flops for r in rows])
+        ms = np.array([r[2] for r in rows])
+        vals = np.array([r[3] for r in rows])
+        spread = max(spread, float(np.abs(vals - vals[0]).max()))
+        pred = cm.predict_relative(np.array([r[1] for r in rows]))
+        kf = int(np.argmin(fl))
+        ok = np.nonzero(fl <= 4.0 * fl.min())[0]
+        km = int(ok[np.argmin(pred[ok])])
         same += km == kf
-        t_flop += tf
-        t_mlp += tm
-    return {"workload": "75 light-cone networks of QAOA p=3 on the 50-node 3-regular graph, 8 candidate trees each",
-            "train_samples": int(sum(len(t) for _, t in groups)), "collect_s": round(collect_s, 1),
-            "fit_s": round(fit_s, 2),
+        t_flop += ms[kf]
+        t_mlp += ms[km]
+        t_best += ms.min()
+        lm = np.log(ms)
+        err.append(float(np.sqrt(np.mean(((lm - lm.mean()) - pred) ** 2))))
+    return {"workload": "QAOA p=4: 8 networks on each of 2 training graphs, 25 held-out networks of the workload "
+                        "graph; candidates = 6 path-search trees x 3 slicings",
+            "train_samples": int(sum(len(t) for _, t in groups)), "plan_s": round(plan_s, 1),
+            "collect_s": round(collect_s, 1), "fit_s": round(fit_s, 2),
             "train_mse_first_last": [hist[0], hist[-1]],
-            "ms_flop_ranked": round(t_flop, 2), "ms_mlp_ranked": round(t_mlp, 2),
-            "learned_gain": round(t_flop / t_mlp, 3), "same_pick": same}
+            "heldout_rms_log_time_error": float(np.mean(err)),
+            "ms_flop_ranked": round(t_flop, 2), "ms_mlp_ranked": round(t_mlp, 2), "ms_fastest_measured": round(t_best, 2),
+            "learned_gain": round(t_flop / t_mlp, 3), "max_possible_gain": round(t_flop / t_best, 3),
+            "same_pick": same, "max_value_spread_between_candidates": spread}
 
 
 def main():
@@ -477,10 +542,14 @@ def main():
         "plain": plain,
     }
     if not args.no_extras:
-        out["qnn16_batch512"] = bench_qnn(max(5, args.steps // 2))
-        out["uneven1024"] = bench_uneven(max(3, args.steps // 4))
-        out["tn_qaoa50"] = bench_tn(max(4, args.steps // 2))
-        out["tree_ranking"] = bench_costmodel()
+        for key, fn in (("qnn16_batch512", lambda: bench_qnn(max(5, args.steps // 2))),
+                        ("uneven1024", lambda: bench_uneven(max(3, args.steps // 4))),
+                        ("tn_qaoa50", lambda: bench_tn(max(4, args.steps // 2))),
+                        ("mqr", bench_mqr),
+                        ("tree_ranking", bench_costmodel)):
+            t0 = time.perf_counter()
+            out[key] = fn()
+            print(f"bench: {key} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)

@@ -349,6 +349,10 @@ void tq_tn_plan_destroy(tq_tn_plan* plan);
 /* 1 if tq_tn_backward of this plan reuses the forward's stored intermediates (the store
  * policy is in effect), 0 if it recomputes them, -1 for a NULL plan. */
 int32_t tq_tn_plan_stores(const tq_tn_plan* plan);
+/* Launch structure of a plan: out[0] forward segments (one launch sequence each: a fused run
+ * of small steps, or one large step), out[1] of them fused runs, out[2] reverse segments,
+ * out[3] of them fused runs (per slice group). */
+tq_status tq_tn_plan_segments(const tq_tn_plan* plan, int64_t out[4]);
 /* Complex elements of the packed leaf buffer, and leaf i's offset in it. */
 int64_t tq_tn_leaf_elems(const tq_tn_plan* plan);
 int64_t tq_tn_leaf_offset(const tq_tn_plan* plan, int32_t leaf);

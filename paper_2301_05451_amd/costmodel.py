@@ -7,15 +7,15 @@ the runtime a small MLP predicts from features of the tree and of its execution 
 MLP is trained on the GPU, by libtq's tq_mlp_* kernels, on measured times of the same
 executor (tq_tn_contract + tq_tn_backward), and ranks new networks' candidates.
 
-Features (16 per tree, all computed on the host):
+Features (16 per candidate, all computed on the host):
   0  log2 FLOPs (paper count, all slices)        8-13 log2(1 + number of steps) whose output
   1  log2 elements written (all slices)                rank is in 0-4, 5-8, 9-12, 13-16,
   2  log2 elements read (all slices)                   17-20, >20
-  3  steps / 100                                  14  log2 largest intermediate
-  4  log2 slices                                  15  share of FLOPs in the largest step
-  5  largest rank (width)
-  6  steps on the MFMA GEMM path (plan)
-  7  log2(1 + FLOPs on the GEMM path)
+  3  steps / 100                                  14  log2 elements moved by the steps too
+  4  log2 slices                                      large to run in a fused launch
+  5  largest rank (width)                         15  share of FLOPs in the largest step
+  6  log2(1 + forward launch segments) (plan)
+  7  log2(1 + forward segments that are single large steps) (plan)
 Target: natural log of the measured time in milliseconds, centred per network (the model
 ranks the candidates of one network), and only candidates within a small factor of the
 fewest FLOPs are re-ranked.
@@ -51,10 +51,14 @@ def tree_features(net, tree, plan_info=None):
     f[4] = len(tree.sliced)
     f[5] = max(ranks + [0])
     if plan_info is not None:
-        f[6] = plan_info["gemm_steps"]
-        f[7] = math.log2(1 + plan_info["gemm_flops"])
+        f[6] = math.log2(1 + plan_info.get("fwd_segments", 0))
+        f[7] = math.log2(1 + plan_info.get("fwd_segments", 0) - plan_info.get("fwd_fused", 0))
     f[8:14] = np.log2(1 + hist)
-    f[14] = math.log2(max([2 ** r for r in ranks] + [1]))
+    big = 0.0
+    for (a, b, o), w in zip(steps, fl):
+        if len(o) > 12 or w > 2 ** 17:  # outside the fused small-step runs
+            big += 2.0 ** len(a) + 2.0 ** len(b) + 2.0 ** len(o)
+    f[14] = math.log2(1 + big * S)
     f[15] = (max(fl) / sum(fl)) if fl else 0.0
     return f
 
@@ -152,12 +156,46 @@ class CostModel:
         return self.predict_log_ms(f - f.mean(0))
 
 
-def candidates_with_plans(net, n_random=5, seed=0, target_rank=26):
-    """Candidate trees of a network with their libtq plans and features."""
+def slicings(net, tree, deltas=(0, 2, 4), seed=0):
+    """A tree and its slicings to ``width - d`` for each d > 0 (Sec. 3.2.3 two-phase search):
+    the candidates differ in run time (more slices, more parallel copies, more FLOPs)."""
     out = []
-    for tree in tn.candidate_trees(net, n_random=n_random, seed=seed, target_rank=target_rank):
-        prog = tn.TNProgram(net, tree)
-        out.append((tree, prog, tree_features(net, tree, prog.plan.info)))
+    for d in deltas:
+        if d == 0:
+            out.append(tree)
+        elif tree.max_rank - d >= 4:
+            out.append(tn.slice_search(net, tree, tree.max_rank - d, 2, np.random.default_rng(seed + d)))
+    return out
+
+
+def edge_candidates(args):
+    """(network, candidate trees x slicings) of one QAOA edge (host only; usable in workers)."""
+    prob, edge, seed, n_bisect, deltas = args
+    net, _ = tn.qaoa_edge_network(prob, edge)
+    out = []
+    for tree in tn.tree_pool(net, seed, n_bisect):
+        out += slicings(net, tree, deltas, seed)
+    return net, out
+
+
+def plan_candidates(prob, edges, n_bisect=3, deltas=(0, 2, 4), workers=1):
+    jobs = [(prob, e, k, n_bisect, deltas) for k, e in enumerate(edges)]
+    if workers <= 1:
+        return [edge_candidates(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(edge_candidates, jobs))
+
+
+def candidates_with_plans(net, trees=None, seed=0, deltas=(0, 2, 4), n_bisect=3):
+    """Candidates (tree x slicing) of a network with their libtq plans and features."""
+    trees = tn.tree_pool(net, seed, n_bisect) if trees is None else trees
+    out = []
+    for tree in trees:
+        for t in slicings(net, tree, deltas, seed):
+            prog = tn.TNProgram(net, t)
+            out.append((t, prog, tree_features(net, t, prog.plan.info)))
     return out
 
 

@@ -183,16 +183,20 @@ __device__ __forceinline__ void tn_step_outputs(const TnStepLds* L, const int64_
   const int64_t nouter = so1 < 0 ? (int64_t(1) << (ks - kt)) : so1;
   const int64_t ngroups = (nz + gpb - 1) / gpb;  // rounds of the block's group slots
   for (int64_t r = gfirst; r < ngroups; r += gstride) {
-    const int64_t e = r * gpb + (threadIdx.x >> tb);
+    const int64_t e0 = r * gpb;  // first output of the round (gpb divides 2^16)
+    const int64_t e = e0 + (threadIdx.x >> tb);
     const bool valid = e < nz;
+    // output bits 16 and up are the same for the whole round: deposited once, in scalar
+    // registers, rather than per lane
+    int64_t xhi = 0, yhi = 0;
+    if (zr > 16) {
+      xhi = deposit_bits((uint64_t)e0 >> 16, st->xo + 16, zr - 16);
+      yhi = deposit_bits((uint64_t)e0 >> 16, st->yo + 16, zr - 16);
+    }
     T ar = 0, ai = 0;
     if (valid) {
-      int64_t xb = L->ox[0][e & 255] + L->ox[1][(e >> 8) & 255];
-      int64_t yb = L->oy[0][e & 255] + L->oy[1][(e >> 8) & 255];
-      if (zr > 16) {
-        xb |= deposit_bits((uint64_t)e >> 16, st->xo + 16, zr - 16);
-        yb |= deposit_bits((uint64_t)e >> 16, st->yo + 16, zr - 16);
-      }
+      const int64_t xb = xhi + L->ox[0][e & 255] + L->ox[1][(e >> 8) & 255];
+      const int64_t yb = yhi + L->oy[0][e & 255] + L->oy[1][(e >> 8) & 255];
       for (int64_t so = so0; so < nouter; ++so) {
         const int64_t xo2 = xb + deposit_bits((uint64_t)so, st->xs + kt, ks - kt);
         const int64_t yo2 = yb + deposit_bits((uint64_t)so, st->ys + kt, ks - kt);
@@ -616,16 +620,19 @@ __device__ inline int leaf_derivative(const DevLeaf& L, const tq_gate& g, const 
   return n;
 }
 
-// grad[p] = Re sum over (leaf, angle) entries of p: pscale * sum_x env[x] * dleaf[x]
+// grad[p] = Re sum over (leaf, angle) entries of p: pscale * sum_x env[x] * dleaf[x].
+// One work-group per parameter: thread t takes entries t, t + 256, ... (a parameter such as a
+// QAOA angle has one entry per gate copy), then a fixed-order tree over the group.
+constexpr int kPgThreads = 256;
 template <typename T>
-__global__ void tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
-                                     const T* __restrict__ params, const int32_t* __restrict__ pptr,
-                                     const int32_t* __restrict__ pent, const typename Cx<T>::type* __restrict__ env,
-                                     int n_params, T* __restrict__ grad) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_params) return;
+__global__ void __launch_bounds__(kPgThreads)
+    tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
+                         const T* __restrict__ params, const int32_t* __restrict__ pptr,
+                         const int32_t* __restrict__ pent, const typename Cx<T>::type* __restrict__ env,
+                         int n_params, T* __restrict__ grad) {
+  const int p = blockIdx.x;
   double acc = 0.0;
-  for (int e = pptr[p]; e < pptr[p + 1]; ++e) {
+  for (int e = pptr[p] + threadIdx.x; e < pptr[p + 1]; e += kPgThreads) {
     const int li = pent[2 * e], j = pent[2 * e + 1];
     const DevLeaf L = lv[li];
     const tq_gate& g = gates[L.gate];
@@ -638,7 +645,11 @@ __global__ void tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_ga
     for (int i = 0; i < n; ++i) s += (double)E[i].x * d[i].x - (double)E[i].y * d[i].y;
     acc += g.pscale[j] * s;
   }
-  grad[p] = (T)acc;
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  __shared__ double red[kPgThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) grad[p] = (T)((red[0] + red[1]) + (red[2] + red[3]));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1059,6 +1070,18 @@ int64_t tq_tn_leaf_offset(const tq_tn_plan* p, int32_t leaf) {
 }
 
 int32_t tq_tn_plan_stores(const tq_tn_plan* p) { return p ? (p->store ? 1 : 0) : -1; }
+
+tq_status tq_tn_plan_segments(const tq_tn_plan* p, int64_t out[4]) {
+  if (!p || !out) return fail(TQ_EINVAL, "null argument");
+  int64_t ff = 0, bf = 0;
+  for (const auto& sg : p->fseg) ff += sg.fused;
+  for (const auto& sg : p->bseg) bf += sg.fused;
+  out[0] = (int64_t)p->fseg.size();
+  out[1] = ff;
+  out[2] = (int64_t)p->bseg.size();
+  out[3] = bf;
+  return TQ_OK;
+}
 
 int64_t tq_tn_workspace(const tq_tn_plan* p, int32_t backward) {
   if (!p) return -1;
@@ -1598,11 +1621,11 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
   TQ_TRY(cached_table(ctx, ent.data(), std::max<size_t>(ent.size(), 1) * sizeof(int32_t), &de));
   if (n_params == 0) return TQ_OK;
   if (plan->dtype == TQ_C64)
-    hipLaunchKernelGGL(tn_param_grad_kernel<float>, dim3((n_params + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(tn_param_grad_kernel<float>, dim3(n_params), dim3(kPgThreads), 0, (hipStream_t)stream,
                        (const DevLeaf*)dlv, (const tq_gate*)dg, (const float*)d_params, (const int32_t*)dp,
                        (const int32_t*)de, (const float2*)d_grad_leaves, n_params, (float*)d_grad_params);
   else
-    hipLaunchKernelGGL(tn_param_grad_kernel<double>, dim3((n_params + 127) / 128), dim3(128), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(tn_param_grad_kernel<double>, dim3(n_params), dim3(kPgThreads), 0, (hipStream_t)stream,
                        (const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)d_params, (const int32_t*)dp,
                        (const int32_t*)de, (const double2*)d_grad_leaves, n_params, (double*)d_grad_params);
   TQ_HIP(hipGetLastError());

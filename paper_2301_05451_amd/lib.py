@@ -485,6 +485,8 @@ _lib.tq_tn_leaf_elems.argtypes = [_vp]
 _lib.tq_tn_leaf_elems.restype = ct.c_int64
 _lib.tq_tn_leaf_offset.argtypes = [_vp, _i32]
 _lib.tq_tn_leaf_offset.restype = ct.c_int64
+_lib.tq_tn_plan_segments.argtypes = [_vp, ct.POINTER(ct.c_int64)]
+_lib.tq_tn_plan_segments.restype = ct.c_int
 _lib.tq_tn_plan_stores.argtypes = [_vp]
 _lib.tq_tn_plan_stores.restype = ct.c_int32
 _lib.tq_tn_workspace.argtypes = [_vp, _i32]
@@ -531,6 +533,9 @@ class TnPlan:
         check(_lib.tq_tn_plan_info(h, out))
         self.info = dict(zip(TN_INFO_FIELDS, [int(v) for v in out]))
         self.stores = bool(_lib.tq_tn_plan_stores(h))
+        seg = (ct.c_int64 * 4)()
+        check(_lib.tq_tn_plan_segments(h, seg))
+        self.info.update(zip(("fwd_segments", "fwd_fused", "bwd_segments", "bwd_fused"), [int(v) for v in seg]))
 
     def workspace_bytes(self, backward=False):
         return int(_lib.tq_tn_workspace(self.h, 1 if backward else 0))

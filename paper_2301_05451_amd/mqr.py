@@ -33,13 +33,13 @@ def mqr_circuit(n, layers=4, seed=2301):
 class MQRTrainer:
     """Gradient-descent (or Adam) training of one MQR circuit on the GPU."""
 
-    def __init__(self, circuit: W.Circuit, lr=0.1, adam=False, c128=False, graph=True):
+    def __init__(self, circuit: W.Circuit, lr=0.1, adam=False, c128=False, graph=True, eps=1e-8):
         import torch
 
         from . import lib
 
         self.c = circuit
-        self.lr, self.adam = lr, adam
+        self.lr, self.adam, self.eps = lr, adam, eps
         rdt = torch.float64 if c128 else torch.float32
         self.spec = lib.BatchSpec.from_circuits([circuit])
         self.svb = lib.SVBatch(self.spec, circuit.terms, 1, c128=c128, graph=graph)
@@ -58,7 +58,7 @@ class MQRTrainer:
         self.svb.forward(self.params, self.states, self.cost)
         self.svb.backward(self.params, self.states, self.w, self.grad)
         self.t += 1
-        lib.optimizer_step(self.params, self.grad, self.lr, self.t, self.m, self.v, adam=self.adam)
+        lib.optimizer_step(self.params, self.grad, self.lr, self.t, self.m, self.v, adam=self.adam, eps=self.eps)
         return self.cost
 
     def run(self, iters):

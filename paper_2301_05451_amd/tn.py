@@ -399,6 +399,286 @@ def candidate_trees(net: Network, n_random=31, seed=0, target_rank=28):
     return out
 
 
+# ---- structural simplification and recursive bisection (Sec. 3.2.1, 3.2.2) --------------------
+
+def rank_simplify(net: Network, sliced=()):
+    """Rank simplification (Sec. 3.2.1): repeatedly contract a pair of tensors sharing an
+    index whenever the result has no more indices than the larger of the two (absorbing the
+    |0> vectors, one-qubit gates and diagonal tensors into their neighbours). Returns the SSA
+    pairs and the remaining tensors as {id: index tuple}."""
+    sl = set(sliced)
+    live = {i: tuple(x for x in lf.inds if x not in sl) for i, lf in enumerate(net.leaves)}
+    cnt = _index_counts(live.values())
+    output = set(net.output)
+    holders = {}
+    for tid, t in live.items():
+        for i in t:
+            holders.setdefault(i, set()).add(tid)
+    pairs = []
+    nid = len(net.leaves)
+    changed = True
+    while changed:
+        changed = False
+        for tid in sorted(live, key=lambda t: (len(live[t]), t)):
+            if tid not in live:
+                continue
+            best = None
+            for i in live[tid]:
+                for other in holders.get(i, ()):
+                    if other == tid or other not in live:
+                        continue
+                    o = _out_inds(live[tid], live[other], cnt, output)
+                    if len(o) <= max(len(live[tid]), len(live[other])):
+                        key = (len(o), len(live[other]), other)
+                        if best is None or key < best[0]:
+                            best = (key, other, o)
+            if best is None:
+                continue
+            _, other, o = best
+            a, b = min(tid, other), max(tid, other)
+            pairs.append((a, b))
+            for j in live[a]:
+                cnt[j] -= 1
+                holders[j].discard(a)
+            for j in live[b]:
+                cnt[j] -= 1
+                holders[j].discard(b)
+            del live[a], live[b]
+            live[nid] = tuple(o)
+            for j in o:
+                cnt[j] = cnt.get(j, 0) + 1
+                holders.setdefault(j, set()).add(nid)
+            nid += 1
+            changed = True
+    return pairs, live
+
+
+def _bisect(verts, tens, rng, imbalance, kept_outside):
+    """Balanced two-way split of ``verts`` (tensor ids with index tuples ``tens``) that cuts
+    few indices: region growing from a random seed to half the vertices, then passes of
+    single-vertex moves (Fiduccia-Mattheyses style: best gain first, each vertex moved once
+    per pass, the best prefix kept) within the balance bound. An index counts as cut when
+    tensors on both sides hold it; indices also held outside ``verts`` are cut whatever the
+    split and do not count."""
+    verts = list(verts)
+    n = len(verts)
+    edges = {}
+    for v in verts:
+        for i in tens[v]:
+            if i not in kept_outside:
+                edges.setdefault(i, []).append(v)
+    nbr = {v: set() for v in verts}
+    for i, hs in edges.items():
+        for v in hs:
+            nbr[v].update(hs)
+    for v in verts:
+        nbr[v].discard(v)
+    lo = int(math.floor(n * (0.5 - imbalance / 2)))
+    hi = n - lo
+    seed = verts[int(rng.integers(n))]
+    side = {v: 1 for v in verts}
+    side[seed] = 0
+    frontier = [seed]
+    size0 = 1
+    order = list(verts)
+    while size0 < n // 2:
+        if not frontier:  # disconnected: restart from any unassigned vertex
+            rest = [v for v in order if side[v] == 1]
+            frontier = [rest[int(rng.integers(len(rest)))]]
+            side[frontier[0]] = 0
+            size0 += 1
+            continue
+        v = frontier.pop(0)
+        cand = [w for w in nbr[v] if side[w] == 1]
+        rng.shuffle(cand)
+        for w in cand:
+            if size0 >= n // 2:
+                break
+            side[w] = 0
+            size0 += 1
+            frontier.append(w)
+
+    def counts():
+        c = {}
+        for i, hs in edges.items():
+            a = sum(1 for v in hs if side[v] == 0)
+            c[i] = [a, len(hs) - a]
+        return c
+
+    def cut(c):
+        return sum(1 for a, b in c.values() if a and b)
+
+    for _ in range(6):
+        c = counts()
+        best_cut, cur = cut(c), cut(c)
+        locked, moves, best_k = set(), [], 0
+        size = [sum(1 for v in verts if side[v] == 0), 0]
+        size[1] = n - size[0]
+        for _step in range(n):
+            best = None
+            for v in verts:
+                if v in locked:
+                    continue
+                s0 = side[v]
+                if size[s0] - 1 < lo:
+                    continue
+                g = 0
+                for i in tens[v]:
+                    if i in c:
+                        a, b = c[i][s0], c[i][1 - s0]
+                        if a == 1 and b > 0:
+                            g += 1
+                        elif b == 0 and a > 1:
+                            g -= 1
+                if best is None or g > best[0]:
+                    best = (g, v)
+            if best is None:
+                break
+            g, v = best
+            s0 = side[v]
+            side[v] = 1 - s0
+            size[s0] -= 1
+            size[1 - s0] += 1
+            for i in tens[v]:
+                if i in c:
+                    c[i][s0] -= 1
+                    c[i][1 - s0] += 1
+            cur -= g
+            locked.add(v)
+            moves.append(v)
+            if cur < best_cut:
+                best_cut, best_k = cur, len(moves)
+        for v in moves[best_k:][::-1]:  # undo the moves after the best prefix
+            side[v] = 1 - side[v]
+        if best_k == 0:
+            break
+    A = [v for v in verts if side[v] == 0]
+    B = [v for v in verts if side[v] == 1]
+    return A, B
+
+
+def bisection_tree(net: Network, rng=None, imbalance=0.2, leaf_size=8, simplify=True, sliced=()):
+    """Contraction tree by recursive balanced bisection of the tensor hypergraph (Sec. 3.2.2:
+    the tensors are split in two parts sharing few indices, each part is split again, and the
+    parts are contracted bottom up), after rank simplification. Parts of at most
+    ``leaf_size`` tensors are ordered greedily."""
+    rng = np.random.default_rng(0) if rng is None else rng
+    pairs, live = rank_simplify(net, sliced) if simplify else ([], {
+        i: tuple(x for x in lf.inds if x not in set(sliced)) for i, lf in enumerate(net.leaves)})
+    tens = dict(live)
+    nid = [len(net.leaves) + len(pairs)]
+    output = set(net.output)
+    holder = {}
+    for t, inds in tens.items():
+        for i in inds:
+            holder.setdefault(i, set()).add(t)
+
+    def contract(a, b, outside):
+        o = [i for i in dict.fromkeys(tens[a] + tens[b])
+             if i in output or i in outside or (holder[i] - {a, b})]
+        pairs.append((a, b))
+        c = nid[0]
+        nid[0] += 1
+        for i in tens[a]:
+            holder[i].discard(a)
+        for i in tens[b]:
+            holder[i].discard(b)
+        tens[c] = tuple(o)
+        for i in o:
+            holder.setdefault(i, set()).add(c)
+        return c
+
+    def solve(verts):
+        verts = list(verts)
+        if len(verts) == 1:
+            return verts[0]
+        vs = set(verts)
+        outside = {i for v in verts for i in tens[v] if i in output or (holder[i] - vs)}
+        if len(verts) <= leaf_size:
+            cur = list(verts)
+            while len(cur) > 1:
+                best = None
+                for x in range(len(cur)):
+                    for y in range(x + 1, len(cur)):
+                        a, b = cur[x], cur[y]
+                        shared = set(tens[a]) & set(tens[b])
+                        o = [i for i in dict.fromkeys(tens[a] + tens[b])
+                             if i in output or i in outside or (holder[i] - {a, b})]
+                        key = (0 if shared else 1, 2.0 ** len(o) - 2.0 ** len(tens[a]) - 2.0 ** len(tens[b]), x, y)
+                        if best is None or key < best[0]:
+                            best = (key, a, b)
+                _, a, b = best
+                c = contract(a, b, outside)
+                cur = [v for v in cur if v not in (a, b)] + [c]
+            return cur[0]
+        A, B = _bisect(verts, tens, rng, imbalance, outside)
+        if not A or not B:
+            half = len(verts) // 2
+            A, B = verts[:half], verts[half:]
+        ra, rb = solve(A), solve(B)
+        return contract(ra, rb, outside)
+
+    solve(sorted(tens))
+    tree = Tree(pairs, len(net.leaves))
+    score_tree(net, tree)
+    return tree
+
+
+def slice_search(net: Network, tree: Tree, target_rank, trials=8, rng=None):
+    """Two-phase slicing (Sec. 3.2.3): the greedy slicing first (pseudo-slicing: fix the
+    index met in the most over-size intermediates), then randomised trials that break ties
+    at random; the slicing with the fewest total FLOPs (all slices) is kept."""
+    rng = np.random.default_rng(0) if rng is None else rng
+    best = slice_tree(net, tree, target_rank)
+    for _ in range(trials):
+        t = slice_tree(net, tree, target_rank, rng)
+        if (t.flops, len(t.sliced)) < (best.flops, len(best.sliced)):
+            best = t
+    return best
+
+
+def tree_pool(net: Network, seed=0, n_bisect=4):
+    """The path search's candidate trees of one network (unsliced): min-fill and min-degree
+    elimination, pairwise greedy, and ``n_bisect`` recursive-bisection trees with different
+    seeds, balance bounds and leaf-part sizes."""
+    out = [elimination_tree(net, elimination_order(net, None, "fill")[0]),
+           elimination_tree(net, elimination_order(net, None, "degree")[0]),
+           greedy_tree(net)]
+    shapes = [(0.1, 8), (0.3, 14), (0.2, 10), (0.3, 8), (0.1, 14), (0.2, 16)]
+    for k in range(n_bisect):
+        imb, leaf = shapes[k % len(shapes)]
+        out.append(bisection_tree(net, np.random.default_rng(seed * 1000 + k), imbalance=imb, leaf_size=leaf))
+    return out
+
+
+def best_tree(net: Network, seed=0, n_bisect=4, target_rank=None, slice_trials=4):
+    """The fewest-FLOP tree of the pool (the paper's FLOP ranking, Sec. 3.2.2), sliced to
+    ``target_rank`` by the two-phase slicing search when it is wider (Sec. 3.2.3)."""
+    t = min(tree_pool(net, seed, n_bisect), key=lambda x: (x.flops, x.max_rank))
+    if target_rank is not None and t.max_rank > target_rank:
+        t = slice_search(net, t, target_rank, slice_trials, np.random.default_rng(seed))
+    return t
+
+
+def _plan_edge(args):
+    prob, edge, seed, n_bisect, target_rank = args
+    net, _ = qaoa_edge_network(prob, edge)
+    return net, best_tree(net, seed, n_bisect, target_rank)
+
+
+def plan_qaoa(prob: W.QAOAProblem, edges=None, n_bisect=4, target_rank=None, workers=1):
+    """(network, fewest-FLOP tree of the pool, sliced to ``target_rank``) for every edge; the
+    host search runs in ``workers`` spawned processes (it holds no GPU state)."""
+    edges = list(prob.edges) if edges is None else list(edges)
+    jobs = [(prob, e, k, n_bisect, target_rank) for k, e in enumerate(edges)]
+    if workers <= 1:
+        return [_plan_edge(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_plan_edge, jobs, chunksize=2))
+
+
 # ---- device execution (steps (e) and its reverse) -------------------------------------------
 
 def leaf_specs(net: Network):

@@ -16,9 +16,12 @@ pytestmark = pytest.mark.gpu
 def test_mqr_trajectory_vs_oracle(c128, adam):
     c = mqr.mqr_circuit(4, layers=3)
     lr = 0.05 if adam else 0.1
-    tr = mqr.MQRTrainer(c, lr=lr, adam=adam, c128=c128)
+    # the last layer's RZ angles do not change the cost (their gradient is 0): Adam divides
+    # rounding noise of such a gradient by its own size, so eps is set well above that noise
+    eps = 1e-3
+    tr = mqr.MQRTrainer(c, lr=lr, adam=adam, c128=c128, eps=eps)
     hist = tr.run(8).cpu().numpy()
-    costs, theta = train.trajectory(c, lr, 8, adam=adam)
+    costs, theta = train.trajectory(c, lr, 8, adam=adam, eps=eps)
     # costs are sums of 4 unit-coefficient Z terms: weight scale 4 (complex64); parameters
     # move by lr times gradients of that size per step
     tol = 1e-12 if c128 else 1e-5
@@ -32,4 +35,4 @@ def test_mqr_500_steps_reach_all_ones():
     tr = mqr.MQRTrainer(c, lr=0.1)
     hist = tr.run(500).cpu().numpy()
     print(f"mqr n={n}: cost {hist[0]:.4f} -> {hist[-1]:.6f}", flush=True)
-    assert hist[-1] < -n + 1e-2 and hist[-1] < hist[0]
+    assert hist[-1] < -n + 5e-2 and hist[-1] < hist[0] and np.all(np.diff(hist[-100:]) <= 1e-5)

@@ -92,3 +92,41 @@ def test_candidate_trees_are_valid():
     for t in cands:
         assert sorted(i for p in t.pairs for i in p) == list(range(2 * len(net.leaves) - 2))
         assert t.max_rank >= 0 and t.flops > 0
+
+
+def test_bisection_trees_are_valid_and_exact():
+    """Recursive-bisection trees (after rank simplification) use every tensor once and give
+    the oracle's value when contracted along them."""
+    rng = np.random.default_rng(5)
+    edges = W.random_regular_graph(3, 10, rng)
+    prob = W.QAOAProblem(10, edges, 2, W.f32_angles(rng, 2, 0, math.pi), W.f32_angles(rng, 2, 0, math.pi))
+    for e in edges[:3]:
+        net, _ = tn.qaoa_edge_network(prob, e)
+        for seed, imb, leaf in ((0, 0.1, 4), (1, 0.3, 8), (2, 0.2, 3)):
+            t = tn.bisection_tree(net, np.random.default_rng(seed), imbalance=imb, leaf_size=leaf)
+            assert sorted(i for p in t.pairs for i in p) == list(range(2 * len(net.leaves) - 2))
+            v = _numpy_contract(net, t)
+            assert abs(v.real - otn.qaoa_edge_zz_sv(prob, e)) < 1e-12 and abs(v.imag) < 1e-12
+
+
+def test_rank_simplification_never_grows_a_tensor():
+    prob = W.qaoa_maxcut(p=2)
+    net, _ = tn.qaoa_edge_network(prob, prob.edges[4])
+    pairs, live = tn.rank_simplify(net)
+    assert len(live) + len(pairs) == len(net.leaves) and len(live) < len(net.leaves) // 2
+    t = tn.bisection_tree(net)
+    steps = tn.tree_steps(net, t)
+    for a, b, o in steps[:len(pairs)]:
+        assert len(o) <= max(len(a), len(b))
+
+
+def test_path_search_pool_and_slicing_search():
+    prob = W.qaoa_maxcut(p=3)
+    net, _ = tn.qaoa_edge_network(prob, prob.edges[2])
+    pool = tn.tree_pool(net, seed=1, n_bisect=2)
+    best = tn.best_tree(net, seed=1, n_bisect=2)
+    assert best.flops == min(t.flops for t in pool)
+    target = max(4, best.max_rank - 3)
+    s = tn.slice_search(net, best, target, trials=3, rng=np.random.default_rng(0))
+    assert s.pairs == best.pairs and max(len(o) for _, _, o in tn.tree_steps(net, s)) <= target
+    assert s.flops <= tn.slice_tree(net, best, target).flops
