@@ -335,81 +335,33 @@ def bench_mqr():
 def bench_costmodel():
     """Learned ranking of contraction trees and slicings (QAOA p = 4): the cost-model MLP is
     trained on the GPU from measured times (value + gradient) of the candidates (path-search
-    trees x slicings to width, width - 2, width - 4) of 8 light-cone networks on each of two
-    other seeded 50-node graphs, then picks one candidate for each of 25 networks of the
+    trees x slicings to width, width - 2, width - 4) of 10 light-cone networks on each of
+    three other seeded 50-node graphs, then picks one candidate for each of 25 networks of the
     workload graph (held out); its picks are timed against the fewest-FLOP picks and against
     the fastest measured candidate (the most any ranking could gain)."""
-    import numpy as np
-    import torch
-
-    from paper_2301_05451_amd import costmodel, tn
+    from paper_2301_05451_amd import costmodel
     from paper_2301_05451_amd import workloads as W
-
-    def graph(seed, p=4):
-        r = np.random.default_rng(seed)
-        edges = W.random_regular_graph(3, 50, r)
-        return W.QAOAProblem(50, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
 
     t0 = time.perf_counter()
     train = []
-    for seed in (2001, 2002):
-        g = graph(seed)
-        train += costmodel.plan_candidates(g, g.edges[::9][:8], workers=_workers())
+    for seed in (2001, 2002, 2003):
+        g = costmodel.qaoa_graph(seed)
+        train += costmodel.plan_candidates(g, g.edges[::7][:10], workers=_workers())
     prob = W.qaoa_maxcut(p=4)
     test = costmodel.plan_candidates(prob, prob.edges[::3], workers=_workers())
     plan_s = time.perf_counter() - t0
     print(f"bench: ranking candidates planned in {plan_s:.1f} s", file=sys.stderr, flush=True)
-
-    def measure(net, trees):
-        pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
-        rows = []
-        for t in trees:
-            prog = tn.TNProgram(net, t)
-            rows.append((t, costmodel.tree_features(net, t, prog.plan.info), costmodel.time_program(prog, pt, reps=3),
-                         prog.value(pt).cpu().numpy()[0]))
-            del prog
-        return rows
-
     t1 = time.perf_counter()
-    groups = []
-    for net, trees in train:
-        rows = measure(net, trees)
-        groups.append((np.array([r[1] for r in rows]), np.log(np.array([r[2] for r in rows]))))
-    collect_s = time.perf_counter() - t1
-    cm = costmodel.CostModel(seed=0)
-    t2 = time.perf_counter()
-    hist = cm.fit_groups(groups, epochs=800, lr=3e-3)
-    torch.cuda.synchronize()
-    fit_s = time.perf_counter() - t2
-    t_flop = t_mlp = t_best = 0.0
-    same = 0
-    spread = 0.0
-    err = []
-    for net, trees in test:
-        rows = measure(net, trees)
-        fl = np.array([r[0].flops for r in rows])
-        ms = np.array([r[2] for r in rows])
-        vals = np.array([r[3] for r in rows])
-        spread = max(spread, float(np.abs(vals - vals[0]).max()))
-        pred = cm.predict_relative(np.array([r[1] for r in rows]))
-        kf = int(np.argmin(fl))
-        ok = np.nonzero(fl <= 4.0 * fl.min())[0]
-        km = int(ok[np.argmin(pred[ok])])
-        same += km == kf
-        t_flop += ms[kf]
-        t_mlp += ms[km]
-        t_best += ms.min()
-        lm = np.log(ms)
-        err.append(float(np.sqrt(np.mean(((lm - lm.mean()) - pred) ** 2))))
-    return {"workload": "QAOA p=4: 8 networks on each of 2 training graphs, 25 held-out networks of the workload "
-                        "graph; candidates = 6 path-search trees x 3 slicings",
-            "train_samples": int(sum(len(t) for _, t in groups)), "plan_s": round(plan_s, 1),
-            "collect_s": round(collect_s, 1), "fit_s": round(fit_s, 2),
-            "train_mse_first_last": [hist[0], hist[-1]],
-            "heldout_rms_log_time_error": float(np.mean(err)),
-            "ms_flop_ranked": round(t_flop, 2), "ms_mlp_ranked": round(t_mlp, 2), "ms_fastest_measured": round(t_best, 2),
-            "learned_gain": round(t_flop / t_mlp, 3), "max_possible_gain": round(t_flop / t_best, 3),
-            "same_pick": same, "max_value_spread_between_candidates": spread}
+    r = costmodel.ranking_experiment(train, test, reps=5,
+                                     log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    r.update({"workload": "QAOA p=4: 10 networks on each of 3 training graphs, 25 held-out networks of the "
+                          "workload graph; candidates = 6 path-search trees x 3 slicings",
+              "plan_s": round(plan_s, 1), "measure_and_fit_s": round(time.perf_counter() - t1, 1)})
+    for k in ("ms_flop_ranked", "ms_mlp_ranked", "ms_fastest_measured"):
+        r[k] = round(r[k], 2)
+    r["learned_gain"] = round(r["learned_gain"], 3)
+    r["max_possible_gain"] = round(r["max_possible_gain"], 3)
+    return r
 
 
 def main():

@@ -188,6 +188,75 @@ def plan_candidates(prob, edges, n_bisect=3, deltas=(0, 2, 4), workers=1):
         return list(ex.map(edge_candidates, jobs))
 
 
+def qaoa_graph(seed, p=4, n=50):
+    """A seeded random 3-regular graph with QAOA angles (training and held-out graphs)."""
+    from . import workloads as W
+    r = np.random.default_rng(seed)
+    edges = W.random_regular_graph(3, n, r)
+    return W.QAOAProblem(n, edges, p, W.f32_angles(r, p, 0, math.pi), W.f32_angles(r, p, 0, math.pi))
+
+
+def measure_candidates(net, trees, reps=3, spread=8.0):
+    """(tree, features, median ms of value + gradient, value) of each candidate within
+    ``spread`` times the fewest FLOPs (costlier ones are never picked, so not run)."""
+    import torch
+    fmin = min(t.flops for t in trees)
+    pt = torch.tensor(net.params, dtype=torch.float32, device="cuda")
+    rows = []
+    for t in trees:
+        if t.flops > spread * fmin:
+            continue
+        prog = tn.TNProgram(net, t)
+        rows.append((t, tree_features(net, t, prog.plan.info), time_program(prog, pt, reps=reps),
+                     prog.value(pt).cpu().numpy()[0]))
+        del prog
+    return rows
+
+
+def ranking_experiment(train, test, seed=0, trust=4.0, reps=3, margin=0.05, log=None):
+    """Trains a CostModel on the measured candidates of the ``train`` networks and compares,
+    on the ``test`` networks, the measured time of its picks with the fewest-FLOP picks and
+    with the fastest measured candidate. ``train``/``test``: lists of (network, trees). The
+    model leaves the fewest-FLOP pick only when it predicts the other candidate faster by
+    more than ``margin`` in log time (its held-out error is of that order)."""
+    import torch
+    groups = []
+    for k, (net, trees) in enumerate(train):
+        rows = measure_candidates(net, trees, reps)
+        groups.append((np.array([r[1] for r in rows]), np.log(np.array([r[2] for r in rows]))))
+        if log:
+            log(f"ranking: train network {k}, {len(rows)} candidates")
+    cm = CostModel(seed=seed)
+    hist = cm.fit_groups(groups, epochs=800, lr=3e-3)
+    torch.cuda.synchronize()
+    t_flop = t_mlp = t_best = 0.0
+    same, spread, err = 0, 0.0, []
+    for k, (net, trees) in enumerate(test):
+        rows = measure_candidates(net, trees, reps)
+        fl = np.array([r[0].flops for r in rows])
+        ms = np.array([r[2] for r in rows])
+        vals = np.array([r[3] for r in rows])
+        spread = max(spread, float(np.abs(vals - vals[0]).max()))
+        pred = cm.predict_relative(np.array([r[1] for r in rows]))
+        kf = int(np.argmin(fl))
+        ok = np.nonzero(fl <= trust * fl.min())[0]
+        km = int(ok[np.argmin(pred[ok])])
+        if pred[kf] - pred[km] <= margin:
+            km = kf
+        same += km == kf
+        t_flop += ms[kf]
+        t_mlp += ms[km]
+        t_best += ms.min()
+        lm = np.log(ms)
+        err.append(float(np.sqrt(np.mean(((lm - lm.mean()) - pred) ** 2))))
+        if log:
+            log(f"ranking: held-out network {k}, {len(rows)} candidates")
+    return {"train_samples": int(sum(len(t) for _, t in groups)), "train_mse_first_last": [hist[0], hist[-1]],
+            "heldout_rms_log_time_error": float(np.mean(err)), "ms_flop_ranked": t_flop, "ms_mlp_ranked": t_mlp,
+            "ms_fastest_measured": t_best, "learned_gain": t_flop / t_mlp, "max_possible_gain": t_flop / t_best,
+            "same_pick": same, "networks": len(test), "max_value_spread_between_candidates": spread}
+
+
 def candidates_with_plans(net, trees=None, seed=0, deltas=(0, 2, 4), n_bisect=3):
     """Candidates (tree x slicing) of a network with their libtq plans and features."""
     trees = tn.tree_pool(net, seed, n_bisect) if trees is None else trees
