@@ -39,6 +39,16 @@ def cpu_model():
     return platform.processor()
 
 
+def cpu_threads():
+    """Threads the oracle's numpy can use: the BLAS pools' sizes (threadpoolctl), else 1."""
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        return max([int(p.get("num_threads", 1)) for p in info] + [1])
+    except Exception:
+        return 1
+
+
 def cpu_baseline(c, seconds_hint=True):
     """The oracle (complex128 numpy) on a bounded sample: the first brickwork layer (84 of
     the 1670 gates) on the full 24-qubit register, scaled to gates*amps/s."""
@@ -48,12 +58,91 @@ def cpu_baseline(c, seconds_hint=True):
     t0 = time.perf_counter()
     osv.run(c.n, sample, c.params)
     dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS")
     return {"value": len(sample) * (1 << c.n) / dt, "unit": "gate*amps/s",
-            "cores": int(threads) if threads and threads.isdigit() else os.cpu_count(),
-            "kind": "oracle",
+            "cores": cpu_threads(), "kind": "oracle",
             "sample": f"first brickwork layer ({len(sample)} gates) of the 24-qubit circuit, complex128, "
-                      f"{dt:.1f} s on {cpu_model()} (numpy tensordot per gate)"}
+                      f"{dt:.1f} s on {cpu_model()} (numpy tensordot per gate; elementwise work runs on one "
+                      f"core, the tensordot products on the BLAS threads)"}
+
+
+def cpu_plan():
+    """The oracle timed on every workload (the CPU-baseline plan), bounded samples stated per
+    entry; wall times with time.perf_counter. Long: minutes (the whole 24-qubit circuit)."""
+    import numpy as np
+
+    from oracle import sv as osv
+    from oracle import tn as otn
+    from paper_2301_05451_amd import workloads as W
+
+    def log(m):
+        print("cpu-plan: " + m, file=sys.stderr, flush=True)
+
+    out = {"cpu": cpu_model(), "os_cpu_count": os.cpu_count(), "blas_threads": cpu_threads(),
+           "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+    c1 = W.hea_ring()
+    t0 = time.perf_counter()
+    osv.circuit_f(c1)
+    out["hea10_s_per_circuit"] = time.perf_counter() - t0
+    c2 = W.brickwork()
+    t0 = time.perf_counter()
+    psi = osv.initial_state(c2.n).reshape((2,) * c2.n)
+    for k in range(0, len(c2.gates), 84):  # the whole circuit, in chunks (progress lines)
+        psi = osv.run(c2.n, c2.gates[k:k + 84], c2.params, init=psi.reshape(-1)).reshape((2,) * c2.n)
+        log(f"brickwork24 {min(k + 84, len(c2.gates))}/{len(c2.gates)} gates, {time.perf_counter() - t0:.0f} s")
+    dt = time.perf_counter() - t0
+    out["brickwork24_full_s"] = dt
+    out["brickwork24_gate_amps_per_s"] = len(c2.gates) * (1 << c2.n) / dt
+    del psi
+    gates, x, theta, y = W.qnn_batch()
+    n = 16
+    t0 = time.perf_counter()
+    for b in range(32):
+        osv.circuit_f(W.Circuit(n, gates, np.concatenate([x[b], theta]), 1, W.zterms([([0], 1.0, 0)])))
+    fwd = (time.perf_counter() - t0) / 32
+    cb = W.Circuit(n, gates, np.concatenate([x[0], theta]), 1, W.zterms([([0], 1.0, 0)]))
+    t0 = time.perf_counter()
+    for p in range(0, 272, 17):  # 16 of the 272 parameters, two shifted circuits each
+        for sft in (np.pi / 2, -np.pi / 2):
+            pp = cb.params.copy()
+            pp[p] += sft
+            osv.circuit_f(cb, pp)
+    ps = (time.perf_counter() - t0) / 16
+    out["qnn16"] = {"forward_s_per_sample": fwd, "forward_512_s_extrapolated": fwd * 512,
+                    "param_shift_s_per_parameter": ps, "param_shift_s_per_sample_extrapolated": ps * 272,
+                    "sample": "forward of 32 of the 512 samples; parameter shift of 16 of 272 parameters of one sample"}
+    log("qnn16 done")
+    circs = W.uneven_batch()
+    per_n = {}
+    for nq in range(8, 21):
+        sel = [cc for cc in circs if cc.n == nq][:2]
+        t0 = time.perf_counter()
+        for cc in sel:
+            osv.circuit_f(cc)
+        per_n[nq] = (time.perf_counter() - t0) / max(1, len(sel))
+        log(f"uneven n={nq}: {per_n[nq]:.2f} s per circuit")
+    hist = {nq: sum(1 for cc in circs if cc.n == nq) for nq in range(8, 21)}
+    out["uneven1024"] = {"s_per_circuit_by_n": per_n,
+                         "forward_s_extrapolated": sum(per_n[k] * hist[k] for k in per_n),
+                         "sample": "2 circuits per qubit count, forward only; total extrapolated to the batch's n histogram"}
+    prob3 = W.qaoa_maxcut(p=3)
+    cones = sorted((len(otn.qaoa_cone(prob3, e)[3]), e) for e in prob3.edges)
+    small = [e for sz, e in cones if sz <= 24]
+    t0 = time.perf_counter()
+    for e in small:
+        otn.qaoa_edge_zz_sv(prob3, e)
+    cone_sv = (time.perf_counter() - t0) / max(1, len(small))
+    t0 = time.perf_counter()
+    for _, e in cones[:4]:
+        otn.qaoa_edge_zz_tn(prob3, e)
+    tn4 = (time.perf_counter() - t0) / 4
+    out["qaoa50"] = {"p3_cone_sv_s_per_network": cone_sv, "p3_cone_sv_networks": len(small),
+                     "p3_einsum_tn_s_per_network": tn4,
+                     "sample": "QAOA p=3 (cones of 19-30 qubits): cone state vector for the cones of at most 24 "
+                               "qubits, the oracle's einsum network for the 4 smallest cones. At p=4 every cone "
+                               "has 30 or more qubits (a 16 GiB complex128 state) and the einsum order does not "
+                               "finish within minutes, so p=4 is not timed on the CPU."}
+    log("qaoa done")
+    return out
 
 
 def measured_traffic():
@@ -125,6 +214,9 @@ def bench_qnn(steps):
         svb.backward(params, states, w, grad)
 
     ms = _timed(step, steps, 3)
+    fwd_ms = _timed(lambda: svb.forward(params, states, out), steps, 2)
+    fpa = lib.plan_info(n, gates)["flops_per_amp"]
+    fwd_flops = fpa * (1 << n) * B
     # GPU parameter shift on 4 samples (2P shifted circuits each), same weights
     sel = slice(0, 4)
     ps_ms = _timed(lambda: sv.param_shift_grad_gpu(params.reshape(B, P)[sel], gates, n, terms, 1, w[sel]), 2, 1)
@@ -153,7 +245,12 @@ def bench_qnn(steps):
             "max_abs_grad_diff_vs_param_shift": err,
             "single_call_loop_circuits_per_s": 1 / (loop_ms * 1e-3),
             "batched_speedup_vs_single_calls": round(loop_ms / (ms / B), 1),
-            "levels": svb.info["levels"], "graph_replays": svb.info["graph_replays"]}
+            "levels": svb.info["levels"], "graph_replays": svb.info["graph_replays"],
+            "forward_ms": round(fwd_ms, 4),
+            "roofline_forward": {"bound": "alu", "kernel": "sv_batch_stage_kernel (all levels of one forward)",
+                                 "achieved": round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                                 "unit": "TFLOP/s", "frac": round(fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+                                 "algorithmic_flops": fwd_flops, "flops_per_amp": fpa}}
 
 
 def bench_uneven(steps):
@@ -188,6 +285,7 @@ def bench_uneven(steps):
 
     ms = _timed(step, steps, 3)
     gate_amps = int(sum(c.gates.shape[0] << c.n for c in circs))
+    fwd_flops = float(sum(lib.plan_info(c.n, c.gates)["flops_per_amp"] * (1 << c.n) for c in circs))
     # single-circuit calls, one circuit per call
     specs1 = [lib.BatchSpec.from_circuits([c]) for c in circs]
     offs = spec.param_off
@@ -210,7 +308,11 @@ def bench_uneven(steps):
             "autotuned_forward": list(tf[:2]), "autotuned_backward": list(tb[:2]),
             "single_call_loop_grad_circuits_per_s": len(circs) / (loop_ms * 1e-3),
             "batched_speedup_vs_single_calls": round(loop_ms / ms, 1),
-            "levels": svb.info["levels"], "items": svb.info["items"]}
+            "levels": svb.info["levels"], "items": svb.info["items"],
+            "roofline_forward": {"bound": "alu", "kernel": "sv_batch_stage_kernel (all levels of one forward)",
+                                 "achieved": round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                                 "unit": "TFLOP/s", "frac": round(fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+                                 "algorithmic_flops": fwd_flops}}
 
 
 def _workers():
@@ -370,6 +472,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="also time the oracle on every workload (minutes; adds cpu_plan to the JSON line)")
+    ap.add_argument("--extras", default="qnn16_batch512,uneven1024,tn_qaoa50,mqr,tree_ranking",
+                    help="comma-separated measurements besides the headline")
     ap.add_argument("--plain-steps", type=int, default=1, help="steps of the one-sweep-per-gate path")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--reg-bits", type=int, default=0)
@@ -458,6 +564,14 @@ def main():
     roof.update({"kernel": "sv_stage_kernel<float,%d>" % info["reg_bits"], "launches_per_step": stages,
                  "avg_launch_us": round(stage_ms * 1e3, 2)})
 
+    # the expectation value alone (partial-sum + final launches): a streaming read of the state
+    ev_ms = _timed(lambda: lib.expval(psi, spec, c.terms, 1), args.steps, 2)
+    ev_bytes = (1 << n) * 8
+    expval_roof = {"bound": "hbm", "kernel": "expval_partial_kernel + expval_final_kernel", "terms": int(c.terms.shape[0]),
+                   "achieved": round(ev_bytes / (ev_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(ev_bytes / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "us": round(ev_ms * 1e3, 2),
+                   "algorithmic_bytes": ev_bytes}
+
     # the plain path (one HBM sweep per gate) on the same circuit, for comparison
     plain = None
     if args.plain_steps > 0:
@@ -490,20 +604,26 @@ def main():
                    "flops_per_amp": info["flops_per_amp"], "phases": info["phases"],
                    "exchanges": info["exchanges"]},
         "roofline": roof,
+        "roofline_expval": expval_roof,
         "expval_sum_z": float(f[0, 0]),
         "plain": plain,
     }
     if not args.no_extras:
+        wanted = set(x.strip() for x in args.extras.split(",") if x.strip())
         for key, fn in (("qnn16_batch512", lambda: bench_qnn(max(5, args.steps // 2))),
                         ("uneven1024", lambda: bench_uneven(max(3, args.steps // 4))),
                         ("tn_qaoa50", lambda: bench_tn(max(4, args.steps // 2))),
                         ("mqr", bench_mqr),
                         ("tree_ranking", bench_costmodel)):
+            if key not in wanted:
+                continue
             t0 = time.perf_counter()
             out[key] = fn()
             print(f"bench: {key} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(c)
+    if args.cpu_plan:
+        out["cpu_plan"] = cpu_plan()
     print(json.dumps(out), flush=True)
 
 
