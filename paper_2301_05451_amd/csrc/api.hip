@@ -18,12 +18,31 @@ tq_status fail(tq_status st, const std::string& msg) {
 }
 
 Schedule::~Schedule() {
-  void* ptrs[] = {d_gates,  d_rec,       d_rec_gates,   d_ops,         d_phases,
-                  d_stages, d_dslot,     d_pslot_ptr,   d_pslot_idx,   d_pslot_scale, d_stage_slot0,
-                  d_adj_runs};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  // every device table of a schedule lives in one allocation (see Packer)
+  if (d_blob) (void)hipFree(d_blob);
 }
+
+// Packs a schedule's host tables into one device allocation with a single copy: each table
+// starts on a 256-byte boundary, and its pointer is set to its place in the block.
+struct Packer {
+  std::vector<unsigned char> host;
+  std::vector<std::pair<size_t, void**>> dst;
+  template <typename V>
+  void add(const std::vector<V>& v, void** out) {
+    const size_t at = (host.size() + 255) & ~size_t(255);
+    host.resize(at + std::max<size_t>(v.size() * sizeof(V), 16), 0);
+    if (!v.empty()) std::memcpy(host.data() + at, v.data(), v.size() * sizeof(V));
+    dst.push_back({at, out});
+  }
+  tq_status upload(void** blob) {
+    void* d = nullptr;
+    TQ_HIP(hipMalloc(&d, std::max<size_t>(host.size(), 256)));
+    if (!host.empty()) TQ_HIP(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
+    *blob = d;
+    for (auto& e : dst) *e.second = (unsigned char*)d + e.first;
+    return TQ_OK;
+  }
+};
 
 tq_status scratch(tq_ctx* ctx, int slot, size_t bytes, void** out, bool zero) {
   if (bytes == 0) bytes = 256;
@@ -103,14 +122,6 @@ tq_status stage_upload(tq_ctx* ctx, int slot, const void* host, size_t bytes, hi
   return TQ_OK;
 }
 
-template <typename V>
-static tq_status to_device(const std::vector<V>& v, void** dev) {
-  size_t bytes = std::max<size_t>(v.size() * sizeof(V), 16);
-  TQ_HIP(hipMalloc(dev, bytes));
-  if (!v.empty()) TQ_HIP(hipMemcpy(*dev, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
-  return TQ_OK;
-}
-
 // Cache key of a schedule: the gate records themselves plus the shape (an exact key: two
 // structures share a schedule only if their bytes are equal).
 static std::string schedule_key(const tq_gate* g, int n_gates, int n, int mode, int t, int R, int c) {
@@ -120,9 +131,8 @@ static std::string schedule_key(const tq_gate* g, int n_gates, int n, int mode, 
   return k;
 }
 
-static tq_status upload_schedule(Schedule& s, const tq_gate* g, int n_gates) {
-  std::vector<tq_gate> gv(g, g + n_gates);
-  TQ_TRY(to_device(gv, &s.d_gates));
+static void pack_schedule(Schedule& s, const tq_gate* g, int n_gates, Packer& pk) {
+  pk.add(std::vector<tq_gate>(g, g + n_gates), &s.d_gates);
   std::vector<int32_t> rec, rg;
   for (const Recipe& r : s.recipes) {
     rec.push_back(r.kind);
@@ -132,12 +142,11 @@ static tq_status upload_schedule(Schedule& s, const tq_gate* g, int n_gates) {
     rg.insert(rg.end(), r.gates.begin(), r.gates.end());
   }
   rec.push_back(0); rec.push_back(0); rec.push_back(0); rec.push_back((int32_t)rg.size());  // sentinel
-  TQ_TRY(to_device(rec, &s.d_rec));
-  TQ_TRY(to_device(rg, &s.d_rec_gates));
-  TQ_TRY(to_device(s.dops, &s.d_ops));
-  TQ_TRY(to_device(s.phases, &s.d_phases));
-  TQ_TRY(to_device(s.dstages, &s.d_stages));
-  return TQ_OK;
+  pk.add(rec, &s.d_rec);
+  pk.add(rg, &s.d_rec_gates);
+  pk.add(s.dops, &s.d_ops);
+  pk.add(s.phases, &s.d_phases);
+  pk.add(s.dstages, &s.d_stages);
 }
 
 // Default fused shapes (the autotuner may override): 2^12-amplitude tiles (32 KiB of LDS for
@@ -186,7 +195,9 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
   s->n_gates = n_gates;
   lower_ops(g, n_gates, n, mode == 0, s->recipes, s->ops);
   if (mode == 0) build_stages(*s);
-  TQ_TRY(upload_schedule(*s, g, n_gates));
+  Packer pk;
+  pack_schedule(*s, g, n_gates, pk);
+  TQ_TRY(pk.upload(&s->d_blob));
   *out = s.get();
   ctx->schedules.emplace(key, std::move(s));
   return TQ_OK;
@@ -224,18 +235,20 @@ tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gate
   lower_adjoint_ops(g, n_gates, s->ops, s->adj_runs);
   build_stages(*s);
   build_adjoint_slots(*s, g, n_gates);
-  TQ_TRY(upload_schedule(*s, g, n_gates));
-  TQ_TRY(to_device(s->dslot, &s->d_dslot));
-  TQ_TRY(to_device(s->adj_runs, &s->d_adj_runs));
+  Packer pk;
+  pack_schedule(*s, g, n_gates, pk);
+  pk.add(s->dslot, &s->d_dslot);
+  pk.add(s->adj_runs, &s->d_adj_runs);
   std::vector<int32_t> slot_pairs;  // per stage: (first slot, slot count), read by batched launches
   for (size_t k = 0; k < s->stage_slot0.size(); ++k) {
     slot_pairs.push_back(s->stage_slot0[k]);
     slot_pairs.push_back(s->stage_nslot[k]);
   }
-  TQ_TRY(to_device(slot_pairs, &s->d_stage_slot0));
-  TQ_TRY(to_device(s->pslot_ptr, &s->d_pslot_ptr));
-  TQ_TRY(to_device(s->pslot_idx, &s->d_pslot_idx));
-  TQ_TRY(to_device(s->pslot_scale, &s->d_pslot_scale));
+  pk.add(slot_pairs, &s->d_stage_slot0);
+  pk.add(s->pslot_ptr, &s->d_pslot_ptr);
+  pk.add(s->pslot_idx, &s->d_pslot_idx);
+  pk.add(s->pslot_scale, &s->d_pslot_scale);
+  TQ_TRY(pk.upload(&s->d_blob));
   *out = s.get();
   ctx->schedules.emplace(key, std::move(s));
   return TQ_OK;

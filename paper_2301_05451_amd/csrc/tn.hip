@@ -1189,7 +1189,6 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg);
 
 template <typename T>
 static tq_status tn_forward_group(TnRun<T>& R) {
-  using C = typename Cx<T>::type;
   const tq_tn_plan* p = R.p;
   // sliced leaves: restrict each to the group's slices
   for (int li : p->sliced_leaves) {

@@ -152,6 +152,7 @@ struct Schedule {
   void* d_ops = nullptr;        // DevOp
   void* d_phases = nullptr;     // DevPhase
   void* d_stages = nullptr;     // DevStage
+  void* d_blob = nullptr;       // the one allocation holding all of the above
   int n_gates = 0;
   ~Schedule();
 };
