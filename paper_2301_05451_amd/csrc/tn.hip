@@ -501,6 +501,73 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// The same batched complex GEMM for complex128 on FP64 MFMA (16x16x4, double operands and
+// accumulation); identical tiling and real view, so the same size requirements.
+__global__ void __launch_bounds__(256)
+    tn_zgemm_mfma_kernel(const double2* __restrict__ A, int64_t as, const double2* __restrict__ B, int64_t bs,
+                         double2* __restrict__ Cm, int64_t cs, int M, int N, int K) {
+  __shared__ double sA[kGemmBK][kGemmBM + 2];   // [k][m]
+  __shared__ double sB[kGemmBK][kGemmBN + 2];   // [k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int m0 = blockIdx.y * kGemmBM;
+  const int n0c = blockIdx.x * (kGemmBN / 2);  // complex column
+  const double2* a = A + as * blockIdx.z;
+  const double2* b = B + bs * blockIdx.z;
+  double2* c = Cm + cs * blockIdx.z;
+  typedef double double4v __attribute__((ext_vector_type(4)));
+  double4v acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += kGemmBK / 2) {  // complex k
+    {
+      const int r = tid >> 2, kk = (tid & 3) * 2;
+      const double2 v0 = a[(int64_t)(m0 + r) * K + k0 + kk];
+      const double2 v1 = a[(int64_t)(m0 + r) * K + k0 + kk + 1];
+      sA[2 * kk + 0][r] = v0.x;
+      sA[2 * kk + 1][r] = v0.y;
+      sA[2 * kk + 2][r] = v1.x;
+      sA[2 * kk + 3][r] = v1.y;
+    }
+    {
+      const int kr = tid >> 5, cc = tid & 31;
+      const double2 v = b[(int64_t)(k0 + kr) * N + n0c + cc];
+      sB[2 * kr + 0][2 * cc + 0] = v.x;
+      sB[2 * kr + 0][2 * cc + 1] = v.y;
+      sB[2 * kr + 1][2 * cc + 0] = -v.y;
+      sB[2 * kr + 1][2 * cc + 1] = v.x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmBK; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = sA[kl][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = sB[kl][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of the FP64 16x16x4 (checked on the device; it differs from the FP32 one):
+  // lane l, register r -> row l/16 + 4 r, column l % 16
+  double* cf = reinterpret_cast<double*>(c);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * r;
+        const int col = 2 * n0c + wn + 16 * j + (lane & 15);
+        cf[(int64_t)row * (2 * N) + col] = acc[i][j][r];
+      }
+}
+
 // Sliced leaf restriction: out[g][j] = leaf[j with the sliced bits of slice s0+g inserted].
 template <typename T>
 __global__ void tn_slice_gather_kernel(const typename Cx<T>::type* __restrict__ leaf, typename Cx<T>::type* __restrict__ out,
@@ -690,7 +757,7 @@ static TnExec make_exec(const std::vector<int>& xi, const std::vector<int>& yi, 
   // GEMM eligibility: every Z index in exactly one of (X and Y) -> batch, or X only (M), or
   // Y only (N); every summed index in both (K); no broadcast.
   std::vector<int> bI, mI, nI, kI;
-  bool ok = allow_gemm && csz == 8;
+  bool ok = allow_gemm;  // FP32 MFMA for complex64, FP64 MFMA for complex128
   for (int id : zi) {
     const bool inx = pos_of(xi, id) >= 0, iny = pos_of(yi, id) >= 0;
     if (inx && iny) bI.push_back(id);
@@ -1225,7 +1292,7 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
     C* z = R.tptr(ex.z, &zs);
     const int64_t copies = p->t[ex.z].sdep ? R.g : 1;
     if (ex.method == 1) {
-      if constexpr (sizeof(T) == 4) {
+      {
         // permute X -> [b][m][k], Y -> [b][k][n] into the group's scratch, then GEMM per copy
         C* pbuf = R.ws + p->perm_off;
         const int64_t half = p->perm_elems / 2;
@@ -1251,10 +1318,15 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
         }
         TQ_HIP(hipGetLastError());
         for (int64_t c = 0; c < copies; ++c) {
-          hipLaunchKernelGGL(tn_cgemm_mfma_kernel, dim3((unsigned)(ex.N / 32), (unsigned)(ex.M / 64), (unsigned)ex.B),
-                             dim3(256), 0, R.st, (const float2*)(xa + xas * c), ex.M * ex.K,
-                             (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c), ex.M * ex.N, (int)ex.M,
-                             (int)ex.N, (int)ex.K);
+          const dim3 grid((unsigned)(ex.N / 32), (unsigned)(ex.M / 64), (unsigned)ex.B);
+          if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL(tn_cgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const float2*)(xa + xas * c),
+                               ex.M * ex.K, (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c),
+                               ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
+          else
+            hipLaunchKernelGGL(tn_zgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const double2*)(xa + xas * c),
+                               ex.M * ex.K, (const double2*)(ya + yas * c), ex.K * ex.N, (double2*)(z + zs * c),
+                               ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
         }
         TQ_HIP(hipGetLastError());
         return TQ_OK;

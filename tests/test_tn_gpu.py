@@ -119,22 +119,26 @@ def _gemm_network(rs, permuted):
     return (A, B, Cc), inds
 
 
+@pytest.mark.parametrize("c128", [False, True])
 @pytest.mark.parametrize("permuted", [False, True])
-def test_dense_step_on_mfma_gemm_path(permuted):
+def test_dense_step_on_mfma_gemm_path(permuted, c128):
+    """A dense step on the MFMA complex GEMM (FP32 for complex64, FP64 for complex128)."""
     from paper_2301_05451_amd import lib
 
     rs = np.random.default_rng(3)
     (A, B, Cc), inds = _gemm_network(rs, permuted)
-    plan = lib.TnPlan(inds, [(0, 1), (2, 3)])
+    plan = lib.TnPlan(inds, [(0, 1), (2, 3)], c128=c128)
     assert plan.info["gemm_steps"] == 1
-    leaves = torch.tensor(np.concatenate([A, B, Cc]), dtype=torch.complex64, device="cuda")
+    cdt = torch.complex128 if c128 else torch.complex64
+    tol = 1e-12 if c128 else 1e-5
+    leaves = torch.tensor(np.concatenate([A, B, Cc]), dtype=cdt, device="cuda")
     v = lib.tn_contract(plan, leaves).cpu().numpy()[0]
     At, Bt, Ct = A.reshape((2,) * 13), B.reshape((2,) * 12), Cc.reshape((2,) * 14)
     want = np.einsum(At, inds[0], Bt, inds[1], Ct, inds[2], [])
-    assert abs(v - want) / abs(want) <= 1e-5
-    env = lib.tn_backward(plan, leaves, torch.ones(1, device="cuda")).cpu().numpy()
+    assert abs(v - want) / abs(want) <= tol
+    env = lib.tn_backward(plan, leaves, torch.ones(1, dtype=cdt, device="cuda")).cpu().numpy()
     envA = np.einsum(Bt, inds[1], Ct, inds[2], inds[0]).reshape(-1)
-    assert np.abs(env[: 2 ** 13] - envA).max() / np.abs(envA).max() <= 1e-5
+    assert np.abs(env[: 2 ** 13] - envA).max() / np.abs(envA).max() <= tol
 
 
 def test_plan_validation():
