@@ -406,6 +406,24 @@ def bench_tn(steps):
                          "ms": round(ms, 3), "tflops": fl / (ms * 1e-3) / 1e12,
                          "mfma_frac_fp32": fl / (ms * 1e-3) / 157.3e12,
                          "sampled_rel_err": float(max(errs))}
+    # the same step in complex128 on FP64 MFMA (peak 78.6 TFLOP/s)
+    plan2 = lib.TnPlan([b + m + k, b + k + nn], [(0, 1)], out_inds=b + m + nn, c128=True)
+    leaves2 = leaves.to(torch.complex128)
+    work2 = torch.empty(max(plan2.workspace_bytes(False), 16), dtype=torch.uint8, device="cuda")
+    ms2 = _timed(lambda: lib.tn_contract(plan2, leaves2, work2), steps, 2)
+    C2 = lib.tn_contract(plan2, leaves2, work2).reshape(2, 1 << 12, 1 << 12)
+    A2 = leaves2[:plan2.leaf_offsets[1]].reshape(2, 1 << 12, 1 << 10)
+    B2 = leaves2[plan2.leaf_offsets[1]:].reshape(2, 1 << 10, 1 << 12)
+    errs2 = []
+    for _ in range(16):
+        bb, mm, nn_ = int(rs.integers(2)), int(rs.integers(1 << 12)), int(rs.integers(1 << 12))
+        a = A2[bb, mm].cpu().numpy()
+        bcol = B2[bb, :, nn_].cpu().numpy()
+        errs2.append(abs(complex(C2[bb, mm, nn_].item()) - np.dot(a, bcol)) /
+                     np.sqrt(np.sum(np.abs(a) ** 2) * np.sum(np.abs(bcol) ** 2)))
+    res["dense_step_c128"] = {"shape": "batch 2, M = N = 4096, K = 1024 complex128", "gemm_steps": plan2.info["gemm_steps"],
+                              "ms": round(ms2, 3), "tflops": fl / (ms2 * 1e-3) / 1e12,
+                              "mfma_frac_fp64": fl / (ms2 * 1e-3) / 78.6e12, "sampled_rel_err": float(max(errs2))}
     return res
 
 

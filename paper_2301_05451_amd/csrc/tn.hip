@@ -150,11 +150,15 @@ __device__ __forceinline__ void tn_build_tables(const DevTnStep* __restrict__ gs
     tx[i] = deposit_bits((uint64_t)i, st->xs, kt);
     ty[i] = deposit_bits((uint64_t)i, st->ys, kt);
   }
+  // only the entries an output index can select are built (2^z0 and 2^z1 of them; entry 0
+  // of the second table is 0 for outputs below 2^8)
   const int z0 = st->zr < 8 ? st->zr : 8;
   const int z1 = st->zr < 8 ? 0 : (st->zr < 16 ? st->zr - 8 : 8);
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+  for (int i = threadIdx.x; i < (1 << z0); i += blockDim.x) {
     L->ox[0][i] = deposit_bits((uint64_t)i, st->xo, z0);
     L->oy[0][i] = deposit_bits((uint64_t)i, st->yo, z0);
+  }
+  for (int i = threadIdx.x; i < (1 << z1); i += blockDim.x) {
     L->ox[1][i] = deposit_bits((uint64_t)i, st->xo + 8, z1);
     L->oy[1][i] = deposit_bits((uint64_t)i, st->yo + 8, z1);
   }
