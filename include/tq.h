@@ -242,6 +242,17 @@ tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const 
 tq_status tq_optimizer_step(tq_dtype dt, int32_t kind, void* d_params, const void* d_grad, void* d_m, void* d_v,
                             int32_t t, double lr, double beta1, double beta2, double eps, int64_t n, void* stream);
 
+/* tq_sv_backward for observables that are real combinations of Pauli strings with X, Y and
+ * Z factors (at most 16 terms): lambda = sum_o w_o O_o psi is formed from the strings
+ * directly, the reverse sweep is the same. The workspace is the size tq_sv_backward_workspace
+ * reports for the same batch and gate lists (the terms do not change it). Errors as
+ * tq_sv_backward. */
+tq_status tq_sv_backward_pauli(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                               const int32_t* n_params, const void* d_params, const void* d_states,
+                               const tq_pauli_term* terms, int32_t n_terms, int32_t n_obs, const void* d_grad_out,
+                               void* d_grad, const tq_sv_opts* opts, void* d_work, int64_t work_bytes,
+                               void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Compiled batches. The paper compiles a circuit once and evaluates it many times with new
  * parameters (Sec. 2, reusable objects), and runs one circuit over a batch of inputs with

@@ -229,9 +229,14 @@ def marginal_probs(psi, n, qubits):
     return np.transpose(m, [kept.index(q) for q in qubits]).reshape(-1)
 
 
-def circuit_f(c: W.Circuit, params=None, shift=None, init=None):
+def circuit_f(c: W.Circuit, params=None, shift=None, init=None, pauli=None):
+    """Outputs of the circuit's observable: its Z-string terms, or ``pauli`` (PAULI_DTYPE
+    records) when given."""
     p = c.params if params is None else params
-    return expvals(run(c.n, c.gates, p, init, shift), c.n, c.terms, c.n_obs)
+    psi = run(c.n, c.gates, p, init, shift)
+    if pauli is not None:
+        return pauli_expvals(psi, c.n, pauli, c.n_obs)
+    return expvals(psi, c.n, c.terms, c.n_obs)
 
 
 # ---- brute force -------------------------------------------------------------------
@@ -272,9 +277,10 @@ def full_unitary(n, gates, params):
 
 # ---- gradients ---------------------------------------------------------------------
 
-def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None):
+def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None, pauli=None):
     """d(sum_o w_o <O_o>)/d params by the shift rule of each gate (two-term, or four-term for
-    the controlled rotations), per parameter occurrence."""
+    the controlled rotations), per parameter occurrence; O_o from the Z-string terms or from
+    ``pauli``."""
     p = c.params if params is None else np.asarray(params, dtype=np.float64)
     w = np.ones(c.n_obs) if weights is None else np.asarray(weights, dtype=np.float64)
     grad = np.zeros(p.shape[0])
@@ -285,14 +291,14 @@ def param_shift_grad(c: W.Circuit, params=None, weights=None, init=None):
                 continue
             d = 0.0
             for s, coef in shift_rule(int(g["op"])):
-                fp = circuit_f(c, p, (k, j, s), init)
-                fm = circuit_f(c, p, (k, j, -s), init)
+                fp = circuit_f(c, p, (k, j, s), init, pauli)
+                fm = circuit_f(c, p, (k, j, -s), init, pauli)
                 d += coef * float(np.dot(w, fp - fm))
             grad[pi] += float(g["pscale"][j]) * d
     return grad
 
 
-def fd_grad(c: W.Circuit, params=None, weights=None, h=1e-5, init=None):
+def fd_grad(c: W.Circuit, params=None, weights=None, h=1e-5, init=None, pauli=None):
     """Central finite differences with respect to each parameter."""
     p = (c.params if params is None else np.asarray(params, dtype=np.float64)).copy()
     w = np.ones(c.n_obs) if weights is None else np.asarray(weights, dtype=np.float64)
@@ -300,5 +306,5 @@ def fd_grad(c: W.Circuit, params=None, weights=None, h=1e-5, init=None):
     for i in range(p.shape[0]):
         pp = p.copy(); pp[i] += h
         pm = p.copy(); pm[i] -= h
-        grad[i] = float(np.dot(w, circuit_f(c, pp, None, init) - circuit_f(c, pm, None, init))) / (2 * h)
+        grad[i] = float(np.dot(w, circuit_f(c, pp, None, init, pauli) - circuit_f(c, pm, None, init, pauli))) / (2 * h)
     return grad

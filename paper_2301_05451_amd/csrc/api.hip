@@ -434,11 +434,38 @@ static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // psi and lambda copies (one state each per circuit), the adjoint gate matrices and the
 // per-tile gradient partial sums. With d_work == nullptr only the schedules and tables are
 // prepared (cached in the context) and *need receives the workspace bytes.
+// Pauli terms of an observable over bit positions of an n-qubit index.
+static tq_status pauli_for_n(int n, const tq_pauli_term* pt, int n_pt, int n_obs, AdjPauli* out) {
+  if (n_pt < 0 || n_pt > kAdjPauliTerms || (n_pt > 0 && !pt))
+    return fail(TQ_EINVAL, "the backward pass takes 0.." + std::to_string(kAdjPauliTerms) + " Pauli terms");
+  *out = AdjPauli{};
+  out->n = n_pt;
+  for (int k = 0; k < n_pt; ++k) {
+    if (pt[k].obs < 0 || pt[k].obs >= n_obs) return fail(TQ_EINVAL, "term obs index out of range");
+    if (n < 64 && ((pt[k].x_mask | pt[k].z_mask) >> n) != 0) return fail(TQ_EINVAL, "term names a qubit >= n");
+    uint64_t f = 0, m = 0;
+    int ny = 0;
+    for (int q = 0; q < n; ++q) {
+      const bool xb = (pt[k].x_mask >> q) & 1ull, zb = (pt[k].z_mask >> q) & 1ull;
+      if (xb) f |= 1ull << (n - 1 - q);
+      if (zb) m |= 1ull << (n - 1 - q);
+      ny += xb && zb;
+    }
+    out->f[k] = f;
+    out->m[k] = m;
+    out->c[k] = pt[k].coeff;
+    out->ob[k] = pt[k].obs;
+    out->cls[k] = ny & 3;
+  }
+  return TQ_OK;
+}
+
 template <typename T>
 static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
                                const void* d_params, const void* d_states, const tq_zterm* terms, int n_terms,
                                int n_obs, const void* d_grad_out, void* d_grad, const tq_sv_opts* opts,
-                               void* d_work, int64_t work_bytes, int64_t* need, hipStream_t stream) {
+                               void* d_work, int64_t work_bytes, int64_t* need, hipStream_t stream,
+                               const tq_pauli_term* pterms = nullptr, int n_pterms = 0) {
   using C = typename Cx<T>::type;
   const int dt = sizeof(T) == 4 ? TQ_C64 : TQ_C128;
   const bool exec = d_work != nullptr || need == nullptr;
@@ -453,6 +480,7 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
     std::vector<int> mem;
     size_t psi, lam, mats, part;
     int n, n_params;
+    AdjPauli pauli;
   };
   std::vector<Run> runs;
   size_t ws = 256;
@@ -467,7 +495,8 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
       size_t i1 = i0 + 1;
       while (i1 < gr.members.size() && gr.members[i1] == gr.members[i1 - 1] + 1) ++i1;
       Run r{s, tt, std::vector<int>(gr.members.begin() + i0, gr.members.begin() + i1), 0, 0, 0, 0, gr.n,
-            gr.n_params};
+            gr.n_params, AdjPauli{}};
+      if (pterms) TQ_TRY(pauli_for_n(gr.n, pterms, n_pterms, n_obs, &r.pauli));
       const size_t count = r.mem.size();
       const int64_t namps = int64_t(1) << gr.n;
       const int64_t ntiles = s->stages.empty() ? 1 : (int64_t(1) << (gr.n - s->stages[0].t));
@@ -499,7 +528,7 @@ static tq_status sv_backward_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate
                              (double*)(w + r.part), (const uint64_t*)r.tt, (const double*)(r.tt + n_terms * 8),
                              (const int32_t*)(r.tt + n_terms * 16), n_terms,
                              (const T*)d_grad_out + (int64_t)r.mem[0] * n_obs, n_obs, (T*)d_grad, r.n_params,
-                             (int)r.mem.size(), stream));
+                             (int)r.mem.size(), stream, pterms ? &r.pauli : nullptr));
   }
   return TQ_OK;
 }
@@ -678,5 +707,23 @@ extern "C" tq_status tq_sv_backward(tq_ctx* ctx, tq_dtype dt, const tq_batch* ba
   if (dt == TQ_C128)
     return sv_backward_t<double>(ctx, batch, gates, n_params, d_params, d_states, terms, n_terms, n_obs, d_grad_out,
                                  d_grad, opts, d_work, work_bytes, nullptr, (hipStream_t)stream);
+  return fail(TQ_EINVAL, "unknown dtype");
+}
+
+extern "C" tq_status tq_sv_backward_pauli(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                                          const int32_t* n_params, const void* d_params, const void* d_states,
+                                          const tq_pauli_term* terms, int32_t n_terms, int32_t n_obs,
+                                          const void* d_grad_out, void* d_grad, const tq_sv_opts* opts, void* d_work,
+                                          int64_t work_bytes, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (!d_work) return fail(TQ_EWORKSPACE, "tq_sv_backward_pauli needs a workspace (size from tq_sv_backward_workspace)");
+  if (n_terms < 0 || n_terms > kAdjPauliTerms || (n_terms > 0 && !terms))
+    return fail(TQ_EINVAL, "the backward pass takes 0.." + std::to_string(kAdjPauliTerms) + " Pauli terms");
+  if (dt == TQ_C64)
+    return sv_backward_t<float>(ctx, batch, gates, n_params, d_params, d_states, nullptr, 0, n_obs, d_grad_out, d_grad,
+                                opts, d_work, work_bytes, nullptr, (hipStream_t)stream, terms, n_terms);
+  if (dt == TQ_C128)
+    return sv_backward_t<double>(ctx, batch, gates, n_params, d_params, d_states, nullptr, 0, n_obs, d_grad_out,
+                                 d_grad, opts, d_work, work_bytes, nullptr, (hipStream_t)stream, terms, n_terms);
   return fail(TQ_EINVAL, "unknown dtype");
 }

@@ -59,6 +59,45 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// lambda = sum_k w_{obs_k} coeff_k P_k psi for Pauli strings with X / Y factors, with
+// (P psi)_x = i^nY (-1)^{|(x ^ f) & m|} psi_{x ^ f} (f = flip mask, m = sign mask over bit
+// positions, nY = number of Y factors, all per term); psi copied to the working buffer.
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    adj_init_pauli_kernel(const typename Cx<T>::type* __restrict__ psi_in, BatchMap smap_in,
+                          typename Cx<T>::type* __restrict__ psi, typename Cx<T>::type* __restrict__ lam,
+                          BatchMap smap_w, int64_t namps, AdjPauli P, const T* __restrict__ grad_out, int n_obs) {
+  using C = typename Cx<T>::type;
+  const int circ = blockIdx.y;
+  const C* src = psi_in + smap_in.at(circ);
+  C* p = psi + smap_w.at(circ);
+  C* l = lam + smap_w.at(circ);
+  const T* w = grad_out + (int64_t)circ * n_obs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
+    double lr = 0.0, li = 0.0;
+    for (int k = 0; k < P.n; ++k) {
+      const uint64_t y = (uint64_t)i ^ P.f[k];
+      const C a = src[y];
+      double s = (double)w[P.ob[k]] * P.c[k];
+      if (__popcll(y & P.m[k]) & 1) s = -s;
+      // multiply a by s * i^cls
+      const double ar = (double)a.x, ai = (double)a.y;
+      switch (P.cls[k]) {
+        case 0: lr += s * ar; li += s * ai; break;
+        case 1: lr -= s * ai; li += s * ar; break;
+        case 2: lr -= s * ar; li -= s * ai; break;
+        default: lr += s * ai; li -= s * ar; break;
+      }
+    }
+    p[i] = src[i];
+    C b;
+    b.x = (T)lr;
+    b.y = (T)li;
+    l[i] = b;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ uint32_t adj_swz(uint32_t li) {
   constexpr int G = sizeof(T) == 4 ? 5 : 4;
@@ -474,7 +513,7 @@ template <typename T>
 tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap, const void* d_states_in,
                          BatchMap smap_in, void* psi, void* lam, BatchMap smap_w, void* mats, double* partial,
                          const uint64_t* pm, const double* cf, const int32_t* ob, int n_terms, const T* grad_out,
-                         int n_obs, T* grad, int n_params, int count, hipStream_t stream) {
+                         int n_obs, T* grad, int n_params, int count, hipStream_t stream, const AdjPauli* pauli) {
   using C = typename Cx<T>::type;
   const int n = s.n;
   const int64_t namps = int64_t(1) << n;
@@ -490,9 +529,14 @@ tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap,
     const int cn = std::min(65535, count - c0);
     int64_t b = (namps + 255) / 256;
     b = std::min<int64_t>(b, std::max<int64_t>(1, 4096 / cn));
-    hipLaunchKernelGGL(adj_init_kernel<T>, dim3((unsigned)b, cn), dim3(256), 0, stream, (const C*)d_states_in,
-                       smap_in.shifted(c0), (C*)psi, (C*)lam, smap_w.shifted(c0), namps, pm, cf, ob, n_terms,
-                       grad_out + (int64_t)c0 * n_obs, n_obs);
+    if (pauli)
+      hipLaunchKernelGGL(adj_init_pauli_kernel<T>, dim3((unsigned)b, cn), dim3(256), 0, stream, (const C*)d_states_in,
+                         smap_in.shifted(c0), (C*)psi, (C*)lam, smap_w.shifted(c0), namps, *pauli,
+                         grad_out + (int64_t)c0 * n_obs, n_obs);
+    else
+      hipLaunchKernelGGL(adj_init_kernel<T>, dim3((unsigned)b, cn), dim3(256), 0, stream, (const C*)d_states_in,
+                         smap_in.shifted(c0), (C*)psi, (C*)lam, smap_w.shifted(c0), namps, pm, cf, ob, n_terms,
+                         grad_out + (int64_t)c0 * n_obs, n_obs);
     TQ_HIP(hipGetLastError());
   }
   const int R = std::min(s.R, std::min(s.t, s.n));
@@ -647,9 +691,9 @@ template tq_status launch_batch_adjoint<double>(const BatchLaunch&, const void*,
 
 template tq_status launch_adjoint<float>(const Schedule&, const void*, BatchMap, const void*, BatchMap, void*, void*,
                                          BatchMap, void*, double*, const uint64_t*, const double*, const int32_t*, int,
-                                         const float*, int, float*, int, int, hipStream_t);
+                                         const float*, int, float*, int, int, hipStream_t, const AdjPauli*);
 template tq_status launch_adjoint<double>(const Schedule&, const void*, BatchMap, const void*, BatchMap, void*, void*,
                                           BatchMap, void*, double*, const uint64_t*, const double*, const int32_t*,
-                                          int, const double*, int, double*, int, int, hipStream_t);
+                                          int, const double*, int, double*, int, int, hipStream_t, const AdjPauli*);
 
 }  // namespace tq

@@ -477,11 +477,22 @@ tq_status launch_init_basis(void* d_states, BatchMap smap, int n, int count, int
                             hipStream_t stream);
 // sv_adjoint.hip
 constexpr int kAdjMatEntries = kAdjMatStride;
+constexpr int kAdjPauliTerms = 16;  // Pauli terms with X / Y factors per adjoint call
+struct AdjPauli {              // terms over bit positions of an n-qubit index
+  uint64_t f[kAdjPauliTerms];  // flip masks (X or Y)
+  uint64_t m[kAdjPauliTerms];  // sign masks (Y or Z)
+  double c[kAdjPauliTerms];    // coefficients
+  int32_t ob[kAdjPauliTerms];  // outputs
+  int32_t cls[kAdjPauliTerms]; // number of Y factors mod 4
+  int32_t n;
+};
+// pauli == nullptr: lambda from the Z-string terms (pm, cf, ob); else from the Pauli terms.
 template <typename T>
 tq_status launch_adjoint(const Schedule& s, const void* d_params, BatchMap pmap, const void* d_states_in,
                          BatchMap smap_in, void* psi, void* lam, BatchMap smap_w, void* mats, double* partial,
                          const uint64_t* pm, const double* cf, const int32_t* ob, int n_terms, const T* grad_out,
-                         int n_obs, T* grad, int n_params, int count, hipStream_t stream);
+                         int n_obs, T* grad, int n_params, int count, hipStream_t stream,
+                         const AdjPauli* pauli = nullptr);
 
 // expval.hip
 int expval_groups(int n, int cn);

@@ -328,6 +328,30 @@ def sv_backward(states, params, spec: BatchSpec, terms, n_obs, grad_out, mode=0,
     return grad
 
 
+_lib.tq_sv_backward_pauli.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
+                                      _vp, ct.POINTER(SvOpts), _vp, ct.c_int64, _vp]
+_lib.tq_sv_backward_pauli.restype = ct.c_int
+
+
+def sv_backward_pauli(states, params, spec: BatchSpec, pauli_terms, n_obs, grad_out, tile_bits=0, reg_bits=0,
+                      ctx=None):
+    """Adjoint gradients for Pauli-string observables (tq_sv_backward_pauli)."""
+    import torch
+    _check_tensors(states, params, spec)
+    ctx = ctx or context(states.device.index)
+    pt = np.ascontiguousarray(pauli_terms, dtype=W.PAULI_DTYPE)
+    grad_out = grad_out.to(device=params.device, dtype=params.dtype).contiguous()
+    grad = torch.empty_like(params)
+    o = _opts(0, tile_bits, reg_bits, 0)
+    need = sv_backward_workspace(states, spec, W.zterms([]), n_obs, 0, tile_bits, reg_bits, ctx)
+    work = torch.empty(need, dtype=torch.uint8, device=states.device)
+    check(_lib.tq_sv_backward_pauli(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data,
+                                    spec.n_params.ctypes.data, params.data_ptr(), states.data_ptr(), pt.ctypes.data,
+                                    int(pt.shape[0]), int(n_obs), grad_out.data_ptr(), grad.data_ptr(), ct.byref(o),
+                                    work.data_ptr(), ct.c_int64(work.numel()), _stream()))
+    return grad
+
+
 def sv_backward_workspace(states, spec: BatchSpec, terms, n_obs, mode=0, tile_bits=0, reg_bits=0, ctx=None):
     """Workspace bytes tq_sv_backward needs for this batch (tq_sv_backward_workspace)."""
     ctx = ctx or context(states.device.index)

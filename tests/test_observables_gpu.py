@@ -154,3 +154,31 @@ def test_tn_with_controlled_rotations():
         assert abs(v.real - want) <= 1e-12 and abs(v.imag) <= 1e-12
         c.terms, c.n_obs = W.zterms([(zq, 1.0, 0)]), 1
         assert np.abs(prog.grad(p).cpu().numpy() - osv.param_shift_grad(c)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_adjoint_gradients_of_pauli_observables(c128):
+    """tq_sv_backward_pauli against the oracle's parameter-shift rule for X/Y/Z strings
+    (including controlled rotations, four-term rule) over two outputs with weights."""
+    from paper_2301_05451_amd import lib
+
+    cdt, rdt = _types(c128)
+    rng = np.random.default_rng(860)
+    pt = W.pauli_terms([({0: "X", 1: "Y"}, 0.8, 0), ({1: "Z"}, -0.5, 0), ({0: "Y", 2: "X"}, 1.1, 1),
+                        ({2: "Y"}, 0.3, 1)])
+    w = np.array([[0.9, -1.2]])
+    scale = 0.9 * (0.8 + 0.5) + 1.2 * (1.1 + 0.3)
+    for n in (3, 6, 11):
+        c = W.random_circuit(n, 40, rng, ops=OPS, n_params=9)
+        c.n_obs = 2
+        spec = lib.BatchSpec.from_circuits([c])
+        p = torch.tensor(c.params, dtype=rdt, device="cuda")
+        psi = lib.zero_states(spec, cdt)
+        lib.sv_apply(psi, p, spec)
+        f = lib.expval_pauli(psi, spec, pt, 2).cpu().numpy()[0]
+        want_f = osv.pauli_expvals(osv.run(n, c.gates, c.params), n, pt, 2)
+        assert np.abs(f - want_f).max() <= TOL[c128] * 2.7
+        g = lib.sv_backward_pauli(psi, p, spec, pt, 2, torch.tensor(w, dtype=rdt, device="cuda")).cpu().numpy()
+        gw = osv.param_shift_grad(c, weights=w[0], pauli=pt)
+        print(f"pauli adjoint n={n} c128={c128}: max|d grad| = {np.abs(g - gw).max():.2e}", flush=True)
+        assert np.abs(g - gw).max() <= TOL[c128] * scale

@@ -304,3 +304,22 @@ def test_marginal_probabilities():
     assert np.allclose(p02.reshape(2, 2), p20.reshape(2, 2).T, atol=1e-16)
     ghz = np.zeros(2 ** n); ghz[0] = ghz[-1] = 1 / math.sqrt(2)
     assert np.allclose(sv.marginal_probs(ghz, n, [1, 3]), [0.5, 0, 0, 0.5], atol=1e-16)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_param_shift_for_pauli_observables_vs_fd(seed):
+    rng = np.random.default_rng(700 + seed)
+    n = 3
+    c = W.random_circuit(n, 14, rng, n_params=5)
+    c.n_obs = 2
+    pt = W.pauli_terms([({0: "X", 1: "Y"}, 0.8, 0), ({2: "Y"}, -0.5, 1), ({0: "Z", 2: "X"}, 1.1, 1)])
+    w = np.array([1.3, -0.4])
+    assert np.allclose(sv.param_shift_grad(c, weights=w, pauli=pt), sv.fd_grad(c, weights=w, pauli=pt), atol=1e-8)
+
+
+def test_pauli_gradient_closed_form():
+    # RY(theta) on |0>: <X> = sin(theta), d/dtheta = cos(theta)
+    t = 0.9
+    c = W.Circuit(1, W.GateList().add(W.RY, [0], [0]).array(), np.array([t]), 1)
+    g = sv.param_shift_grad(c, pauli=W.pauli_terms([({0: "X"}, 1.0, 0)]))
+    assert abs(g[0] - math.cos(t)) < 1e-14
