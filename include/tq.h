@@ -189,6 +189,15 @@ typedef struct {
 tq_status tq_expval_pauli(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const void* d_states,
                           const tq_pauli_term* terms, int32_t n_terms, int32_t n_obs, void* d_out, void* stream);
 
+/* Host only: Pauli decomposition of a Hermitian matrix `herm` (2^k x 2^k complex, row-major,
+ * interleaved doubles; row index with qubits[0] as its most significant bit) on the k <= 6
+ * listed qubits: H = sum_P c_P P, c_P = Tr(P H) / 2^k. Writes the strings with |c_P| > tol as
+ * terms of output `obs` to `out` (capacity `cap`; NULL to count) and returns their number,
+ * or -1 (tq_last_error) on bad arguments or too small a capacity. With tq_expval_pauli this
+ * gives <psi|H|psi> for a general Hermitian observable. */
+int32_t tq_pauli_decompose(const double* herm, int32_t k, const int32_t* qubits, double tol, int32_t obs,
+                           tq_pauli_term* out, int32_t cap);
+
 /* Sec. 5.1.1 probability measurement: d_out[i * 2^n_sel + y] = probability that the listed
  * qubits read y (qubits[0] is the most significant bit of y), i.e. the sum of |psi_i|^2 over
  * every other qubit (the state is used as given, not normalised). 1 <= n_sel <= 24, at most

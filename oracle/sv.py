@@ -242,24 +242,23 @@ def circuit_f(c: W.Circuit, params=None, shift=None, init=None, pauli=None):
 # ---- brute force -------------------------------------------------------------------
 
 def embed(n, U, qubits):
-    """Full 2**n x 2**n matrix of U acting on ``qubits`` (textbook kron construction)."""
+    """Full 2**n x 2**n matrix of U acting on ``qubits`` (textbook kron construction; the first
+    listed qubit is the high bit of U's index)."""
     k = len(qubits)
     if k == 1:
         q = qubits[0]
         return np.kron(np.kron(np.eye(2**q), U), np.eye(2 ** (n - q - 1)))
-    # two qubits: expand U = sum_{ab,cd} U[ab,cd] |ab><cd| as a sum of kron products
+    # expand U = sum_{r,s} U[r,s] |r><s| as a sum of kron products of one-qubit |r_j><s_j|
     full = np.zeros((2**n, 2**n), dtype=np.complex128)
-    qa, qb = qubits
-    for r in range(4):
-        for s in range(4):
+    for r in range(2**k):
+        for s in range(2**k):
             if U[r, s] == 0:
                 continue
             ops = [np.eye(2, dtype=np.complex128)] * n
-            ea = np.zeros((2, 2)); ea[r >> 1, s >> 1] = 1
-            eb = np.zeros((2, 2)); eb[r & 1, s & 1] = 1
-            ops = list(ops)
-            ops[qa] = ea
-            ops[qb] = eb
+            for j, q in enumerate(qubits):
+                e = np.zeros((2, 2))
+                e[(r >> (k - 1 - j)) & 1, (s >> (k - 1 - j)) & 1] = 1
+                ops[q] = e
             m = ops[0]
             for o in ops[1:]:
                 m = np.kron(m, o)

@@ -344,3 +344,69 @@ extern "C" tq_status tq_probs(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, c
   if (dt == TQ_C128) return probs_t<double>(ctx, batch, d_states, qubits, n_sel, d_out, (hipStream_t)stream);
   return fail(TQ_EINVAL, "unknown dtype");
 }
+
+// Pauli decomposition of a Hermitian matrix on k qubits: H = sum_P c_P P with
+// c_P = Tr(P H) / 2^k, real for Hermitian H (host only).
+extern "C" int32_t tq_pauli_decompose(const double* herm, int32_t k, const int32_t* qubits, double tol, int32_t obs,
+                                      tq_pauli_term* out, int32_t cap) {
+  if (!herm || !qubits || k < 1 || k > 6) {
+    fail(TQ_EINVAL, "tq_pauli_decompose: 1..6 qubits and a matrix are required");
+    return -1;
+  }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < i; ++j)
+      if (qubits[i] == qubits[j] || qubits[i] < 0 || qubits[i] > 63) {
+        fail(TQ_EINVAL, "tq_pauli_decompose: qubits must be distinct and in 0..63");
+        return -1;
+      }
+  const int dim = 1 << k;
+  int count = 0;
+  // string s: digit j (base 4) is the factor on qubits[j]: 0 I, 1 X, 2 Y, 3 Z; the matrix
+  // index has qubits[0] as its most significant bit
+  for (int s = 0; s < (1 << (2 * k)); ++s) {
+    double re = 0.0, im = 0.0;
+    // Tr(P H) = sum_{a,b} P[a][b] H[b][a]; P[a][b] = prod_j p_j[a_j][b_j]
+    for (int a = 0; a < dim; ++a) {
+      int b = 0;
+      double pr = 1.0, pi = 0.0;  // P[a][b] for the unique b with a nonzero entry
+      for (int j = 0; j < k; ++j) {
+        const int d = (s >> (2 * j)) & 3;
+        const int bit = k - 1 - j;
+        const int aj = (a >> bit) & 1;
+        int bj = aj;
+        double fr = 1.0, fi = 0.0;
+        if (d == 1) bj = 1 - aj;                                  // X
+        else if (d == 2) { bj = 1 - aj; fr = 0.0; fi = aj ? 1.0 : -1.0; }  // Y: [[0,-i],[i,0]]
+        else if (d == 3) fr = aj ? -1.0 : 1.0;                     // Z
+        b |= bj << bit;
+        const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
+        pr = nr;
+        pi = ni;
+      }
+      const double hr = herm[2 * (b * dim + a)], hi = herm[2 * (b * dim + a) + 1];
+      re += pr * hr - pi * hi;
+      im += pr * hi + pi * hr;
+    }
+    (void)im;  // zero for a Hermitian H
+    const double c = re / dim;
+    if (std::abs(c) <= tol) continue;
+    if (out && count < cap) {
+      tq_pauli_term t{};
+      for (int j = 0; j < k; ++j) {
+        const int d = (s >> (2 * j)) & 3;
+        const uint64_t bit = 1ull << qubits[j];
+        if (d == 1 || d == 2) t.x_mask |= bit;
+        if (d == 2 || d == 3) t.z_mask |= bit;
+      }
+      t.coeff = c;
+      t.obs = obs;
+      out[count] = t;
+    }
+    ++count;
+  }
+  if (out && count > cap) {
+    fail(TQ_ESIZE, "tq_pauli_decompose: capacity " + std::to_string(cap) + " < " + std::to_string(count));
+    return -1;
+  }
+  return count;
+}

@@ -280,6 +280,30 @@ def optimizer_step(params, grad, lr, step=1, m=None, v=None, adam=False, beta1=0
     return params
 
 
+_lib.tq_pauli_decompose.argtypes = [_vp, _i32, _vp, ct.c_double, _i32, _vp, _i32]
+_lib.tq_pauli_decompose.restype = ct.c_int32
+
+
+def pauli_decompose(herm, qubits, obs=0, tol=1e-14):
+    """Pauli terms of a Hermitian matrix on ``qubits`` (tq_pauli_decompose)."""
+    h = np.ascontiguousarray(np.asarray(herm, dtype=np.complex128)).view(np.float64)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    n = _lib.tq_pauli_decompose(h.ctypes.data, int(q.shape[0]), q.ctypes.data, float(tol), int(obs), None, 0)
+    if n < 0:
+        raise TQError(1, last_error())
+    out = np.zeros(n, dtype=W.PAULI_DTYPE)
+    if n:
+        check(0 if _lib.tq_pauli_decompose(h.ctypes.data, int(q.shape[0]), q.ctypes.data, float(tol), int(obs),
+                                           out.ctypes.data, n) == n else 1)
+    return out
+
+
+def expval_hermitian(states, spec: BatchSpec, herm, qubits, ctx=None):
+    """[count] <psi|H|psi> for a Hermitian matrix H on the listed qubits (decomposition +
+    tq_expval_pauli)."""
+    return expval_pauli(states, spec, pauli_decompose(herm, qubits), 1, ctx)[:, 0]
+
+
 def lower_gates(gates):
     """The gate list as the kernels apply it (tq_lower_gates: controlled rotations lowered)."""
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)

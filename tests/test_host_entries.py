@@ -1,0 +1,47 @@
+"""CPU checks of the library's host-only entry points against the oracle: the Pauli
+decomposition of a Hermitian observable (its terms rebuild the observable's expectation value
+on random states) and the lowering of controlled rotations."""
+import numpy as np
+import pytest
+
+from oracle import sv as osv
+from paper_2301_05451_amd import workloads as W
+
+
+def _hermitian(rng, k):
+    a = rng.normal(size=(1 << k, 1 << k)) + 1j * rng.normal(size=(1 << k, 1 << k))
+    return a + a.conj().T
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_pauli_decomposition_rebuilds_the_observable(k):
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(900 + k)
+    n = 6
+    for _ in range(3):
+        h = _hermitian(rng, k)
+        qs = [int(q) for q in rng.choice(n, size=k, replace=False)]
+        terms = lib.pauli_decompose(h, qs, obs=2)
+        assert len(terms) <= 4 ** k and (terms["obs"] == 2).all()
+        big = osv.embed(n, h, qs)
+        for _ in range(3):
+            psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+            psi /= np.linalg.norm(psi)
+            want = osv.expval_hermitian(psi, big)
+            got = osv.pauli_expvals(psi, n, terms, 3)[2]
+            assert abs(got - want) <= 1e-12 * max(1.0, np.abs(h).sum())
+
+
+def test_pauli_decomposition_of_known_matrices():
+    from paper_2301_05451_amd import lib
+
+    x = np.array([[0, 1], [1, 0]], dtype=complex)
+    z = np.diag([1.0, -1.0]).astype(complex)
+    t = lib.pauli_decompose(np.kron(x, z) * 0.5 + np.eye(4), [4, 1])
+    got = {(int(r["x"]), int(r["z"])): float(r["coeff"]) for r in t}
+    # X on qubit 4 (first listed), Z on qubit 1, and the identity
+    assert got == {(1 << 4, 1 << 1): 0.5, (0, 0): 1.0}
+    assert len(lib.pauli_decompose(np.zeros((2, 2)), [0])) == 0
+    with pytest.raises(lib.TQError):
+        lib.pauli_decompose(np.eye(4), [1, 1])

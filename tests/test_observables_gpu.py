@@ -182,3 +182,28 @@ def test_adjoint_gradients_of_pauli_observables(c128):
         gw = osv.param_shift_grad(c, weights=w[0], pauli=pt)
         print(f"pauli adjoint n={n} c128={c128}: max|d grad| = {np.abs(g - gw).max():.2e}", flush=True)
         assert np.abs(g - gw).max() <= TOL[c128] * scale
+
+
+@pytest.mark.parametrize("c128", [False, True])
+def test_hermitian_observable_vs_oracle(c128):
+    # a general Hermitian observable on 3 qubits, decomposed into Pauli strings by the library
+    # and measured on the device, against <psi|O|psi> with the full matrix on the host
+    from paper_2301_05451_amd import lib
+
+    cdt, rdt = _types(c128)
+    rng = np.random.default_rng(850)
+    n = 7
+    circs = [W.random_circuit(n, 40, rng) for _ in range(3)]
+    spec = lib.BatchSpec.from_circuits(circs)
+    psi = lib.zero_states(spec, cdt)
+    lib.sv_apply(psi, torch.tensor(np.concatenate([c.params for c in circs]), dtype=rdt, device="cuda"), spec)
+    a = rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))
+    h = a + a.conj().T
+    qs = [5, 0, 3]
+    got = lib.expval_hermitian(psi, spec, h, qs).cpu().numpy()
+    host = psi.cpu().numpy().astype(np.complex128)
+    big = osv.embed(n, h, qs)
+    for i in range(3):
+        o = int(spec.state_off[i])
+        want = osv.expval_hermitian(host[o:o + (1 << n)], big)
+        assert abs(got[i] - want) <= TOL[c128] * np.abs(h).sum(), (i, got[i], want)
