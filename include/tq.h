@@ -150,9 +150,12 @@ tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_
 tq_status tq_sv_init(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, int64_t basis, void* d_states,
                      void* stream);
 
-/* Shape of the schedule tq_sv_apply uses for one circuit structure (host only, builds and
- * caches it like tq_sv_apply does). out[0] = HBM sweeps (kernel launches: stages in fused
- * mode, ops in plain mode), out[1] = scheduled ops after fusion, out[2] = register phases,
+/* Shape of the schedule tq_sv_apply uses for one circuit structure (opts->mode 0 or 1), or
+ * of the reverse-sweep schedule tq_sv_backward uses (opts->mode 2). Host only: with a
+ * context a forward schedule is built and cached (with its device tables) as tq_sv_apply
+ * does; with ctx == NULL, or in mode 2, it is built on the host, measured and dropped.
+ * out[0] = HBM sweeps (kernel launches: stages in fused and reverse modes, ops in plain
+ * mode), out[1] = scheduled ops after fusion, out[2] = register phases,
  * out[3] = LDS exchanges, out[4] = tile bits used, out[5] = register bits used,
  * out[6] = real flops per amplitude summed over ops (14 per 2x2, 6 per diagonal, 0 for
  * CNOT/CZ), out[7] = one-qubit matrices built per circuit. */
@@ -359,11 +362,14 @@ typedef struct {
  * The batched calls (tq_tn_*_batch) always recompute. */
 enum { TQ_TN_RECOMPUTE = 0, TQ_TN_STORE = 1, TQ_TN_AUTO = 2 };
 
-/* Host-only: classifies every step (batch / contracted / kept / summed-out indices), picks
- * its kernel (direct bit-indexed contraction, or bit-permute + FP32-MFMA complex GEMM when
- * M, N, K are all large), and sizes the workspace. Errors: TQ_EINVAL if the tree does not
- * use every leaf exactly once, an id is out of range, or the result's open indices differ
- * from out_inds as a set. */
+/* Host-side planning: classifies every step (batch / contracted / kept / summed-out
+ * indices), picks its kernel (direct bit-indexed contraction, or bit-permute + MFMA complex
+ * GEMM, FP32 for complex64 and FP64 for complex128, when M, N, K are all large), sizes the
+ * workspace, then copies the step tables to the context's device. With ctx == NULL the plan
+ * is built on the host only: the query calls below (stores, segments, leaf offsets,
+ * workspace, info) work on it, and every call that would run it fails with TQ_EINVAL.
+ * Errors: TQ_EINVAL if the tree does not use every leaf exactly once, an id is out of
+ * range, or the result's open indices differ from out_inds as a set. */
 tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* desc, tq_tn_plan** out);
 void tq_tn_plan_destroy(tq_tn_plan* plan);
 /* 1 if tq_tn_backward of this plan reuses the forward's stored intermediates (the store

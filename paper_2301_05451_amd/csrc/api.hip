@@ -159,27 +159,46 @@ static void default_shape(int dt, int n, int* t, int* R, int* c) {
   if (*t > n) *t = n;
 }
 
+// Resolved and checked (tile, register, coalesced) bits of a forward schedule.
+static tq_status forward_shape(size_t lds_max, int dt, int n, int mode, const tq_sv_opts* opts, int* t, int* R,
+                               int* c) {
+  default_shape(dt, n, t, R, c);
+  if (opts) {
+    if (opts->tile_bits) *t = std::min(opts->tile_bits, n);
+    if (opts->reg_bits) *R = opts->reg_bits;
+    if (opts->coal_bits) *c = opts->coal_bits;
+  }
+  if (mode != 0) {
+    *t = *R = *c = 0;
+    return TQ_OK;
+  }
+  const size_t csz = dt == TQ_C64 ? 8 : 16;
+  if (*t < 1 || *t > 14 || (csz << *t) > lds_max)
+    return fail(TQ_EINVAL, "tile_bits " + std::to_string(*t) + " does not fit LDS for this dtype");
+  if (*R < 1 || *R > 5) return fail(TQ_EINVAL, "reg_bits must be in 1..5");
+  if (dt == TQ_C128 && *R > 4) return fail(TQ_EINVAL, "reg_bits must be <= 4 for complex128 (register file)");
+  // the stage kernels are compiled for work-groups of at most 512 threads
+  if (*t - std::min(*R, *t) > 9) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 9 (512 threads)");
+  if (*c < 0 || *c > 10) return fail(TQ_EINVAL, "coal_bits must be in 0..10");
+  return TQ_OK;
+}
+
+// Host construction of a forward schedule of a checked shape (no device copies).
+static void build_schedule(const tq_gate* g, int n_gates, int n, int mode, int t, int R, int c, Schedule& s) {
+  s.n = n;
+  s.mode = mode;
+  s.t = t;
+  s.R = R;
+  s.c = c;
+  s.n_gates = n_gates;
+  lower_ops(g, n_gates, n, mode == 0, s.recipes, s.ops);
+  if (mode == 0) build_stages(s);
+}
+
 tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, int mode, const tq_sv_opts* opts,
                        Schedule** out) {
   int t, R, c;
-  default_shape(dt, n, &t, &R, &c);
-  if (opts) {
-    if (opts->tile_bits) t = std::min(opts->tile_bits, n);
-    if (opts->reg_bits) R = opts->reg_bits;
-    if (opts->coal_bits) c = opts->coal_bits;
-  }
-  if (mode == 0) {
-    const size_t csz = dt == TQ_C64 ? 8 : 16;
-    if (t < 1 || t > 14 || (csz << t) > ctx->lds_max)
-      return fail(TQ_EINVAL, "tile_bits " + std::to_string(t) + " does not fit LDS for this dtype");
-    if (R < 1 || R > 5) return fail(TQ_EINVAL, "reg_bits must be in 1..5");
-    if (dt == TQ_C128 && R > 4) return fail(TQ_EINVAL, "reg_bits must be <= 4 for complex128 (register file)");
-    // the stage kernels are compiled for work-groups of at most 512 threads
-    if (t - std::min(R, t) > 9) return fail(TQ_EINVAL, "tile_bits - reg_bits must be <= 9 (512 threads)");
-    if (c < 0 || c > 10) return fail(TQ_EINVAL, "coal_bits must be in 0..10");
-  } else {
-    t = R = c = 0;
-  }
+  TQ_TRY(forward_shape(ctx->lds_max, dt, n, mode, opts, &t, &R, &c));
   std::string key = schedule_key(g, n_gates, n, mode, t, R, c);
   auto it = ctx->schedules.find(key);
   if (it != ctx->schedules.end()) {
@@ -187,14 +206,7 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
     return TQ_OK;
   }
   auto s = std::make_unique<Schedule>();
-  s->n = n;
-  s->mode = mode;
-  s->t = t;
-  s->R = R;
-  s->c = c;
-  s->n_gates = n_gates;
-  lower_ops(g, n_gates, n, mode == 0, s->recipes, s->ops);
-  if (mode == 0) build_stages(*s);
+  build_schedule(g, n_gates, n, mode, t, R, c, *s);
   Packer pk;
   pack_schedule(*s, g, n_gates, pk);
   TQ_TRY(pk.upload(&s->d_blob));
@@ -203,21 +215,44 @@ tq_status get_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n
   return TQ_OK;
 }
 
+// Resolved and checked shape of a reverse-sweep schedule (two tiles in LDS).
+static tq_status adjoint_shape(size_t lds_max, int dt, int n, const tq_sv_opts* opts, int* t, int* R, int* c) {
+  *t = dt == TQ_C64 ? 12 : 11;
+  *R = dt == TQ_C64 ? 4 : 3;
+  *c = dt == TQ_C64 ? 5 : 4;
+  if (opts) {
+    if (opts->tile_bits) *t = opts->tile_bits;
+    if (opts->reg_bits) *R = opts->reg_bits;
+    if (opts->coal_bits) *c = opts->coal_bits;
+  }
+  *t = std::min(*t, n);
+  const size_t csz = dt == TQ_C64 ? 8 : 16;
+  if (*t < 1 || *t > 13 || 2 * (csz << *t) + 16384 > lds_max)
+    return fail(TQ_EINVAL, "adjoint tile_bits " + std::to_string(*t) + " does not fit LDS (two tiles)");
+  if (*R < 1 || *R > 4) return fail(TQ_EINVAL, "adjoint reg_bits must be in 1..4");
+  if (*t - std::min(*R, *t) > 9) return fail(TQ_EINVAL, "adjoint tile_bits - reg_bits must be <= 9 (512 threads)");
+  return TQ_OK;
+}
+
+// Host construction of a reverse-sweep schedule of a checked shape (no device copies).
+static void build_adjoint_schedule(const tq_gate* g, int n_gates, int n, int t, int R, int c, Schedule& s) {
+  s.n = n;
+  s.mode = 2;
+  s.adjoint = true;
+  s.t = t;
+  s.R = R;
+  s.c = c;
+  s.n_gates = n_gates;
+  lower_adjoint_ops(g, n_gates, s.ops, s.adj_runs);
+  build_stages(s);
+  build_adjoint_slots(s, g, n_gates);
+}
+
 // Reverse-sweep schedule of a circuit structure (cached; key mode 2).
 tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gates, int n, const tq_sv_opts* opts,
                                Schedule** out) {
-  int t = dt == TQ_C64 ? 12 : 11, R = dt == TQ_C64 ? 4 : 3, c = dt == TQ_C64 ? 5 : 4;
-  if (opts) {
-    if (opts->tile_bits) t = opts->tile_bits;
-    if (opts->reg_bits) R = opts->reg_bits;
-    if (opts->coal_bits) c = opts->coal_bits;
-  }
-  t = std::min(t, n);
-  const size_t csz = dt == TQ_C64 ? 8 : 16;
-  if (t < 1 || t > 13 || 2 * (csz << t) + 16384 > ctx->lds_max)
-    return fail(TQ_EINVAL, "adjoint tile_bits " + std::to_string(t) + " does not fit LDS (two tiles)");
-  if (R < 1 || R > 4) return fail(TQ_EINVAL, "adjoint reg_bits must be in 1..4");
-  if (t - std::min(R, t) > 9) return fail(TQ_EINVAL, "adjoint tile_bits - reg_bits must be <= 9 (512 threads)");
+  int t, R, c;
+  TQ_TRY(adjoint_shape(ctx->lds_max, dt, n, opts, &t, &R, &c));
   std::string key = schedule_key(g, n_gates, n, 2, t, R, c);
   auto it = ctx->schedules.find(key);
   if (it != ctx->schedules.end()) {
@@ -225,16 +260,7 @@ tq_status get_adjoint_schedule(tq_ctx* ctx, int dt, const tq_gate* g, int n_gate
     return TQ_OK;
   }
   auto s = std::make_unique<Schedule>();
-  s->n = n;
-  s->mode = 2;
-  s->adjoint = true;
-  s->t = t;
-  s->R = R;
-  s->c = c;
-  s->n_gates = n_gates;
-  lower_adjoint_ops(g, n_gates, s->ops, s->adj_runs);
-  build_stages(*s);
-  build_adjoint_slots(*s, g, n_gates);
+  build_adjoint_schedule(g, n_gates, n, t, R, c, *s);
   Packer pk;
   pack_schedule(*s, g, n_gates, pk);
   pk.add(s->dslot, &s->d_dslot);
@@ -636,15 +662,28 @@ tq_status tq_sv_init(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, int64_t ba
 
 tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_gate* gates, int32_t n_gates,
                           const tq_sv_opts* opts, int64_t out[8]) {
-  if (!ctx || !out) return fail(TQ_EINVAL, "null argument");
+  if (!out) return fail(TQ_EINVAL, "null argument");
   if (dt != TQ_C64 && dt != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
   if (n_qubits < 1 || n_qubits > 34) return fail(TQ_ENOTSUP, "n_qubits must be in 1..34");
   TQ_TRY(validate_gates(gates, n_gates, n_qubits, 0x7fffffff));
   const int mode = opts ? opts->mode : 0;
-  if (mode != 0 && mode != 1) return fail(TQ_ENOTSUP, "sv mode must be 0 (fused) or 1 (plain)");
+  if (mode < 0 || mode > 2) return fail(TQ_ENOTSUP, "plan mode must be 0 (fused), 1 (plain) or 2 (reverse sweep)");
   const GateView gv(gates, n_gates);
-  Schedule* s;
-  TQ_TRY(get_schedule(ctx, dt, gv.g, gv.n, n_qubits, mode, opts, &s));
+  const size_t lds_max = ctx ? ctx->lds_max : 160 * 1024;
+  Schedule local;
+  const Schedule* s = &local;
+  int t, R, c;
+  if (mode == 2) {
+    TQ_TRY(adjoint_shape(lds_max, dt, n_qubits, opts, &t, &R, &c));
+    build_adjoint_schedule(gv.g, gv.n, n_qubits, t, R, c, local);
+  } else if (ctx) {
+    Schedule* cached;
+    TQ_TRY(get_schedule(ctx, dt, gv.g, gv.n, n_qubits, mode, opts, &cached));
+    s = cached;
+  } else {
+    TQ_TRY(forward_shape(lds_max, dt, n_qubits, mode, opts, &t, &R, &c));
+    build_schedule(gv.g, gv.n, n_qubits, mode, t, R, c, local);
+  }
   int64_t flops = 0, mats = 0;
   for (const HostOp& o : s->ops) {
     if (o.kind == K_MAT1) flops += 14, ++mats;
@@ -653,12 +692,12 @@ tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_g
   int64_t xch = 0;
   for (const DevPhase& p : s->phases) xch += p.xchg;
   for (const DevStage& d : s->dstages) xch += d.store_xchg;
-  out[0] = mode == 0 ? (int64_t)s->stages.size() : (int64_t)s->ops.size();
+  out[0] = mode != 1 ? (int64_t)s->stages.size() : (int64_t)s->ops.size();
   out[1] = (int64_t)s->ops.size();
   out[2] = (int64_t)s->phases.size();
   out[3] = xch;
-  out[4] = mode == 0 ? std::min(s->t, n_qubits) : 0;
-  out[5] = mode == 0 ? std::min(s->R, std::min(s->t, n_qubits)) : 0;
+  out[4] = mode != 1 ? std::min(s->t, n_qubits) : 0;
+  out[5] = mode != 1 ? std::min(s->R, std::min(s->t, n_qubits)) : 0;
   out[6] = flops;
   out[7] = mats;
   return TQ_OK;

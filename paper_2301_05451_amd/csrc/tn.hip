@@ -104,6 +104,7 @@ struct tq_tn_plan {
   void* d_leaf_env = nullptr;          // (leaf offset, environment offset, elements) of unsliced leaves
   int n_leaf_env = 0;
   bool store = false;                  // the reverse pass reuses the forward's intermediates
+  bool host_only = false;              // built without a context: no device tables, cannot run
   ~tq_tn_plan();
 };
 
@@ -805,6 +806,11 @@ static TnExec make_exec(const std::vector<int>& xi, const std::vector<int>& yi, 
 
 }  // namespace tq
 
+static tq_status runnable(const tq_tn_plan* p) {
+  if (p->host_only) return tq::fail(TQ_EINVAL, "the plan was built without a context: it can be queried but not run");
+  return TQ_OK;
+}
+
 tq_tn_plan::~tq_tn_plan() {
   void* p[] = {d_fwd, d_bwd, d_perm, d_bperm, d_gather, d_ffused, d_bfused, d_leaf_env};
   for (void* x : p)
@@ -816,7 +822,7 @@ using namespace tq;
 extern "C" {
 
 tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) {
-  if (!ctx || !d || !out) return fail(TQ_EINVAL, "null argument");
+  if (!d || !out) return fail(TQ_EINVAL, "null argument");
   *out = nullptr;
   if (d->dtype != TQ_C64 && d->dtype != TQ_C128) return fail(TQ_EINVAL, "unknown dtype");
   const int L = d->n_leaves;
@@ -1101,8 +1107,9 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     le.push_back(int64_t(1) << t.rank);
   }
   p->n_leaf_env = (int)(le.size() / 3);
-  // device copies of the step tables
-  {
+  // device copies of the step tables (none for a host-only plan)
+  p->host_only = !ctx;
+  if (ctx) {
     std::vector<DevTnStep> fs, bs;
     std::vector<uint8_t> pt;
     for (auto& f : p->fwd) {
@@ -1458,6 +1465,7 @@ extern "C" {
 tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, void* d_out, void* d_work,
                          int64_t work_bytes, void* stream) {
   if (!ctx || !plan || !d_leaves || !d_out || !d_work) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
   if (plan->dtype == TQ_C64)
     return tn_contract_t<float>(ctx, plan, d_leaves, d_out, d_work, work_bytes, (hipStream_t)stream);
   return tn_contract_t<double>(ctx, plan, d_leaves, d_out, d_work, work_bytes, (hipStream_t)stream);
@@ -1466,6 +1474,7 @@ tq_status tq_tn_contract(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leav
 tq_status tq_tn_backward(tq_ctx* ctx, const tq_tn_plan* plan, const void* d_leaves, const void* d_grad_out,
                          void* d_grad_leaves, void* d_work, int64_t work_bytes, void* stream) {
   if (!ctx || !plan || !d_leaves || !d_grad_out || !d_grad_leaves || !d_work) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
   if (plan->dtype == TQ_C64)
     return tn_backward_t<float>(ctx, plan, d_leaves, d_grad_out, d_grad_leaves, d_work, work_bytes,
                                 (hipStream_t)stream);
@@ -1600,6 +1609,7 @@ static tq_status tn_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans
     const tq_tn_plan* p = plans[i];
     if (!p || !d_leaves[i] || !d_out[i] || !d_work[i] || (mode == 1 && !d_gout[i]))
       return fail(TQ_EINVAL, "null plan or buffer for network " + std::to_string(i));
+    TQ_TRY(runnable(p));
     if (work_bytes[i] < tq_tn_workspace(p, mode))
       return fail(TQ_EWORKSPACE, "workspace too small for network " + std::to_string(i));
     if (p->n_slices != 1 || p->fwd.empty()) {
@@ -1643,6 +1653,7 @@ tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate*
                              const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const, const void* d_params,
                              void* d_leaves, void* stream) {
   if (!ctx || !plan || !leaves || !d_leaves) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
   if (n_gates > 0 && (!gates || !d_params)) return fail(TQ_EINVAL, "null gates or params");
   if (n_const > 0 && !const_vals) return fail(TQ_EINVAL, "null constant values");
   TQ_TRY(validate_gates(gates, n_gates, 1 << 30, 0x7fffffff));
@@ -1669,6 +1680,7 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
                            const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
                            const void* d_grad_leaves, void* d_grad_params, void* stream) {
   if (!ctx || !plan || !leaves || !d_grad_leaves || !d_grad_params) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
   if (n_params < 0) return fail(TQ_EINVAL, "negative n_params");
   TQ_TRY(validate_gates(gates, n_gates, 1 << 30, n_params));
   std::vector<DevLeaf> dl;

@@ -12,7 +12,8 @@ import numpy as np
 from . import workloads as W
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtq.so")
+# TQ_LIBRARY selects another build of the same library (e.g. the host-sanitizer build)
+LIB_PATH = os.environ.get("TQ_LIBRARY") or os.path.join(_HERE, "libtq.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2301_05451_amd.build`")
@@ -206,13 +207,15 @@ def sv_apply(states, params, spec: BatchSpec, mode=0, tile_bits=0, reg_bits=0, c
 PLAN_FIELDS = ("sweeps", "ops", "phases", "exchanges", "tile_bits", "reg_bits", "flops_per_amp", "mats")
 
 
-def plan_info(n, gates, dtype_c128=False, mode=0, tile_bits=0, reg_bits=0, coal_bits=0, ctx=None):
-    """Schedule shape for one circuit structure (tq_sv_plan_info), as a dict."""
-    ctx = ctx or context()
+def plan_info(n, gates, dtype_c128=False, mode=0, tile_bits=0, reg_bits=0, coal_bits=0, ctx=None, host=False):
+    """Schedule shape for one circuit structure (tq_sv_plan_info), as a dict. mode 0 fused,
+    1 plain, 2 the reverse sweep of the adjoint; ``host`` builds it without a context (no
+    device needed)."""
+    h = None if host else (ctx or context()).h
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
     out = (ct.c_int64 * 8)()
     o = _opts(mode, tile_bits, reg_bits, coal_bits)
-    check(_lib.tq_sv_plan_info(ctx.h, TQ_C128 if dtype_c128 else TQ_C64, int(n), g.ctypes.data, int(g.shape[0]),
+    check(_lib.tq_sv_plan_info(h, TQ_C128 if dtype_c128 else TQ_C64, int(n), g.ctypes.data, int(g.shape[0]),
                                ct.byref(o), out))
     return dict(zip(PLAN_FIELDS, [int(v) for v in out]))
 
@@ -558,8 +561,9 @@ class TnPlan:
     """Owns a tq_tn_plan built from leaf index lists, an SSA tree and sliced indices."""
 
     def __init__(self, leaf_inds, pairs, sliced=(), out_inds=(), c128=False, slice_group=0, mem_budget=0,
-                 ctx=None, store_policy=TN_RECOMPUTE):
-        self.ctx = ctx or context()
+                 ctx=None, store_policy=TN_RECOMPUTE, host_only=False):
+        # host_only: planned without a context (no device needed); it can be queried, not run
+        self.ctx = None if host_only else (ctx or context())
         self.c128 = bool(c128)
         ranks = np.array([len(x) for x in leaf_inds], dtype=np.int32)
         flat = np.array([i for x in leaf_inds for i in x] or [0], dtype=np.int32)
@@ -571,7 +575,7 @@ class TnPlan:
                    len(out_inds), oi.ctypes.data, TQ_C128 if c128 else TQ_C64, int(slice_group), int(mem_budget),
                    int(store_policy), 0)
         h = _vp()
-        check(_lib.tq_tn_plan_create(self.ctx.h, ct.byref(d), ct.byref(h)))
+        check(_lib.tq_tn_plan_create(self.ctx.h if self.ctx else None, ct.byref(d), ct.byref(h)))
         self.h = h
         self.n_leaves = len(leaf_inds)
         self.leaf_elems = int(_lib.tq_tn_leaf_elems(h))
@@ -587,6 +591,11 @@ class TnPlan:
 
     def workspace_bytes(self, backward=False):
         return int(_lib.tq_tn_workspace(self.h, 1 if backward else 0))
+
+    @property
+    def ctx_h(self):
+        # a host-only plan is passed with the default context; the library refuses to run it
+        return (self.ctx or context()).h
 
     def __del__(self):
         try:
@@ -612,7 +621,7 @@ def tn_contract(plan: TnPlan, leaves, work=None):
     out = torch.empty(1 << plan.n_out, dtype=cdt, device=leaves.device)
     need = plan.workspace_bytes(False)
     work = work if work is not None and work.numel() >= need else _ws(need, leaves.device)
-    check(_lib.tq_tn_contract(plan.ctx.h, plan.h, leaves.data_ptr(), out.data_ptr(), work.data_ptr(), need,
+    check(_lib.tq_tn_contract(plan.ctx_h, plan.h, leaves.data_ptr(), out.data_ptr(), work.data_ptr(), need,
                               _stream()))
     return out
 
@@ -628,7 +637,7 @@ def tn_backward(plan: TnPlan, leaves, grad_out, work=None):
     grad = torch.empty(plan.leaf_elems, dtype=cdt, device=leaves.device)
     need = plan.workspace_bytes(True)
     work = work if work is not None and work.numel() >= need else _ws(need, leaves.device)
-    check(_lib.tq_tn_backward(plan.ctx.h, plan.h, leaves.data_ptr(), g.data_ptr(), grad.data_ptr(), work.data_ptr(),
+    check(_lib.tq_tn_backward(plan.ctx_h, plan.h, leaves.data_ptr(), g.data_ptr(), grad.data_ptr(), work.data_ptr(),
                               need, _stream()))
     return grad
 
@@ -655,7 +664,7 @@ def tn_contract_batch(plans, leaves, works=None):
         need = pl.workspace_bytes(False)
         ws.append(works[k] if works is not None and works[k].numel() >= need else _ws(need, lv.device))
     need = (ct.c_int64 * max(1, len(plans)))(*[pl.workspace_bytes(False) for pl in plans])
-    check(_lib.tq_tn_contract_batch(plans[0].ctx.h if plans else context().h, len(plans),
+    check(_lib.tq_tn_contract_batch(plans[0].ctx_h if plans else context().h, len(plans),
                                     _ptrs([pl.h.value for pl in plans]), _ptrs([x.data_ptr() for x in leaves]),
                                     _ptrs([o.data_ptr() for o in outs]), _ptrs([w.data_ptr() for w in ws]), need,
                                     _stream()))
@@ -675,7 +684,7 @@ def tn_backward_batch(plans, leaves, grad_outs, works=None):
         need = pl.workspace_bytes(True)
         ws.append(works[k] if works is not None and works[k].numel() >= need else _ws(need, lv.device))
     need = (ct.c_int64 * max(1, len(plans)))(*[pl.workspace_bytes(True) for pl in plans])
-    check(_lib.tq_tn_backward_batch(plans[0].ctx.h if plans else context().h, len(plans),
+    check(_lib.tq_tn_backward_batch(plans[0].ctx_h if plans else context().h, len(plans),
                                     _ptrs([pl.h.value for pl in plans]), _ptrs([x.data_ptr() for x in leaves]),
                                     _ptrs([g.data_ptr() for g in gs]), _ptrs([e.data_ptr() for e in envs]),
                                     _ptrs([w.data_ptr() for w in ws]), need, _stream()))
@@ -690,7 +699,7 @@ def tn_build_leaves(plan: TnPlan, gates, leaf_specs, const_vals, params):
     ls = np.ascontiguousarray(leaf_specs, dtype=TN_LEAF_DTYPE)
     cv = np.ascontiguousarray(np.asarray(const_vals, dtype=np.complex128).view(np.float64))
     out = torch.empty(plan.leaf_elems, dtype=cdt, device=params.device)
-    check(_lib.tq_tn_build_leaves(plan.ctx.h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
+    check(_lib.tq_tn_build_leaves(plan.ctx_h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
                                   cv.ctypes.data, int(cv.shape[0] // 2), params.data_ptr(), out.data_ptr(),
                                   _stream()))
     return out
@@ -702,7 +711,7 @@ def tn_param_grad(plan: TnPlan, gates, leaf_specs, params, grad_leaves):
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
     ls = np.ascontiguousarray(leaf_specs, dtype=TN_LEAF_DTYPE)
     out = torch.empty(params.numel(), dtype=params.dtype, device=params.device)
-    check(_lib.tq_tn_param_grad(plan.ctx.h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
+    check(_lib.tq_tn_param_grad(plan.ctx_h, plan.h, g.ctypes.data, int(g.shape[0]), ls.ctypes.data,
                                 params.data_ptr(), int(params.numel()), grad_leaves.contiguous().data_ptr(),
                                 out.data_ptr(), _stream()))
     return out

@@ -45,3 +45,31 @@ def test_pauli_decomposition_of_known_matrices():
     assert len(lib.pauli_decompose(np.zeros((2, 2)), [0])) == 0
     with pytest.raises(lib.TQError):
         lib.pauli_decompose(np.eye(4), [1, 1])
+
+
+def test_schedule_shape_without_a_device():
+    # the headline circuit's fused schedule as the bench reports it, built with no context
+    from paper_2301_05451_amd import lib
+
+    c = W.brickwork()
+    info = lib.plan_info(c.n, c.gates, host=True)
+    assert (info["sweeps"], info["tile_bits"], info["reg_bits"]) == (14, 12, 4)
+    assert info["flops_per_amp"] == 6468
+    plain = lib.plan_info(c.n, c.gates, mode=1, host=True)
+    assert plain["sweeps"] == len(c.gates)
+    rev = lib.plan_info(c.n, c.gates, mode=2, host=True)
+    assert rev["sweeps"] >= 1 and rev["tile_bits"] == 12
+    with pytest.raises(lib.TQError):
+        lib.plan_info(c.n, c.gates, mode=3, host=True)
+
+
+def test_network_plan_without_a_device():
+    from paper_2301_05451_amd import lib
+    from paper_2301_05451_amd import tn
+
+    prob = W.qaoa_maxcut(p=3)
+    net, _ = tn.qaoa_edge_network(prob, prob.edges[0])
+    tree = tn.best_tree(net, seed=0, n_bisect=2)
+    p = lib.TnPlan([lf.inds for lf in net.leaves], tree.pairs, tree.sliced, net.output, host_only=True)
+    assert p.ctx is None and p.info["flops"] > 0
+    assert p.workspace_bytes(True) >= p.workspace_bytes(False) > 0

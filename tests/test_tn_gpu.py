@@ -150,6 +150,14 @@ def test_plan_validation():
         lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], sliced=[7])  # sliced index in no leaf
     with pytest.raises(lib.TQError):
         lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], out_inds=[5])  # no tensor carries index 5
+    # a plan built without a context has the same shape as a device plan and cannot run
+    host = lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], out_inds=[0, 2], host_only=True)
+    dev = lib.TnPlan([[0, 1], [1, 2]], [(0, 1)], out_inds=[0, 2])
+    assert host.info == dev.info and host.workspace_bytes(True) == dev.workspace_bytes(True)
+    leaves = torch.ones(8, dtype=torch.complex64, device="cuda")
+    assert torch.allclose(lib.tn_contract(dev, leaves).cpu(), torch.full((4,), 2, dtype=torch.complex64))
+    with pytest.raises(lib.TQError):
+        lib.tn_contract(host, leaves)
 
 
 @pytest.mark.parametrize("c128", [False, True])
