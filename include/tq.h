@@ -164,7 +164,7 @@ tq_status tq_sv_plan_info(tq_ctx* ctx, tq_dtype dt, int32_t n_qubits, const tq_g
 
 /* Sec. 4 cost: d_out[i * n_obs + o] = sum over terms with obs == o of
  * coeff * <psi_i| Z-string |psi_i> (real, written in the dtype's real precision). Each
- * thread sums |psi|^2 with the terms' signs over its own amplitudes (32 per 2^13-amplitude
+ * thread sums |psi|^2 with the terms' signs over its own amplitudes (16 per 2^12-amplitude
  * chunk) in the state's precision; all further accumulation (over threads, work-groups and
  * terms) is in double with a fixed order, so repeated calls are bitwise equal. Terms name
  * qubits (bit q = qubit q). */

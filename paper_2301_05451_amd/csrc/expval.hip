@@ -1,14 +1,14 @@
 // Expectation values of sums of Pauli-Z strings (the VQC cost of Sec. 4):
 // <O_o> = sum over terms k with obs_k = o of coeff_k * sum_x |psi_x|^2 (-1)^popcount(x & m_k).
 //
-// The state is read in chunks of 2^13 contiguous amplitudes, so the index bits at and above
-// 13 are fixed per chunk: their parity is one uniform sign per term. Within a chunk, a
-// thread holds 32 amplitudes (index = it * 256 + thread id); the sums of all terms over them
-// are read off one Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's
-// precision, as is the thread's running sum over its chunks. Everything above (waves, the
-// group, the groups of a circuit) is a fixed-order double tree, so repeated runs are
-// bitwise equal.
+// The state is read in chunks of 2^12 contiguous amplitudes, so the index bits at and above
+// 12 are fixed per chunk: their parity is one uniform sign per term. Within a chunk, a
+// thread holds 16 amplitudes; the sums of all terms over them are read off one
+// Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's precision, as is the
+// thread's running sum over its chunks. Everything above (waves, the group, the groups of a
+// circuit) is a fixed-order double tree, so repeated runs are bitwise equal.
 #include <mutex>
+#include <type_traits>
 
 #include "sv_device.h"
 
@@ -54,104 +54,146 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Chunk size of the partial-sum kernel: 2^kExpChunkBits amplitudes, 16 per thread.
+constexpr int kExpChunkBits = 12;
+constexpr int kExpVals = 16;
+
 // Work-groups per circuit of the partial-sum kernel: about kExpGroups over the launch, at
 // most one per 2^13-amplitude chunk.
 constexpr int kExpGroups = 512;
-constexpr bool kExpPrefetch = true;
 
 int expval_groups(int n, int cn) {
-  const int cb = n < 13 ? n : 13;
+  const int cb = n < kExpChunkBits ? n : kExpChunkBits;
   const int64_t chunks = int64_t(1) << (n - cb);
   const int64_t want = std::max<int64_t>(1, kExpGroups / std::max(cn, 1));
   return (int)std::min<int64_t>(chunks, want);
 }
 
-// One work-group walks the 2^13-amplitude chunks j = blockIdx.x, blockIdx.x + gridDim.x, ...
-// of its circuit (a fixed sequence, so the sums repeat bitwise), loading the next chunk
-// while it transforms the current one, and writes one partial sum per term.
-template <typename T, int KT>
-__global__ void __launch_bounds__(kExpThreads)
-    expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int n,
-                          const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial) {
+// Vector width of the partial-sum kernel's loads: A amplitudes per 16-byte load (2 for
+// complex64, 1 for complex128). A circuit whose state is not 16-byte aligned is read one
+// amplitude per load instead (the same sums, in another order).
+template <typename T>
+struct ExpVec {
+  static constexpr int A = 16 / (int)sizeof(typename Cx<T>::type);
+};
+
+// Per-term table of a launch, in LDS: (the term's mask over the chunk-index bits << 4) | the
+// index u of its Walsh-Hadamard coefficient over the thread's 16 values.
+template <int KT>
+struct ExpTermTab {
+  uint32_t c[KT];
+};
+
+// One work-group's share of one circuit: a contiguous range of its 2^cb-amplitude chunks,
+// the next chunk's loads in flight while the current one is transformed. In a chunk a thread reads
+// A amplitudes per load at index (it << (lgA + 8)) | (tid << lgA) | e, it < nit, e < A:
+// their |psi|^2 values p[(it << lgA) | e] go through one Walsh-Hadamard transform
+// W[u] = sum_v (-1)^{|v & u|} p[v], and a term with mask m reads W at u = the mask's bits over
+// (it, e), with the sign of the mask's thread bits (fixed per thread: one bit per term in
+// tpar) and chunk bits (one bit per term and chunk in cpar). The transform and a thread's sum
+// over its chunks are in the state's precision; the partial sums below are in double.
+template <typename T, int KT, int A>
+__device__ __forceinline__ void expval_partial_body(const typename Cx<T>::type* __restrict__ s, int n,
+                                                    const uint64_t* __restrict__ pmask, int nk, T (&acc)[KT],
+                                                    T (*wsh)[kExpThreads], ExpTermTab<KT>& tab) {
   using C = typename Cx<T>::type;
-  constexpr int kMaxIt = 32;
-  const C* s = st + smap.at(blockIdx.y);
-  const int cb = n < 13 ? n : 13;
-  const uint32_t namp = 1u << cb;
-  const uint32_t lo_mask = namp - 1;
-  const int64_t nchunk = int64_t(1) << (n - cb);
+  using V = typename std::conditional<A == 2, typename std::conditional<sizeof(T) == 4, float4, double4>::type,
+                                      C>::type;
+  constexpr int lgA = A == 2 ? 1 : 0;
+  constexpr int kLoads = kExpVals / A;  // loads per thread and chunk
+  const int cb = n < kExpChunkBits ? n : kExpChunkBits;
   const uint32_t tid = threadIdx.x;
-  const int lg = cb > 8 ? cb - 8 : 0;
-  const int nit = 1 << lg;
-  const uint32_t tcl = tid & (namp - 1);
-  uint32_t mlo[KT];
-  T acc[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    mlo[k] = k < nk ? (uint32_t)(pmask[k] & lo_mask) : 0u;
-    acc[k] = (T)0;
+  const int tb = cb - lgA < 8 ? cb - lgA : 8;  // thread bits of a chunk index
+  const int nit = 1 << (cb - lgA - tb);
+  const uint32_t tcl = tid & ((1u << tb) - 1);
+  const bool live = tid < (1u << tb);
+  const int64_t nchunk = int64_t(1) << (n - cb);
+  const V* sv = (const V*)s;  // index in units of A amplitudes
+  if (tid < KT) {
+    const uint64_t m = tid < (uint32_t)nk ? pmask[tid] : 0ull;
+    const uint32_t u = ((((uint32_t)m >> (lgA + 8)) & (uint32_t)(nit - 1)) << lgA) | ((uint32_t)m & (uint32_t)(A - 1));
+    tab.c[tid] = ((uint32_t)(m >> cb) << 4) | u;  // n - cb <= 28 chunk bits
   }
-  // loc = it * 256 + tid within a chunk. The thread id (low 8 bits) gives one sign per term
-  // and thread; over the iteration bits a term's sum is one coefficient of the Walsh-Hadamard
-  // transform of the thread's |psi|^2 values, W[u] = sum_it (-1)^{|it & u|} p[it], with u the
-  // term's mask bits 8..12. The transform and a thread's sum over its chunks run in the
-  // state's precision; everything after that (waves, the group, the circuit) is in double.
-  __shared__ T wsh[kMaxIt][kExpThreads];  // per-thread column: indexable storage for W[u]
-  C nxt[kMaxIt];
-  int64_t j = blockIdx.x;
-  if (kExpPrefetch && j < nchunk) {
+  uint32_t tpar = 0;  // bit k: parity of term k's mask over this thread's index bits
 #pragma unroll
-    for (int it = 0; it < kMaxIt; ++it) {
+  for (int k = 0; k < KT; ++k)
+    if (k < nk) tpar |= ((uint32_t)__popc(tid & ((uint32_t)pmask[k] >> lgA) & 0xffu) & 1u) << k;
+  __syncthreads();
+  V nxt[kLoads];
+  auto load = [&](int64_t j) {
+#pragma unroll
+    for (int it = 0; it < kLoads; ++it) {
       const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
-      nxt[it] = s[((uint64_t)j << cb) + (itc << 8) + tcl];
+      nxt[it] = sv[(((uint64_t)j << cb) >> lgA) + ((itc << 8) | tcl)];
     }
-  }
-  for (; j < nchunk; j += gridDim.x) {
-    if (!kExpPrefetch) {
+  };
+  // this group's chunks: a contiguous range (a fixed sequence, so the sums repeat bitwise)
+  const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per;
+  const int64_t j1 = j0 + per < nchunk ? j0 + per : nchunk;
+  int64_t j = j0;
+  if (j < j1) load(j);
+  for (; j < j1; ++j) {
+    T pv[kExpVals];
 #pragma unroll
-      for (int it = 0; it < kMaxIt; ++it) {
-        const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
-        nxt[it] = s[((uint64_t)j << cb) + (itc << 8) + tcl];
+    for (int it = 0; it < kLoads; ++it) {
+      const bool on = it < nit && live;
+      if constexpr (A == 2) {
+        const T p0 = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
+        const T p1 = nxt[it].z * nxt[it].z + nxt[it].w * nxt[it].w;
+        pv[2 * it] = on ? p0 : (T)0;
+        pv[2 * it + 1] = on ? p1 : (T)0;
+      } else {
+        const T p = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
+        pv[it] = on ? p : (T)0;
       }
     }
-    T pv[kMaxIt];
+    if (j + 1 < j1) load(j + 1);  // next chunk in flight
 #pragma unroll
-    for (int it = 0; it < kMaxIt; ++it) {
-      const T p = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
-      pv[it] = (it < nit && tid < namp) ? p : (T)0;
-    }
-    const int64_t jn = j + gridDim.x;
-    if (kExpPrefetch && jn < nchunk) {  // next chunk in flight while this one is transformed
+    for (int h = 1; h < kExpVals; h <<= 1) {
 #pragma unroll
-      for (int it = 0; it < kMaxIt; ++it) {
-        const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
-        nxt[it] = s[((uint64_t)jn << cb) + (itc << 8) + tcl];
-      }
-    }
-#pragma unroll
-    for (int h = 1; h < kMaxIt; h <<= 1) {
-#pragma unroll
-      for (int i = 0; i < kMaxIt; ++i)
+      for (int i = 0; i < kExpVals; ++i)
         if ((i & h) == 0) {
           const T a = pv[i], b = pv[i | h];
           pv[i] = a + b;
           pv[i | h] = a - b;
         }
     }
+    const int nv = nit * A;
 #pragma unroll
-    for (int it = 0; it < kMaxIt; ++it)
-      if (it < nit) wsh[it][tid] = pv[it];
-    const uint64_t hi = (uint64_t)j << cb;
+    for (int v = 0; v < kExpVals; ++v)
+      if (v < nv) wsh[v][tid] = pv[v];
+    const uint32_t jj = (uint32_t)j << 4;
+    // the table is read again per chunk (not held in registers across the loop)
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       if (k < nk) {
-        const uint32_t u = (mlo[k] >> 8) & (uint32_t)(nit - 1);
-        const T w = wsh[u][tid];
-        const uint32_t par = (uint32_t)(__popc(tid & mlo[k] & 0xffu) + __popcll(hi & pmask[k])) & 1u;
+        const uint32_t c = tab.c[k];
+        const T w = wsh[c & 15u][tid];
+        const uint32_t par = ((tpar >> k) ^ (uint32_t)__popc(jj & c)) & 1u;
         acc[k] += par ? -w : w;
       }
     }
   }
+}
+
+// Partial sums of every term over one work-group's chunks of circuit blockIdx.y.
+template <typename T, int KT>
+__global__ void __launch_bounds__(kExpThreads)
+    expval_partial_kernel(const typename Cx<T>::type* __restrict__ st, BatchMap smap, int n,
+                          const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial) {
+  const typename Cx<T>::type* s = st + smap.at(blockIdx.y);
+  __shared__ T wsh[kExpVals][kExpThreads];  // per-thread column: indexable storage for W[u]
+  __shared__ ExpTermTab<KT> tab;
+  T acc[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) acc[k] = (T)0;
+  constexpr int A = ExpVec<T>::A;
+  if (A > 1 && (reinterpret_cast<uintptr_t>(s) & 15) == 0)
+    expval_partial_body<T, KT, A>(s, n, pmask, nk, acc, wsh, tab);
+  else
+    expval_partial_body<T, KT, 1>(s, n, pmask, nk, acc, wsh, tab);
   __shared__ double red[kExpThreads / 64][KT];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -170,41 +212,64 @@ __global__ void __launch_bounds__(kExpThreads)
   }
 }
 
-// One work-group per circuit: each wave sums the partials of one term at a time (lane l adds
-// groups l, l + 64, ... in four interleaved chains, then chains and lanes are combined in a
-// fixed order), and thread 0 accumulates coeff * S_k into its observable in term order.
-// Circuit i of the launch writes output row rows.at(i).
+// One work-group of 16 waves per circuit: wave w sums the partials of terms w, w + 16, ...;
+// a lane adds groups lane + 64 c (c < 8) of each of its terms per block of 512 groups, all
+// loads of a block issued before any add, in eight chains per term, then chains and lanes
+// are combined in a fixed order; each observable's thread accumulates coeff * S_k over its
+// terms in term order. Circuit i of the launch writes output row rows.at(i).
+constexpr int kExpFinalThreads = 1024;
+
 template <typename T, int KT>
-__global__ void __launch_bounds__(kExpThreads)
+__global__ void __launch_bounds__(kExpFinalThreads)
     expval_final_kernel(const double* __restrict__ partial, int nb, int nk, const double* __restrict__ coeff,
                         const int32_t* __restrict__ obs, int n_obs, double* __restrict__ outacc, int first,
                         int last, T* __restrict__ out, BatchMap rows) {
+  constexpr int kW = kExpFinalThreads / 64;
+  constexpr int TPW = (KT + kW - 1) / kW;  // terms per wave
   __shared__ double sk[KT];
   const int circ = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k = wv; k < nk; k += kExpThreads / 64) {
-    const double* pk = partial + ((int64_t)circ * KT + k) * nb;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
-    int b = lane;
-    for (; b + 192 < nb; b += 256) {
-      x0 += pk[b];
-      x1 += pk[b + 64];
-      x2 += pk[b + 128];
-      x3 += pk[b + 192];
+  double x[TPW][8];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[t][c] = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += 512) {
+    double v[TPW][8];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int k = wv + kW * t;
+      const double* pk = partial + ((int64_t)circ * KT + (k < nk ? k : 0)) * nb;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int b = b0 + lane + 64 * c;
+        v[t][c] = (k < nk && b < nb) ? pk[b] : 0.0;
+      }
     }
-    for (; b < nb; b += 64) x0 += pk[b];
-    double x = (x0 + x1) + (x2 + x3);
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    if (lane == 0) sk[k] = x;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) x[t][c] += v[t][c];
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int k = wv + kW * t;
+    double y = ((x[t][0] + x[t][1]) + (x[t][2] + x[t][3])) + ((x[t][4] + x[t][5]) + (x[t][6] + x[t][7]));
+    for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off, 64);
+    if (k < nk && lane == 0) sk[k] = y;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double* acc = outacc + (int64_t)circ * n_obs;
-    if (first)
-      for (int o = 0; o < n_obs; ++o) acc[o] = 0.0;
-    for (int k = 0; k < nk; ++k) acc[obs[k]] += coeff[k] * sk[k];
+  // thread o owns observable o: its terms' coeff * S_k added in term order (onto what the
+  // earlier term chunks left in outacc), written out after the last chunk
+  for (int o = threadIdx.x; o < n_obs; o += kExpFinalThreads) {
+    double* acc = outacc + (int64_t)circ * n_obs + o;
+    double a = first ? 0.0 : *acc;
+    for (int k = 0; k < nk; ++k)
+      if (obs[k] == o) a += coeff[k] * sk[k];
     if (last)
-      for (int o = 0; o < n_obs; ++o) out[rows.at(circ) * n_obs + o] = (T)acc[o];
+      out[rows.at(circ) * n_obs + o] = (T)a;
+    else
+      *acc = a;
   }
 }
 
@@ -214,7 +279,7 @@ static void launch_chunk(const typename Cx<T>::type* d_states, BatchMap smap, in
                          double* outacc, int first, int last, T* out, BatchMap rows, hipStream_t stream) {
   hipLaunchKernelGGL((expval_partial_kernel<T, KT>), dim3((unsigned)nb, (unsigned)cn), dim3(kExpThreads), 0, stream,
                      d_states, smap, n, pm, nk, partial);
-  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3((unsigned)cn), dim3(kExpThreads), 0, stream, partial, nb, nk,
+  hipLaunchKernelGGL((expval_final_kernel<T, KT>), dim3((unsigned)cn), dim3(kExpFinalThreads), 0, stream, partial, nb, nk,
                      cf, ob, n_obs, outacc, first, last, out, rows);
 }
 

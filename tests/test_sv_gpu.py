@@ -245,3 +245,39 @@ def test_expval_more_than_32_terms(name):
         want = osv.expvals(host[b << n:(b + 1) << n], n, terms, 5)
         tol = 1e-5 if name == "c64" else 1e-12
         assert np.all(np.abs(got[b] - want) <= tol * coef), (b, got[b], want)
+
+
+@pytest.mark.parametrize("name", ["c64", "c128"])
+def test_expval_states_at_odd_offsets(name):
+    """States that start at odd amplitude offsets (not 16-byte aligned in complex64) and of
+    every size from one qubit up: the kernel reads them one amplitude per load, and 16-byte
+    aligned ones two per load; both against the oracle."""
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(231)
+    ns = [1, 2, 5, 8, 9, 10, 13, 14, 16]
+    offs, o = [], 1
+    for n in ns:
+        offs.append(o)
+        o += (1 << n) + int(rng.integers(0, 3))
+    total = o
+    v = rng.normal(size=total) + 1j * rng.normal(size=total)
+    cdt = torch.complex64 if name == "c64" else torch.complex128
+    psi = torch.tensor(v, dtype=cdt, device="cuda")
+    g = W.GateList().array()
+    spec = lib.BatchSpec(ns, np.zeros(len(ns)), np.zeros(len(ns)), np.zeros(len(ns)), offs, np.zeros(len(ns)), g)
+    for n_terms in (3, 9):
+        rows = []
+        for k in range(n_terms):
+            rows.append(({0, int(rng.integers(0, 16))} if k % 2 else {int(rng.integers(0, 16))}, float(rng.normal()),
+                         k % 2))
+        host = psi.cpu().numpy().astype(np.complex128)
+        for i, n in enumerate(ns):
+            trm = W.zterms([(sorted(q for q in qs if q < n) or [0], c, ob) for qs, c, ob in rows])
+            sp = lib.BatchSpec([n], [0], [0], [0], [offs[i]], [0], g)
+            got = lib.expval(psi, sp, trm, 2).cpu().numpy()[0]
+            seg = host[offs[i]:offs[i] + (1 << n)]
+            want = osv.expvals(seg, n, trm, 2)
+            scale = np.linalg.norm(seg) ** 2 * np.abs(trm["coeff"]).sum()
+            assert np.abs(got - want).max() <= (1e-5 if name == "c64" else 1e-12) * scale, (n, got, want)
+    del spec
