@@ -423,11 +423,16 @@ tq_status tq_tn_backward_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* 
  * observable tensors, with conjugate copies for the bra half). kind per leaf: 0 constant
  * (const_vals[const_off ..], complex128 interleaved), 1 one-qubit gate [out, in],
  * 2 one-qubit diagonal gate over its wire index, 3 two-qubit diagonal gate over its two wire
- * indices, 4 two-qubit gate [out_a, out_b, in_a, in_b]; conj = 1 for the bra copy. */
+ * indices, 4 two-qubit gate [out_a, out_b, in_a, in_b]; conj = 1 for the bra copy.
+ * flip (anti-diagonal reduction, Sec. 3.2.1): the leaf stores entry e ^ flip of its kind's
+ * tensor at element e (bit 0 = its last listed index), so an anti-diagonal gate (X, or Y as
+ * a diagonal then X) needs no tensor: the wire's later tensors read that index flipped.
+ * Must be below 2^rank. */
 typedef struct {
   int32_t kind;
   int32_t gate;
-  int32_t conj;
+  int16_t conj;
+  uint16_t flip;
   int32_t const_off;
 } tq_tn_leaf;
 

@@ -636,6 +636,7 @@ __global__ void tn_fill_kernel(typename Cx<T>::type* __restrict__ p, int64_t n, 
 struct DevLeaf {
   int32_t kind, gate, conj, const_off;
   int64_t off;
+  int32_t flip, _pad;  // element e holds the kind's entry e ^ flip
 };
 
 template <typename T>
@@ -646,11 +647,13 @@ __global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leave
   if (li >= n_leaves) return;
   const DevLeaf L = lv[li];
   typename Cx<T>::type* o = out + L.off;
+  const int f = L.flip;  // entry i of the kind's tensor goes to element i ^ f
   const double sg = L.conj ? -1.0 : 1.0;
   if (L.kind == 0) {
     // constants are copied as given (the caller supplies conjugated values if needed)
     const int r = L.gate;  // number of entries for constants is carried in gate
-    for (int i = 0; i < r; ++i) o[i] = to_cx<T>(dcx{cv[2 * (L.const_off + i)], cv[2 * (L.const_off + i) + 1]});
+    for (int i = 0; i < r; ++i)
+      o[i ^ f] = to_cx<T>(dcx{cv[2 * (L.const_off + i)], cv[2 * (L.const_off + i) + 1]});
     return;
   }
   const tq_gate& g = gates[L.gate];
@@ -658,23 +661,23 @@ __global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leave
   gate_angles(g, params, a);
   if (L.kind == 1) {
     const dmat2 M = gate_mat2(g.op, a);
-    for (int i = 0; i < 4; ++i) o[i] = to_cx<T>(dcx{M.m[i].x, sg * M.m[i].y});
+    for (int i = 0; i < 4; ++i) o[i ^ f] = to_cx<T>(dcx{M.m[i].x, sg * M.m[i].y});
   } else if (L.kind == 2) {
     for (int b = 0; b < 2; ++b) {
       dcx d = diag_entry(g, g.q[0], b, b, a);
-      o[b] = to_cx<T>(dcx{d.x, sg * d.y});
+      o[b ^ f] = to_cx<T>(dcx{d.x, sg * d.y});
     }
   } else if (L.kind == 3) {
     for (int idx = 0; idx < 4; ++idx) {
       dcx d = diag_entry(g, g.q[0], idx >> 1, idx & 1, a);
-      o[idx] = to_cx<T>(dcx{d.x, sg * d.y});
+      o[idx ^ f] = to_cx<T>(dcx{d.x, sg * d.y});
     }
   } else {  // two-qubit non-diagonal: CNOT [out_c, out_t, in_c, in_t]
     for (int i = 0; i < 16; ++i) {
       const int oc = (i >> 3) & 1, ot = (i >> 2) & 1, ic = (i >> 1) & 1, it = i & 1;
       double v = 0;
       if (g.op == TQ_CNOT) v = (oc == ic) && (ot == (ic ? 1 - it : it)) ? 1.0 : 0.0;
-      o[i] = to_cx<T>(dcx{v, 0.0});
+      o[i ^ f] = to_cx<T>(dcx{v, 0.0});
     }
   }
 }
@@ -714,7 +717,7 @@ __global__ void __launch_bounds__(kPgThreads)
     const int n = leaf_derivative(L, g, a, j, d);
     const typename Cx<T>::type* E = env + L.off;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += (double)E[i].x * d[i].x - (double)E[i].y * d[i].y;
+    for (int i = 0; i < n; ++i) s += (double)E[i ^ L.flip].x * d[i].x - (double)E[i ^ L.flip].y * d[i].y;
     acc += g.pscale[j] * s;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -1442,9 +1445,11 @@ static tq_status leaf_table(tq_ctx* ctx, const tq_tn_plan* p, const tq_gate* gat
   for (int l = 0; l < p->n_leaves; ++l) {
     const tq_tn_leaf& x = lv[l];
     const int rank = (int)p->t[l].inds.size() + (int)p->t[l].sliced_pos.size();
-    DevLeaf d{x.kind, x.gate, x.conj, x.const_off, p->leaf_off[l]};
+    DevLeaf d{x.kind, x.gate, x.conj, x.const_off, p->leaf_off[l], x.flip, 0};
     static const int want_rank[5] = {-1, 2, 1, 2, 4};
     if (x.kind < 0 || x.kind > 4) return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": unknown kind");
+    if (x.flip >= (1 << std::min(rank, 15)))
+      return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": flip mask beyond the leaf's rank");
     if (x.kind == 0) {
       if (x.const_off < 0 || x.const_off + (1 << rank) > n_const)
         return fail(TQ_EINVAL, "leaf " + std::to_string(l) + ": constant values out of range");

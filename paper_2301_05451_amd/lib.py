@@ -526,7 +526,8 @@ class TnDesc(ct.Structure):
 TN_RECOMPUTE, TN_STORE, TN_AUTO = 0, 1, 2
 
 
-TN_LEAF_DTYPE = np.dtype([("kind", "<i4"), ("gate", "<i4"), ("conj", "<i4"), ("const_off", "<i4")])
+TN_LEAF_DTYPE = np.dtype([("kind", "<i4"), ("gate", "<i4"), ("conj", "<i2"), ("flip", "<u2"), ("const_off", "<i4")])
+assert TN_LEAF_DTYPE.itemsize == 16
 
 _lib.tq_tn_plan_create.argtypes = [_vp, ct.POINTER(TnDesc), ct.POINTER(_vp)]
 _lib.tq_tn_plan_create.restype = ct.c_int

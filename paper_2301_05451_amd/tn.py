@@ -6,13 +6,18 @@ the contraction, runs in libtq kernels (tq_tn_contract / tq_tn_backward):
 (a) circuit -> network: the expectation value <psi|O|psi> needs the circuit followed by
     its complex-conjugate copy (Sec. 3.2.1). Gates outside the reverse light cone of the
     measured qubits cancel against their conjugates and are dropped.
-(b) structural simplification, diagonal part: a diagonal gate (RZ, Z, CZ, RZZ) does not
+(b) structural simplification (Sec. 3.2.1): a diagonal gate (RZ, Z, CZ, RZZ) does not
     start a new index on its qubits; it becomes a tensor on the existing wire indices, so
-    a wire index may join many tensors (a hyperedge, Sec. 3.2.1 and its figure).
-(c) contraction trees: greedy and random-greedy pairwise orders (the default pathfinders
-    listed in Sec. 3.2.2), scored by the paper's FLOP count p(2q-1) per pairwise step.
-(d) slicing (Sec. 3.2.3): greedily fix indices until every intermediate fits the target
-    size; the value is the sum of the identical sub-network contractions.
+    a wire index may join many tensors (a hyperedge, Sec. 3.2.1 and its figure). An
+    anti-diagonal gate (X; Y as a diagonal then X) becomes no tensor at all: it flips its
+    wire, and the wire's later tensors are built with that index complemented. Rank
+    simplification then absorbs every tensor whose contraction with a neighbour does not
+    raise the rank (|0> vectors, one-qubit gates, diagonals).
+(c) contraction trees: the path search's pool (min-fill and min-degree elimination,
+    pairwise greedy, and the own recursive balanced bisection of the tensor hypergraph,
+    Sec. 3.2.2), ranked by the paper's FLOP count p(2q-1) per pairwise step.
+(d) slicing (Sec. 3.2.3): the two-phase search fixes indices until every intermediate fits
+    the target size; the value is the sum of the identical sub-network contractions.
 
 Every index has dimension 2. A tensor with index list [i_0, .., i_{r-1}] is stored as 2^r
 complex numbers with i_0 the most significant bit.
@@ -42,6 +47,7 @@ class Leaf:
     gate: int = -1         # index into the circuit's gate list
     conj: bool = False     # bra-side copy
     value: np.ndarray = None  # LEAF_CONST data (complex128, 2^rank)
+    flip: int = 0          # element e holds entry e ^ flip (bit 0 = last index): flipped wires
 
 
 @dataclasses.dataclass
@@ -108,7 +114,19 @@ def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
     leaves = []
     ket = {q: new() for q in used}
     bra = {q: new() for q in used}
+    # anti-diagonal reduction (Sec. 3.2.1): X is no tensor, it flips its wire, and Y is the
+    # diagonal diag(i, -i) then a flip; every later tensor on a flipped wire reads that index
+    # complemented (the ket and bra halves flip alike, so their final identity is unchanged)
+    flipped = {q: 0 for q in used}
+
+    def fmask(qs):
+        m = 0
+        for k, q in enumerate(qs):
+            m |= flipped[q] << (len(qs) - 1 - k)
+        return m
+
     e0 = np.array([1.0, 0.0], dtype=np.complex128)
+    ydiag = np.array([1j, -1j], dtype=np.complex128)
     for q in used:
         leaves.append(Leaf([ket[q]], LEAF_CONST, value=e0))
         leaves.append(Leaf([bra[q]], LEAF_CONST, value=e0))
@@ -116,19 +134,27 @@ def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
         g = gates[k]
         op = int(g["op"])
         qs = [int(q) for q in g["q"][: W.N_QUBITS[op]]]
+        if op in (W.X, W.Y):
+            q = qs[0]
+            if op == W.Y:
+                leaves.append(Leaf([ket[q]], LEAF_CONST, value=ydiag, flip=flipped[q]))
+                leaves.append(Leaf([bra[q]], LEAF_CONST, value=ydiag.conj(), flip=flipped[q]))
+            flipped[q] ^= 1
+            continue
         if op in _DIAG:
             kind = LEAF_DIAG1 if len(qs) == 1 else LEAF_DIAG2
-            leaves.append(Leaf([ket[q] for q in qs], kind, k, False))
-            leaves.append(Leaf([bra[q] for q in qs], kind, k, True))
+            leaves.append(Leaf([ket[q] for q in qs], kind, k, False, flip=fmask(qs)))
+            leaves.append(Leaf([bra[q] for q in qs], kind, k, True, flip=fmask(qs)))
             continue
         kout = [new() for _ in qs]
         bout = [new() for _ in qs]
         kind = LEAF_GATE1 if len(qs) == 1 else LEAF_GATE2
-        leaves.append(Leaf(kout + [ket[q] for q in qs], kind, k, False))
-        leaves.append(Leaf(bout + [bra[q] for q in qs], kind, k, True))
+        leaves.append(Leaf(kout + [ket[q] for q in qs], kind, k, False, flip=fmask(qs)))
+        leaves.append(Leaf(bout + [bra[q] for q in qs], kind, k, True, flip=fmask(qs)))
         for i, q in enumerate(qs):
             ket[q] = kout[i]
             bra[q] = bout[i]
+            flipped[q] = 0
     # observable: identity merges the ket and bra wire; Z adds a [1, -1] vector on it
     merged = {}
     for q in used:
@@ -137,7 +163,7 @@ def circuit_network(c: W.Circuit, zqubits, use_light_cone=True):
         lf.inds = [merged.get(i, i) for i in lf.inds]
     zv = np.array([1.0, -1.0], dtype=np.complex128)
     for q in zqubits:
-        leaves.append(Leaf([ket[q]], LEAF_CONST, value=zv))
+        leaves.append(Leaf([ket[q]], LEAF_CONST, value=zv, flip=flipped[q]))
     # renumber indices densely
     ren = {}
     for lf in leaves:
@@ -691,6 +717,7 @@ def leaf_specs(net: Network):
         specs[i]["kind"] = lf.kind
         specs[i]["gate"] = lf.gate
         specs[i]["conj"] = 1 if lf.conj else 0
+        specs[i]["flip"] = lf.flip
         if lf.kind == LEAF_CONST:
             specs[i]["const_off"] = sum(len(c) for c in consts)
             consts.append(np.asarray(lf.value, dtype=np.complex128).reshape(-1))

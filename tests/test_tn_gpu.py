@@ -50,6 +50,33 @@ def test_random_circuits_value_and_grad(c128):
         assert np.abs(g - osv.param_shift_grad(c)).max() <= tol
 
 
+@pytest.mark.parametrize("c128", [False, True])
+def test_anti_diagonal_reduction_value_and_grad(c128):
+    """Circuits rich in X and Y: those gates become wire flips (no tensors), and the later
+    tensors on a flipped wire, including parameterised ones and the Z observable, are built
+    with that index complemented; values and gradients against the oracle."""
+    tol = 1e-12 if c128 else 1e-5
+    rng = np.random.default_rng(61)
+    ops = [W.X, W.Y, W.X, W.Y, W.RX, W.RY, W.RZ, W.U3, W.CNOT, W.CZ, W.RZZ, W.H]
+    for n in (2, 4, 6):
+        c = W.random_circuit(n, 36, rng, ops=ops, n_params=8)
+        zq = [n - 1] if n == 2 else [0, n // 2]
+        net = tn.circuit_network(c, zq)
+        assert any(lf.flip for lf in net.leaves)
+        n_xy = int(np.isin(c.gates["op"], [W.X, W.Y]).sum())
+        assert len(net.leaves) < 2 * (len(c.gates) - n_xy) + 2 * n + len(zq) + 2 * n_xy
+        print(f"tn flips n={n} c128={c128}", flush=True)
+        prog = tn.TNProgram(net, tn.greedy_tree(net), c128=c128)
+        p = _params(net, c128)
+        v = prog.value(p).cpu().numpy()[0]
+        psi = osv.run(n, c.gates, c.params)
+        want = float(np.dot(np.abs(psi) ** 2, osv.zstring_diag(n, zq)))
+        assert abs(v.real - want) <= tol and abs(v.imag) <= tol
+        g = prog.grad(p).cpu().numpy()
+        c.terms, c.n_obs = W.zterms([(zq, 1.0, 0)]), 1
+        assert np.abs(g - osv.param_shift_grad(c)).max() <= 2 * tol
+
+
 def _qaoa10():
     r = np.random.default_rng(11)
     edges = W.random_regular_graph(3, 10, r)

@@ -13,18 +13,19 @@ from paper_2301_05451_amd import workloads as W
 
 
 def _leaf_value(net, lf):
-    """Leaf tensor of the planner's network (built here with the oracle's gate matrices)."""
+    """Leaf tensor of the planner's network (built here with the oracle's gate matrices;
+    element e holds entry e ^ flip)."""
     if lf.kind == tn.LEAF_CONST:
-        return np.asarray(lf.value, dtype=np.complex128)
-    g = net.gates[lf.gate]
-    U = osv.gate_matrix(int(g["op"]), osv.gate_angles(g, net.params))
-    if lf.kind == tn.LEAF_DIAG1:
-        v = np.diag(U).copy()
-    elif lf.kind == tn.LEAF_DIAG2:
-        v = np.diag(U).copy()
+        v = np.asarray(lf.value, dtype=np.complex128)
     else:
-        v = U.reshape(-1)
-    return np.conj(v) if lf.conj else v
+        g = net.gates[lf.gate]
+        U = osv.gate_matrix(int(g["op"]), osv.gate_angles(g, net.params))
+        if lf.kind in (tn.LEAF_DIAG1, tn.LEAF_DIAG2):
+            v = np.diag(U).copy()
+        else:
+            v = U.reshape(-1)
+        v = np.conj(v) if lf.conj else v
+    return v[np.arange(v.size) ^ lf.flip]
 
 
 def _numpy_contract(net, tree):
