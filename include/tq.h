@@ -322,6 +322,19 @@ tq_status tq_svb_autotune(tq_ctx* ctx, tq_svb* b, const void* d_params, void* d_
  * [5] graph replays, [6] forward tile bits, [7] forward register bits. */
 tq_status tq_svb_info(const tq_svb* b, int64_t out[8]);
 
+/* Persistence of the autotune table (Sec. 2: compiled objects reused across runs), host only.
+ * tq_ctx_export_tuning writes the context's tuned shapes, its own and imported ones, to `buf`
+ * (capacity `cap` bytes; NULL to query the size) and returns the byte count, or -1
+ * (tq_last_error) on a NULL context or too small a capacity. Layout: a 16-byte header
+ * ("TQTU", version 1, record count, 0) then 40-byte records: a 32-byte digest of (batch
+ * structure, pass), tile bits, register bits. tq_ctx_import_tuning reads such a buffer into
+ * a context: later tq_svb_create calls whose structure digest matches start from the
+ * imported shape (a shape changes speed only; one the structure cannot take falls back to
+ * the defaults). TQ_EINVAL on a malformed buffer or a shape outside tile 1..14 / register
+ * 1..5, in which case nothing is imported. */
+int64_t tq_ctx_export_tuning(const tq_ctx* ctx, void* buf, int64_t cap);
+tq_status tq_ctx_import_tuning(tq_ctx* ctx, const void* buf, int64_t len);
+
 /* ---------------------------------------------------------------------------------------
  * Tensor-network mode (Sec. 3.2). A closed or open network of leaf tensors whose indices all
  * have dimension 2; an index may be shared by any number of tensors (hyperedge, Sec. 3.2.1).

@@ -86,6 +86,7 @@ struct tq_svb {
   std::vector<tq_zterm> terms;
   int n_obs = 1;
   tq_svb_opts opts{};
+  bool adj_tuned = false;  // the adjoint shape came from a tuning table
   std::string key;
   int64_t grad_elems = 0;  // 1 + largest parameter offset + count
   // forward
@@ -418,10 +419,104 @@ std::string structure_key(const tq_svb* b) {
   return k;
 }
 
+// Digest of a structure key plus its length and pass, as a map key: two running
+// 64-bit hashes (FNV-1a, and a multiply-xorshift), the key's length and the pass letter.
+// Imported shapes are matched by it; a collision could only pick a slower valid shape.
+std::string tuning_digest(const std::string& key, char pass) {
+  uint64_t a = 1469598103934665603ull, c = 0x9e3779b97f4a7c15ull;
+  for (unsigned char ch : key) {
+    a = (a ^ ch) * 1099511628211ull;
+    c = (c + ch) * 0xff51afd7ed558ccdull;
+    c ^= c >> 33;
+  }
+  const uint64_t rec[4] = {a, c, (uint64_t)key.size(), (uint64_t)(unsigned char)pass};
+  return std::string((const char*)rec, sizeof rec);
+}
+
+// A tuned shape for (structure, pass): this context's own autotune result, else an imported
+// one, else none.
+bool find_tuned(const tq_ctx* ctx, const std::string& key, char pass, std::pair<int, int>* out) {
+  auto it = ctx->tuned.find(key + (pass == 'f' ? ":f" : ":b"));
+  if (it != ctx->tuned.end()) {
+    *out = it->second;
+    return true;
+  }
+  auto jt = ctx->tuned_digest.find(tuning_digest(key, pass));
+  if (jt != ctx->tuned_digest.end()) {
+    *out = jt->second;
+    return true;
+  }
+  return false;
+}
+
+// Serialised autotune table: header then one record per (structure, pass).
+struct TuneFileHead {
+  char magic[4];  // "TQTU"
+  uint32_t version, count, pad;
+};
+struct TuneFileRec {
+  char digest[32];
+  int32_t t, r;
+};
+static_assert(sizeof(TuneFileRec) == 40, "tuning record layout");
+
 }  // namespace
 }  // namespace tq
 
 extern "C" {
+
+int64_t tq_ctx_export_tuning(const tq_ctx* ctx, void* buf, int64_t cap) {
+  using namespace tq;
+  if (!ctx || cap < 0) {
+    fail(TQ_EINVAL, "tq_ctx_export_tuning: null context or negative capacity");
+    return -1;
+  }
+  std::map<std::string, std::pair<int, int>> recs(ctx->tuned_digest.begin(), ctx->tuned_digest.end());
+  for (const auto& kv : ctx->tuned) {  // own results replace imported ones of the same digest
+    const std::string& k = kv.first;
+    recs[tuning_digest(k.substr(0, k.size() - 2), k.back())] = kv.second;
+  }
+  const int64_t need = (int64_t)sizeof(TuneFileHead) + (int64_t)recs.size() * (int64_t)sizeof(TuneFileRec);
+  if (!buf) return need;
+  if (cap < need) {
+    fail(TQ_ESIZE, "tq_ctx_export_tuning: " + std::to_string(need) + " bytes needed");
+    return -1;
+  }
+  TuneFileHead h{{'T', 'Q', 'T', 'U'}, 1u, (uint32_t)recs.size(), 0u};
+  std::memcpy(buf, &h, sizeof h);
+  unsigned char* p = (unsigned char*)buf + sizeof h;
+  for (const auto& kv : recs) {
+    TuneFileRec r{};
+    std::memcpy(r.digest, kv.first.data(), sizeof r.digest);
+    r.t = kv.second.first;
+    r.r = kv.second.second;
+    std::memcpy(p, &r, sizeof r);
+    p += sizeof r;
+  }
+  return need;
+}
+
+tq_status tq_ctx_import_tuning(tq_ctx* ctx, const void* buf, int64_t len) {
+  using namespace tq;
+  if (!ctx || (!buf && len > 0)) return fail(TQ_EINVAL, "null argument");
+  TuneFileHead h{};
+  if (len < (int64_t)sizeof h) return fail(TQ_EINVAL, "tuning buffer shorter than its header");
+  std::memcpy(&h, buf, sizeof h);
+  if (std::memcmp(h.magic, "TQTU", 4) != 0 || h.version != 1u)
+    return fail(TQ_EINVAL, "not a tuning table of this library version");
+  if (len != (int64_t)sizeof h + (int64_t)h.count * (int64_t)sizeof(TuneFileRec))
+    return fail(TQ_EINVAL, "tuning buffer length does not match its record count");
+  std::vector<std::pair<std::string, std::pair<int, int>>> got;
+  const unsigned char* p = (const unsigned char*)buf + sizeof h;
+  for (uint32_t i = 0; i < h.count; ++i, p += sizeof(TuneFileRec)) {
+    TuneFileRec r;
+    std::memcpy(&r, p, sizeof r);
+    if (r.t < 1 || r.t > 14 || r.r < 1 || r.r > 5) return fail(TQ_EINVAL, "tuning record with an invalid shape");
+    got.emplace_back(std::string(r.digest, sizeof r.digest), std::make_pair((int)r.t, (int)r.r));
+  }
+  for (auto& g : got) ctx->tuned_digest[g.first] = g.second;  // all records valid: apply
+  return TQ_OK;
+}
 
 tq_status tq_svb_create(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
                         const int32_t* n_params, const tq_zterm* terms, int32_t n_terms, int32_t n_obs,
@@ -479,19 +574,27 @@ tq_status tq_svb_create(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const t
   for (int i = 0; i < b->count; ++i) b->grad_elems = std::max(b->grad_elems, b->param_off[i] + b->n_params[i]);
   b->key = structure_key(b.get());
   // start from a tuned shape for this structure unless the caller fixed one
-  auto tf = ctx->tuned.find(b->key + ":f");
-  if (tf != ctx->tuned.end() && !b->opts.tile_bits && !b->opts.reg_bits) {
-    b->opts.tile_bits = tf->second.first;
-    b->opts.reg_bits = tf->second.second;
+  std::pair<int, int> tsh;
+  bool tuned_fwd = false;
+  if (!b->opts.tile_bits && !b->opts.reg_bits && find_tuned(ctx, b->key, 'f', &tsh)) {
+    b->opts.tile_bits = tsh.first;
+    b->opts.reg_bits = tsh.second;
+    tuned_fwd = true;
   }
-  auto ta = ctx->tuned.find(b->key + ":b");
-  if (ta != ctx->tuned.end() && !b->opts.adj_tile_bits && !b->opts.adj_reg_bits) {
-    b->opts.adj_tile_bits = ta->second.first;
-    b->opts.adj_reg_bits = ta->second.second;
+  if (!b->opts.adj_tile_bits && !b->opts.adj_reg_bits && find_tuned(ctx, b->key, 'b', &tsh)) {
+    b->opts.adj_tile_bits = tsh.first;
+    b->opts.adj_reg_bits = tsh.second;
+    b->adj_tuned = true;
   }
   int T, R, c;
   fwd_shape(b.get(), &T, &R, &c);
-  TQ_TRY(build_forward(b.get(), T, R, c));
+  tq_status bst = build_forward(b.get(), T, R, c);
+  if (bst == TQ_EINVAL && tuned_fwd) {  // a tuned shape this structure cannot take: defaults
+    b->opts.tile_bits = b->opts.reg_bits = 0;
+    fwd_shape(b.get(), &T, &R, &c);
+    bst = build_forward(b.get(), T, R, c);
+  }
+  TQ_TRY(bst);
   TQ_TRY(build_ngroups(b.get()));
   TQ_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   *out = b.release();
@@ -521,7 +624,14 @@ tq_status tq_svb_backward(tq_ctx* ctx, tq_svb* b, const void* d_params, const vo
   if (!b->adj_built) {
     int T, R, c;
     adj_shape(b, &T, &R, &c);
-    TQ_TRY(build_adjoint(b, T, R, c));
+    tq_status bst = build_adjoint(b, T, R, c);
+    if (bst == TQ_EINVAL && b->adj_tuned) {  // a tuned shape this structure cannot take: defaults
+      b->opts.adj_tile_bits = b->opts.adj_reg_bits = 0;
+      b->adj_tuned = false;
+      adj_shape(b, &T, &R, &c);
+      bst = build_adjoint(b, T, R, c);
+    }
+    TQ_TRY(bst);
   }
   hipStream_t s = (hipStream_t)stream;
   const std::array<const void*, 4> key{d_params, d_states, d_grad_out, d_grad};

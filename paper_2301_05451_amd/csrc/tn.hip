@@ -289,11 +289,48 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// A run of small steps in one launch: one work-group per slice copy executes the steps in
-// order, with a barrier between steps (each step reads tensors the earlier ones wrote).
+// Large direct steps of many networks in one launch (a round of a batch): item i owns
+// blocks first[i] .. first[i + 1] - 1 and runs them as tn_direct_kernel would (kb = 0).
+struct DevDirectItem {
+  const DevTnStep* st;
+  const void* x;
+  const void* y;
+  void* z;
+  int32_t tb, rb;
+};
+static_assert(sizeof(DevDirectItem) == 40, "DevDirectItem layout");
+constexpr int kTnMultiMaxItems = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_direct_multi_kernel(const int32_t* __restrict__ first, const DevDirectItem* __restrict__ items, int n) {
+  using C = typename Cx<T>::type;
+  __shared__ int32_t fb[kTnMultiMaxItems + 1];
+  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
+  __shared__ T red[16];
+  __shared__ TnStepLds L;
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) fb[i] = first[i];
+  __syncthreads();
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n - 1;  // the item whose block range holds b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fb[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const DevDirectItem d = items[lo];
+  tn_build_tables<T>(d.st, &L, tx, ty);
+  __syncthreads();
+  tn_step_outputs<T>(&L, tx, ty, (const C*)d.x, (const C*)d.y, (C*)d.z, d.tb, b - fb[lo], d.rb, red);
+}
+
+// A run of small steps in one launch: one work-group per slice copy. The host orders a run's
+// steps by dependency level (a step's level is one more than the levels of the steps that
+// produce its operands); the steps of one level are independent and run on different waves
+// at once, with one barrier between levels (each level reads tensors the earlier ones wrote).
 struct DevFused {
   int32_t step;   // index in the plan's step table
-  int32_t flags;  // bit 0: X from the leaf buffer, bit 1: Y from the leaf buffer
+  int32_t flags;  // bit 0: X from the leaf buffer, bit 1: Y from the leaf buffer; bits 8..31 on
+                  // the first entry of a level: the number of entries in that level
   int64_t xo, xs, yo, ys, zo, zs;  // complex-element offsets and per-copy strides
 };
 static_assert(sizeof(DevFused) == 56, "DevFused layout");
@@ -302,38 +339,148 @@ static_assert(sizeof(DevFused) == 56, "DevFused layout");
 // (outputs x summed assignments) at most 2^16 complex products.
 constexpr int kTnFusedMaxOut = 12;
 constexpr int kTnFusedMaxWork = 16;
+constexpr int kTnFusedThreads = 1024;  // 16 waves: up to 16 steps of a level at once
 
+// Byte i of a step record's position arrays, read through aligned words with a wave-uniform
+// index (scalar loads; byte loads would be vector loads, each a memory round trip).
+__device__ __forceinline__ int tn_pos_byte(const uint32_t* __restrict__ w, int i) {
+  const int off = 8 + i;  // the arrays start after zr and ks
+  return (int)((w[off >> 2] >> (8 * (off & 3))) & 0xffu);
+}
+
+// One wave's share of one small step (output rank zr, ks summed bits, zr + ks <= 16, so
+// every operand index fits 32 bits): output rounds r = part, part + parts, ... of 64 / 2^tb
+// outputs, 2^tb lanes per output. A lane's summed assignments are its low tb bits (from the
+// lane), the next cb <= 3 bits (unrolled, offsets from uniform registers) and the remaining
+// bits walked in Gray-code order (one uniform bit toggle per block of 2^cb products). The
+// lanes of an output add their sums by a butterfly: a fixed order, so results repeat bitwise.
 template <typename T>
-__device__ __forceinline__ void tn_run_list(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list,
-                                            int n, const typename Cx<T>::type* __restrict__ leaves,
-                                            typename Cx<T>::type* __restrict__ ws, int64_t c, int64_t* tx,
-                                            int64_t* ty, T* red, TnStepLds* L) {
+__device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, const typename Cx<T>::type* __restrict__ x,
+                                             const typename Cx<T>::type* __restrict__ y,
+                                             typename Cx<T>::type* __restrict__ z, int part, int parts) {
   using C = typename Cx<T>::type;
-  for (int k = 0; k < n; ++k) {
-    const DevFused f = list[k];
-    const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
-    const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
-    C* z = ws + f.zo + f.zs * c;
-    tn_build_tables<T>(steps + f.step, L, tx, ty);
-    __syncthreads();
-    // enough lanes per output to give the 256 threads work: 2^tb with tb = 8 - zr, capped
-    // by the summed bits and at 8
-    int tb = 8 - L->st.zr;
-    tb = tb < 0 ? 0 : tb;
-    tb = tb > L->st.ks ? L->st.ks : tb;
-    tn_step_outputs<T>(L, tx, ty, x, y, z, tb, 0, 1, red);
-    __syncthreads();
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(stp);
+  const int zr = (int)w[0], ks = (int)w[1];
+  constexpr int XO = 0, YO = kTnMaxBits, XS = 2 * kTnMaxBits, YS = 3 * kTnMaxBits;
+  const int lane = threadIdx.x & 63;
+  int tb = 6 - zr;
+  tb = tb < 0 ? 0 : (tb > ks ? ks : tb);
+  const int opr = 64 >> tb;  // outputs per round
+  const int lsub = lane & ((1 << tb) - 1), lhi = lane >> tb;
+  // summed bits 0..tb-1: from the lane
+  uint32_t xl = 0, yl = 0;
+  for (int j = 0; j < tb; ++j) {
+    const int px = tn_pos_byte(w, XS + j), py = tn_pos_byte(w, YS + j);
+    const uint32_t bit = (uint32_t)(lsub >> j) & 1u;
+    if (px != kNone) xl |= bit << px;
+    if (py != kNone) yl |= bit << py;
+  }
+  // output bits below lo: from the lane (opr = 2^(6 - tb) outputs per round)
+  const int lo = zr < 6 - tb ? zr : 6 - tb;
+  for (int i = 0; i < lo; ++i) {
+    const int px = tn_pos_byte(w, XO + i), py = tn_pos_byte(w, YO + i);
+    const uint32_t bit = (uint32_t)(lhi >> i) & 1u;
+    if (px != kNone) xl |= bit << px;
+    if (py != kNone) yl |= bit << py;
+  }
+  // summed bits tb..tb+cb-1: 2^cb uniform offsets
+  const int nhb = ks - tb;
+  const int cb = nhb < 3 ? nhb : 3;
+  const int nin = 1 << cb;
+  uint32_t ix[8], iy[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    ix[v] = 0;
+    iy[v] = 0;
+    for (int j = 0; j < cb; ++j) {
+      const int px = tn_pos_byte(w, XS + tb + j), py = tn_pos_byte(w, YS + tb + j);
+      if (((v >> j) & 1) && px != kNone) ix[v] |= 1u << px;
+      if (((v >> j) & 1) && py != kNone) iy[v] |= 1u << py;
+    }
+  }
+  const int nu = 1 << (nhb - cb);
+  const int nz = 1 << zr;
+  for (int r = part; r * opr < nz; r += parts) {
+    // output bits lo.. of the round: uniform
+    const int e0 = r * opr;
+    uint32_t xr = 0, yr = 0;
+    for (int i = lo; i < zr; ++i) {
+      const int px = tn_pos_byte(w, XO + i), py = tn_pos_byte(w, YO + i);
+      const uint32_t bit = (uint32_t)(e0 >> i) & 1u;
+      if (px != kNone) xr |= bit << px;
+      if (py != kNone) yr |= bit << py;
+    }
+    const int e = e0 + lhi;
+    const bool valid = e < nz;
+    uint32_t xb = xr | xl, yb = yr | yl;
+    T ar = 0, ai = 0;
+    for (int u = 0; u < nu; ++u) {
+      if (valid) {
+        C a[8], b[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          if (v < nin) {
+            a[v] = x[xb | ix[v]];
+            b[v] = y[yb | iy[v]];
+          }
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+          if (v < nin) {
+            ar += a[v].x * b[v].x - a[v].y * b[v].y;
+            ai += a[v].x * b[v].y + a[v].y * b[v].x;
+          }
+      }
+      if (u + 1 < nu) {  // Gray code: the next block differs in one summed bit
+        const int j = tb + cb + __builtin_ctz((unsigned)(u + 1));
+        const int px = tn_pos_byte(w, XS + j), py = tn_pos_byte(w, YS + j);
+        if (px != kNone) xb ^= 1u << px;
+        if (py != kNone) yb ^= 1u << py;
+      }
+    }
+    for (int off = 1; off < (1 << tb); off <<= 1) {
+      ar += __shfl_xor(ar, off, 64);
+      ai += __shfl_xor(ai, off, 64);
+    }
+    if (valid && lsub == 0) {
+      C o;
+      o.x = ar;
+      o.y = ai;
+      z[e] = o;
+    }
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ void tn_run_list(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list,
+                                            int n, const typename Cx<T>::type* __restrict__ leaves,
+                                            typename Cx<T>::type* __restrict__ ws, int64_t c) {
+  using C = typename Cx<T>::type;
+  const int W = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6);
+  for (int k = 0; k < n;) {
+    const int m = max(1, list[k].flags >> 8);  // entries of this level
+    // a level of m >= W steps: wave w takes entries w, w + W, ...; a smaller level gives
+    // each step q = W / m waves, which split its output rounds
+    const int q = m >= W ? 1 : W / m;
+    const int first = m >= W ? wave : wave / q;
+    const int stride = m >= W ? W : m;  // (with q > 1 a wave takes at most one entry)
+    for (int i = first; i < m; i += stride) {
+      const DevFused f = list[k + i];
+      const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
+      const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
+      C* z = ws + f.zo + f.zs * c;
+      tn_wave_step<T>(steps + f.step, x, y, z, q > 1 ? wave % q : 0, q);
+      if (q > 1) break;
+    }
+    __syncthreads();
+    k += m;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTnFusedThreads)
     tn_fused_kernel(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list, int n,
                     const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
-  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
-  __shared__ T red[16];
-  __shared__ TnStepLds L;
-  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x, tx, ty, red, &L);
+  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x);
 }
 
 // Many networks at once: items of one launch, one work-group each.
@@ -362,13 +509,9 @@ struct DevEnvItem {  // leaf environments of one unsliced network into its gradi
 static_assert(sizeof(DevEnvItem) == 32, "DevEnvItem layout");
 
 template <typename T>
-__global__ void __launch_bounds__(256) tn_fused_multi_kernel(const DevFusedItem* __restrict__ items) {
-  __shared__ int64_t tx[1 << kTnTabBits], ty[1 << kTnTabBits];
-  __shared__ T red[16];
-  __shared__ TnStepLds L;
+__global__ void __launch_bounds__(kTnFusedThreads) tn_fused_multi_kernel(const DevFusedItem* __restrict__ items) {
   const DevFusedItem& d = items[blockIdx.x];
-  tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0, tx,
-                 ty, red, &L);
+  tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0);
 }
 
 template <typename T>
@@ -1101,6 +1244,40 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
       }
     }
   }
+  // order each fused run by dependency level and mark the levels (a topological order: a
+  // step's operands come from leaves, earlier segments or lower levels of its run)
+  auto levelize = [](std::vector<DevFused>& lst, const tq_tn_plan::Seg& sg, const std::vector<TnExec>& ex,
+                     bool reverse) {
+    std::map<int, int> made;  // tensor (or environment slot) -> level in this run
+    std::vector<std::pair<int, int>> order;  // (level, position in the run)
+    for (int i = 0; i < sg.count; ++i) {
+      const TnExec& e = ex[lst[sg.list + i].step];
+      int l = 0;
+      auto it = made.find(e.x);
+      if (it != made.end()) l = std::max(l, it->second);
+      if (!reverse) {  // the reverse pass reads forward values as its y operands
+        it = made.find(e.y);
+        if (it != made.end()) l = std::max(l, it->second);
+      }
+      made[e.z] = l + 1;
+      order.emplace_back(l + 1, i);
+    }
+    std::stable_sort(order.begin(), order.end());
+    std::vector<DevFused> run;
+    for (auto& o : order) run.push_back(lst[sg.list + o.second]);
+    for (size_t i = 0; i < run.size();) {
+      size_t j = i;
+      while (j < run.size() && order[j].first == order[i].first) ++j;
+      for (size_t k = i; k < j; ++k) run[k].flags &= 0xff;
+      run[i].flags |= (int32_t)((j - i) << 8);
+      i = j;
+    }
+    std::copy(run.begin(), run.end(), lst.begin() + sg.list);
+  };
+  for (const auto& sg : p->fseg)
+    if (sg.fused) levelize(ff, sg, p->fwd, false);
+  for (const auto& sg : p->bseg)
+    if (sg.fused) levelize(bf, sg, p->bwd, true);
   std::vector<int64_t> le;
   for (int l = 0; l < L; ++l) {
     const TnTensorInfo& t = p->t[l];
@@ -1221,27 +1398,36 @@ struct TnRun {
   int64_t esz(int i) const { return int64_t(1) << p->t[i].rank; }
 };
 
-// One large direct step over the device: 2^tb lanes per output, enough lanes in total
-// (about 2^16) to fill the machine, at most 256 per output.
-template <typename T>
-static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep& h, const typename Cx<T>::type* x,
-                           int64_t xs, const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs,
-                           int64_t copies) {
-  using C = typename Cx<T>::type;
+// Launch shape of a direct step: 2^tb lanes per output, enough lanes in total (about 2^16)
+// to fill the machine, at most 256 per output; rb work-groups over the output rounds; a step
+// with few outputs and many summed assignments also splits its summed range over 2^kb
+// chunks of work-groups (up to about 2^17 lanes, within the plan's partial-sum region).
+static void direct_shape(const DevTnStep& h, int64_t copies, int64_t split_elems, int* tbp, int* kbp, unsigned* rbp) {
   const int zr = h.zr, ks = h.ks;
   int tb = std::max(0, 16 - zr);
   tb = std::min(tb, std::min(8, ks));
   const int64_t nz = int64_t(1) << zr;
   const int64_t gpb = 256 >> tb;
   const int64_t rounds = (nz + gpb - 1) / gpb;
-  // few outputs with many summed assignments: split the summed range over work-groups too,
-  // up to about 2^17 lanes, within the plan's partial-sum region
   const int kt = std::min(ks, kTnTabBits);
   int kb = 0;
-  while (kb < ks - kt && (nz << (tb + kb)) * copies < (int64_t(1) << 17) &&
-         (nz << (kb + 1)) * copies <= R.p->split_elems)
+  while (kb < ks - kt && (nz << (tb + kb)) * copies < (int64_t(1) << 17) && (nz << (kb + 1)) * copies <= split_elems)
     ++kb;
-  const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
+  *tbp = tb;
+  *kbp = kb;
+  *rbp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
+}
+
+// One large direct step over the device (shape from direct_shape).
+template <typename T>
+static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep& h, const typename Cx<T>::type* x,
+                           int64_t xs, const typename Cx<T>::type* y, int64_t ys, typename Cx<T>::type* z, int64_t zs,
+                           int64_t copies) {
+  using C = typename Cx<T>::type;
+  int tb, kb;
+  unsigned rb;
+  direct_shape(h, copies, R.p->split_elems, &tb, &kb, &rb);
+  const int64_t nz = int64_t(1) << h.zr;
   C* P = R.ws + R.p->split_off;
   const int64_t ps = nz << kb;
   for (int64_t c0 = 0; c0 < copies; c0 += 65535) {
@@ -1259,7 +1445,8 @@ static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep&
 // A run of small steps: one work-group per slice copy (grid x; copies <= 2^24).
 template <typename T>
 static tq_status tn_fused(TnRun<T>& R, const DevTnStep* steps, const void* list, int n, int64_t copies) {
-  hipLaunchKernelGGL(tn_fused_kernel<T>, dim3((unsigned)copies), dim3(256), 0, R.st, steps, (const DevFused*)list, n,
+  hipLaunchKernelGGL(tn_fused_kernel<T>, dim3((unsigned)copies), dim3(kTnFusedThreads), 0, R.st, steps,
+                     (const DevFused*)list, n,
                      R.leaves, R.ws);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
@@ -1521,7 +1708,16 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
     blob.insert(blob.end(), (const unsigned char*)x, (const unsigned char*)x + bytes);
     return off;
   };
-  auto rounds = [&](bool fwd, std::vector<std::pair<size_t, int>>& tab) {
+  // per round: the fused runs (one launch), and the plain direct steps of every network
+  // (one multi-network launch, up to kTnMultiMaxItems per launch; the rest launch alone)
+  struct DirectRound {
+    size_t first_off = 0, items_off = 0;
+    int count = 0;
+    int64_t blocks = 0;
+  };
+  std::vector<std::vector<char>> fdone, bdone;  // [round][network]: run by a multi launch
+  auto rounds = [&](bool fwd, std::vector<std::pair<size_t, int>>& tab, std::vector<std::vector<DirectRound>>& dtab,
+                    std::vector<std::vector<char>>& done) {
     size_t rmax = 0;
     for (size_t i = 0; i < n; ++i) rmax = std::max(rmax, (fwd ? P[i]->fseg : P[i]->bseg).size());
     for (size_t r = 0; r < rmax; ++r) {
@@ -1540,10 +1736,61 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
         ++cnt;
       }
       tab.push_back({off, cnt});
+      // direct steps of this round
+      std::vector<DevDirectItem> items;
+      std::vector<char> dn(n, 0);
+      for (size_t i = 0; i < n; ++i) {
+        const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;
+        if (r >= segs.size() || segs[r].fused) continue;
+        const size_t k = (size_t)segs[r].first;
+        const TnExec& ex = fwd ? P[i]->fwd[k] : P[i]->bwd[k];
+        if (ex.method != 0) continue;
+        int tb, kb;
+        unsigned rb;
+        direct_shape(ex.dev, 1, P[i]->split_elems, &tb, &kb, &rb);
+        if (kb != 0) continue;
+        DevDirectItem d{};
+        d.st = (const DevTnStep*)(fwd ? P[i]->d_fwd : P[i]->d_bwd) + k;
+        int64_t st;
+        if (fwd) {
+          d.x = R[i].tptr(ex.x, &st);
+          d.y = R[i].tptr(ex.y, &st);
+          d.z = R[i].tptr(ex.z, &st);
+        } else {
+          d.x = R[i].eptr(ex.x);
+          d.y = R[i].tptr(ex.y, &st);
+          d.z = R[i].eptr(ex.z);
+        }
+        d.tb = tb;
+        d.rb = (int32_t)rb;
+        items.push_back(d);
+        dn[i] = 1;
+      }
+      std::vector<DirectRound> drs;
+      for (size_t a = 0; a < items.size(); a += kTnMultiMaxItems) {
+        const size_t b = std::min(items.size(), a + (size_t)kTnMultiMaxItems);
+        DirectRound dr;
+        std::vector<int32_t> first;
+        int64_t blocks = 0;
+        for (size_t j = a; j < b; ++j) {
+          first.push_back((int32_t)blocks);
+          blocks += items[j].rb;
+        }
+        first.push_back((int32_t)blocks);
+        dr.first_off = put(first.data(), first.size() * sizeof(int32_t));
+        while (blob.size() % 16) blob.push_back(0);
+        dr.items_off = put(items.data() + a, (b - a) * sizeof(DevDirectItem));
+        dr.count = (int)(b - a);
+        dr.blocks = blocks;
+        drs.push_back(dr);
+      }
+      dtab.push_back(drs);
+      done.push_back(dn);
     }
   };
   std::vector<std::pair<size_t, int>> ftab, btab;
-  rounds(true, ftab);
+  std::vector<std::vector<DirectRound>> fdt, bdt;
+  rounds(true, ftab, fdt, fdone);
   size_t head_off = 0, tail_off = 0;
   if (mode == 0) {
     tail_off = blob.size();
@@ -1557,7 +1804,7 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
       DevCopyItem c{G[i], (C*)Wk[i] + P[i]->env_off[P[i]->root], int64_t(1) << P[i]->t[P[i]->root].rank};
       put(&c, sizeof c);
     }
-    rounds(false, btab);
+    rounds(false, btab, bdt, bdone);
     tail_off = blob.size();
     for (size_t i = 0; i < n; ++i) {
       DevEnvItem e{(const int64_t*)P[i]->d_leaf_env, Wk[i], O[i], P[i]->n_leaf_env, 0};
@@ -1567,22 +1814,29 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
   void* dev;
   TQ_TRY(stage_upload(ctx, S_TNB, blob.data(), blob.size(), stream, &dev));
   const unsigned char* db = (const unsigned char*)dev;
-  auto run_rounds = [&](bool fwd, const std::vector<std::pair<size_t, int>>& tab) -> tq_status {
+  auto run_rounds = [&](bool fwd, const std::vector<std::pair<size_t, int>>& tab,
+                        const std::vector<std::vector<DirectRound>>& dtab,
+                        const std::vector<std::vector<char>>& done) -> tq_status {
     for (size_t r = 0; r < tab.size(); ++r) {
       if (tab[r].second > 0) {
-        hipLaunchKernelGGL(tn_fused_multi_kernel<T>, dim3((unsigned)tab[r].second), dim3(256), 0, stream,
+        hipLaunchKernelGGL(tn_fused_multi_kernel<T>, dim3((unsigned)tab[r].second), dim3(kTnFusedThreads), 0, stream,
                            (const DevFusedItem*)(db + tab[r].first));
+        TQ_HIP(hipGetLastError());
+      }
+      for (const DirectRound& dr : dtab[r]) {
+        hipLaunchKernelGGL(tn_direct_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
+                           (const int32_t*)(db + dr.first_off), (const DevDirectItem*)(db + dr.items_off), dr.count);
         TQ_HIP(hipGetLastError());
       }
       for (size_t i = 0; i < n; ++i) {
         const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;
-        if (r < segs.size() && !segs[r].fused)
+        if (r < segs.size() && !segs[r].fused && !done[r][i])
           TQ_TRY(fwd ? tn_fwd_wide<T>(R[i], segs[r]) : tn_bwd_wide<T>(R[i], segs[r]));
       }
     }
     return TQ_OK;
   };
-  TQ_TRY(run_rounds(true, ftab));
+  TQ_TRY(run_rounds(true, ftab, fdt, fdone));
   if (mode == 0) {
     hipLaunchKernelGGL(tn_copy_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
                        (const DevCopyItem*)(db + tail_off));
@@ -1592,7 +1846,7 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
   hipLaunchKernelGGL(tn_copy_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
                      (const DevCopyItem*)(db + head_off));
   TQ_HIP(hipGetLastError());
-  TQ_TRY(run_rounds(false, btab));
+  TQ_TRY(run_rounds(false, btab, bdt, bdone));
   hipLaunchKernelGGL(tn_env_multi_kernel<T>, dim3((unsigned)n), dim3(256), 0, stream,
                      (const DevEnvItem*)(db + tail_off));
   TQ_HIP(hipGetLastError());

@@ -216,6 +216,8 @@ struct tq_ctx {
   std::vector<void*> retired;
   // autotune results: key -> (t, R)
   std::unordered_map<std::string, std::pair<int, int>> tuned;
+  // imported autotune results: digest of (structure, pass) -> (t, R)
+  std::unordered_map<std::string, std::pair<int, int>> tuned_digest;
 };
 
 namespace tq {

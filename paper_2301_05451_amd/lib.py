@@ -283,6 +283,41 @@ def optimizer_step(params, grad, lr, step=1, m=None, v=None, adam=False, beta1=0
     return params
 
 
+_lib.tq_ctx_export_tuning.argtypes = [_vp, _vp, ct.c_int64]
+_lib.tq_ctx_export_tuning.restype = ct.c_int64
+_lib.tq_ctx_import_tuning.argtypes = [_vp, _vp, ct.c_int64]
+_lib.tq_ctx_import_tuning.restype = ct.c_int
+
+
+def export_tuning(ctx=None) -> bytes:
+    """The context's autotune table as bytes (tq_ctx_export_tuning)."""
+    ctx = ctx or context()
+    n = _lib.tq_ctx_export_tuning(ctx.h, None, 0)
+    if n < 0:
+        raise TQError(1, last_error())
+    buf = ct.create_string_buffer(int(n))
+    if _lib.tq_ctx_export_tuning(ctx.h, buf, n) != n:
+        raise TQError(2, last_error())
+    return buf.raw
+
+
+def import_tuning(data: bytes, ctx=None):
+    """Load an autotune table written by export_tuning into the context (tq_ctx_import_tuning)."""
+    ctx = ctx or context()
+    buf = ct.create_string_buffer(bytes(data), len(data))
+    check(_lib.tq_ctx_import_tuning(ctx.h, buf, len(data)))
+
+
+def save_tuning(path, ctx=None):
+    with open(path, "wb") as f:
+        f.write(export_tuning(ctx))
+
+
+def load_tuning(path, ctx=None):
+    with open(path, "rb") as f:
+        import_tuning(f.read(), ctx)
+
+
 _lib.tq_pauli_decompose.argtypes = [_vp, _i32, _vp, ct.c_double, _i32, _vp, _i32]
 _lib.tq_pauli_decompose.restype = ct.c_int32
 

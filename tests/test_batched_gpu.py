@@ -164,6 +164,27 @@ def test_autotune_keeps_results():
     # a new compiled batch of the same structure starts from the tuned shape
     again = lib.SVBatch(spec, TERMS, 2)
     assert (again.info["tile_bits"], again.info["reg_bits"]) == (tf[0], tf[1])
+    # the table survives export / import into a fresh context (as across processes)
+    table = lib.export_tuning()
+    assert table[:4] == b"TQTU" and (len(table) - 16) % 40 == 0 and len(table) >= 16 + 40 * 2
+    fresh = lib.Context(0)
+    lib.import_tuning(table, ctx=fresh)
+    moved = lib.SVBatch(spec, TERMS, 2, ctx=fresh)
+    assert (moved.info["tile_bits"], moved.info["reg_bits"]) == (tf[0], tf[1])
+    m_states = moved.new_states()
+    m_out = moved.forward(params, m_states)
+    m_grad = moved.backward(params, m_states, gw)
+    torch.cuda.synchronize()
+    assert torch.equal(m_out, out) and torch.equal(m_grad, grad)
+    assert lib.export_tuning(ctx=fresh) == table
+    with pytest.raises(lib.TQError):
+        lib.import_tuning(b"TQTU" + bytes(8), ctx=fresh)  # truncated header
+    bad = bytearray(table)
+    bad[16 + 32:16 + 36] = (99).to_bytes(4, "little")  # tile bits out of range
+    with pytest.raises(lib.TQError):
+        lib.import_tuning(bytes(bad), ctx=fresh)
+    moved.close()
+    fresh.close()
 
 
 def test_qnn512_batch_matches_single_structure_path_and_oracle():
