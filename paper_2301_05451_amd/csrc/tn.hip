@@ -243,6 +243,73 @@ __device__ __forceinline__ void tn_step_outputs(const TnStepLds* L, const int64_
   }
 }
 
+// Wide steps with one lane per output and few summed bits (ks <= kTnWideMaxKs): each lane
+// takes kTnWideOpl outputs per round (e = e0 + tid + 256 j, so every load instruction stays
+// coalesced across the lanes), and issues all their loads before any multiply, which keeps
+// several times more bytes in flight per lane than one output at a time. Same sums in the
+// same order as tn_step_outputs with 2^0 lanes per output.
+constexpr int kTnWideOpl = 4;
+constexpr int kTnWideMaxKs = 3;
+
+template <typename T>
+__device__ __forceinline__ void tn_step_outputs_wide(const TnStepLds* L, const int64_t* tx, const int64_t* ty,
+                                                     const typename Cx<T>::type* __restrict__ x,
+                                                     const typename Cx<T>::type* __restrict__ y,
+                                                     typename Cx<T>::type* __restrict__ z, int64_t gfirst,
+                                                     int64_t gstride) {
+  using C = typename Cx<T>::type;
+  const DevTnStep* st = &L->st;
+  const int zr = st->zr, nt = 1 << st->ks;
+  const int64_t nz = int64_t(1) << zr;
+  const int64_t per = (int64_t)blockDim.x * kTnWideOpl;  // outputs per round (divides 2^16)
+  for (int64_t r = gfirst; r * per < nz; r += gstride) {
+    const int64_t e0 = r * per;
+    int64_t xhi = 0, yhi = 0;  // output bits 16 and up: the same for the whole round
+    if (zr > 16) {
+      xhi = deposit_bits((uint64_t)e0 >> 16, st->xo + 16, zr - 16);
+      yhi = deposit_bits((uint64_t)e0 >> 16, st->yo + 16, zr - 16);
+    }
+    int64_t xb[kTnWideOpl], yb[kTnWideOpl];
+    bool ok[kTnWideOpl];
+#pragma unroll
+    for (int j = 0; j < kTnWideOpl; ++j) {
+      const int64_t e = e0 + threadIdx.x + (int64_t)blockDim.x * j;
+      ok[j] = e < nz;
+      xb[j] = xhi + L->ox[0][e & 255] + L->ox[1][(e >> 8) & 255];
+      yb[j] = yhi + L->oy[0][e & 255] + L->oy[1][(e >> 8) & 255];
+    }
+    T ar[kTnWideOpl], ai[kTnWideOpl];
+#pragma unroll
+    for (int j = 0; j < kTnWideOpl; ++j) ar[j] = ai[j] = 0;
+    for (int sl = 0; sl < nt; ++sl) {
+      C a[kTnWideOpl], b[kTnWideOpl];
+#pragma unroll
+      for (int j = 0; j < kTnWideOpl; ++j)
+        if (ok[j]) {
+          a[j] = x[xb[j] + tx[sl]];
+          b[j] = y[yb[j] + ty[sl]];
+        }
+#pragma unroll
+      for (int j = 0; j < kTnWideOpl; ++j)
+        if (ok[j]) {
+          ar[j] += a[j].x * b[j].x - a[j].y * b[j].y;
+          ai[j] += a[j].x * b[j].y + a[j].y * b[j].x;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kTnWideOpl; ++j)
+      if (ok[j]) {
+        C o;
+        o.x = ar[j];
+        o.y = ai[j];
+        z[e0 + threadIdx.x + (int64_t)blockDim.x * j] = o;
+      }
+  }
+}
+
+// The kernel takes the wide form for these steps (the host sizes the grid alike).
+__host__ __device__ __forceinline__ bool tn_wide_form(int tb, int ks) { return tb == 0 && ks <= kTnWideMaxKs; }
+
 // One step over the whole device; blockIdx.y = slice copy (stride 0 for shared tensors).
 // With kb > 0 the summed range is also split over 2^kb chunks of work-groups: block x runs
 // output rounds (x mod rb) for chunk (x / rb) and writes partial sums P[e][chunk]; the
@@ -260,7 +327,10 @@ __global__ void __launch_bounds__(256)
   const typename Cx<T>::type* x = X + xs * blockIdx.y;
   const typename Cx<T>::type* y = Y + ys * blockIdx.y;
   if (kb == 0) {
-    tn_step_outputs<T>(&L, tx, ty, x, y, Z + zs * blockIdx.y, tb, blockIdx.x, gridDim.x, red);
+    if (tn_wide_form(tb, L.st.ks))
+      tn_step_outputs_wide<T>(&L, tx, ty, x, y, Z + zs * blockIdx.y, blockIdx.x, gridDim.x);
+    else
+      tn_step_outputs<T>(&L, tx, ty, x, y, Z + zs * blockIdx.y, tb, blockIdx.x, gridDim.x, red);
     return;
   }
   const int kt = L.st.ks < kTnTabBits ? L.st.ks : kTnTabBits;
@@ -290,16 +360,29 @@ __global__ void __launch_bounds__(256)
 }
 
 // Large direct steps of many networks in one launch (a round of a batch): item i owns
-// blocks first[i] .. first[i + 1] - 1 and runs them as tn_direct_kernel would (kb = 0).
+// blocks first[i] .. first[i + 1] - 1 and runs them as tn_direct_kernel would: kb = 0 writes
+// the outputs; kb > 0 splits the summed range over 2^kb chunks of rb blocks each and writes
+// partial sums P[e][chunk], added afterwards by tn_chunk_sum_multi_kernel.
 struct DevDirectItem {
   const DevTnStep* st;
   const void* x;
   const void* y;
   void* z;
-  int32_t tb, rb;
+  void* P;  // partial sums (kb > 0)
+  int32_t tb, rb, kb, pad;
 };
-static_assert(sizeof(DevDirectItem) == 40, "DevDirectItem layout");
+static_assert(sizeof(DevDirectItem) == 56, "DevDirectItem layout");
 constexpr int kTnMultiMaxItems = 1024;
+
+// The item of block b: the largest i with fb[i] <= b (fb in LDS, n items).
+__device__ __forceinline__ int tn_item_of(const int32_t* fb, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fb[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -312,15 +395,58 @@ __global__ void __launch_bounds__(256)
   for (int i = threadIdx.x; i <= n; i += blockDim.x) fb[i] = first[i];
   __syncthreads();
   const int b = (int)blockIdx.x;
-  int lo = 0, hi = n - 1;  // the item whose block range holds b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (fb[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  const DevDirectItem d = items[lo];
+  const int it = tn_item_of(fb, n, b);
+  const DevDirectItem d = items[it];
+  const int lb = b - fb[it];
   tn_build_tables<T>(d.st, &L, tx, ty);
   __syncthreads();
-  tn_step_outputs<T>(&L, tx, ty, (const C*)d.x, (const C*)d.y, (C*)d.z, d.tb, b - fb[lo], d.rb, red);
+  if (d.kb == 0) {
+    if (tn_wide_form(d.tb, L.st.ks))
+      tn_step_outputs_wide<T>(&L, tx, ty, (const C*)d.x, (const C*)d.y, (C*)d.z, lb, d.rb);
+    else
+      tn_step_outputs<T>(&L, tx, ty, (const C*)d.x, (const C*)d.y, (C*)d.z, d.tb, lb, d.rb, red);
+    return;
+  }
+  const int kt = L.st.ks < kTnTabBits ? L.st.ks : kTnTabBits;
+  const int64_t per = (int64_t(1) << (L.st.ks - kt)) >> d.kb;  // outer chunks per split
+  const int64_t c = lb / d.rb;
+  tn_step_outputs<T>(&L, tx, ty, (const C*)d.x, (const C*)d.y, (C*)d.P + c, d.tb, lb % d.rb, d.rb, red, c * per,
+                     (c + 1) * per, int64_t(1) << d.kb);
+}
+
+// z[e] = sum over chunks in order of P[e][chunk] for the kb > 0 items of a round: item i owns
+// blocks first[i] .. first[i + 1] - 1 (the same sums, in the same order, as
+// tn_chunk_sum_kernel).
+struct DevChunkItem {
+  const void* P;
+  void* z;
+  int64_t nz;
+  int32_t nchunks, pad;
+};
+static_assert(sizeof(DevChunkItem) == 32, "DevChunkItem layout");
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    tn_chunk_sum_multi_kernel(const int32_t* __restrict__ first, const DevChunkItem* __restrict__ items, int n) {
+  using C = typename Cx<T>::type;
+  __shared__ int32_t fb[kTnMultiMaxItems + 1];
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) fb[i] = first[i];
+  __syncthreads();
+  const int b = (int)blockIdx.x;
+  const int it = tn_item_of(fb, n, b);
+  const DevChunkItem d = items[it];
+  const int nblk = fb[it + 1] - fb[it];
+  const C* p = (const C*)d.P;
+  C* z = (C*)d.z;
+  for (int64_t e = (int64_t)(b - fb[it]) * blockDim.x + threadIdx.x; e < d.nz; e += (int64_t)nblk * blockDim.x) {
+    C v{(T)0, (T)0};
+    for (int c = 0; c < d.nchunks; ++c) {
+      const C q = p[e * d.nchunks + c];
+      v.x += q.x;
+      v.y += q.y;
+    }
+    z[e] = v;
+  }
 }
 
 // A run of small steps in one launch: one work-group per slice copy. The host orders a run's
@@ -331,9 +457,22 @@ struct DevFused {
   int32_t step;   // index in the plan's step table
   int32_t flags;  // bit 0: X from the leaf buffer, bit 1: Y from the leaf buffer; bits 8..31 on
                   // the first entry of a level: the number of entries in that level
+  int32_t r0;     // first output round of this step in its level's list of rounds
+  int32_t rn;     // output rounds of this step (tn_wave_rounds)
+  int32_t lw;     // on the first entry of a level: the level's total rounds
+  int32_t pad;
   int64_t xo, xs, yo, ys, zo, zs;  // complex-element offsets and per-copy strides
 };
-static_assert(sizeof(DevFused) == 56, "DevFused layout");
+static_assert(sizeof(DevFused) == 72, "DevFused layout");
+
+// Output rounds of a small step on one wave: 64 / 2^tb outputs per round, tb = the lanes per
+// output (6 - zr, within 0..ks).
+__host__ __device__ __forceinline__ int tn_wave_rounds(int zr, int ks) {
+  int tb = 6 - zr;
+  tb = tb < 0 ? 0 : (tb > ks ? ks : tb);
+  const int opr = 64 >> tb;
+  return ((1 << zr) + opr - 1) / opr;
+}
 
 // Steps run inside a fused run when their output has at most 2^12 elements and their work
 // (outputs x summed assignments) at most 2^16 complex products.
@@ -341,27 +480,29 @@ constexpr int kTnFusedMaxOut = 12;
 constexpr int kTnFusedMaxWork = 16;
 constexpr int kTnFusedThreads = 1024;  // 16 waves: up to 16 steps of a level at once
 
-// Byte i of a step record's position arrays, read through aligned words with a wave-uniform
-// index (scalar loads; byte loads would be vector loads, each a memory round trip).
-__device__ __forceinline__ int tn_pos_byte(const uint32_t* __restrict__ w, int i) {
-  const int off = 8 + i;  // the arrays start after zr and ks
-  return (int)((w[off >> 2] >> (8 * (off & 3))) & 0xffu);
-}
+// A small step's record as a fused run keeps it in LDS: output rank, summed bits, and the
+// first 16 entries of each position array (a small step has at most 16 bits in all).
+struct TnSmallStep {
+  int32_t zr, ks;
+  uint8_t pos[4][16];  // output bits in X, in Y; summed bits in X, in Y (kNone if absent)
+};
+static_assert(sizeof(TnSmallStep) == 72, "TnSmallStep layout");
+constexpr int kTnRunCap = 512;  // entries of one fused run (the host splits longer runs)
 
 // One wave's share of one small step (output rank zr, ks summed bits, zr + ks <= 16, so
-// every operand index fits 32 bits): output rounds r = part, part + parts, ... of 64 / 2^tb
-// outputs, 2^tb lanes per output. A lane's summed assignments are its low tb bits (from the
+// every operand index fits 32 bits): output rounds r0 <= r < r1 of 64 / 2^tb outputs, 2^tb
+// lanes per output. A lane's summed assignments are its low tb bits (from the
 // lane), the next cb <= 3 bits (unrolled, offsets from uniform registers) and the remaining
 // bits walked in Gray-code order (one uniform bit toggle per block of 2^cb products). The
 // lanes of an output add their sums by a butterfly: a fixed order, so results repeat bitwise.
 template <typename T>
-__device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, const typename Cx<T>::type* __restrict__ x,
+__device__ __forceinline__ void tn_wave_step(const TnSmallStep* stp, const typename Cx<T>::type* __restrict__ x,
                                              const typename Cx<T>::type* __restrict__ y,
-                                             typename Cx<T>::type* __restrict__ z, int part, int parts) {
+                                             typename Cx<T>::type* __restrict__ z, int r0, int r1) {
   using C = typename Cx<T>::type;
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(stp);
-  const int zr = (int)w[0], ks = (int)w[1];
-  constexpr int XO = 0, YO = kTnMaxBits, XS = 2 * kTnMaxBits, YS = 3 * kTnMaxBits;
+  const int zr = stp->zr, ks = stp->ks;
+  constexpr int XO = 0, YO = 1, XS = 2, YS = 3;
+  auto tn_pos_byte = [stp](int arr, int i) -> int { return stp->pos[arr][i]; };
   const int lane = threadIdx.x & 63;
   int tb = 6 - zr;
   tb = tb < 0 ? 0 : (tb > ks ? ks : tb);
@@ -370,7 +511,7 @@ __device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, 
   // summed bits 0..tb-1: from the lane
   uint32_t xl = 0, yl = 0;
   for (int j = 0; j < tb; ++j) {
-    const int px = tn_pos_byte(w, XS + j), py = tn_pos_byte(w, YS + j);
+    const int px = tn_pos_byte(XS, j), py = tn_pos_byte(YS, j);
     const uint32_t bit = (uint32_t)(lsub >> j) & 1u;
     if (px != kNone) xl |= bit << px;
     if (py != kNone) yl |= bit << py;
@@ -378,7 +519,7 @@ __device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, 
   // output bits below lo: from the lane (opr = 2^(6 - tb) outputs per round)
   const int lo = zr < 6 - tb ? zr : 6 - tb;
   for (int i = 0; i < lo; ++i) {
-    const int px = tn_pos_byte(w, XO + i), py = tn_pos_byte(w, YO + i);
+    const int px = tn_pos_byte(XO, i), py = tn_pos_byte(YO, i);
     const uint32_t bit = (uint32_t)(lhi >> i) & 1u;
     if (px != kNone) xl |= bit << px;
     if (py != kNone) yl |= bit << py;
@@ -393,19 +534,19 @@ __device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, 
     ix[v] = 0;
     iy[v] = 0;
     for (int j = 0; j < cb; ++j) {
-      const int px = tn_pos_byte(w, XS + tb + j), py = tn_pos_byte(w, YS + tb + j);
+      const int px = tn_pos_byte(XS, tb + j), py = tn_pos_byte(YS, tb + j);
       if (((v >> j) & 1) && px != kNone) ix[v] |= 1u << px;
       if (((v >> j) & 1) && py != kNone) iy[v] |= 1u << py;
     }
   }
   const int nu = 1 << (nhb - cb);
   const int nz = 1 << zr;
-  for (int r = part; r * opr < nz; r += parts) {
+  for (int r = r0; r < r1 && r * opr < nz; ++r) {
     // output bits lo.. of the round: uniform
     const int e0 = r * opr;
     uint32_t xr = 0, yr = 0;
     for (int i = lo; i < zr; ++i) {
-      const int px = tn_pos_byte(w, XO + i), py = tn_pos_byte(w, YO + i);
+      const int px = tn_pos_byte(XO, i), py = tn_pos_byte(YO, i);
       const uint32_t bit = (uint32_t)(e0 >> i) & 1u;
       if (px != kNone) xr |= bit << px;
       if (py != kNone) yr |= bit << py;
@@ -432,7 +573,7 @@ __device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, 
       }
       if (u + 1 < nu) {  // Gray code: the next block differs in one summed bit
         const int j = tb + cb + __builtin_ctz((unsigned)(u + 1));
-        const int px = tn_pos_byte(w, XS + j), py = tn_pos_byte(w, YS + j);
+        const int px = tn_pos_byte(XS, j), py = tn_pos_byte(YS, j);
         if (px != kNone) xb ^= 1u << px;
         if (py != kNone) yb ^= 1u << py;
       }
@@ -450,26 +591,58 @@ __device__ __forceinline__ void tn_wave_step(const DevTnStep* __restrict__ stp, 
   }
 }
 
+// A fused run (n <= kTnRunCap entries): its entry list and compact step records are first
+// copied to LDS, then the levels run as below, reading all of their metadata from LDS.
 template <typename T>
 __device__ __forceinline__ void tn_run_list(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list,
                                             int n, const typename Cx<T>::type* __restrict__ leaves,
-                                            typename Cx<T>::type* __restrict__ ws, int64_t c) {
+                                            typename Cx<T>::type* __restrict__ ws, int64_t c, DevFused* lf,
+                                            TnSmallStep* ls) {
   using C = typename Cx<T>::type;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(list);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(lf);
+    constexpr int kw = (int)(sizeof(DevFused) / 4);
+    for (int i = threadIdx.x; i < n * kw; i += blockDim.x) dst[i] = src[i];
+  }
+  __syncthreads();
+  {
+    // words 0-1: zr, ks; then 4 words from each position array (byte offsets 8, 8 + 40, ...)
+    constexpr int kw = (int)(sizeof(TnSmallStep) / 4);  // 18
+    for (int i = threadIdx.x; i < n * kw; i += blockDim.x) {
+      const int e = i / kw, w = i % kw;
+      const uint32_t* st = reinterpret_cast<const uint32_t*>(steps + lf[e].step);
+      const int sw = w < 2 ? w : 2 + ((w - 2) >> 2) * (kTnMaxBits / 4) + ((w - 2) & 3);
+      reinterpret_cast<uint32_t*>(ls + e)[w] = st[sw];
+    }
+  }
+  __syncthreads();
   const int W = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6);
   for (int k = 0; k < n;) {
-    const int m = max(1, list[k].flags >> 8);  // entries of this level
-    // a level of m >= W steps: wave w takes entries w, w + W, ...; a smaller level gives
-    // each step q = W / m waves, which split its output rounds
-    const int q = m >= W ? 1 : W / m;
-    const int first = m >= W ? wave : wave / q;
-    const int stride = m >= W ? W : m;  // (with q > 1 a wave takes at most one entry)
-    for (int i = first; i < m; i += stride) {
-      const DevFused f = list[k + i];
-      const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
-      const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
-      C* z = ws + f.zo + f.zs * c;
-      tn_wave_step<T>(steps + f.step, x, y, z, q > 1 ? wave % q : 0, q);
-      if (q > 1) break;
+    const int m = max(1, lf[k].flags >> 8);  // entries of this level
+    // the level's output rounds, in entry order, split into W contiguous shares: a wave runs
+    // its share's rounds entry by entry (a large step spreads over several waves)
+    const int total = lf[k].lw;
+    const int share = (total + W - 1) / W;
+    int w0 = wave * share;
+    const int w1 = min(total, w0 + share);
+    if (w0 < w1) {
+      int lo = 0, hi = m - 1;  // the entry holding round w0
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lf[k + mid].r0 <= w0) lo = mid; else hi = mid - 1;
+      }
+      for (int i = lo; w0 < w1 && i < m; ++i) {
+        const DevFused& f = lf[k + i];
+        const int end = min(w1, f.r0 + f.rn);
+        if (end > w0) {
+          const C* x = ((f.flags & 1) ? leaves : ws) + f.xo + f.xs * c;
+          const C* y = ((f.flags & 2) ? leaves : ws) + f.yo + f.ys * c;
+          C* z = ws + f.zo + f.zs * c;
+          tn_wave_step<T>(ls + k + i, x, y, z, w0 - f.r0, end - f.r0);
+          w0 = end;
+        }
+      }
     }
     __syncthreads();
     k += m;
@@ -480,7 +653,9 @@ template <typename T>
 __global__ void __launch_bounds__(kTnFusedThreads)
     tn_fused_kernel(const DevTnStep* __restrict__ steps, const DevFused* __restrict__ list, int n,
                     const typename Cx<T>::type* __restrict__ leaves, typename Cx<T>::type* __restrict__ ws) {
-  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x);
+  __shared__ DevFused lf[kTnRunCap];
+  __shared__ TnSmallStep ls[kTnRunCap];
+  tn_run_list<T>(steps, list, n, leaves, ws, blockIdx.x, lf, ls);
 }
 
 // Many networks at once: items of one launch, one work-group each.
@@ -510,8 +685,11 @@ static_assert(sizeof(DevEnvItem) == 32, "DevEnvItem layout");
 
 template <typename T>
 __global__ void __launch_bounds__(kTnFusedThreads) tn_fused_multi_kernel(const DevFusedItem* __restrict__ items) {
+  __shared__ DevFused lf[kTnRunCap];
+  __shared__ TnSmallStep ls[kTnRunCap];
   const DevFusedItem& d = items[blockIdx.x];
-  tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0);
+  tn_run_list<T>(d.steps, d.list, d.n, (const typename Cx<T>::type*)d.leaves, (typename Cx<T>::type*)d.ws, 0, lf,
+                 ls);
 }
 
 template <typename T>
@@ -1045,9 +1223,33 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
       if (!inA && live[id] > 0) nI.push_back(id);
     }
     TnTensorInfo C;
-    C.inds = bI;
-    C.inds.insert(C.inds.end(), mI.begin(), mI.end());
-    C.inds.insert(C.inds.end(), nI.begin(), nI.end());
+    // index order of the result: [b][m][n] when the step can run as a GEMM (its output
+    // layout); otherwise the larger operand's kept indices, in that operand's order, as the
+    // low bits, so that the lanes of the direct kernel read the larger operand and write the
+    // result at consecutive addresses (the other operand's indices go on top)
+    int n_summed_both = 0;
+    bool one_sided_sum = false;
+    for (int id : A.inds)
+      if (live[id] <= 0) {
+        if (std::find(B.inds.begin(), B.inds.end(), id) != B.inds.end()) ++n_summed_both;
+        else one_sided_sum = true;
+      }
+    for (int id : B.inds)
+      if (live[id] <= 0 && std::find(A.inds.begin(), A.inds.end(), id) == A.inds.end()) one_sided_sum = true;
+    const bool gemm_like = !one_sided_sum && mI.size() >= 6 && nI.size() >= 5 && n_summed_both >= 3 &&
+                           mI.size() + nI.size() + n_summed_both >= 18;
+    if (gemm_like) {
+      C.inds = bI;
+      C.inds.insert(C.inds.end(), mI.begin(), mI.end());
+      C.inds.insert(C.inds.end(), nI.begin(), nI.end());
+    } else {
+      const TnTensorInfo& big = A.rank >= B.rank ? A : B;
+      const TnTensorInfo& other = A.rank >= B.rank ? B : A;
+      for (int id : other.inds)
+        if (live[id] > 0 && std::find(big.inds.begin(), big.inds.end(), id) == big.inds.end()) C.inds.push_back(id);
+      for (int id : big.inds)
+        if (live[id] > 0) C.inds.push_back(id);
+    }
     for (int id : C.inds) live[id]++;
     C.rank = (int)C.inds.size();
     if (C.rank > 34) return fail(TQ_ENOTSUP, "intermediate of rank " + std::to_string(C.rank) + " (slice more)");
@@ -1190,7 +1392,8 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
       const TnExec& ex = p->fwd[k];
       const int shared = p->t[ex.z].sdep ? 0 : 1;
       if (small(ex)) {
-        if (p->fseg.empty() || !p->fseg.back().fused || p->fseg.back().shared != shared) {
+        if (p->fseg.empty() || !p->fseg.back().fused || p->fseg.back().shared != shared ||
+            p->fseg.back().count == kTnRunCap) {
           tq_tn_plan::Seg sg;
           sg.fused = 1;
           sg.first = (int)k;
@@ -1218,7 +1421,7 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     for (size_t k = 0; k < p->bwd.size(); ++k) {
       const TnExec& ex = p->bwd[k];
       if (small(ex)) {
-        if (p->bseg.empty() || !p->bseg.back().fused) {
+        if (p->bseg.empty() || !p->bseg.back().fused || p->bseg.back().count == kTnRunCap) {
           tq_tn_plan::Seg sg;
           sg.fused = 1;
           sg.first = (int)k;
@@ -1268,8 +1471,17 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     for (size_t i = 0; i < run.size();) {
       size_t j = i;
       while (j < run.size() && order[j].first == order[i].first) ++j;
-      for (size_t k = i; k < j; ++k) run[k].flags &= 0xff;
+      int32_t r0 = 0;
+      for (size_t k = i; k < j; ++k) {
+        const DevTnStep& d = ex[run[k].step].dev;
+        run[k].flags &= 0xff;
+        run[k].r0 = r0;
+        run[k].rn = tn_wave_rounds(d.zr, d.ks);
+        run[k].lw = 0;
+        r0 += run[k].rn;
+      }
       run[i].flags |= (int32_t)((j - i) << 8);
+      run[i].lw = r0;
       i = j;
     }
     std::copy(run.begin(), run.end(), lst.begin() + sg.list);
@@ -1408,11 +1620,13 @@ static void direct_shape(const DevTnStep& h, int64_t copies, int64_t split_elems
   tb = std::min(tb, std::min(8, ks));
   const int64_t nz = int64_t(1) << zr;
   const int64_t gpb = 256 >> tb;
-  const int64_t rounds = (nz + gpb - 1) / gpb;
   const int kt = std::min(ks, kTnTabBits);
   int kb = 0;
   while (kb < ks - kt && (nz << (tb + kb)) * copies < (int64_t(1) << 17) && (nz << (kb + 1)) * copies <= split_elems)
     ++kb;
+  // the wide form (kb = 0 only) takes kTnWideOpl outputs per lane and round
+  const int64_t per = (kb == 0 && tn_wide_form(tb, ks)) ? gpb * kTnWideOpl : gpb;
+  const int64_t rounds = (nz + per - 1) / per;
   *tbp = tb;
   *kbp = kb;
   *rbp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rounds, 16384));
@@ -1445,6 +1659,7 @@ static tq_status tn_direct(TnRun<T>& R, const DevTnStep* dstep, const DevTnStep&
 // A run of small steps: one work-group per slice copy (grid x; copies <= 2^24).
 template <typename T>
 static tq_status tn_fused(TnRun<T>& R, const DevTnStep* steps, const void* list, int n, int64_t copies) {
+  if (n > kTnRunCap) return fail(TQ_EINVAL, "fused run longer than the LDS staging holds");
   hipLaunchKernelGGL(tn_fused_kernel<T>, dim3((unsigned)copies), dim3(kTnFusedThreads), 0, R.st, steps,
                      (const DevFused*)list, n,
                      R.leaves, R.ws);
@@ -1710,12 +1925,13 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
   };
   // per round: the fused runs (one launch), and the plain direct steps of every network
   // (one multi-network launch, up to kTnMultiMaxItems per launch; the rest launch alone)
-  struct DirectRound {
+  struct DirectRound {  // one multi-network launch: kind 0 direct steps, 1 chunk sums
     size_t first_off = 0, items_off = 0;
-    int count = 0;
+    int count = 0, kind = 0;
     int64_t blocks = 0;
   };
   std::vector<std::vector<char>> fdone, bdone;  // [round][network]: run by a multi launch
+  bool bad_run = false;                         // a fused run longer than the LDS staging holds
   auto rounds = [&](bool fwd, std::vector<std::pair<size_t, int>>& tab, std::vector<std::vector<DirectRound>>& dtab,
                     std::vector<std::vector<char>>& done) {
     size_t rmax = 0;
@@ -1732,12 +1948,14 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
         it.leaves = L[i];
         it.ws = Wk[i];
         it.n = segs[r].count;
+        if (it.n > kTnRunCap) bad_run = true;
         put(&it, sizeof it);
         ++cnt;
       }
       tab.push_back({off, cnt});
       // direct steps of this round
       std::vector<DevDirectItem> items;
+      std::vector<DevChunkItem> chunks;
       std::vector<char> dn(n, 0);
       for (size_t i = 0; i < n; ++i) {
         const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;
@@ -1748,7 +1966,6 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
         int tb, kb;
         unsigned rb;
         direct_shape(ex.dev, 1, P[i]->split_elems, &tb, &kb, &rb);
-        if (kb != 0) continue;
         DevDirectItem d{};
         d.st = (const DevTnStep*)(fwd ? P[i]->d_fwd : P[i]->d_bwd) + k;
         int64_t st;
@@ -1761,29 +1978,45 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
           d.y = R[i].tptr(ex.y, &st);
           d.z = R[i].eptr(ex.z);
         }
+        d.P = R[i].ws + P[i]->split_off;
         d.tb = tb;
         d.rb = (int32_t)rb;
+        d.kb = kb;
         items.push_back(d);
+        if (kb > 0) {
+          DevChunkItem ci{};
+          ci.P = d.P;
+          ci.z = d.z;
+          ci.nz = int64_t(1) << ex.dev.zr;
+          ci.nchunks = 1 << kb;
+          chunks.push_back(ci);
+        }
         dn[i] = 1;
       }
       std::vector<DirectRound> drs;
-      for (size_t a = 0; a < items.size(); a += kTnMultiMaxItems) {
-        const size_t b = std::min(items.size(), a + (size_t)kTnMultiMaxItems);
-        DirectRound dr;
-        std::vector<int32_t> first;
-        int64_t blocks = 0;
-        for (size_t j = a; j < b; ++j) {
+      auto pack = [&](auto& vec, auto blocks_of, int kind) {
+        using Item = typename std::decay<decltype(vec[0])>::type;
+        for (size_t a = 0; a < vec.size(); a += kTnMultiMaxItems) {
+          const size_t b = std::min(vec.size(), a + (size_t)kTnMultiMaxItems);
+          DirectRound dr;
+          std::vector<int32_t> first;
+          int64_t blocks = 0;
+          for (size_t j = a; j < b; ++j) {
+            first.push_back((int32_t)blocks);
+            blocks += blocks_of(vec[j]);
+          }
           first.push_back((int32_t)blocks);
-          blocks += items[j].rb;
+          dr.first_off = put(first.data(), first.size() * sizeof(int32_t));
+          while (blob.size() % 16) blob.push_back(0);
+          dr.items_off = put(vec.data() + a, (b - a) * sizeof(Item));
+          dr.count = (int)(b - a);
+          dr.blocks = blocks;
+          dr.kind = kind;
+          drs.push_back(dr);
         }
-        first.push_back((int32_t)blocks);
-        dr.first_off = put(first.data(), first.size() * sizeof(int32_t));
-        while (blob.size() % 16) blob.push_back(0);
-        dr.items_off = put(items.data() + a, (b - a) * sizeof(DevDirectItem));
-        dr.count = (int)(b - a);
-        dr.blocks = blocks;
-        drs.push_back(dr);
-      }
+      };
+      pack(items, [](const DevDirectItem& d) { return (int64_t)d.rb << d.kb; }, 0);
+      pack(chunks, [](const DevChunkItem& c) { return (int64_t)grid_for(c.nz); }, 1);
       dtab.push_back(drs);
       done.push_back(dn);
     }
@@ -1811,6 +2044,7 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
       put(&e, sizeof e);
     }
   }
+  if (bad_run) return fail(TQ_EINVAL, "fused run longer than the LDS staging holds");
   void* dev;
   TQ_TRY(stage_upload(ctx, S_TNB, blob.data(), blob.size(), stream, &dev));
   const unsigned char* db = (const unsigned char*)dev;
@@ -1823,9 +2057,13 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
                            (const DevFusedItem*)(db + tab[r].first));
         TQ_HIP(hipGetLastError());
       }
-      for (const DirectRound& dr : dtab[r]) {
-        hipLaunchKernelGGL(tn_direct_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
-                           (const int32_t*)(db + dr.first_off), (const DevDirectItem*)(db + dr.items_off), dr.count);
+      for (const DirectRound& dr : dtab[r]) {  // direct launches first, then their chunk sums
+        if (dr.kind == 0)
+          hipLaunchKernelGGL(tn_direct_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
+                             (const int32_t*)(db + dr.first_off), (const DevDirectItem*)(db + dr.items_off), dr.count);
+        else
+          hipLaunchKernelGGL(tn_chunk_sum_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
+                             (const int32_t*)(db + dr.first_off), (const DevChunkItem*)(db + dr.items_off), dr.count);
         TQ_HIP(hipGetLastError());
       }
       for (size_t i = 0; i < n; ++i) {
