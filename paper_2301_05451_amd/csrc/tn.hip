@@ -1071,11 +1071,14 @@ static TnExec make_exec(const std::vector<int>& xi, const std::vector<int>& yi, 
     d.xo[i] = px >= 0 ? (uint8_t)px : kNone;
     d.yo[i] = py >= 0 ? (uint8_t)py : kNone;
   }
+  // summed bit j of the assignment counter: X's summed indices from its least significant
+  // up, then Y's own ones likewise, so that the low counter bits (spread over the lanes of an
+  // output) are the operands' low address bits
   std::vector<int> summed;
-  for (int id : xi)
-    if (!zs.count(id)) summed.push_back(id);
-  for (int id : yi)
-    if (!zs.count(id) && std::find(summed.begin(), summed.end(), id) == summed.end()) summed.push_back(id);
+  for (auto it = xi.rbegin(); it != xi.rend(); ++it)
+    if (!zs.count(*it)) summed.push_back(*it);
+  for (auto it = yi.rbegin(); it != yi.rend(); ++it)
+    if (!zs.count(*it) && std::find(summed.begin(), summed.end(), *it) == summed.end()) summed.push_back(*it);
   d.ks = (int)summed.size();
   for (int j = 0; j < d.ks; ++j) {
     const int px = pos_of(xi, summed[j]), py = pos_of(yi, summed[j]);
