@@ -620,6 +620,9 @@ void tq_ctx_destroy(tq_ctx* ctx) {
     if (ctx->scratch[i]) (void)hipFree(ctx->scratch[i]);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   for (auto& kv : ctx->tables) (void)hipFree(kv.second.dev);
   for (void* p : ctx->retired) (void)hipFree(p);
   delete ctx;

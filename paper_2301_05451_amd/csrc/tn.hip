@@ -1336,14 +1336,29 @@ tq_status tq_tn_plan_create(tq_ctx* ctx, const tq_tn_desc* d, tq_tn_plan** out) 
     e += p->G * (int64_t(1) << p->t[i].rank);
   }
   p->ws_bwd = e;
-  // reverse execs: D_x = contract(D_z, y) -> x inds, D_y = contract(D_z, x) -> y inds
+  // reverse execs: D_x = contract(D_z, y), D_y = contract(D_z, x). The environment of an
+  // intermediate is laid out with the indices it shares with its parent's environment as the
+  // low bits, in the parent's order (so a reverse step reads D_z and writes D_x at matching
+  // addresses); leaves and the root keep their own layout.
+  std::vector<std::vector<int>> elay(p->t.size());
+  for (size_t i = 0; i < p->t.size(); ++i) elay[i] = p->t[i].inds;
   for (size_t s = p->fwd.size(); s-- > 0;) {
     const TnExec& f = p->fwd[s];
-    TnExec ex1 = make_exec(p->t[f.z].inds, p->t[f.y].inds, p->t[f.x].inds, false, csz);
+    for (int child : {f.x, f.y}) {
+      if (p->t[child].leaf >= 0) continue;
+      std::vector<int> lay;
+      for (int id : p->t[child].inds)
+        if (std::find(elay[f.z].begin(), elay[f.z].end(), id) == elay[f.z].end()) lay.push_back(id);
+      for (int id : elay[f.z])
+        if (std::find(p->t[child].inds.begin(), p->t[child].inds.end(), id) != p->t[child].inds.end())
+          lay.push_back(id);
+      elay[child] = lay;
+    }
+    TnExec ex1 = make_exec(elay[f.z], p->t[f.y].inds, elay[f.x], false, csz);
     ex1.x = f.z;
     ex1.y = f.y;
     ex1.z = f.x;
-    TnExec ex2 = make_exec(p->t[f.z].inds, p->t[f.x].inds, p->t[f.y].inds, false, csz);
+    TnExec ex2 = make_exec(elay[f.z], p->t[f.x].inds, elay[f.y], false, csz);
     ex2.x = f.z;
     ex2.y = f.x;
     ex2.z = f.y;
@@ -2048,6 +2063,11 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
     }
   }
   if (bad_run) return fail(TQ_EINVAL, "fused run longer than the LDS staging holds");
+  if (!ctx->side) {
+    TQ_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    TQ_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    TQ_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
   void* dev;
   TQ_TRY(stage_upload(ctx, S_TNB, blob.data(), blob.size(), stream, &dev));
   const unsigned char* db = (const unsigned char*)dev;
@@ -2055,19 +2075,34 @@ static tq_status tn_batch_t(tq_ctx* ctx, const std::vector<const tq_tn_plan*>& P
                         const std::vector<std::vector<DirectRound>>& dtab,
                         const std::vector<std::vector<char>>& done) -> tq_status {
     for (size_t r = 0; r < tab.size(); ++r) {
+      // the fused runs and the direct steps of a round belong to different networks: when a
+      // round has both, the direct launches go to the context's second stream (forked from and
+      // joined back into the caller's stream), so the latency-bound runs on a few CUs overlap
+      // the bandwidth-bound steps
+      const bool fork = tab[r].second > 0 && !dtab[r].empty();
+      hipStream_t ds = stream;
+      if (fork) {
+        TQ_HIP(hipEventRecord(ctx->ev_fork, stream));
+        TQ_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+        ds = ctx->side;
+      }
+      for (const DirectRound& dr : dtab[r]) {  // direct launches first, then their chunk sums
+        if (dr.kind == 0)
+          hipLaunchKernelGGL(tn_direct_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, ds,
+                             (const int32_t*)(db + dr.first_off), (const DevDirectItem*)(db + dr.items_off), dr.count);
+        else
+          hipLaunchKernelGGL(tn_chunk_sum_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, ds,
+                             (const int32_t*)(db + dr.first_off), (const DevChunkItem*)(db + dr.items_off), dr.count);
+        TQ_HIP(hipGetLastError());
+      }
       if (tab[r].second > 0) {
         hipLaunchKernelGGL(tn_fused_multi_kernel<T>, dim3((unsigned)tab[r].second), dim3(kTnFusedThreads), 0, stream,
                            (const DevFusedItem*)(db + tab[r].first));
         TQ_HIP(hipGetLastError());
       }
-      for (const DirectRound& dr : dtab[r]) {  // direct launches first, then their chunk sums
-        if (dr.kind == 0)
-          hipLaunchKernelGGL(tn_direct_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
-                             (const int32_t*)(db + dr.first_off), (const DevDirectItem*)(db + dr.items_off), dr.count);
-        else
-          hipLaunchKernelGGL(tn_chunk_sum_multi_kernel<T>, dim3((unsigned)dr.blocks), dim3(256), 0, stream,
-                             (const int32_t*)(db + dr.first_off), (const DevChunkItem*)(db + dr.items_off), dr.count);
-        TQ_HIP(hipGetLastError());
+      if (fork) {
+        TQ_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+        TQ_HIP(hipStreamWaitEvent(stream, ctx->ev_join, 0));
       }
       for (size_t i = 0; i < n; ++i) {
         const auto& segs = fwd ? P[i]->fseg : P[i]->bseg;

@@ -214,6 +214,9 @@ struct tq_ctx {
   uint64_t table_clock = 0;
   // scratch buffers replaced by larger ones (freed with the context)
   std::vector<void*> retired;
+  // second stream and fork/join events of the batched TN rounds (created on first use)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // autotune results: key -> (t, R)
   std::unordered_map<std::string, std::pair<int, int>> tuned;
   // imported autotune results: digest of (structure, pass) -> (t, R)
