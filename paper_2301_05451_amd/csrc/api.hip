@@ -623,6 +623,10 @@ void tq_ctx_destroy(tq_ctx* ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  for (int i = 0; i < 4; ++i) {
+    if (ctx->pool[i]) (void)hipStreamDestroy(ctx->pool[i]);
+    if (ctx->pool_done[i]) (void)hipEventDestroy(ctx->pool_done[i]);
+  }
   for (auto& kv : ctx->tables) (void)hipFree(kv.second.dev);
   for (void* p : ctx->retired) (void)hipFree(p);
   delete ctx;

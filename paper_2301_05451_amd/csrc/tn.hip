@@ -2158,15 +2158,35 @@ static tq_status tn_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans
     O[k].push_back(d_out[i]);
     Wk[k].push_back(d_work[i]);
   }
-  if (!P[0].empty()) TQ_TRY(tn_batch_t<float>(ctx, P[0], L[0], G[0], O[0], Wk[0], mode, stream));
-  if (!P[1].empty()) TQ_TRY(tn_batch_t<double>(ctx, P[1], L[1], G[1], O[1], Wk[1], mode, stream));
-  for (int i : rest) {
-    if (mode == 0)
-      TQ_TRY(tq_tn_contract(ctx, plans[i], d_leaves[i], d_out[i], d_work[i], work_bytes[i], stream));
-    else
-      TQ_TRY(tq_tn_backward(ctx, plans[i], d_leaves[i], d_gout[i], d_out[i], d_work[i], work_bytes[i], stream));
+  // the other (sliced) networks run one by one, spread over the context's stream pool (forked
+  // from the caller's stream before the rounds start and joined back at the end), so their
+  // many small launches overlap each other and the rounds
+  constexpr int kPool = 4;
+  const int np = (int)std::min<size_t>(rest.size(), kPool);
+  if (np > 0) {
+    if (!ctx->ev_fork) TQ_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    for (int k = 0; k < np; ++k)
+      if (!ctx->pool[k]) {
+        TQ_HIP(hipStreamCreateWithFlags(&ctx->pool[k], hipStreamNonBlocking));
+        TQ_HIP(hipEventCreateWithFlags(&ctx->pool_done[k], hipEventDisableTiming));
+      }
+    TQ_HIP(hipEventRecord(ctx->ev_fork, stream));
+    for (int k = 0; k < np; ++k) TQ_HIP(hipStreamWaitEvent(ctx->pool[k], ctx->ev_fork, 0));
   }
-  return TQ_OK;
+  tq_status st = TQ_OK;
+  for (size_t k = 0; k < rest.size() && st == TQ_OK; ++k) {
+    const int i = rest[k];
+    hipStream_t s = ctx->pool[k % kPool];
+    st = mode == 0 ? tq_tn_contract(ctx, plans[i], d_leaves[i], d_out[i], d_work[i], work_bytes[i], s)
+                   : tq_tn_backward(ctx, plans[i], d_leaves[i], d_gout[i], d_out[i], d_work[i], work_bytes[i], s);
+  }
+  if (st == TQ_OK && !P[0].empty()) st = tn_batch_t<float>(ctx, P[0], L[0], G[0], O[0], Wk[0], mode, stream);
+  if (st == TQ_OK && !P[1].empty()) st = tn_batch_t<double>(ctx, P[1], L[1], G[1], O[1], Wk[1], mode, stream);
+  for (int k = 0; k < np; ++k) {  // join, also after an error, so no pool work outlives the call's order
+    TQ_HIP(hipEventRecord(ctx->pool_done[k], ctx->pool[k]));
+    TQ_HIP(hipStreamWaitEvent(stream, ctx->pool_done[k], 0));
+  }
+  return st;
 }
 
 }  // namespace tq

@@ -217,6 +217,9 @@ struct tq_ctx {
   // second stream and fork/join events of the batched TN rounds (created on first use)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // streams that run the batched TN calls' sliced networks side by side, with their join events
+  hipStream_t pool[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t pool_done[4] = {nullptr, nullptr, nullptr, nullptr};
   // autotune results: key -> (t, R)
   std::unordered_map<std::string, std::pair<int, int>> tuned;
   // imported autotune results: digest of (structure, pass) -> (t, R)

@@ -244,19 +244,20 @@ def test_qaoa50_p4_narrowest_edge_sliced_vs_unsliced():
 @pytest.mark.parametrize("c128", [False, True])
 def test_batched_networks_match_single_calls_and_oracle(c128):
     """tq_tn_contract_batch / tq_tn_backward_batch over the 75 light-cone networks of the
-    p = 2 QAOA problem on a 50-node graph plus one sliced network (which takes the
-    one-by-one route): values and gradients equal the single-network calls, and values
-    match the cone state vector of the oracle on sampled edges."""
+    p = 2 QAOA problem on a 50-node graph plus six sliced networks (which take the one-by-one
+    route, on several streams): values and gradients equal the single-network calls, and
+    values match the cone state vector of the oracle on sampled edges."""
     prob = W.qaoa_maxcut(p=2)
     progs, pars = [], []
     for e in prob.edges:
         net, _ = tn.qaoa_edge_network(prob, e)
         progs.append(tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]), c128=c128))
         pars.append(_params(net, c128))
-    net0, _ = tn.qaoa_edge_network(prob, prob.edges[0])
-    t0 = tn.elimination_tree(net0, tn.elimination_order(net0)[0])
-    progs.append(tn.TNProgram(net0, tn.slice_tree(net0, t0, max(2, t0.max_rank - 2)), c128=c128))
-    pars.append(_params(net0, c128))
+    for e in prob.edges[:6]:  # sliced copies: the one-by-one route, spread over the stream pool
+        net0, _ = tn.qaoa_edge_network(prob, e)
+        t0 = tn.elimination_tree(net0, tn.elimination_order(net0)[0])
+        progs.append(tn.TNProgram(net0, tn.slice_tree(net0, t0, max(2, t0.max_rank - 2)), c128=c128))
+        pars.append(_params(net0, c128))
     batch = tn.TNBatch(progs)
     vals = [v.cpu().numpy() for v in batch.values(pars)]
     grads = [g.cpu().numpy() for g in batch.grads(pars)]
@@ -267,7 +268,8 @@ def test_batched_networks_match_single_calls_and_oracle(c128):
     for k in (0, 17, 41, 74):
         want = otn.qaoa_edge_zz_sv(prob, prob.edges[k])
         assert abs(vals[k][0].real - want) <= max(tol, 1e-5), k
-    assert abs(vals[-1][0] - vals[0][0]) <= 2 * tol
+    for k in range(6):
+        assert abs(vals[75 + k][0] - vals[k][0]) <= 2 * tol, k
 
 
 def _p4_graph(n=16, seed=41):
