@@ -320,7 +320,7 @@ def _workers():
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def bench_tn(steps):
+def bench_tn(steps, configs=("p3", "p4", "p4_sliced20"), batch_only=False):
     """QAOA MaxCut on a seeded random 3-regular graph of 50 nodes (75 edges): one light-cone
     network per edge for <Z_i Z_j>, value + gradient of (gamma, beta), all 75 networks in
     one batched call. Trees: the fewest-FLOP tree of the path search's pool (min-fill,
@@ -335,6 +335,8 @@ def bench_tn(steps):
 
     res = {}
     for name, p, target in (("p3", 3, None), ("p4", 4, None), ("p4_sliced20", 4, 20)):
+        if name not in configs:
+            continue
         prob = W.qaoa_maxcut(p=p)
         t0 = time.perf_counter()
         planned = tn.plan_qaoa(prob, target_rank=target, workers=_workers())
@@ -354,7 +356,7 @@ def bench_tn(steps):
             batch.values(pars)
             batch.grads(pars)
 
-        ms1 = _timed(run_single, 1, 1)
+        ms1 = _timed(run_single, 1, 1) if not batch_only else float("nan")
         ms = _timed(run_batch, max(2, steps // 2), 1)
         vb = torch.stack([v[0] for v in batch.values(pars)]).cpu().numpy()
         vs = np.array([pg.value(pt).cpu().numpy()[0] for pg, pt in zip(progs, pars)])
@@ -368,8 +370,8 @@ def bench_tn(steps):
         res[name] = {"networks": len(progs), "plan_s": round(plan_s, 2),
                      "ms_value_and_grad_all": round(ms, 3),
                      "grad_networks_per_s": len(progs) / (ms * 1e-3),
-                     "single_calls_ms": round(ms1, 3),
-                     "batched_speedup_vs_single_calls": round(ms1 / ms, 2),
+                     "single_calls_ms": round(ms1, 3) if not batch_only else None,
+                     "batched_speedup_vs_single_calls": round(ms1 / ms, 2) if not batch_only else None,
                      "batched_equals_single": bool(np.array_equal(vb, vs)),
                      "maxcut_value": float(np.sum((1.0 - vb.real) / 2.0)),
                      "contraction_flops_per_pass": flops,
@@ -382,6 +384,8 @@ def bench_tn(steps):
                      "max_width": max(pg.tree.max_rank for pg in progs),
                      "sliced_networks": sum(1 for pg in progs if pg.tree.sliced),
                      "slices_total": sum(2 ** len(pg.tree.sliced) for pg in progs)}
+    if batch_only:
+        return res
     # dense step: C[b,m,n] = sum_k A[b,m,k] B[b,k,n], b = 1 bit, M = N = 2^12, K = 2^10
     b, m, k, nn = [0], list(range(1, 13)), list(range(13, 23)), list(range(23, 35))
     plan = lib.TnPlan([b + m + k, b + k + nn], [(0, 1)], out_inds=b + m + nn)
@@ -496,6 +500,10 @@ def main():
     ap.add_argument("--extras", default="qnn16_batch512,uneven1024,tn_qaoa50,mqr,tree_ranking",
                     help="comma-separated measurements besides the headline")
     ap.add_argument("--plain-steps", type=int, default=1, help="steps of the one-sweep-per-gate path")
+    ap.add_argument("--tn-configs", default="p3,p4,p4_sliced20",
+                    help="QAOA network sets of the tn_qaoa50 measurement (for profiling one of them)")
+    ap.add_argument("--tn-batch-only", action="store_true",
+                    help="tn_qaoa50: time the batched calls only (no single-call loop, no dense step)")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--reg-bits", type=int, default=0)
     ap.add_argument("--coal-bits", type=int, default=0)
@@ -631,7 +639,8 @@ def main():
         wanted = set(x.strip() for x in args.extras.split(",") if x.strip())
         for key, fn in (("qnn16_batch512", lambda: bench_qnn(max(5, args.steps // 2))),
                         ("uneven1024", lambda: bench_uneven(max(3, args.steps // 4))),
-                        ("tn_qaoa50", lambda: bench_tn(max(4, args.steps // 2))),
+                        ("tn_qaoa50", lambda: bench_tn(max(4, args.steps // 2), args.tn_configs.split(","),
+                                                       args.tn_batch_only)),
                         ("mqr", bench_mqr),
                         ("tree_ranking", bench_costmodel)):
             if key not in wanted:
