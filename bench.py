@@ -208,6 +208,10 @@ def bench_qnn(steps):
     out = torch.empty(B, 1, device="cuda")
     w = torch.empty(B, 1, device="cuda")
     grad = torch.zeros_like(params)
+    # shapes (tile and register bits) of both passes chosen by the autotuner, on the device
+    tuned_f = svb.autotune(params, states, which=0, reps=3)
+    svb.forward(params, states, out)
+    tuned_b = svb.autotune(params, states, which=1, reps=3)
 
     def step():
         svb.forward(params, states, out)
@@ -247,6 +251,8 @@ def bench_qnn(steps):
             "single_call_loop_circuits_per_s": 1 / (loop_ms * 1e-3),
             "batched_speedup_vs_single_calls": round(loop_ms / (ms / B), 1),
             "levels": svb.info["levels"], "graph_replays": svb.info["graph_replays"],
+            "autotuned_forward": [int(tuned_f[0]), int(tuned_f[1])],
+            "autotuned_backward": [int(tuned_b[0]), int(tuned_b[1])],
             "forward_ms": round(fwd_ms, 4),
             "roofline_forward": {"bound": "alu", "kernel": "sv_batch_stage_kernel (all levels of one forward)",
                                  "achieved": round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
