@@ -70,85 +70,93 @@ int expval_groups(int n, int cn) {
 }
 
 // Vector width of the partial-sum kernel's loads: A amplitudes per 16-byte load (2 for
-// complex64, 1 for complex128). A circuit whose state is not 16-byte aligned is read one
-// amplitude per load instead (the same sums, in another order).
+// complex64, 1 for complex128). A circuit whose state is not 16-byte aligned, or holds fewer
+// than 2^12 amplitudes, is read one amplitude per load instead (the same sums, in another
+// order).
 template <typename T>
 struct ExpVec {
   static constexpr int A = 16 / (int)sizeof(typename Cx<T>::type);
 };
 
-// Per-term table of a launch, in LDS: (the term's mask over the chunk-index bits << 4) | the
-// index u of its Walsh-Hadamard coefficient over the thread's 16 values.
-template <int KT>
-struct ExpTermTab {
-  uint32_t c[KT];
-};
-
 // One work-group's share of one circuit: a contiguous range of its 2^cb-amplitude chunks,
-// the next chunk's loads in flight while the current one is transformed. In a chunk a thread reads
-// A amplitudes per load at index (it << (lgA + 8)) | (tid << lgA) | e, it < nit, e < A:
+// the next chunk's loads in flight while the current one is transformed. In a chunk a thread
+// reads A amplitudes per load at index (it << (lgA + 8)) | (tid << lgA) | e, it < nit, e < A:
 // their |psi|^2 values p[(it << lgA) | e] go through one Walsh-Hadamard transform
 // W[u] = sum_v (-1)^{|v & u|} p[v], and a term with mask m reads W at u = the mask's bits over
-// (it, e), with the sign of the mask's thread bits (fixed per thread: one bit per term in
-// tpar) and chunk bits (one bit per term and chunk in cpar). The transform and a thread's sum
-// over its chunks are in the state's precision; the partial sums below are in double.
-template <typename T, int KT, int A>
+// (it, e). The sign of the mask's chunk bits is the same for the whole wave: lane k of every
+// wave holds term k's chunk mask, and one ballot per chunk gives all terms' signs as a scalar
+// bit mask, applied in a multiply-add with a scalar +-1. The sign of the mask's thread bits
+// is fixed per thread and applied once, after the last chunk. The transform and a thread's
+// sum over its chunks are in the state's precision; the partial sums below are in double.
+template <typename T, int KT, int A, bool FULL>
 __device__ __forceinline__ void expval_partial_body(const typename Cx<T>::type* __restrict__ s, int n,
                                                     const uint64_t* __restrict__ pmask, int nk, T (&acc)[KT],
-                                                    T (*wsh)[kExpThreads], ExpTermTab<KT>& tab) {
+                                                    T (*wsh)[kExpThreads]) {
   using C = typename Cx<T>::type;
   using V = typename std::conditional<A == 2, typename std::conditional<sizeof(T) == 4, float4, double4>::type,
                                       C>::type;
   constexpr int lgA = A == 2 ? 1 : 0;
   constexpr int kLoads = kExpVals / A;  // loads per thread and chunk
-  const int cb = n < kExpChunkBits ? n : kExpChunkBits;
-  const uint32_t tid = threadIdx.x;
-  const int tb = cb - lgA < 8 ? cb - lgA : 8;  // thread bits of a chunk index
-  const int nit = 1 << (cb - lgA - tb);
+  // FULL: n >= kExpChunkBits, so every thread holds 16 live values of every chunk
+  const int cb = FULL ? kExpChunkBits : (n < kExpChunkBits ? n : kExpChunkBits);
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  const int tb = FULL ? 8 : (cb - lgA < 8 ? cb - lgA : 8);  // thread bits of a chunk index
+  const int nit = FULL ? kLoads : 1 << (cb - lgA - tb);
   const uint32_t tcl = tid & ((1u << tb) - 1);
-  const bool live = tid < (1u << tb);
+  const bool live = FULL || tid < (1u << tb);
   const int64_t nchunk = int64_t(1) << (n - cb);
   const V* sv = (const V*)s;  // index in units of A amplitudes
-  if (tid < KT) {
-    const uint64_t m = tid < (uint32_t)nk ? pmask[tid] : 0ull;
+  V buf0[kLoads], buf1[kLoads];
+  auto load = [&](V(&nxt)[kLoads], int64_t j) {
+#pragma unroll
+    for (int it = 0; it < kLoads; ++it) {
+      const uint32_t itc = FULL ? (uint32_t)it : (uint32_t)(it < nit ? it : nit - 1);
+      nxt[it] = sv[(((uint64_t)j << cb) >> lgA) + ((itc << 8) | tcl)];
+    }
+  };
+  // this group's chunks: a contiguous range (a fixed sequence, so the sums repeat bitwise);
+  // every load is issued unconditionally (past the range: the group's last chunk again), so
+  // the number of loads in flight is the same on every path and each wait covers one buffer
+  const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per;
+  const int64_t j1 = j0 + per < nchunk ? j0 + per : nchunk;
+  if (j0 >= j1) return;
+  const int64_t last = j1 - 1;
+  load(buf0, j0);  // in flight during the term set-up below
+  // lane k < nk: term k's chunk mask, its mask over the thread bits, and the element offset
+  // of its W[u] column in wsh; lanes past nk hold zeros, so the padding terms k >= nk of the
+  // template read W[0] with sign +1 (their sums are never reduced) and no loop below branches
+  uint32_t lane_cm = 0, lane_tm = 0, lane_uo = 0;
+  if (lane < (uint32_t)nk) {
+    const uint64_t m = pmask[lane];
     const uint32_t u = ((((uint32_t)m >> (lgA + 8)) & (uint32_t)(nit - 1)) << lgA) | ((uint32_t)m & (uint32_t)(A - 1));
-    tab.c[tid] = ((uint32_t)(m >> cb) << 4) | u;  // n - cb <= 28 chunk bits
+    lane_cm = (uint32_t)(m >> cb);  // n - cb <= 28 chunk bits
+    lane_tm = ((uint32_t)m >> lgA) & 0xffu;
+    lane_uo = u * kExpThreads;
   }
   uint32_t tpar = 0;  // bit k: parity of term k's mask over this thread's index bits
 #pragma unroll
   for (int k = 0; k < KT; ++k)
-    if (k < nk) tpar |= ((uint32_t)__popc(tid & ((uint32_t)pmask[k] >> lgA) & 0xffu) & 1u) << k;
-  __syncthreads();
-  V nxt[kLoads];
-  auto load = [&](int64_t j) {
-#pragma unroll
-    for (int it = 0; it < kLoads; ++it) {
-      const uint32_t itc = (uint32_t)(it < nit ? it : nit - 1);
-      nxt[it] = sv[(((uint64_t)j << cb) >> lgA) + ((itc << 8) | tcl)];
-    }
-  };
-  // this group's chunks: a contiguous range (a fixed sequence, so the sums repeat bitwise)
-  const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
-  const int64_t j0 = (int64_t)blockIdx.x * per;
-  const int64_t j1 = j0 + per < nchunk ? j0 + per : nchunk;
-  int64_t j = j0;
-  if (j < j1) load(j);
-  for (; j < j1; ++j) {
+    tpar |= ((uint32_t)__popc(tid & (uint32_t)__builtin_amdgcn_readlane((int)lane_tm, k)) & 1u) << k;
+  T* const wcol = &wsh[0][tid];
+  // Chunk j from buffer `cur` (when `use`); the other buffer's loads, issued just before, stay
+  // in flight meanwhile. The two buffers alternate, so nothing is copied between them.
+  auto chunk = [&](V(&cur)[kLoads], int64_t j, bool use) {
     T pv[kExpVals];
 #pragma unroll
     for (int it = 0; it < kLoads; ++it) {
-      const bool on = it < nit && live;
+      const bool on = FULL || (it < nit && live);
       if constexpr (A == 2) {
-        const T p0 = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
-        const T p1 = nxt[it].z * nxt[it].z + nxt[it].w * nxt[it].w;
+        const T p0 = cur[it].x * cur[it].x + cur[it].y * cur[it].y;
+        const T p1 = cur[it].z * cur[it].z + cur[it].w * cur[it].w;
         pv[2 * it] = on ? p0 : (T)0;
         pv[2 * it + 1] = on ? p1 : (T)0;
       } else {
-        const T p = nxt[it].x * nxt[it].x + nxt[it].y * nxt[it].y;
+        const T p = cur[it].x * cur[it].x + cur[it].y * cur[it].y;
         pv[it] = on ? p : (T)0;
       }
     }
-    if (j + 1 < j1) load(j + 1);  // next chunk in flight
+    if (!use) return;
 #pragma unroll
     for (int h = 1; h < kExpVals; h <<= 1) {
 #pragma unroll
@@ -159,23 +167,27 @@ __device__ __forceinline__ void expval_partial_body(const typename Cx<T>::type* 
           pv[i | h] = a - b;
         }
     }
-    const int nv = nit * A;
+    // all 16 coefficients are stored (those past nit * A belong to the zero padding of a
+    // small chunk and are read by no term), so the stores do not branch
 #pragma unroll
-    for (int v = 0; v < kExpVals; ++v)
-      if (v < nv) wsh[v][tid] = pv[v];
-    const uint32_t jj = (uint32_t)j << 4;
-    // the table is read again per chunk (not held in registers across the loop)
-    asm volatile("" ::: "memory");
+    for (int v = 0; v < kExpVals; ++v) wcol[v * kExpThreads] = pv[v];
+    // bit k: parity of term k's chunk bits in chunk j (the same in every wave of the group)
+    const uint64_t cpar = __builtin_amdgcn_ballot_w64((__popc((uint32_t)j & lane_cm) & 1) != 0);
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
-      if (k < nk) {
-        const uint32_t c = tab.c[k];
-        const T w = wsh[c & 15u][tid];
-        const uint32_t par = ((tpar >> k) ^ (uint32_t)__popc(jj & c)) & 1u;
-        acc[k] += par ? -w : w;
-      }
+      const uint32_t uo = (uint32_t)__builtin_amdgcn_readlane((int)lane_uo, k);
+      acc[k] = fma(unit_sign<T>((uint32_t)(cpar >> k) & 1u), wcol[uo], acc[k]);
     }
+  };
+  for (int64_t j = j0; j < j1; j += 2) {
+    load(buf1, j + 1 < j1 ? j + 1 : last);
+    chunk(buf0, j, true);
+    load(buf0, j + 2 < j1 ? j + 2 : last);
+    chunk(buf1, j + 1, j + 1 < j1);
   }
+#pragma unroll
+  for (int k = 0; k < KT; ++k)
+    if ((tpar >> k) & 1u) acc[k] = -acc[k];
 }
 
 // Partial sums of every term over one work-group's chunks of circuit blockIdx.y.
@@ -185,15 +197,16 @@ __global__ void __launch_bounds__(kExpThreads)
                           const uint64_t* __restrict__ pmask, int nk, double* __restrict__ partial) {
   const typename Cx<T>::type* s = st + smap.at(blockIdx.y);
   __shared__ T wsh[kExpVals][kExpThreads];  // per-thread column: indexable storage for W[u]
-  __shared__ ExpTermTab<KT> tab;
   T acc[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) acc[k] = (T)0;
   constexpr int A = ExpVec<T>::A;
-  if (A > 1 && (reinterpret_cast<uintptr_t>(s) & 15) == 0)
-    expval_partial_body<T, KT, A>(s, n, pmask, nk, acc, wsh, tab);
+  if (n < kExpChunkBits)  // a small state: one chunk, read one amplitude per load
+    expval_partial_body<T, KT, 1, false>(s, n, pmask, nk, acc, wsh);
+  else if (A > 1 && (reinterpret_cast<uintptr_t>(s) & 15) == 0)
+    expval_partial_body<T, KT, A, true>(s, n, pmask, nk, acc, wsh);
   else
-    expval_partial_body<T, KT, 1>(s, n, pmask, nk, acc, wsh, tab);
+    expval_partial_body<T, KT, 1, true>(s, n, pmask, nk, acc, wsh);
   __shared__ double red[kExpThreads / 64][KT];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -226,9 +239,14 @@ __global__ void __launch_bounds__(kExpFinalThreads)
                         int last, T* __restrict__ out, BatchMap rows) {
   constexpr int kW = kExpFinalThreads / 64;
   constexpr int TPW = (KT + kW - 1) / kW;  // terms per wave
-  __shared__ double sk[KT];
+  __shared__ double sk[KT], sc[KT];
+  __shared__ int32_t so[KT];
   const int circ = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x < nk) {  // the terms' coefficients and observables, read once per group
+    sc[threadIdx.x] = coeff[threadIdx.x];
+    so[threadIdx.x] = obs[threadIdx.x];
+  }
   double x[TPW][8];
 #pragma unroll
   for (int t = 0; t < TPW; ++t)
@@ -265,7 +283,7 @@ __global__ void __launch_bounds__(kExpFinalThreads)
     double* acc = outacc + (int64_t)circ * n_obs + o;
     double a = first ? 0.0 : *acc;
     for (int k = 0; k < nk; ++k)
-      if (obs[k] == o) a += coeff[k] * sk[k];
+      if (so[k] == o) a += sc[k] * sk[k];
     if (last)
       out[rows.at(circ) * n_obs + o] = (T)a;
     else
@@ -306,12 +324,22 @@ tq_status launch_expval(const typename Cx<T>::type* d_states, BatchMap smap, int
     for (int k0 = 0; k0 < n_terms; k0 += 32) {
       const int nk = std::min(32, n_terms - k0);
       const int first = k0 == 0, last = k0 + 32 >= n_terms;
+      // the smallest term count of the templates that holds nk (every template term costs
+      // the same per chunk, used or not)
+      auto go = [&](auto kt) {
+        launch_chunk<T, decltype(kt)::value>(d_states, sm, n, nb, cn, d_pmask + k0, d_coeff + k0, d_obs + k0, nk,
+                                             n_obs, partial, outacc, first, last, d_out, rm, stream);
+      };
       if (nk <= 4)
-        launch_chunk<T, 4>(d_states, sm, n, nb, cn, d_pmask + k0, d_coeff + k0, d_obs + k0, nk, n_obs, partial, outacc,
-                           first, last, d_out, rm, stream);
+        go(std::integral_constant<int, 4>());
+      else if (nk <= 8)
+        go(std::integral_constant<int, 8>());
+      else if (nk <= 16)
+        go(std::integral_constant<int, 16>());
+      else if (nk <= 24)
+        go(std::integral_constant<int, 24>());
       else
-        launch_chunk<T, 32>(d_states, sm, n, nb, cn, d_pmask + k0, d_coeff + k0, d_obs + k0, nk, n_obs, partial,
-                            outacc, first, last, d_out, rm, stream);
+        go(std::integral_constant<int, 32>());
     }
     TQ_HIP(hipGetLastError());
   }

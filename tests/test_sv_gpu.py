@@ -196,21 +196,24 @@ def test_brickwork24_full_size_in_bench_configuration():
         del psi, got, d
 
 
-@pytest.mark.parametrize("name,n", [("c64", 14), ("c64", 20), ("c128", 17)])
-def test_expval_random_z_strings_many_blocks(name, n):
+@pytest.mark.parametrize("name,n,n_terms", [("c64", 14, 27), ("c64", 20, 27), ("c128", 17, 27), ("c64", 16, 6),
+                                            ("c64", 13, 12), ("c128", 12, 20), ("c64", 11, 16), ("c128", 9, 7)])
+def test_expval_random_z_strings_many_blocks(name, n, n_terms):
     """Random multi-qubit Z-strings (qubits anywhere in the index, so every block and every
     per-thread bit group of the reduction contributes signs) on a random state, several
-    observables, against the oracle's expectation values of the same amplitudes."""
+    observables, against the oracle's expectation values of the same amplitudes. The term
+    counts reach each term-table size of the kernels (8, 16, 24, 32); n = 12 is exactly one
+    2^12-amplitude chunk, n < 12 a partial one."""
     from paper_2301_05451_amd import lib
 
-    rng = np.random.default_rng(100 + n)
+    rng = np.random.default_rng(100 + n + 1000 * n_terms)
     v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     v /= np.linalg.norm(v)
     cdt = torch.complex64 if name == "c64" else torch.complex128
     psi = torch.tensor(v, dtype=cdt, device="cuda")
     spec = lib.BatchSpec.uniform(n, W.GateList().array(), 1, 1)
     spec_terms = []
-    for k in range(27):
+    for k in range(n_terms):
         qs = sorted(int(q) for q in rng.choice(n, size=int(rng.integers(1, min(n, 6) + 1)), replace=False))
         spec_terms.append((qs, float(rng.normal()), k % 3))
     terms = W.zterms(spec_terms)
