@@ -184,6 +184,81 @@ def _timed(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+PEAKS = {}
+
+
+def measure_peaks(reps=5):
+    """Attainable peaks of this device from libtq's fixed probe kernels (tq_peak_probe): best of
+    `reps` timings with HIP events on the launch stream, of one launch (the 8 GiB buffers and the
+    compute probes, milliseconds each) or of 20 back-to-back launches (the state-sized buffers,
+    tens of microseconds each, as the state kernels run). The 8 GiB stream
+    copy and read are far beyond the L2 and the 256 MiB last-level cache, so they measure HBM.
+    The 256 MiB copy and the 128 MiB read have the footprint of a 2^24-amplitude complex64
+    state: data of that size stays partly in the last-level cache between passes, which is
+    what the state kernels see."""
+    import torch
+
+    from paper_2301_05451_amd import lib
+
+    def best(kind, buf, iters=1, launches=1):
+        w = lib.peak_probe(kind, buf, iters)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(launches):
+                w = lib.peak_probe(kind, buf, iters)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b) / launches)
+        return w / (min(ms) * 1e-3), min(ms)
+
+    big = torch.zeros(8 << 30, dtype=torch.uint8, device="cuda")
+    hbm_copy, hbm_copy_ms = best(lib.PEAK_COPY, big)
+    hbm_read, hbm_read_ms = best(lib.PEAK_READ, big)
+    del big
+    torch.cuda.empty_cache()
+    st = torch.zeros(1 << 28, dtype=torch.uint8, device="cuda")
+    st_copy, st_copy_ms = best(lib.PEAK_COPY, st, launches=20)
+    st_read, st_read_ms = best(lib.PEAK_READ, st[: 1 << 27], launches=20)
+    del st
+    out = torch.zeros(2048 * 256 * 8, dtype=torch.uint8, device="cuda")
+    fma, fma_ms = best(lib.PEAK_FP32_FMA, out, 32768)
+    m32, m32_ms = best(lib.PEAK_FP32_MFMA, out, 4096)
+    m64, m64_ms = best(lib.PEAK_FP64_MFMA, out, 2048)
+    del out
+    torch.cuda.synchronize()
+    PEAKS.update({"hbm_copy_GBs": hbm_copy / 1e9, "hbm_read_GBs": hbm_read / 1e9, "state_copy_GBs": st_copy / 1e9,
+                  "state_read_GBs": st_read / 1e9, "fp32_fma_TFLOPs": fma / 1e12, "fp32_mfma_TFLOPs": m32 / 1e12,
+                  "fp64_mfma_TFLOPs": m64 / 1e12})
+
+    def bw(v, ms):
+        return {"GBs": round(v / 1e9, 1), "frac_of_datasheet": round(v / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms, 3)}
+
+    def fl(v, ms, sheet):
+        return {"TFLOPs": round(v / 1e12, 2), "datasheet": round(sheet, 1),
+                "frac_of_datasheet": round(v / 1e12 / sheet, 4), "ms": round(ms, 3)}
+
+    return {
+        "method": "libtq probe kernels (tq_peak_probe), best of %d timings (HIP events) of one launch, or of "
+                  "20 back-to-back launches for the state-sized buffers" % reps,
+        "hbm_copy_8GiB": bw(hbm_copy, hbm_copy_ms),
+        "hbm_read_8GiB": bw(hbm_read, hbm_read_ms),
+        "copy_256MiB_state_footprint": bw(st_copy, st_copy_ms),
+        "read_128MiB_state": bw(st_read, st_read_ms),
+        "fp32_fma_nonpacked": fl(fma, fma_ms, ALU_PEAK_TFLOPS),
+        "fp32_mfma_16x16x4": fl(m32, m32_ms, 157.3),
+        "fp64_mfma_16x16x4": fl(m64, m64_ms, 78.6),
+    }
+
+
+def _mfrac(achieved, key):
+    """achieved / the measured attainable peak `key` (same unit), or None when not measured."""
+    v = PEAKS.get(key)
+    return round(achieved / v, 4) if v else None
+
+
 def bench_qnn(steps):
     """16-qubit, 8-layer QNN over 512 samples (angle-encoded inputs, shared weights), MSE loss
     on <Z0>: one training step = compiled-batch forward + loss gradient + adjoint backward,
@@ -257,6 +332,7 @@ def bench_qnn(steps):
             "roofline_forward": {"bound": "alu", "kernel": "sv_batch_stage_kernel (all levels of one forward)",
                                  "achieved": round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                                  "unit": "TFLOP/s", "frac": round(fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+                                 "frac_measured": _mfrac(fwd_flops / (fwd_ms * 1e-3) / 1e12, "fp32_fma_TFLOPs"),
                                  "algorithmic_flops": fwd_flops, "flops_per_amp": fpa}}
 
 
@@ -319,6 +395,7 @@ def bench_uneven(steps):
             "roofline_forward": {"bound": "alu", "kernel": "sv_batch_stage_kernel (all levels of one forward)",
                                  "achieved": round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                                  "unit": "TFLOP/s", "frac": round(fwd_flops / (fwd_ms * 1e-3) / 1e12 / ALU_PEAK_TFLOPS, 4),
+                                 "frac_measured": _mfrac(fwd_flops / (fwd_ms * 1e-3) / 1e12, "fp32_fma_TFLOPs"),
                                  "algorithmic_flops": fwd_flops}}
 
 
@@ -416,6 +493,7 @@ def bench_tn(steps, configs=("p3", "p4", "p4_sliced20"), batch_only=False):
     res["dense_step"] = {"shape": "batch 2, M = N = 4096, K = 1024 complex", "gemm_steps": plan.info["gemm_steps"],
                          "ms": round(ms, 3), "tflops": fl / (ms * 1e-3) / 1e12,
                          "mfma_frac_fp32": fl / (ms * 1e-3) / 157.3e12,
+                         "mfma_frac_fp32_measured": _mfrac(fl / (ms * 1e-3) / 1e12, "fp32_mfma_TFLOPs"),
                          "sampled_rel_err": float(max(errs))}
     # the same step in complex128 on FP64 MFMA (peak 78.6 TFLOP/s)
     plan2 = lib.TnPlan([b + m + k, b + k + nn], [(0, 1)], out_inds=b + m + nn, c128=True)
@@ -434,7 +512,9 @@ def bench_tn(steps, configs=("p3", "p4", "p4_sliced20"), batch_only=False):
                      np.sqrt(np.sum(np.abs(a) ** 2) * np.sum(np.abs(bcol) ** 2)))
     res["dense_step_c128"] = {"shape": "batch 2, M = N = 4096, K = 1024 complex128", "gemm_steps": plan2.info["gemm_steps"],
                               "ms": round(ms2, 3), "tflops": fl / (ms2 * 1e-3) / 1e12,
-                              "mfma_frac_fp64": fl / (ms2 * 1e-3) / 78.6e12, "sampled_rel_err": float(max(errs2))}
+                              "mfma_frac_fp64": fl / (ms2 * 1e-3) / 78.6e12,
+                              "mfma_frac_fp64_measured": _mfrac(fl / (ms2 * 1e-3) / 1e12, "fp64_mfma_TFLOPs"),
+                              "sampled_rel_err": float(max(errs2))}
     return res
 
 
@@ -515,6 +595,7 @@ def main():
     ap.add_argument("--coal-bits", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the QNN batch, uneven batch and tensor-network measurements")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the attainable-peak probes")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="calibration only: 10 device-to-device copies of this many bytes (the known "
                          "traffic that scales the HBM byte counters), then exit")
@@ -538,6 +619,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 10}), flush=True)
         return
+
+    peaks = None if args.no_peaks else measure_peaks()
 
     c = W.brickwork()
     n, G = c.n, c.gates.shape[0]
@@ -586,13 +669,16 @@ def main():
     t_alu = flops_per_stage / (ALU_PEAK_TFLOPS * 1e12)
     if t_alu >= t_hbm:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
+                "frac": round(tflops / ALU_PEAK_TFLOPS, 4), "frac_measured": _mfrac(tflops, "fp32_fma_TFLOPs"),
+                "traffic": measured_traffic(),
                 "algorithmic_bytes": bytes_per_stage, "algorithmic_flops": flops_per_stage,
                 "peak_published_fp32_vector": ALU_PEAK_PUBLISHED_TFLOPS,
-                "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                "hbm_achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "hbm_frac_measured": _mfrac(gbs, "state_copy_GBs")}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "frac_measured": _mfrac(gbs, "state_copy_GBs"),
+                "traffic": measured_traffic(),
                 "algorithmic_bytes": bytes_per_stage}
     roof.update({"kernel": "sv_stage_kernel<float,%d>" % info["reg_bits"], "launches_per_step": stages,
                  "avg_launch_us": round(stage_ms * 1e3, 2)})
@@ -602,7 +688,8 @@ def main():
     ev_bytes = (1 << n) * 8
     expval_roof = {"bound": "hbm", "kernel": "expval_partial_kernel + expval_final_kernel", "terms": int(c.terms.shape[0]),
                    "achieved": round(ev_bytes / (ev_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                   "frac": round(ev_bytes / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "us": round(ev_ms * 1e3, 2),
+                   "frac": round(ev_bytes / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "frac_measured": _mfrac(ev_bytes / (ev_ms * 1e-3) / 1e9, "state_read_GBs"), "us": round(ev_ms * 1e3, 2),
                    "algorithmic_bytes": ev_bytes}
 
     # the plain path (one HBM sweep per gate) on the same circuit, for comparison
@@ -624,6 +711,7 @@ def main():
         plain = {"gate*amps/s": G * (1 << n) / (pms * 1e-3), "ms_per_step": round(pms, 3),
                  "sweeps": pinfo["sweeps"],
                  "avg_sweep_GBs": round(pinfo["sweeps"] * bytes_per_stage / (pms * 1e-3) / 1e9, 1),
+                 "avg_sweep_frac_measured": _mfrac(pinfo["sweeps"] * bytes_per_stage / (pms * 1e-3) / 1e9, "state_copy_GBs"),
                  "expval_agrees": bool(abs(float(fp[0, 0]) - float(f[0, 0])) < 1e-4)}
 
     out = {
@@ -638,6 +726,7 @@ def main():
                    "exchanges": info["exchanges"]},
         "roofline": roof,
         "roofline_expval": expval_roof,
+        "measured_peaks": peaks,
         "expval_sum_z": float(f[0, 0]),
         "plain": plain,
     }

@@ -490,6 +490,26 @@ tq_status tq_mlp_train_step(tq_ctx* ctx, const tq_mlp_desc* desc, float* d_param
                             const float* d_y, int32_t batch, float* d_loss, float* d_grad, void* d_work,
                             int64_t work_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Attainable peaks. The rooflines the kernels are graded against (HBM bandwidth for the
+ * sweeps, vector and matrix-core rates for the stage and contraction kernels) are quoted
+ * both against the datasheet and against what fixed kernels reach on the device at hand.
+ * ------------------------------------------------------------------------------------- */
+
+/* Enqueues one probe launch on `stream` and sets *work to the work it does; the caller times
+ * the launch with events on that stream. kind 0: stream copy, the first half of the device
+ * buffer d_buf is copied to the second half (one 16-byte vector per thread), *work = bytes
+ * (half read plus half written). kind 4: stream read of all of d_buf, *work = bytes; it
+ * writes nothing unless the buffer's values sum to -1 in a thread's share, and then only the
+ * first float of d_buf. For kinds 0 and 4, bytes is a positive multiple of 32 KiB, at most
+ * 8 TiB. kind 1: FP32 fused multiply-add chains, non-packed (2048 x 256 threads x iters x 8
+ * FMAs; *work in flops). kind 2: FP32 16x16x4 matrix-core accumulations (8192 waves x iters
+ * x 8, 2048 flops each). kind 3: the same with FP64. Kinds 1-3 write one value per thread to
+ * d_buf, which must hold 2048 x 256 floats (kinds 1, 2) or doubles (kind 3). Errors:
+ * TQ_EINVAL (null pointer, unknown kind, iters < 1), TQ_ESIZE (buffer too small, or not a
+ * multiple of 32 KiB for kinds 0 and 4). */
+tq_status tq_peak_probe(int32_t kind, void* d_buf, uint64_t bytes, int32_t iters, double* work, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -283,6 +283,21 @@ def optimizer_step(params, grad, lr, step=1, m=None, v=None, adam=False, beta1=0
     return params
 
 
+_lib.tq_peak_probe.argtypes = [_i32, _vp, ct.c_uint64, _i32, ct.POINTER(ct.c_double), _vp]
+_lib.tq_peak_probe.restype = ct.c_int
+
+PEAK_COPY, PEAK_FP32_FMA, PEAK_FP32_MFMA, PEAK_FP64_MFMA, PEAK_READ = 0, 1, 2, 3, 4
+
+
+def peak_probe(kind, buf, iters=1):
+    """Enqueue one attainable-peak probe launch (tq_peak_probe) on the current stream over the
+    device tensor buf; returns the work it does (bytes for PEAK_COPY and PEAK_READ, flops otherwise)."""
+    w = ct.c_double(0.0)
+    check(_lib.tq_peak_probe(int(kind), buf.data_ptr(), ct.c_uint64(buf.numel() * buf.element_size()), int(iters),
+                             ct.byref(w), _stream()))
+    return w.value
+
+
 _lib.tq_ctx_export_tuning.argtypes = [_vp, _vp, ct.c_int64]
 _lib.tq_ctx_export_tuning.restype = ct.c_int64
 _lib.tq_ctx_import_tuning.argtypes = [_vp, _vp, ct.c_int64]

@@ -73,3 +73,21 @@ def test_network_plan_without_a_device():
     p = lib.TnPlan([lf.inds for lf in net.leaves], tree.pairs, tree.sliced, net.output, host_only=True)
     assert p.ctx is None and p.info["flops"] > 0
     assert p.workspace_bytes(True) >= p.workspace_bytes(False) > 0
+
+
+def test_peak_probe_rejects_bad_arguments_on_the_host():
+    """Argument checks of tq_peak_probe run before any launch (the pointer is never used)."""
+    import ctypes as ct
+
+    from paper_2301_05451_amd import lib
+
+    w = ct.c_double(0.0)
+    dummy = ct.c_void_p(0x1000)
+    assert lib._lib.tq_peak_probe(7, dummy, ct.c_uint64(1 << 20), 1, ct.byref(w), None) == 1       # unknown kind
+    assert lib._lib.tq_peak_probe(0, dummy, ct.c_uint64(3 << 14), 1, ct.byref(w), None) == 2       # not 32 KiB
+    assert lib._lib.tq_peak_probe(0, dummy, ct.c_uint64(0), 1, ct.byref(w), None) == 2
+    assert lib._lib.tq_peak_probe(1, dummy, ct.c_uint64(1 << 20), 1, ct.byref(w), None) == 2       # < 2 MiB
+    assert lib._lib.tq_peak_probe(3, dummy, ct.c_uint64(1 << 21), 1, ct.byref(w), None) == 2       # < 4 MiB
+    assert lib._lib.tq_peak_probe(2, dummy, ct.c_uint64(1 << 21), 0, ct.byref(w), None) == 1       # iters < 1
+    assert lib._lib.tq_peak_probe(0, None, ct.c_uint64(1 << 20), 1, ct.byref(w), None) == 1        # null buffer
+    assert w.value == 0.0
