@@ -5,8 +5,8 @@
 // 12 are fixed per chunk: their parity is one uniform sign per term. Within a chunk, a
 // thread holds 16 amplitudes; the sums of all terms over them are read off one
 // Walsh-Hadamard transform of the thread's |psi|^2 values, in the state's precision, as is the
-// thread's running sum over its chunks. Everything above (waves, the group, the groups of a
-// circuit) is a fixed-order double tree, so repeated runs are bitwise equal.
+// thread's running sum over its chunks. Everything above a thread (the threads of a group, the
+// groups of a circuit) is summed in double in a fixed order, so repeated runs are bitwise equal.
 #include <mutex>
 #include <type_traits>
 
@@ -39,19 +39,18 @@ __device__ __forceinline__ double dpp_add_f64(double v) {
   return v + __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the 64 lanes of a full wave in a fixed order (pairs in quads, half-row and row
-// mirrors, then row broadcasts); every lane gets the total of lane 63.
-__device__ __forceinline__ double wave_sum_f64(double v) {
+// Sum over each aligned group of P lanes (P = 16: a row of 16 lanes; P = 32: two rows) in a
+// fixed order: pairs in quads, quads, half-row and row mirrors, and for P = 32 a row broadcast
+// into the odd rows. The group's total is then in its last lane.
+template <int P>
+__device__ __forceinline__ double lanes_sum_f64(double v) {
+  static_assert(P == 16 || P == 32, "groups of 16 or 32 lanes");
   v = dpp_add_f64<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
   v = dpp_add_f64<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
   v = dpp_add_f64<0x141, 0xf>(v);  // row_half_mirror
-  v = dpp_add_f64<0x140, 0xf>(v);  // row_mirror
-  v = dpp_add_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v = dpp_add_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffull), 63);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  v = dpp_add_f64<0x140, 0xf>(v);  // row_mirror: every lane of a row holds the row's total
+  if constexpr (P == 32) v = dpp_add_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
 }
 
 // Chunk size of the partial-sum kernel: 2^kExpChunkBits amplitudes, 16 per thread.
@@ -207,21 +206,27 @@ __global__ void __launch_bounds__(kExpThreads)
     expval_partial_body<T, KT, A, true>(s, n, pmask, nk, acc, wsh);
   else
     expval_partial_body<T, KT, 1, true>(s, n, pmask, nk, acc, wsh);
-  __shared__ double red[kExpThreads / 64][KT];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // The group's sums of its terms, in rounds of RT terms: every thread stores its sums of the
+  // round's terms, as double, over the transform's LDS array; P = 256 / RT threads per term
+  // each add RT of them (threads s, s + P, s + 2P, ...) in order, P-lane sums finish the term
+  // and the group's last lane writes it. A fixed order, so repeated runs are bitwise equal.
+  constexpr int RT = (int)(sizeof(wsh) / (kExpThreads * sizeof(double)));  // 8 (float), 16 (double)
+  constexpr int P = kExpThreads / RT;
+  double* const red = reinterpret_cast<double*>(&wsh[0][0]);
+  const int tid = threadIdx.x, rk = tid / P, rs = tid % P;  // this thread's term of a round, first thread
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < nk) {  // terms past nk (the template's padding) are not reduced
-      const double x = wave_sum_f64((double)acc[k]);  // the work-group is four full waves
-      if (lane == 0) red[wv][k] = x;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < nk && threadIdx.x < KT) {
-    const int k = threadIdx.x;
+  for (int r = 0; r < KT; r += RT) {
+    __syncthreads();  // the array is free: every thread is past its chunks / the last round's reads
+#pragma unroll
+    for (int k = 0; k < RT; ++k) red[k * kExpThreads + tid] = r + k < KT ? (double)acc[r + k < KT ? r + k : 0] : 0.0;
+    __syncthreads();
     double x = 0.0;
-    for (int w = 0; w < kExpThreads / 64; ++w) x += red[w][k];
-    partial[((int64_t)blockIdx.y * KT + k) * gridDim.x + blockIdx.x] = x;
+#pragma unroll
+    for (int i = 0; i < RT; ++i) x += red[rk * kExpThreads + rs + P * i];
+    x = lanes_sum_f64<P>(x);
+    const int k = r + rk;
+    if (rs == P - 1 && k < nk)  // terms past nk (the template's padding) are not written
+      partial[((int64_t)blockIdx.y * KT + k) * gridDim.x + blockIdx.x] = x;
   }
 }
 
