@@ -247,6 +247,23 @@ __device__ __forceinline__ void reg_mat_group(typename Cx<T>::type (&v)[1 << R],
   }
 }
 
+// Per-thread CZ signs without register-register flips: the CZs with register operands K1
+// and K2 (K2 < 0: none) whose partners are thread or tile bits, with sign words s1, s2 of
+// those bits. Which amplitudes a word applies to is fixed by K1 and K2, so only the flipped
+// ones cost instructions (two XORs each).
+template <typename T, int R, int K1, int K2>
+__device__ __forceinline__ void zg_thread_flips(typename Cx<T>::type (&v)[1 << R], uint32_t s1, uint32_t s2) {
+  const uint32_t s12 = s1 ^ s2;
+#pragma unroll
+  for (int j = 0; j < (1 << R); ++j) {
+    const bool b1 = ((j >> K1) & 1) != 0, b2 = K2 >= 0 && ((j >> (K2 < 0 ? 0 : K2)) & 1) != 0;
+    if (!b1 && !b2) continue;
+    const uint32_t sg = b1 && b2 ? s12 : (b1 ? s1 : s2);
+    v[j].x = flip_sign(v[j].x, sg);
+    v[j].y = flip_sign(v[j].y, sg);
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void apply_op(typename Cx<T>::type (&v)[1 << R], const DevOp op, uint32_t tp,
                                          const typename Cx<T>::type* __restrict__ M, int t, uint32_t tile) {
@@ -284,12 +301,36 @@ __device__ __forceinline__ void apply_op(typename Cx<T>::type (&v)[1 << R], cons
         const uint32_t uni = (uint32_t)op.mat;
         const int k1 = (op.rbit & 15) - 1, k2 = (op.rbit >> 4) - 1;
         if (k1 < 0) {
+          if (uni == 0) return;  // an empty op (phases are padded to an even op count)
 #pragma unroll
           for (int j = 0; j < (1 << R); ++j)
             if ((uni >> j) & 1u) {
               v[j].x = flip_sign(v[j].x, 0x80000000u);
               v[j].y = flip_sign(v[j].y, 0x80000000u);
             }
+        } else if (uni == 0) {
+          const uint32_t s1 = idx_bit(op.pa, tp, t, tile) << 31;
+          const uint32_t s2 = k2 >= 0 ? idx_bit(op.pb, tp, t, tile) << 31 : 0u;
+#define TQ_ZG_K(A, B) zg_thread_flips<T, R, (R > A ? A : R - 1), (R > B ? B : R - 1)>(v, s1, s2)
+#define TQ_ZG_CASE(A)                                       \
+  case A:                                                   \
+    switch (k2) {                                           \
+      case -1: zg_thread_flips<T, R, (R > A ? A : R - 1), -1>(v, s1, s2); break; \
+      case 0: TQ_ZG_K(A, 0); break;                         \
+      case 1: TQ_ZG_K(A, 1); break;                         \
+      case 2: TQ_ZG_K(A, 2); break;                         \
+      default: TQ_ZG_K(A, 3); break;                        \
+    }                                                       \
+    break;
+          switch (k1) { TQ_ZG_CASE(0) TQ_ZG_CASE(1) TQ_ZG_CASE(2) default: switch (k2) {
+              case -1: zg_thread_flips<T, R, (R > 3 ? 3 : R - 1), -1>(v, s1, s2); break;
+              case 0: TQ_ZG_K(3, 0); break;
+              case 1: TQ_ZG_K(3, 1); break;
+              case 2: TQ_ZG_K(3, 2); break;
+              default: TQ_ZG_K(3, 3); break;
+            } }
+#undef TQ_ZG_CASE
+#undef TQ_ZG_K
         } else {
           // this thread's flip mask over j, then bit j moved to the sign position
           uint32_t f = uni;
