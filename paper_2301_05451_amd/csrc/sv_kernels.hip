@@ -527,6 +527,25 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_
                    blockIdx.x, threadIdx.x, true, reinterpret_cast<C*>(smem_raw));
 }
 
+// The same kernel for the default tile of 2^12 amplitudes, its LDS declared with a fixed
+// size. A dynamically sized LDS array starts at a link-time symbol, which the compiler adds
+// to every LDS address (one extra instruction per access); a fixed array's base folds away.
+constexpr int kStaticTileBits = 12;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_waves<T, R>()))) sv_stage_kernel_t12(const DevStage* __restrict__ stg,
+                                                            const DevPhase* __restrict__ phases,
+                                                            const DevOp* __restrict__ ops,
+                                                            const typename Cx<T>::type* __restrict__ mats,
+                                                            int64_t mats_stride,
+                                                            typename Cx<T>::type* __restrict__ state,
+                                                            BatchMap smap) {
+  using C = typename Cx<T>::type;
+  __shared__ __align__(16) C tile_lds[1 << kStaticTileBits];
+  stage_tile<T, R>(stg, phases, ops, mats + (int64_t)blockIdx.y * mats_stride, state + smap.at(blockIdx.y),
+                   blockIdx.x, threadIdx.x, true, tile_lds);
+}
+
 // Heterogeneous batch, one stage level: work-group i runs items[i] (a tile of one circuit's
 // stage `level`). The work-group is sized for the level's largest tile.
 template <typename T, int R>
@@ -653,9 +672,14 @@ static tq_status launch_stages_R(const Schedule& s, void* d_states, BatchMap sma
       const unsigned tiles = 1u << (s.n - t);
       const unsigned threads = 1u << (t - R);
       const size_t lds = sizeof(C) << t;
-      hipLaunchKernelGGL((sv_stage_kernel<T, R>), dim3(tiles, cn), dim3(threads), lds, stream,
-                         (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
-                         mstride, (C*)d_states, sm);
+      if (t == kStaticTileBits)
+        hipLaunchKernelGGL((sv_stage_kernel_t12<T, R>), dim3(tiles, cn), dim3(threads), 0, stream,
+                           (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
+                           mstride, (C*)d_states, sm);
+      else
+        hipLaunchKernelGGL((sv_stage_kernel<T, R>), dim3(tiles, cn), dim3(threads), lds, stream,
+                           (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
+                           mstride, (C*)d_states, sm);
       TQ_HIP(hipGetLastError());
     }
   }
