@@ -680,7 +680,8 @@ def main():
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "frac_measured": _mfrac(gbs, "state_copy_GBs"),
                 "traffic": measured_traffic(),
                 "algorithmic_bytes": bytes_per_stage}
-    roof.update({"kernel": "sv_stage_kernel<float,%d>" % info["reg_bits"], "launches_per_step": stages,
+    kname = "sv_stage_kernel_t12<float,%d>" if info["tile_bits"] == 12 else "sv_stage_kernel<float,%d>"
+    roof.update({"kernel": kname % info["reg_bits"], "launches_per_step": stages,
                  "avg_launch_us": round(stage_ms * 1e3, 2)})
 
     # the expectation value alone (partial-sum + final launches): a streaming read of the state
