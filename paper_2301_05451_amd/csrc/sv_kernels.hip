@@ -563,12 +563,28 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_
                    reinterpret_cast<C*>(smem_raw));
 }
 
-// Basis-state initialisation |b> (Sec. 3.1 default |0..0> for b = 0): vector stores only.
+// Basis-state initialisation |b> (Sec. 3.1 default |0..0> for b = 0): vector stores only,
+// two complex64 amplitudes per 16-byte store where the state is 16-byte aligned (2^n is even).
 template <typename T>
 __global__ void __launch_bounds__(256) init_basis_kernel(typename Cx<T>::type* __restrict__ st, BatchMap smap,
                                                          int64_t namps, int64_t basis) {
   using C = typename Cx<T>::type;
   C* s = st + smap.at(blockIdx.y);
+  if constexpr (sizeof(C) == 8) {
+    if ((reinterpret_cast<uintptr_t>(s) & 15) == 0 && (namps & 1) == 0) {
+      float4* s4 = reinterpret_cast<float4*>(s);
+      for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps / 2;
+           i += (int64_t)gridDim.x * blockDim.x) {
+        float4 v;
+        v.x = (2 * i == basis) ? 1.0f : 0.0f;
+        v.y = 0.0f;
+        v.z = (2 * i + 1 == basis) ? 1.0f : 0.0f;
+        v.w = 0.0f;
+        s4[i] = v;
+      }
+      return;
+    }
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < namps; i += (int64_t)gridDim.x * blockDim.x) {
     C v;
     v.x = (i == basis) ? (T)1 : (T)0;
