@@ -58,7 +58,7 @@ constexpr int kExpChunkBits = 12;
 constexpr int kExpVals = 16;
 
 // Work-groups per circuit of the partial-sum kernel: about kExpGroups over the launch, at
-// most one per 2^13-amplitude chunk.
+// most one per 2^12-amplitude chunk.
 constexpr int kExpGroups = 512;
 
 int expval_groups(int n, int cn) {
