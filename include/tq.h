@@ -145,6 +145,16 @@ tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_
                       const int32_t* n_params, const void* d_params, void* d_states,
                       const tq_sv_opts* opts, void* stream);
 
+/* Sec. 3.1 from the default start: every circuit's state becomes U |basis> (basis = 0 is the
+ * paper's |0..0>); d_states is written, never read. The same result as tq_sv_init followed
+ * by tq_sv_apply with the same arguments, with one HBM pass fewer: in fused mode the first
+ * stage forms |basis> itself (plain mode and gate lists without a stage prepare the state
+ * first). Errors: those of tq_sv_apply, and TQ_EINVAL if basis is outside [0, 2^n) for any
+ * circuit. */
+tq_status tq_sv_run(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates,
+                    const int32_t* n_params, const void* d_params, int64_t basis, void* d_states,
+                    const tq_sv_opts* opts, void* stream);
+
 /* Writes the computational basis state |basis> into every circuit's state (the default
  * initial state of Sec. 3.1 is basis = 0). Errors: TQ_EINVAL if basis is outside [0, 2^n). */
 tq_status tq_sv_init(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, int64_t basis, void* d_states,

@@ -343,9 +343,12 @@ tq_status member_map(tq_ctx* ctx, int slot, const int64_t* all, const std::vecto
   return TQ_OK;
 }
 
+// basis < 0: apply to the states as they are (tq_sv_apply); basis >= 0: to |basis>, which the
+// first fused stage forms in place of reading the states (tq_sv_run).
 template <typename T>
 static tq_status sv_apply_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
-                            const void* d_params, void* d_states, const tq_sv_opts* opts, hipStream_t stream) {
+                            const void* d_params, void* d_states, const tq_sv_opts* opts, hipStream_t stream,
+                            int64_t basis = -1) {
   using C = typename Cx<T>::type;
   std::vector<Group> groups;
   TQ_TRY(group_batch(batch, n_params, groups));
@@ -355,6 +358,8 @@ static tq_status sv_apply_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* g
   for (const Group& gr : groups) {
     const tq_gate* g = gates + gr.gate_off;
     TQ_TRY(validate_gates(g, gr.n_gates, gr.n, gr.n_params));
+    if (basis >= 0 && gr.n < 63 && basis >= (int64_t(1) << gr.n))
+      return fail(TQ_EINVAL, "basis index outside [0, 2^n)");
   }
   for (const Group& gr : groups) {
     const GateView gv(gates + gr.gate_off, gr.n_gates);  // controlled rotations lowered
@@ -367,10 +372,13 @@ static tq_status sv_apply_t(tq_ctx* ctx, const tq_batch* batch, const tq_gate* g
     void* mats;
     TQ_TRY(scratch(ctx, S_MATS, (size_t)count * std::max<size_t>(s->recipes.size(), 1) * 4 * sizeof(C), &mats));
     TQ_TRY(launch_gate_build<T>(*s, d_params, pmap, mats, count, stream));
+    const bool fused_init = basis >= 0 && mode == 0 && !s->stages.empty();
+    if (basis >= 0 && !fused_init)  // no stage to form the basis state in: a preparation pass
+      TQ_TRY(launch_init_basis<T>(d_states, smap, gr.n, count, basis, ctx->n_cu, stream));
     if (mode == 1)
       TQ_TRY(launch_plain<T>(*s, d_states, smap, mats, count, ctx->n_cu, stream));
     else
-      TQ_TRY(launch_stages<T>(*s, d_states, smap, mats, count, stream));
+      TQ_TRY(launch_stages<T>(*s, d_states, smap, mats, count, fused_init ? basis : -1, stream));
   }
   return TQ_OK;
 }
@@ -638,6 +646,17 @@ tq_status tq_sv_apply(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_
   if (dt == TQ_C64) return sv_apply_t<float>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream);
   if (dt == TQ_C128)
     return sv_apply_t<double>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream);
+  return fail(TQ_EINVAL, "unknown dtype");
+}
+
+tq_status tq_sv_run(tq_ctx* ctx, tq_dtype dt, const tq_batch* batch, const tq_gate* gates, const int32_t* n_params,
+                    const void* d_params, int64_t basis, void* d_states, const tq_sv_opts* opts, void* stream) {
+  if (!ctx) return fail(TQ_EINVAL, "null context");
+  if (basis < 0) return fail(TQ_EINVAL, "basis index outside [0, 2^n)");
+  if (dt == TQ_C64)
+    return sv_apply_t<float>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream, basis);
+  if (dt == TQ_C128)
+    return sv_apply_t<double>(ctx, batch, gates, n_params, d_params, d_states, opts, (hipStream_t)stream, basis);
   return fail(TQ_EINVAL, "unknown dtype");
 }
 

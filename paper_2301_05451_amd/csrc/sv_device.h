@@ -469,9 +469,11 @@ tq_status launch_gate_build(const Schedule& s, const void* d_params, BatchMap pm
 template <typename T>
 tq_status launch_plain(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count, int n_cu,
                        hipStream_t stream);
+// basis >= 0: the states are not read; the first stage starts from |basis> (every stage
+// of a schedule with at least one stage; the caller prepares the states otherwise).
 template <typename T>
 tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
-                        hipStream_t stream);
+                        int64_t basis, hipStream_t stream);
 template <typename T>
 tq_status launch_init_basis(void* d_states, BatchMap smap, int n, int count, int64_t basis, int n_cu,
                             hipStream_t stream);

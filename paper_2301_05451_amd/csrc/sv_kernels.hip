@@ -420,7 +420,8 @@ __device__ __forceinline__ void apply_phase_ops(typename Cx<T>::type (&v)[1 << R
 
 // One stage over one tile. Threads with act == false (past the 2^(t-R) a tile of a smaller
 // circuit needs, in a batched work-group sized for the largest) hold no amplitudes and only
-// take part in the barriers.
+// take part in the barriers. basis >= 0: the tile is not read but starts as that part of
+// the basis state |basis> (1 at index basis, 0 elsewhere).
 //
 // LDS addresses: amplitude j of a thread sits at local index tp | rp_j (thread bits and
 // register bits occupy disjoint positions). The swizzle is linear over XOR, so its byte
@@ -431,7 +432,7 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
                                            const DevOp* __restrict__ ops,
                                            const typename Cx<T>::type* __restrict__ M,
                                            typename Cx<T>::type* __restrict__ st, uint32_t tile, uint32_t tid,
-                                           bool act, typename Cx<T>::type* lds) {
+                                           bool act, typename Cx<T>::type* lds, int64_t basis) {
   using C = typename Cx<T>::type;
   constexpr uint32_t E = sizeof(C);
   const gword* const sw = reinterpret_cast<const gword*>(gptr(stg));
@@ -440,14 +441,17 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
   unsigned char* const lb = reinterpret_cast<unsigned char*>(lds);
 
   // global offsets of this thread's amplitudes in the load/store layout
-  C* const sb = st + (stage_tile_base(sw, tile) | stage_thread_offset(sw, tb, tid));
+  const int64_t off = stage_tile_base(sw, tile) | stage_thread_offset(sw, tb, tid);
+  C* const sb = st + off;
   C v[1 << R];
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
     int64_t hi = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) hi |= (int64_t)((j >> k) & 1) << word_byte(sw, kStageLposWord, tb + k);
-    if (act) v[j] = sb[hi]; else v[j] = C{(T)0, (T)0};
+    if (!act) v[j] = C{(T)0, (T)0};
+    else if (basis < 0) v[j] = sb[hi];
+    else v[j] = C{(off | hi) == basis ? (T)1 : (T)0, (T)0};
   }
 
   // load layout: thread bits are the low tb local bits, registers the top R
@@ -520,11 +524,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_
                                                         const DevOp* __restrict__ ops,
                                                         const typename Cx<T>::type* __restrict__ mats,
                                                         int64_t mats_stride, typename Cx<T>::type* __restrict__ state,
-                                                        BatchMap smap) {
+                                                        BatchMap smap, int64_t basis) {
   using C = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   stage_tile<T, R>(stg, phases, ops, mats + (int64_t)blockIdx.y * mats_stride, state + smap.at(blockIdx.y),
-                   blockIdx.x, threadIdx.x, true, reinterpret_cast<C*>(smem_raw));
+                   blockIdx.x, threadIdx.x, true, reinterpret_cast<C*>(smem_raw), basis);
 }
 
 // The same kernel for the default tile of 2^12 amplitudes, its LDS declared with a fixed
@@ -539,11 +543,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_
                                                             const typename Cx<T>::type* __restrict__ mats,
                                                             int64_t mats_stride,
                                                             typename Cx<T>::type* __restrict__ state,
-                                                            BatchMap smap) {
+                                                            BatchMap smap, int64_t basis) {
   using C = typename Cx<T>::type;
   __shared__ __align__(16) C tile_lds[1 << kStaticTileBits];
   stage_tile<T, R>(stg, phases, ops, mats + (int64_t)blockIdx.y * mats_stride, state + smap.at(blockIdx.y),
-                   blockIdx.x, threadIdx.x, true, tile_lds);
+                   blockIdx.x, threadIdx.x, true, tile_lds, basis);
 }
 
 // Heterogeneous batch, one stage level: work-group i runs items[i] (a tile of one circuit's
@@ -560,7 +564,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(stage_
   const DevStage* stg = d.stages + level;
   const bool act = threadIdx.x < (1u << ((int)reinterpret_cast<const gword*>(gptr(stg))[0] - R));
   stage_tile<T, R>(stg, d.phases, d.ops, mats + d.mats_off, states + d.state_off, w.y, threadIdx.x, act,
-                   reinterpret_cast<C*>(smem_raw));
+                   reinterpret_cast<C*>(smem_raw), -1);
 }
 
 // Basis-state initialisation |b> (Sec. 3.1 default |0..0> for b = 0): vector stores only,
@@ -676,7 +680,7 @@ tq_status launch_plain(const Schedule& s, void* d_states, BatchMap smap, const v
 
 template <typename T, int R>
 static tq_status launch_stages_R(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
-                                 hipStream_t stream) {
+                                 int64_t basis, hipStream_t stream) {
   using C = typename Cx<T>::type;
   const int64_t mstride = 4 * (int64_t)s.recipes.size();
   for (int c0 = 0; c0 < count; c0 += 65535) {
@@ -688,14 +692,15 @@ static tq_status launch_stages_R(const Schedule& s, void* d_states, BatchMap sma
       const unsigned tiles = 1u << (s.n - t);
       const unsigned threads = 1u << (t - R);
       const size_t lds = sizeof(C) << t;
+      const int64_t b = k == 0 ? basis : -1;  // only the first stage starts from |basis>
       if (t == kStaticTileBits)
         hipLaunchKernelGGL((sv_stage_kernel_t12<T, R>), dim3(tiles, cn), dim3(threads), 0, stream,
                            (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
-                           mstride, (C*)d_states, sm);
+                           mstride, (C*)d_states, sm, b);
       else
         hipLaunchKernelGGL((sv_stage_kernel<T, R>), dim3(tiles, cn), dim3(threads), lds, stream,
                            (const DevStage*)s.d_stages + k, (const DevPhase*)s.d_phases, (const DevOp*)s.d_ops, Mc,
-                           mstride, (C*)d_states, sm);
+                           mstride, (C*)d_states, sm, b);
       TQ_HIP(hipGetLastError());
     }
   }
@@ -704,14 +709,14 @@ static tq_status launch_stages_R(const Schedule& s, void* d_states, BatchMap sma
 
 template <typename T>
 tq_status launch_stages(const Schedule& s, void* d_states, BatchMap smap, const void* d_mats, int count,
-                        hipStream_t stream) {
+                        int64_t basis, hipStream_t stream) {
   const int R = std::min(s.R, std::min(s.t, s.n));
   switch (R) {
-    case 1: return launch_stages_R<T, 1>(s, d_states, smap, d_mats, count, stream);
-    case 2: return launch_stages_R<T, 2>(s, d_states, smap, d_mats, count, stream);
-    case 3: return launch_stages_R<T, 3>(s, d_states, smap, d_mats, count, stream);
-    case 4: return launch_stages_R<T, 4>(s, d_states, smap, d_mats, count, stream);
-    case 5: return launch_stages_R<T, 5>(s, d_states, smap, d_mats, count, stream);
+    case 1: return launch_stages_R<T, 1>(s, d_states, smap, d_mats, count, basis, stream);
+    case 2: return launch_stages_R<T, 2>(s, d_states, smap, d_mats, count, basis, stream);
+    case 3: return launch_stages_R<T, 3>(s, d_states, smap, d_mats, count, basis, stream);
+    case 4: return launch_stages_R<T, 4>(s, d_states, smap, d_mats, count, basis, stream);
+    case 5: return launch_stages_R<T, 5>(s, d_states, smap, d_mats, count, basis, stream);
     default: return fail(TQ_ENOTSUP, "register bits must be 1..5");
   }
 }
@@ -720,8 +725,8 @@ template tq_status launch_gate_build<float>(const Schedule&, const void*, BatchM
 template tq_status launch_gate_build<double>(const Schedule&, const void*, BatchMap, void*, int, hipStream_t);
 template tq_status launch_plain<float>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
 template tq_status launch_plain<double>(const Schedule&, void*, BatchMap, const void*, int, int, hipStream_t);
-template tq_status launch_stages<float>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
-template tq_status launch_stages<double>(const Schedule&, void*, BatchMap, const void*, int, hipStream_t);
+template tq_status launch_stages<float>(const Schedule&, void*, BatchMap, const void*, int, int64_t, hipStream_t);
+template tq_status launch_stages<double>(const Schedule&, void*, BatchMap, const void*, int, int64_t, hipStream_t);
 
 // ---- heterogeneous batch ---------------------------------------------------------------
 template <typename T, int R>

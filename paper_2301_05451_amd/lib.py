@@ -204,6 +204,21 @@ def sv_apply(states, params, spec: BatchSpec, mode=0, tile_bits=0, reg_bits=0, c
     return states
 
 
+_lib.tq_sv_run.argtypes = [_vp, ct.c_int, ct.POINTER(Batch), _vp, _vp, _vp, ct.c_int64, _vp, ct.POINTER(SvOpts), _vp]
+_lib.tq_sv_run.restype = ct.c_int
+
+
+def sv_run(states, params, spec: BatchSpec, basis=0, mode=0, tile_bits=0, reg_bits=0, coal_bits=0, ctx=None):
+    """|psi_i> <- U_i |basis> for every circuit of ``spec`` (tq_sv_run): the states' contents
+    are not read; in fused mode the first stage forms the basis state itself."""
+    _check_tensors(states, params, spec)
+    ctx = ctx or context(states.device.index)
+    o = _opts(mode, tile_bits, reg_bits, coal_bits)
+    check(_lib.tq_sv_run(ctx.h, _dt(states), ct.byref(spec.c), spec.gates.ctypes.data, spec.n_params.ctypes.data,
+                         params.data_ptr(), ct.c_int64(basis), states.data_ptr(), ct.byref(o), _stream()))
+    return states
+
+
 PLAN_FIELDS = ("sweeps", "ops", "phases", "exchanges", "tile_bits", "reg_bits", "flops_per_amp", "mats")
 
 

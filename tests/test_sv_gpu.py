@@ -49,6 +49,41 @@ def test_random_circuits_all_gates(name, mode):
         assert err <= TOL[name], (n, err)
 
 
+@pytest.mark.parametrize("name", ["c64", "c128"])
+@pytest.mark.parametrize("mode,tile", [(0, 0), (0, 10), (1, 0)])
+def test_run_from_basis_equals_init_then_apply(name, mode, tile):
+    """tq_sv_run(|b>) writes exactly what tq_sv_init(b) followed by tq_sv_apply writes (in fused
+    mode the first stage forms |b> instead of reading the state): a batch of circuits of
+    several sizes (one with no gates), b = 0 and another index, the state buffer filled with
+    NaN beforehand; one case also against the oracle started from |b>."""
+    from paper_2301_05451_amd import lib
+
+    rng = np.random.default_rng(31 + mode + tile)
+    circs = [W.random_circuit(n, 70, rng) for n in (13, 12, 9)]
+    empty = W.random_circuit(13, 0, rng)
+    circs.append(empty)
+    cdt, rdt = _dtypes(name)
+    spec = lib.BatchSpec.from_circuits(circs)
+    params = torch.tensor(np.concatenate([c.params for c in circs]), dtype=rdt, device="cuda")
+    for b in (0, 301):
+        ref = torch.empty(spec.total_amps, dtype=cdt, device="cuda")
+        lib.init_states(ref, spec, b)
+        lib.sv_apply(ref, params, spec, mode=mode, tile_bits=tile)
+        got = torch.full((spec.total_amps,), float("nan"), dtype=cdt, device="cuda")
+        lib.sv_run(got, params, spec, basis=b, mode=mode, tile_bits=tile)
+        torch.cuda.synchronize()
+        print(f"run from |{b}> mode={mode} tile={tile} {name}", flush=True)
+        assert torch.equal(got, ref), (b, (got - ref).abs().max().item())
+    c = circs[0]
+    init = np.zeros(1 << c.n, dtype=np.complex128)
+    init[301] = 1.0
+    want = osv.run(c.n, c.gates, c.params, init=init)
+    err = np.abs(got[: 1 << c.n].cpu().numpy() - want).max()
+    assert err <= TOL[name], err
+    with pytest.raises(lib.TQError):
+        lib.sv_run(got, params, spec, basis=1 << 9, mode=mode, tile_bits=tile)  # outside the 9-qubit circuit
+
+
 @pytest.mark.parametrize("tile", [(6, 2, 2), (7, 3, 3), (8, 4, 4), (10, 4, 5), (10, 5, 3), (12, 4, 5), (13, 4, 5)])
 def test_fused_tile_shapes_ragged(tile):
     t, R, cb = tile
