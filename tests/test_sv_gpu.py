@@ -207,7 +207,8 @@ def test_brickwork24_full_size_in_bench_configuration():
     """The 24-qubit brickwork circuit (all 1670 gates) at full size, fused with the default
     shape (the launch configuration the benchmark times), against the oracle amplitude by
     amplitude; sum_i <Z_i> against the oracle's value; the plain one-sweep-per-gate path
-    against the oracle too."""
+    against the oracle too. tq_sv_run from |0..0> (the call the benchmark times, the first
+    stage forming the start state) must equal the prepared-state result bit for bit."""
     from paper_2301_05451_amd import lib
 
     c = W.brickwork()
@@ -228,7 +229,11 @@ def test_brickwork24_full_size_in_bench_configuration():
               f"|d sum Z| = {abs(f - f_want):.3e}", flush=True)
         assert err <= 1e-5, (mode, err)
         assert abs(f - f_want) <= 1e-5, (mode, f, f_want)
-        del psi, got, d
+        run = torch.full_like(psi, float("nan"))
+        lib.sv_run(run, params, spec, basis=0, mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(run, psi), mode
+        del psi, got, d, run
 
 
 @pytest.mark.parametrize("name,n,n_terms", [("c64", 14, 27), ("c64", 20, 27), ("c128", 17, 27), ("c64", 16, 6),
