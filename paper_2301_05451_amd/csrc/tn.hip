@@ -827,6 +827,86 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// The same product with a 128 x 128 real tile per work-group (128 complex rows, 64 complex
+// columns), each wave 64 x 64 as 4 x 4 MFMA blocks: four times the matrix-core work per
+// barrier and half the L2 reads of the 64 x 64 tile. Requires M % 128 == 0, N % 64 == 0,
+// K % 8 == 0 (the host takes the 64 x 64 kernel otherwise).
+constexpr int kGemm2BM = 128, kGemm2BN = 128;
+
+__global__ void __launch_bounds__(256)
+    tn_cgemm_mfma128_kernel(const float2* __restrict__ A, int64_t as, const float2* __restrict__ B, int64_t bs,
+                            float2* __restrict__ Cm, int64_t cs, int M, int N, int K) {
+  __shared__ float sA[kGemmBK][kGemm2BM + 4];   // [k][m]
+  __shared__ float sB[kGemmBK][kGemm2BN + 4];   // [k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = blockIdx.y * kGemm2BM;
+  const int n0c = blockIdx.x * (kGemm2BN / 2);  // complex column
+  const float2* a = A + as * blockIdx.z;
+  const float2* b = B + bs * blockIdx.z;
+  float2* c = Cm + cs * blockIdx.z;
+  typedef float float4v __attribute__((ext_vector_type(4)));
+  float4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += kGemmBK / 2) {  // complex k
+    // A tile: 128 rows x 8 complex = 128 x 16 real; a thread loads 4 complex of one row
+    {
+      const int r = tid >> 1, kk = (tid & 1) * 4;
+      const float2* src = a + (int64_t)(m0 + r) * K + k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float2 v = src[q];
+        sA[2 * (kk + q) + 0][r] = v.x;
+        sA[2 * (kk + q) + 1][r] = v.y;
+      }
+    }
+    // B tile: 8 complex rows x 64 complex cols -> 16 x 128 real; a thread loads 2 complex
+    {
+      const int kr = tid >> 5, cc = (tid & 31) * 2;
+      const float2* src = b + (int64_t)(k0 + kr) * N + n0c + cc;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float2 v = src[q];
+        const int col = 2 * (cc + q);
+        sB[2 * kr + 0][col + 0] = v.x;
+        sB[2 * kr + 0][col + 1] = v.y;
+        sB[2 * kr + 1][col + 0] = -v.y;
+        sB[2 * kr + 1][col + 1] = v.x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmBK; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[kl][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sB[kl][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of 16x16x4: lane l, register r -> row 4*(l/16) + r, column l % 16
+  float* cf = reinterpret_cast<float*>(c);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int col = 2 * n0c + wn + 16 * j + (lane & 15);
+        cf[(int64_t)row * (2 * N) + col] = acc[i][j][r];
+      }
+}
+
 // The same batched complex GEMM for complex128 on FP64 MFMA (16x16x4, double operands and
 // accumulation); identical tiling and real view, so the same size requirements.
 __global__ void __launch_bounds__(256)
@@ -1758,11 +1838,17 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
         TQ_HIP(hipGetLastError());
         for (int64_t c = 0; c < copies; ++c) {
           const dim3 grid((unsigned)(ex.N / 32), (unsigned)(ex.M / 64), (unsigned)ex.B);
-          if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL(tn_cgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const float2*)(xa + xas * c),
-                               ex.M * ex.K, (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c),
-                               ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
-          else
+          if constexpr (sizeof(T) == 4) {
+            if (ex.M % 128 == 0 && ex.N % 64 == 0)  // the large tile
+              hipLaunchKernelGGL(tn_cgemm_mfma128_kernel, dim3((unsigned)(ex.N / 64), (unsigned)(ex.M / 128),
+                                 (unsigned)ex.B), dim3(256), 0, R.st, (const float2*)(xa + xas * c), ex.M * ex.K,
+                                 (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c), ex.M * ex.N,
+                                 (int)ex.M, (int)ex.N, (int)ex.K);
+            else
+              hipLaunchKernelGGL(tn_cgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const float2*)(xa + xas * c),
+                                 ex.M * ex.K, (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c),
+                                 ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
+          } else
             hipLaunchKernelGGL(tn_zgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const double2*)(xa + xas * c),
                                ex.M * ex.K, (const double2*)(ya + yas * c), ex.K * ex.N, (double2*)(z + zs * c),
                                ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);

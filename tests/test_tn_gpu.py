@@ -134,11 +134,15 @@ def test_qaoa50_p3_edges_vs_cone_state_vector():
     assert done >= 1
 
 
-def _gemm_network(rs, permuted):
-    b, m, k, nn = [0], list(range(1, 8)), list(range(8, 13)), list(range(13, 19))
-    A = (rs.normal(size=2 ** 13) + 1j * rs.normal(size=2 ** 13))
-    B = (rs.normal(size=2 ** 12) + 1j * rs.normal(size=2 ** 12))
-    Cc = (rs.normal(size=2 ** 14) + 1j * rs.normal(size=2 ** 14))
+def _gemm_network(rs, permuted, mb=7, kb=5, nb=6):
+    b = [0]
+    m = list(range(1, 1 + mb))
+    k = list(range(1 + mb, 1 + mb + kb))
+    nn = list(range(1 + mb + kb, 1 + mb + kb + nb))
+    ra, rb, rc = 1 + mb + kb, 1 + kb + nb, 1 + mb + nb
+    A = (rs.normal(size=2 ** ra) + 1j * rs.normal(size=2 ** ra))
+    B = (rs.normal(size=2 ** rb) + 1j * rs.normal(size=2 ** rb))
+    Cc = (rs.normal(size=2 ** rc) + 1j * rs.normal(size=2 ** rc))
     if permuted:
         inds = [k[::-1] + m + b, nn + b + k, m[::-1] + nn + b]
     else:
@@ -146,26 +150,30 @@ def _gemm_network(rs, permuted):
     return (A, B, Cc), inds
 
 
+@pytest.mark.parametrize("shape", [(7, 5, 6), (6, 7, 5)])
 @pytest.mark.parametrize("c128", [False, True])
 @pytest.mark.parametrize("permuted", [False, True])
-def test_dense_step_on_mfma_gemm_path(permuted, c128):
-    """A dense step on the MFMA complex GEMM (FP32 for complex64, FP64 for complex128)."""
+def test_dense_step_on_mfma_gemm_path(permuted, c128, shape):
+    """A dense step on the MFMA complex GEMM (FP32 for complex64, FP64 for complex128). Shape
+    = (bits of M, K, N) with a batch of 2: M = 128, N = 64 runs the FP32 product's 128 x 128
+    tile, M = 64, N = 32 its 64 x 64 tile."""
     from paper_2301_05451_amd import lib
 
+    mb, kb, nb = shape
     rs = np.random.default_rng(3)
-    (A, B, Cc), inds = _gemm_network(rs, permuted)
+    (A, B, Cc), inds = _gemm_network(rs, permuted, mb, kb, nb)
     plan = lib.TnPlan(inds, [(0, 1), (2, 3)], c128=c128)
     assert plan.info["gemm_steps"] == 1
     cdt = torch.complex128 if c128 else torch.complex64
     tol = 1e-12 if c128 else 1e-5
     leaves = torch.tensor(np.concatenate([A, B, Cc]), dtype=cdt, device="cuda")
     v = lib.tn_contract(plan, leaves).cpu().numpy()[0]
-    At, Bt, Ct = A.reshape((2,) * 13), B.reshape((2,) * 12), Cc.reshape((2,) * 14)
+    At, Bt, Ct = (t.reshape((2,) * len(i)) for t, i in zip((A, B, Cc), inds))
     want = np.einsum(At, inds[0], Bt, inds[1], Ct, inds[2], [])
     assert abs(v - want) / abs(want) <= tol
     env = lib.tn_backward(plan, leaves, torch.ones(1, dtype=cdt, device="cuda")).cpu().numpy()
     envA = np.einsum(Bt, inds[1], Ct, inds[2], inds[0]).reshape(-1)
-    assert np.abs(env[: 2 ** 13] - envA).max() / np.abs(envA).max() <= tol
+    assert np.abs(env[: A.size] - envA).max() / np.abs(envA).max() <= tol
 
 
 def test_plan_validation():
