@@ -831,13 +831,13 @@ __global__ void __launch_bounds__(256)
 // columns), each wave 64 x 64 as 4 x 4 MFMA blocks: four times the matrix-core work per
 // barrier and half the L2 reads of the 64 x 64 tile. Requires M % 128 == 0, N % 64 == 0,
 // K % 8 == 0 (the host takes the 64 x 64 kernel otherwise).
-constexpr int kGemm2BM = 128, kGemm2BN = 128;
+constexpr int kGemm2BM = 128, kGemm2BN = 128, kGemm2BK = 32;
 
 __global__ void __launch_bounds__(256)
     tn_cgemm_mfma128_kernel(const float2* __restrict__ A, int64_t as, const float2* __restrict__ B, int64_t bs,
                             float2* __restrict__ Cm, int64_t cs, int M, int N, int K) {
-  __shared__ float sA[kGemmBK][kGemm2BM + 4];   // [k][m]
-  __shared__ float sB[kGemmBK][kGemm2BN + 4];   // [k][n]
+  __shared__ float sA[kGemm2BK][kGemm2BM + 4];   // [k][m]
+  __shared__ float sB[kGemm2BK][kGemm2BN + 4];   // [k][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int m0 = blockIdx.y * kGemm2BM;
@@ -851,24 +851,24 @@ __global__ void __launch_bounds__(256)
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += kGemmBK / 2) {  // complex k
-    // A tile: 128 rows x 8 complex = 128 x 16 real; a thread loads 4 complex of one row
+  for (int k0 = 0; k0 < K; k0 += kGemm2BK / 2) {  // complex k
+    // A tile: 128 rows x 16 complex = 128 x 32 real; a thread loads 8 complex of one row
     {
-      const int r = tid >> 1, kk = (tid & 1) * 4;
+      const int r = tid >> 1, kk = (tid & 1) * 8;
       const float2* src = a + (int64_t)(m0 + r) * K + k0 + kk;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const float2 v = src[q];
         sA[2 * (kk + q) + 0][r] = v.x;
         sA[2 * (kk + q) + 1][r] = v.y;
       }
     }
-    // B tile: 8 complex rows x 64 complex cols -> 16 x 128 real; a thread loads 2 complex
+    // B tile: 16 complex rows x 64 complex cols -> 32 x 128 real; a thread loads 4 complex
     {
-      const int kr = tid >> 5, cc = (tid & 31) * 2;
+      const int kr = tid >> 4, cc = (tid & 15) * 4;
       const float2* src = b + (int64_t)(k0 + kr) * N + n0c + cc;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < 4; ++q) {
         const float2 v = src[q];
         const int col = 2 * (cc + q);
         sB[2 * kr + 0][col + 0] = v.x;
@@ -879,7 +879,7 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kGemmBK; kk += 4) {
+    for (int kk = 0; kk < kGemm2BK; kk += 4) {
       const int kl = kk + (lane >> 4);
       float av[4], bv[4];
 #pragma unroll
@@ -1839,7 +1839,7 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
         for (int64_t c = 0; c < copies; ++c) {
           const dim3 grid((unsigned)(ex.N / 32), (unsigned)(ex.M / 64), (unsigned)ex.B);
           if constexpr (sizeof(T) == 4) {
-            if (ex.M % 128 == 0 && ex.N % 64 == 0)  // the large tile
+            if (ex.M % 128 == 0 && ex.N % 64 == 0 && ex.K % 16 == 0)  // the large tile
               hipLaunchKernelGGL(tn_cgemm_mfma128_kernel, dim3((unsigned)(ex.N / 64), (unsigned)(ex.M / 128),
                                  (unsigned)ex.B), dim3(256), 0, R.st, (const float2*)(xa + xas * c), ex.M * ex.K,
                                  (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c), ex.M * ex.N,
