@@ -974,6 +974,83 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// The FP64 product with the large tile: 128 x 128 real per work-group, each wave 64 x 64 as
+// 4 x 4 MFMA 16x16x4 FP64 blocks, 16 real k per barrier. Requires M % 128 == 0, N % 64 == 0,
+// K % 8 == 0 (the host takes the 64 x 64 kernel otherwise).
+__global__ void __launch_bounds__(256)
+    tn_zgemm_mfma128_kernel(const double2* __restrict__ A, int64_t as, const double2* __restrict__ B, int64_t bs,
+                            double2* __restrict__ Cm, int64_t cs, int M, int N, int K) {
+  __shared__ double sA[kGemmBK][kGemm2BM + 2];   // [k][m]
+  __shared__ double sB[kGemmBK][kGemm2BN + 2];   // [k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = blockIdx.y * kGemm2BM;
+  const int n0c = blockIdx.x * (kGemm2BN / 2);  // complex column
+  const double2* a = A + as * blockIdx.z;
+  const double2* b = B + bs * blockIdx.z;
+  double2* c = Cm + cs * blockIdx.z;
+  typedef double double4v __attribute__((ext_vector_type(4)));
+  double4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += kGemmBK / 2) {  // complex k
+    // A tile: 128 rows x 8 complex = 128 x 16 real; a thread loads 4 complex of one row
+    {
+      const int r = tid >> 1, kk = (tid & 1) * 4;
+      const double2* src = a + (int64_t)(m0 + r) * K + k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = src[q];
+        sA[2 * (kk + q) + 0][r] = v.x;
+        sA[2 * (kk + q) + 1][r] = v.y;
+      }
+    }
+    // B tile: 8 complex rows x 64 complex cols -> 16 x 128 real; a thread loads 2 complex
+    {
+      const int kr = tid >> 5, cc = (tid & 31) * 2;
+      const double2* src = b + (int64_t)(k0 + kr) * N + n0c + cc;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double2 v = src[q];
+        const int col = 2 * (cc + q);
+        sB[2 * kr + 0][col + 0] = v.x;
+        sB[2 * kr + 0][col + 1] = v.y;
+        sB[2 * kr + 1][col + 0] = -v.y;
+        sB[2 * kr + 1][col + 1] = v.x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmBK; kk += 4) {
+      const int kl = kk + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sA[kl][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sB[kl][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of the FP64 16x16x4: lane l, register r -> row l/16 + 4 r, column l % 16
+  double* cf = reinterpret_cast<double*>(c);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + (lane >> 4) + 4 * r;
+        const int col = 2 * n0c + wn + 16 * j + (lane & 15);
+        cf[(int64_t)row * (2 * N) + col] = acc[i][j][r];
+      }
+}
+
 // Sliced leaf restriction: out[g][j] = leaf[j with the sliced bits of slice s0+g inserted].
 template <typename T>
 __global__ void tn_slice_gather_kernel(const typename Cx<T>::type* __restrict__ leaf, typename Cx<T>::type* __restrict__ out,
@@ -1848,10 +1925,17 @@ static tq_status tn_fwd_wide(TnRun<T>& R, const tq_tn_plan::Seg& sg) {
               hipLaunchKernelGGL(tn_cgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const float2*)(xa + xas * c),
                                  ex.M * ex.K, (const float2*)(ya + yas * c), ex.K * ex.N, (float2*)(z + zs * c),
                                  ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
-          } else
-            hipLaunchKernelGGL(tn_zgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const double2*)(xa + xas * c),
-                               ex.M * ex.K, (const double2*)(ya + yas * c), ex.K * ex.N, (double2*)(z + zs * c),
-                               ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
+          } else {
+            if (ex.M % 128 == 0 && ex.N % 64 == 0)  // the large tile
+              hipLaunchKernelGGL(tn_zgemm_mfma128_kernel, dim3((unsigned)(ex.N / 64), (unsigned)(ex.M / 128),
+                                 (unsigned)ex.B), dim3(256), 0, R.st, (const double2*)(xa + xas * c), ex.M * ex.K,
+                                 (const double2*)(ya + yas * c), ex.K * ex.N, (double2*)(z + zs * c), ex.M * ex.N,
+                                 (int)ex.M, (int)ex.N, (int)ex.K);
+            else
+              hipLaunchKernelGGL(tn_zgemm_mfma_kernel, grid, dim3(256), 0, R.st, (const double2*)(xa + xas * c),
+                                 ex.M * ex.K, (const double2*)(ya + yas * c), ex.K * ex.N, (double2*)(z + zs * c),
+                                 ex.M * ex.N, (int)ex.M, (int)ex.N, (int)ex.K);
+          }
         }
         TQ_HIP(hipGetLastError());
         return TQ_OK;
