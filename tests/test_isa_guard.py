@@ -61,6 +61,7 @@ def test_no_misaligned_scalar_loads(src, device_asm):
 NO_SCRATCH = [
     ("sv_kernels.hip", r"_ZN2tq15sv_stage_kernelI[fd]Li[1-4]E"),
     ("sv_kernels.hip", r"_ZN2tq19sv_stage_kernel_t12I[fd]Li[1-4]E"),
+    ("sv_kernels.hip", r"_ZN2tq(15sv_stage_kernel|19sv_stage_kernel_t12|21sv_batch_stage_kernel)IfLi5E"),
     ("sv_kernels.hip", r"_ZN2tq21sv_batch_stage_kernelI[fd]Li[1-4]E"),
     ("sv_adjoint.hip", r"_ZN2tq16adj_stage_kernelIfLi[1-4]E"),
     ("sv_adjoint.hip", r"_ZN2tq16adj_stage_kernelIdLi[1-3]E"),

@@ -84,7 +84,7 @@ def test_run_from_basis_equals_init_then_apply(name, mode, tile):
         lib.sv_run(got, params, spec, basis=1 << 9, mode=mode, tile_bits=tile)  # outside the 9-qubit circuit
 
 
-@pytest.mark.parametrize("tile", [(6, 2, 2), (7, 3, 3), (8, 4, 4), (10, 4, 5), (10, 5, 3), (12, 4, 5), (13, 4, 5)])
+@pytest.mark.parametrize("tile", [(6, 2, 2), (7, 3, 3), (8, 4, 4), (10, 4, 5), (10, 5, 3), (12, 4, 5), (13, 4, 5), (14, 5, 4)])
 def test_fused_tile_shapes_ragged(tile):
     t, R, cb = tile
     rng = np.random.default_rng(10 + t * 7 + R)
