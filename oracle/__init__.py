@@ -14,5 +14,7 @@ Modules:
 * :mod:`oracle.tn`   -- doubled (ket + bra) tensor network of a circuit expectation
   value, pairwise einsum contraction with and without slicing, QAOA light cones.
 * :mod:`oracle.mlp`  -- float64 MLP forward, manual backward and Adam (parity unpinned
-  by the paper; pinned by finite differences and Adam's closed-form first step).
+  by the paper; pinned by finite differences, Adam's closed-form first step and forward
+  invariants: odd symmetry, the small-weight linear limit, biases as weights on a constant
+  unit, an affine output layer, independent rows).
 """

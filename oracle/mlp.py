@@ -2,8 +2,11 @@
 
 The paper has no learned component: this is the reference for the runtime cost model
 that ranks contraction trees. PARITY UNPINNED by the paper. Pinned instead by central
-finite differences of the loss (backward) and by Adam's closed-form first step
-(bias-corrected, the first update is lr * g / (|g| + eps) elementwise).
+finite differences of the loss (backward), by Adam's closed-form first step
+(bias-corrected, the first update is lr * g / (|g| + eps) elementwise), and by properties of
+the forward: with zero biases the network is odd; for small weights it tends to the plain
+product of the weight matrices; a bias equals a weight on a constant unit; the output layer
+is affine; each sample's output depends on its own row only.
 
 Network: x -> tanh(W1 x + b1) -> tanh(W2 h1 + b2) -> W3 h2 + b3 (scalar output).
 Loss: mean squared error over the batch, L = mean_b (yhat_b - y_b)^2.
