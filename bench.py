@@ -437,8 +437,7 @@ def bench_tn(steps, configs=("p3", "p4", "p4_sliced20"), batch_only=False):
         batch = tn.TNBatch(progs)
 
         def run_batch():
-            batch.values(pars)
-            batch.grads(pars)
+            batch.value_and_grads(pars)
 
         ms1 = _timed(run_single, 1, 1) if not batch_only else float("nan")
         ms = _timed(run_batch, max(2, steps // 2), 1)

@@ -654,9 +654,11 @@ class TnPlan:
         seg = (ct.c_int64 * 4)()
         check(_lib.tq_tn_plan_segments(h, seg))
         self.info.update(zip(("fwd_segments", "fwd_fused", "bwd_segments", "bwd_fused"), [int(v) for v in seg]))
+        # a plan never changes: its workspace sizes are read once
+        self._ws_bytes = (int(_lib.tq_tn_workspace(h, 0)), int(_lib.tq_tn_workspace(h, 1)))
 
     def workspace_bytes(self, backward=False):
-        return int(_lib.tq_tn_workspace(self.h, 1 if backward else 0))
+        return self._ws_bytes[1 if backward else 0]
 
     @property
     def ctx_h(self):

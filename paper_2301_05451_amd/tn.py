@@ -784,18 +784,35 @@ class TNBatch:
         leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
         return lib.tn_contract_batch(self.plans, leaves)
 
+    def _unit_grad_outs(self, leaves):
+        """Upstream values of all ones, one shared read-only tensor per output size and dtype."""
+        import torch
+
+        cache = self.__dict__.setdefault("_ones", {})
+        outs = []
+        for p, L in zip(self.programs, leaves):
+            key = (1 << p.plan.n_out, L.dtype, L.device)
+            if key not in cache:
+                cache[key] = torch.ones(key[0], dtype=L.dtype, device=L.device)
+            outs.append(cache[key])
+        return outs
+
     def grads(self, params_list, grad_outs=None):
         """d Re(T_k) / d params_k (times grad_outs[k]) for every network k."""
-        import torch
+        return self.value_and_grads(params_list, grad_outs, values=False)[1]
+
+    def value_and_grads(self, params_list, grad_outs=None, values=True):
+        """Values and d Re(T_k) / d params_k of every network from one build of the leaves:
+        the batched forward, then the batched reverse pass on the same leaves."""
         from . import lib
 
         leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
         if grad_outs is None:
-            grad_outs = [torch.ones(1 << p.plan.n_out, dtype=L.dtype, device=L.device)
-                         for p, L in zip(self.programs, leaves)]
+            grad_outs = self._unit_grad_outs(leaves)
+        vals = lib.tn_contract_batch(self.plans, leaves) if values else None
         envs = lib.tn_backward_batch(self.plans, leaves, grad_outs)
-        return [lib.tn_param_grad(p.plan, p.net.gates, p.specs, q, e)
-                for p, q, e in zip(self.programs, params_list, envs)]
+        return vals, [lib.tn_param_grad(p.plan, p.net.gates, p.specs, q, e)
+                      for p, q, e in zip(self.programs, params_list, envs)]
 
 
 def tn_expval(program: TNProgram, params):

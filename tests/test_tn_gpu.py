@@ -269,6 +269,11 @@ def test_batched_networks_match_single_calls_and_oracle(c128):
     batch = tn.TNBatch(progs)
     vals = [v.cpu().numpy() for v in batch.values(pars)]
     grads = [g.cpu().numpy() for g in batch.grads(pars)]
+    for rep in range(2):  # one leaf build for both passes, the shared unit upstream reused
+        v2, g2 = batch.value_and_grads(pars)
+        for k in range(len(progs)):
+            assert np.array_equal(v2[k].cpu().numpy(), vals[k]), (rep, k)
+            assert np.array_equal(g2[k].cpu().numpy(), grads[k]), (rep, k)
     tol = 1e-12 if c128 else 1e-5
     for k, (pg, pt) in enumerate(zip(progs, pars)):
         assert np.abs(vals[k] - pg.value(pt).cpu().numpy()).max() <= tol, k
