@@ -470,6 +470,22 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
                            const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
                            const void* d_grad_leaves, void* d_grad_params, void* stream);
 
+/* The two calls above for n networks at once, each in one launch (the same results, bit for
+ * bit, as n single calls). Arrays of length n hold each network's arguments as the single
+ * call takes them (host arrays: gates, leaves, const_vals; device buffers: params, leaves,
+ * grad_leaves, grad_params). Every plan of one call must have the same dtype. An error names
+ * the first network whose arguments fail the single call's checks; nothing is launched then.
+ * The upload of the network table is stream-ordered, like tq_tn_contract_batch's. */
+tq_status tq_tn_build_leaves_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                                   const tq_gate* const* gates, const int32_t* n_gates,
+                                   const tq_tn_leaf* const* leaves, const double* const* const_vals,
+                                   const int32_t* n_const, const void* const* d_params, void* const* d_leaves,
+                                   void* stream);
+tq_status tq_tn_param_grad_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                                 const tq_gate* const* gates, const int32_t* n_gates, const tq_tn_leaf* const* leaves,
+                                 const void* const* d_params, const int32_t* n_params,
+                                 const void* const* d_grad_leaves, void* const* d_grad_params, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Cost-model MLP (ranks contraction trees by predicted runtime; Sec. 3.2.2 ranks them by
  * FLOPs, and Sec. 6.6 notes that small pairwise steps make runtime and FLOPs disagree).

@@ -1117,12 +1117,12 @@ struct DevLeaf {
   int32_t flip, _pad;  // element e holds the kind's entry e ^ flip
 };
 
+// Leaf li of one network (one thread per leaf).
 template <typename T>
-__global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leaves, const tq_gate* __restrict__ gates,
-                                     const double* __restrict__ cv, const T* __restrict__ params,
-                                     typename Cx<T>::type* __restrict__ out) {
-  const int li = blockIdx.x * blockDim.x + threadIdx.x;
-  if (li >= n_leaves) return;
+__device__ __forceinline__ void tn_leaf_build_one(const DevLeaf* __restrict__ lv, int li,
+                                                  const tq_gate* __restrict__ gates, const double* __restrict__ cv,
+                                                  const T* __restrict__ params,
+                                                  typename Cx<T>::type* __restrict__ out) {
   const DevLeaf L = lv[li];
   typename Cx<T>::type* o = out + L.off;
   const int f = L.flip;  // entry i of the kind's tensor goes to element i ^ f
@@ -1160,6 +1160,34 @@ __global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leave
   }
 }
 
+template <typename T>
+__global__ void tn_leaf_build_kernel(const DevLeaf* __restrict__ lv, int n_leaves, const tq_gate* __restrict__ gates,
+                                     const double* __restrict__ cv, const T* __restrict__ params,
+                                     typename Cx<T>::type* __restrict__ out) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li < n_leaves) tn_leaf_build_one<T>(lv, li, gates, cv, params, out);
+}
+
+// The leaves of many networks in one launch: network blockIdx.y, its leaves over grid x
+// (blocks past a network's leaf count do nothing).
+struct DevLeafItem {
+  const DevLeaf* lv;
+  const tq_gate* gates;
+  const double* cv;
+  const void* params;
+  void* out;
+  int32_t n_leaves, pad;
+};
+static_assert(sizeof(DevLeafItem) == 48, "DevLeafItem layout");
+
+template <typename T>
+__global__ void tn_leaf_build_multi_kernel(const DevLeafItem* __restrict__ items) {
+  const DevLeafItem it = items[blockIdx.y];
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li < it.n_leaves)
+    tn_leaf_build_one<T>(it.lv, li, it.gates, it.cv, (const T*)it.params, (typename Cx<T>::type*)it.out);
+}
+
 // d(leaf)/d(angle j) for the gate leaf kinds (conjugated for bra copies): the entries of
 // dU/da_j in the leaf's own layout (2x2 [out, in]; diagonal over the wire(s)).
 __device__ inline int leaf_derivative(const DevLeaf& L, const tq_gate& g, const double* a, int j, dcx (&d)[16]) {
@@ -1178,12 +1206,11 @@ __device__ inline int leaf_derivative(const DevLeaf& L, const tq_gate& g, const 
 // QAOA angle has one entry per gate copy), then a fixed-order tree over the group.
 constexpr int kPgThreads = 256;
 template <typename T>
-__global__ void __launch_bounds__(kPgThreads)
-    tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
-                         const T* __restrict__ params, const int32_t* __restrict__ pptr,
-                         const int32_t* __restrict__ pent, const typename Cx<T>::type* __restrict__ env,
-                         int n_params, T* __restrict__ grad) {
-  const int p = blockIdx.x;
+__device__ __forceinline__ void tn_param_grad_one(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
+                                                  const T* __restrict__ params, const int32_t* __restrict__ pptr,
+                                                  const int32_t* __restrict__ pent,
+                                                  const typename Cx<T>::type* __restrict__ env, int p,
+                                                  T* __restrict__ grad) {
   double acc = 0.0;
   for (int e = pptr[p] + threadIdx.x; e < pptr[p + 1]; e += kPgThreads) {
     const int li = pent[2 * e], j = pent[2 * e + 1];
@@ -1203,6 +1230,38 @@ __global__ void __launch_bounds__(kPgThreads)
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) grad[p] = (T)((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPgThreads)
+    tn_param_grad_kernel(const DevLeaf* __restrict__ lv, const tq_gate* __restrict__ gates,
+                         const T* __restrict__ params, const int32_t* __restrict__ pptr,
+                         const int32_t* __restrict__ pent, const typename Cx<T>::type* __restrict__ env,
+                         int n_params, T* __restrict__ grad) {
+  (void)n_params;
+  tn_param_grad_one<T>(lv, gates, params, pptr, pent, env, (int)blockIdx.x, grad);
+}
+
+// The parameter gradients of many networks in one launch: network blockIdx.y, parameter
+// blockIdx.x (groups past a network's parameter count return together, before any barrier).
+struct DevPgItem {
+  const DevLeaf* lv;
+  const tq_gate* gates;
+  const void* params;
+  const int32_t* pptr;
+  const int32_t* pent;
+  const void* env;
+  void* grad;
+  int32_t n_params, pad;
+};
+static_assert(sizeof(DevPgItem) == 64, "DevPgItem layout");
+
+template <typename T>
+__global__ void __launch_bounds__(kPgThreads) tn_param_grad_multi_kernel(const DevPgItem* __restrict__ items) {
+  const DevPgItem it = items[blockIdx.y];
+  if ((int)blockIdx.x >= it.n_params) return;
+  tn_param_grad_one<T>(it.lv, it.gates, (const T*)it.params, it.pptr, it.pent,
+                       (const typename Cx<T>::type*)it.env, (int)blockIdx.x, (T*)it.grad);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2058,6 +2117,62 @@ static tq_status leaf_table(tq_ctx* ctx, const tq_tn_plan* p, const tq_gate* gat
   return TQ_OK;
 }
 
+// Checks one network's leaf-build arguments and fills its launch record (the device tables
+// come from the context's content-keyed cache).
+static tq_status leaf_build_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                                 const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const,
+                                 const void* d_params, void* d_leaves, DevLeafItem& it) {
+  if (!plan || !leaves || !d_leaves) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
+  if (n_gates > 0 && (!gates || !d_params)) return fail(TQ_EINVAL, "null gates or params");
+  if (n_const > 0 && !const_vals) return fail(TQ_EINVAL, "null constant values");
+  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, 0x7fffffff));
+  std::vector<DevLeaf> dl;
+  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, n_const, dl));
+  void *dlv, *dg, *dc;
+  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
+  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
+  TQ_TRY(cached_table(ctx, const_vals, (size_t)n_const * 2 * sizeof(double), &dc));
+  it = DevLeafItem{(const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)dc, d_params, d_leaves, plan->n_leaves, 0};
+  return TQ_OK;
+}
+
+// The same for one network's parameter gradient: the parameter -> (leaf, angle) lists, in
+// leaf order.
+static tq_status param_grad_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
+                                 const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
+                                 const void* d_grad_leaves, void* d_grad_params, DevPgItem& it) {
+  if (!plan || !leaves || !d_grad_leaves || !d_grad_params) return fail(TQ_EINVAL, "null argument");
+  TQ_TRY(runnable(plan));
+  if (n_params < 0) return fail(TQ_EINVAL, "negative n_params");
+  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, n_params));
+  std::vector<DevLeaf> dl;
+  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, 1 << 30, dl));
+  std::vector<std::vector<std::pair<int, int>>> by(n_params);
+  for (int l = 0; l < plan->n_leaves; ++l) {
+    if (leaves[l].kind == 0) continue;
+    const tq_gate& g = gates[leaves[l].gate];
+    for (int j = 0; j < gate_n_angles(g.op); ++j)
+      if (g.pidx[j] >= 0) by[g.pidx[j]].push_back({l, j});
+  }
+  std::vector<int32_t> ptr(1, 0), ent;
+  for (int q = 0; q < n_params; ++q) {
+    for (auto& e : by[q]) {
+      ent.push_back(e.first);
+      ent.push_back(e.second);
+    }
+    ptr.push_back((int32_t)(ent.size() / 2));
+  }
+  void *dlv, *dg, *dp, *de;
+  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
+  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
+  TQ_TRY(cached_table(ctx, ptr.data(), ptr.size() * sizeof(int32_t), &dp));
+  TQ_TRY(cached_table(ctx, ent.data(), std::max<size_t>(ent.size(), 1) * sizeof(int32_t), &de));
+  it = DevPgItem{(const DevLeaf*)dlv, (const tq_gate*)dg, d_params, (const int32_t*)dp, (const int32_t*)de,
+                 d_grad_leaves, d_grad_params, n_params, 0};
+  return TQ_OK;
+}
+
 }  // namespace tq
 
 extern "C" {
@@ -2382,26 +2497,16 @@ tq_status tq_tn_backward_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* 
 tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
                              const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const, const void* d_params,
                              void* d_leaves, void* stream) {
-  if (!ctx || !plan || !leaves || !d_leaves) return fail(TQ_EINVAL, "null argument");
-  TQ_TRY(runnable(plan));
-  if (n_gates > 0 && (!gates || !d_params)) return fail(TQ_EINVAL, "null gates or params");
-  if (n_const > 0 && !const_vals) return fail(TQ_EINVAL, "null constant values");
-  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, 0x7fffffff));
-  std::vector<DevLeaf> dl;
-  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, n_const, dl));
-  void *dlv, *dg, *dc;
-  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
-  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
-  TQ_TRY(cached_table(ctx, const_vals, (size_t)n_const * 2 * sizeof(double), &dc));
-  const int nl = plan->n_leaves;
+  if (!ctx) return fail(TQ_EINVAL, "null argument");
+  DevLeafItem it{};
+  TQ_TRY(leaf_build_item(ctx, plan, gates, n_gates, leaves, const_vals, n_const, d_params, d_leaves, it));
+  const int nl = it.n_leaves;
   if (plan->dtype == TQ_C64)
     hipLaunchKernelGGL(tn_leaf_build_kernel<float>, dim3((nl + 127) / 128), dim3(128), 0, (hipStream_t)stream,
-                       (const DevLeaf*)dlv, nl, (const tq_gate*)dg, (const double*)dc, (const float*)d_params,
-                       (float2*)d_leaves);
+                       it.lv, nl, it.gates, it.cv, (const float*)d_params, (float2*)d_leaves);
   else
     hipLaunchKernelGGL(tn_leaf_build_kernel<double>, dim3((nl + 127) / 128), dim3(128), 0, (hipStream_t)stream,
-                       (const DevLeaf*)dlv, nl, (const tq_gate*)dg, (const double*)dc, (const double*)d_params,
-                       (double2*)d_leaves);
+                       it.lv, nl, it.gates, it.cv, (const double*)d_params, (double2*)d_leaves);
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
@@ -2409,42 +2514,91 @@ tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate*
 tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
                            const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
                            const void* d_grad_leaves, void* d_grad_params, void* stream) {
-  if (!ctx || !plan || !leaves || !d_grad_leaves || !d_grad_params) return fail(TQ_EINVAL, "null argument");
-  TQ_TRY(runnable(plan));
-  if (n_params < 0) return fail(TQ_EINVAL, "negative n_params");
-  TQ_TRY(validate_gates(gates, n_gates, 1 << 30, n_params));
-  std::vector<DevLeaf> dl;
-  TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, 1 << 30, dl));
-  // parameter -> (leaf, angle) entries, in leaf order
-  std::vector<std::vector<std::pair<int, int>>> by(n_params);
-  for (int l = 0; l < plan->n_leaves; ++l) {
-    if (leaves[l].kind == 0) continue;
-    const tq_gate& g = gates[leaves[l].gate];
-    for (int j = 0; j < gate_n_angles(g.op); ++j)
-      if (g.pidx[j] >= 0) by[g.pidx[j]].push_back({l, j});
-  }
-  std::vector<int32_t> ptr(1, 0), ent;
-  for (int q = 0; q < n_params; ++q) {
-    for (auto& e : by[q]) {
-      ent.push_back(e.first);
-      ent.push_back(e.second);
-    }
-    ptr.push_back((int32_t)(ent.size() / 2));
-  }
-  void *dlv, *dg, *dp, *de;
-  TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
-  TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
-  TQ_TRY(cached_table(ctx, ptr.data(), ptr.size() * sizeof(int32_t), &dp));
-  TQ_TRY(cached_table(ctx, ent.data(), std::max<size_t>(ent.size(), 1) * sizeof(int32_t), &de));
+  if (!ctx) return fail(TQ_EINVAL, "null argument");
+  DevPgItem it{};
+  TQ_TRY(param_grad_item(ctx, plan, gates, n_gates, leaves, d_params, n_params, d_grad_leaves, d_grad_params, it));
   if (n_params == 0) return TQ_OK;
   if (plan->dtype == TQ_C64)
     hipLaunchKernelGGL(tn_param_grad_kernel<float>, dim3(n_params), dim3(kPgThreads), 0, (hipStream_t)stream,
-                       (const DevLeaf*)dlv, (const tq_gate*)dg, (const float*)d_params, (const int32_t*)dp,
-                       (const int32_t*)de, (const float2*)d_grad_leaves, n_params, (float*)d_grad_params);
+                       it.lv, it.gates, (const float*)d_params, it.pptr, it.pent, (const float2*)d_grad_leaves,
+                       n_params, (float*)d_grad_params);
   else
     hipLaunchKernelGGL(tn_param_grad_kernel<double>, dim3(n_params), dim3(kPgThreads), 0, (hipStream_t)stream,
-                       (const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)d_params, (const int32_t*)dp,
-                       (const int32_t*)de, (const double2*)d_grad_leaves, n_params, (double*)d_grad_params);
+                       it.lv, it.gates, (const double*)d_params, it.pptr, it.pent, (const double2*)d_grad_leaves,
+                       n_params, (double*)d_grad_params);
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_tn_build_leaves_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                                   const tq_gate* const* gates, const int32_t* n_gates,
+                                   const tq_tn_leaf* const* leaves, const double* const* const_vals,
+                                   const int32_t* n_const, const void* const* d_params, void* const* d_leaves,
+                                   void* stream) {
+  if (!ctx || n < 0 || (n > 0 && (!plans || !gates || !n_gates || !leaves || !const_vals || !n_const || !d_params ||
+                                  !d_leaves)))
+    return fail(TQ_EINVAL, "null argument");
+  if (n == 0) return TQ_OK;
+  std::vector<DevLeafItem> items((size_t)n);
+  int blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TQ_EINVAL, "null plan for network " + std::to_string(i));
+    if (plans[i]->dtype != plans[0]->dtype)
+      return fail(TQ_EINVAL, "network " + std::to_string(i) + ": every network of a batch must have the same dtype");
+    const tq_status st = leaf_build_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], const_vals[i], n_const[i],
+                                         d_params[i], d_leaves[i], items[(size_t)i]);
+    if (st != TQ_OK) return fail(st, "network " + std::to_string(i) + ": " + tq_last_error());
+    blocks = std::max(blocks, (items[(size_t)i].n_leaves + 127) / 128);
+  }
+  if (blocks == 0) return TQ_OK;
+  void* dev;
+  TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevLeafItem), (hipStream_t)stream, &dev));
+  for (int c0 = 0; c0 < n; c0 += 65535) {
+    const int cn = std::min(65535, n - c0);
+    const DevLeafItem* di = (const DevLeafItem*)dev + c0;
+    if (plans[0]->dtype == TQ_C64)
+      hipLaunchKernelGGL(tn_leaf_build_multi_kernel<float>, dim3((unsigned)blocks, (unsigned)cn), dim3(128), 0,
+                         (hipStream_t)stream, di);
+    else
+      hipLaunchKernelGGL(tn_leaf_build_multi_kernel<double>, dim3((unsigned)blocks, (unsigned)cn), dim3(128), 0,
+                         (hipStream_t)stream, di);
+  }
+  TQ_HIP(hipGetLastError());
+  return TQ_OK;
+}
+
+tq_status tq_tn_param_grad_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
+                                 const tq_gate* const* gates, const int32_t* n_gates, const tq_tn_leaf* const* leaves,
+                                 const void* const* d_params, const int32_t* n_params,
+                                 const void* const* d_grad_leaves, void* const* d_grad_params, void* stream) {
+  if (!ctx || n < 0 || (n > 0 && (!plans || !gates || !n_gates || !leaves || !d_params || !n_params ||
+                                  !d_grad_leaves || !d_grad_params)))
+    return fail(TQ_EINVAL, "null argument");
+  if (n == 0) return TQ_OK;
+  std::vector<DevPgItem> items((size_t)n);
+  int blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TQ_EINVAL, "null plan for network " + std::to_string(i));
+    if (plans[i]->dtype != plans[0]->dtype)
+      return fail(TQ_EINVAL, "network " + std::to_string(i) + ": every network of a batch must have the same dtype");
+    const tq_status st = param_grad_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], d_params[i], n_params[i],
+                                         d_grad_leaves[i], d_grad_params[i], items[(size_t)i]);
+    if (st != TQ_OK) return fail(st, "network " + std::to_string(i) + ": " + tq_last_error());
+    blocks = std::max(blocks, n_params[i]);
+  }
+  if (blocks == 0) return TQ_OK;
+  void* dev;
+  TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevPgItem), (hipStream_t)stream, &dev));
+  for (int c0 = 0; c0 < n; c0 += 65535) {
+    const int cn = std::min(65535, n - c0);
+    const DevPgItem* di = (const DevPgItem*)dev + c0;
+    if (plans[0]->dtype == TQ_C64)
+      hipLaunchKernelGGL(tn_param_grad_multi_kernel<float>, dim3((unsigned)blocks, (unsigned)cn), dim3(kPgThreads), 0,
+                         (hipStream_t)stream, di);
+    else
+      hipLaunchKernelGGL(tn_param_grad_multi_kernel<double>, dim3((unsigned)blocks, (unsigned)cn), dim3(kPgThreads),
+                         0, (hipStream_t)stream, di);
+  }
   TQ_HIP(hipGetLastError());
   return TQ_OK;
 }

@@ -618,6 +618,10 @@ _lib.tq_tn_build_leaves.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _v
 _lib.tq_tn_build_leaves.restype = ct.c_int
 _lib.tq_tn_param_grad.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]
 _lib.tq_tn_param_grad.restype = ct.c_int
+_lib.tq_tn_build_leaves_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_tn_build_leaves_batch.restype = ct.c_int
+_lib.tq_tn_param_grad_batch.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.tq_tn_param_grad_batch.restype = ct.c_int
 
 TN_INFO_FIELDS = ("steps", "direct_steps", "gemm_steps", "slices", "slice_group", "flops", "gemm_flops",
                   "max_elems")
@@ -783,6 +787,47 @@ def tn_param_grad(plan: TnPlan, gates, leaf_specs, params, grad_leaves):
                                 params.data_ptr(), int(params.numel()), grad_leaves.contiguous().data_ptr(),
                                 out.data_ptr(), _stream()))
     return out
+
+
+def _i32s(xs):
+    return (ct.c_int32 * max(1, len(xs)))(*[int(x) for x in xs])
+
+
+def tn_build_leaves_batch(plans, gates_list, specs_list, consts_list, params_list):
+    """Packed leaf buffers of many networks in one launch (tq_tn_build_leaves_batch); every
+    plan must have the same dtype. Returns one leaf tensor per plan."""
+    import torch
+    if not plans:
+        return []
+    cdt = torch.complex128 if plans[0].c128 else torch.complex64
+    gs = [np.ascontiguousarray(g, dtype=W.GATE_DTYPE) for g in gates_list]
+    ls = [np.ascontiguousarray(x, dtype=TN_LEAF_DTYPE) for x in specs_list]
+    cv = [np.ascontiguousarray(np.asarray(c, dtype=np.complex128).view(np.float64)) for c in consts_list]
+    outs = [torch.empty(pl.leaf_elems, dtype=cdt, device=q.device) for pl, q in zip(plans, params_list)]
+    check(_lib.tq_tn_build_leaves_batch(plans[0].ctx_h, len(plans), _ptrs([pl.h.value for pl in plans]),
+                                        _ptrs([g.ctypes.data for g in gs]), _i32s([g.shape[0] for g in gs]),
+                                        _ptrs([x.ctypes.data for x in ls]), _ptrs([c.ctypes.data for c in cv]),
+                                        _i32s([c.shape[0] // 2 for c in cv]),
+                                        _ptrs([q.data_ptr() for q in params_list]),
+                                        _ptrs([o.data_ptr() for o in outs]), _stream()))
+    return outs
+
+
+def tn_param_grad_batch(plans, gates_list, specs_list, params_list, grad_leaves_list):
+    """Parameter gradients of many networks in one launch (tq_tn_param_grad_batch)."""
+    import torch
+    if not plans:
+        return []
+    gs = [np.ascontiguousarray(g, dtype=W.GATE_DTYPE) for g in gates_list]
+    ls = [np.ascontiguousarray(x, dtype=TN_LEAF_DTYPE) for x in specs_list]
+    env = [e.contiguous() for e in grad_leaves_list]
+    outs = [torch.empty(q.numel(), dtype=q.dtype, device=q.device) for q in params_list]
+    check(_lib.tq_tn_param_grad_batch(plans[0].ctx_h, len(plans), _ptrs([pl.h.value for pl in plans]),
+                                      _ptrs([g.ctypes.data for g in gs]), _i32s([g.shape[0] for g in gs]),
+                                      _ptrs([x.ctypes.data for x in ls]), _ptrs([q.data_ptr() for q in params_list]),
+                                      _i32s([q.numel() for q in params_list]), _ptrs([e.data_ptr() for e in env]),
+                                      _ptrs([o.data_ptr() for o in outs]), _stream()))
+    return outs
 
 
 # ---- cost-model MLP (tq_mlp_*) ---------------------------------------------------------------

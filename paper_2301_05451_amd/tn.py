@@ -781,8 +781,7 @@ class TNBatch:
 
     def values(self, params_list):
         from . import lib
-        leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
-        return lib.tn_contract_batch(self.plans, leaves)
+        return lib.tn_contract_batch(self.plans, self._leaves(params_list))
 
     def _unit_grad_outs(self, leaves):
         """Upstream values of all ones, one shared read-only tensor per output size and dtype."""
@@ -801,18 +800,34 @@ class TNBatch:
         """d Re(T_k) / d params_k (times grad_outs[k]) for every network k."""
         return self.value_and_grads(params_list, grad_outs, values=False)[1]
 
-    def value_and_grads(self, params_list, grad_outs=None, values=True):
-        """Values and d Re(T_k) / d params_k of every network from one build of the leaves:
-        the batched forward, then the batched reverse pass on the same leaves."""
+    def _same_dtype(self):
+        return len({p.plan.c128 for p in self.programs}) <= 1
+
+    def _leaves(self, params_list):
         from . import lib
 
-        leaves = [p.leaves(q) for p, q in zip(self.programs, params_list)]
+        if not self._same_dtype():
+            return [p.leaves(q) for p, q in zip(self.programs, params_list)]
+        P = self.programs
+        return lib.tn_build_leaves_batch(self.plans, [p.net.gates for p in P], [p.specs for p in P],
+                                         [p.consts for p in P], params_list)
+
+    def value_and_grads(self, params_list, grad_outs=None, values=True):
+        """Values and d Re(T_k) / d params_k of every network from one build of the leaves:
+        the leaves of all networks in one launch, the batched forward, the batched reverse
+        pass on the same leaves, and the chain rule of all networks in one launch."""
+        from . import lib
+
+        leaves = self._leaves(params_list)
         if grad_outs is None:
             grad_outs = self._unit_grad_outs(leaves)
         vals = lib.tn_contract_batch(self.plans, leaves) if values else None
         envs = lib.tn_backward_batch(self.plans, leaves, grad_outs)
-        return vals, [lib.tn_param_grad(p.plan, p.net.gates, p.specs, q, e)
-                      for p, q, e in zip(self.programs, params_list, envs)]
+        P = self.programs
+        if not self._same_dtype():
+            return vals, [lib.tn_param_grad(p.plan, p.net.gates, p.specs, q, e) for p, q, e in zip(P, params_list, envs)]
+        return vals, lib.tn_param_grad_batch(self.plans, [p.net.gates for p in P], [p.specs for p in P], params_list,
+                                             envs)
 
 
 def tn_expval(program: TNProgram, params):

@@ -91,3 +91,35 @@ def test_peak_probe_rejects_bad_arguments_on_the_host():
     assert lib._lib.tq_peak_probe(2, dummy, ct.c_uint64(1 << 21), 0, ct.byref(w), None) == 1       # iters < 1
     assert lib._lib.tq_peak_probe(0, None, ct.c_uint64(1 << 20), 1, ct.byref(w), None) == 1        # null buffer
     assert w.value == 0.0
+
+
+def test_batched_leaf_calls_reject_bad_arguments_on_the_host():
+    """Argument checks of tq_tn_build_leaves_batch / tq_tn_param_grad_batch run before any
+    launch: a null context or arrays, a negative count, and a plan that cannot run (planned
+    without a device) are refused, the last with the failing network named; an empty batch
+    is a no-op. The context pointer below is never dereferenced on these paths."""
+    import ctypes as ct
+
+    from paper_2301_05451_amd import lib
+    from paper_2301_05451_amd import tn
+
+    dummy = ct.c_void_p(0x1000)
+    for f, nargs in ((lib._lib.tq_tn_build_leaves_batch, 9), (lib._lib.tq_tn_param_grad_batch, 9)):
+        assert f(None, 0, *([None] * nargs)) == 1           # null context
+        assert f(dummy, -1, *([None] * nargs)) == 1         # negative count
+        assert f(dummy, 2, *([None] * nargs)) == 1          # null arrays
+        assert f(dummy, 0, *([None] * nargs)) == 0          # empty batch
+    prob = W.qaoa_maxcut(p=1)
+    net, _ = tn.qaoa_edge_network(prob, prob.edges[0])
+    tree = tn.elimination_tree(net, tn.elimination_order(net)[0])
+    p = lib.TnPlan([lf.inds for lf in net.leaves], tree.pairs, tree.sliced, net.output, host_only=True)
+    specs, consts = tn.leaf_specs(net)
+    g = np.ascontiguousarray(net.gates, dtype=W.GATE_DTYPE)
+    ls = np.ascontiguousarray(specs, dtype=lib.TN_LEAF_DTYPE)
+    cv = np.ascontiguousarray(np.asarray(consts, dtype=np.complex128).view(np.float64))
+    one = lambda x: lib._ptrs([x])  # noqa: E731
+    buf = ct.c_void_p(0x2000)
+    st = lib._lib.tq_tn_build_leaves_batch(dummy, 1, one(p.h.value), one(g.ctypes.data), lib._i32s([g.shape[0]]),
+                                           one(ls.ctypes.data), one(cv.ctypes.data), lib._i32s([cv.shape[0] // 2]),
+                                           one(buf.value), one(buf.value), None)
+    assert st != 0 and lib.last_error().startswith("network 0: ")

@@ -285,6 +285,39 @@ def test_batched_networks_match_single_calls_and_oracle(c128):
         assert abs(vals[75 + k][0] - vals[k][0]) <= 2 * tol, k
 
 
+@pytest.mark.parametrize("c128", [False, True])
+def test_batched_leaves_and_param_grads_equal_single_calls(c128):
+    """tq_tn_build_leaves_batch / tq_tn_param_grad_batch (one launch for all networks) give
+    the single calls' results bit for bit, on the 75 p = 2 light-cone networks, with random
+    leaf environments for the chain rule; a batch of mixed dtypes is refused."""
+    from paper_2301_05451_amd import lib
+
+    prob = W.qaoa_maxcut(p=2)
+    progs, pars = [], []
+    for e in prob.edges:
+        net, _ = tn.qaoa_edge_network(prob, e)
+        progs.append(tn.TNProgram(net, tn.elimination_tree(net, tn.elimination_order(net)[0]), c128=c128))
+        pars.append(_params(net, c128))
+    plans = [p.plan for p in progs]
+    gates = [p.net.gates for p in progs]
+    specs = [p.specs for p in progs]
+    Lb = lib.tn_build_leaves_batch(plans, gates, specs, [p.consts for p in progs], pars)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    rdt = torch.float64 if c128 else torch.float32
+    envs = [torch.complex(torch.randn(p.plan.leaf_elems, generator=gen, dtype=rdt),
+                          torch.randn(p.plan.leaf_elems, generator=gen, dtype=rdt)).cuda() for p in progs]
+    Gb = lib.tn_param_grad_batch(plans, gates, specs, pars, envs)
+    for k, (pg, pt) in enumerate(zip(progs, pars)):
+        assert torch.equal(Lb[k], pg.leaves(pt)), k
+        gs = lib.tn_param_grad(pg.plan, pg.net.gates, pg.specs, pt, envs[k])
+        assert torch.equal(Gb[k], gs), k
+        assert bool(torch.isfinite(gs).all()) and float(gs.abs().max()) > 0, k
+    other = tn.TNProgram(progs[0].net, progs[0].tree, c128=not c128)
+    with pytest.raises(RuntimeError, match="same dtype"):
+        lib.tn_build_leaves_batch([plans[0], other.plan], gates[:1] * 2, specs[:1] * 2,
+                                  [progs[0].consts] * 2, [pars[0], _params(progs[0].net, not c128)])
+
+
 def _p4_graph(n=16, seed=41):
     r = np.random.default_rng(seed)
     edges = W.random_regular_graph(3, n, r)
