@@ -473,9 +473,10 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
 /* The two calls above for n networks at once, each in one launch (the same results, bit for
  * bit, as n single calls). Arrays of length n hold each network's arguments as the single
  * call takes them (host arrays: gates, leaves, const_vals; device buffers: params, leaves,
- * grad_leaves, grad_params). Every plan of one call must have the same dtype. An error names
- * the first network whose arguments fail the single call's checks; nothing is launched then.
- * The upload of the network table is stream-ordered, like tq_tn_contract_batch's. */
+ * grad_leaves, grad_params). Every plan of one call must have the same dtype. All networks
+ * are checked before anything is launched; an error names the first network whose arguments
+ * fail the single call's checks. The networks then launch in chunks of 256, each chunk's
+ * table uploaded in stream order, like tq_tn_contract_batch's. */
 tq_status tq_tn_build_leaves_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
                                    const tq_gate* const* gates, const int32_t* n_gates,
                                    const tq_tn_leaf* const* leaves, const double* const* const_vals,

@@ -2117,11 +2117,11 @@ static tq_status leaf_table(tq_ctx* ctx, const tq_tn_plan* p, const tq_gate* gat
   return TQ_OK;
 }
 
-// Checks one network's leaf-build arguments and fills its launch record (the device tables
-// come from the context's content-keyed cache).
+// Checks one network's leaf-build arguments and, when `it` is given, fills its launch record
+// (the device tables come from the context's content-keyed cache).
 static tq_status leaf_build_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
                                  const tq_tn_leaf* leaves, const double* const_vals, int32_t n_const,
-                                 const void* d_params, void* d_leaves, DevLeafItem& it) {
+                                 const void* d_params, void* d_leaves, DevLeafItem* it) {
   if (!plan || !leaves || !d_leaves) return fail(TQ_EINVAL, "null argument");
   TQ_TRY(runnable(plan));
   if (n_gates > 0 && (!gates || !d_params)) return fail(TQ_EINVAL, "null gates or params");
@@ -2129,11 +2129,12 @@ static tq_status leaf_build_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_g
   TQ_TRY(validate_gates(gates, n_gates, 1 << 30, 0x7fffffff));
   std::vector<DevLeaf> dl;
   TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, n_const, dl));
+  if (!it) return TQ_OK;
   void *dlv, *dg, *dc;
   TQ_TRY(cached_table(ctx, dl.data(), dl.size() * sizeof(DevLeaf), &dlv));
   TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
   TQ_TRY(cached_table(ctx, const_vals, (size_t)n_const * 2 * sizeof(double), &dc));
-  it = DevLeafItem{(const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)dc, d_params, d_leaves, plan->n_leaves, 0};
+  *it = DevLeafItem{(const DevLeaf*)dlv, (const tq_gate*)dg, (const double*)dc, d_params, d_leaves, plan->n_leaves, 0};
   return TQ_OK;
 }
 
@@ -2141,13 +2142,14 @@ static tq_status leaf_build_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_g
 // leaf order.
 static tq_status param_grad_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* gates, int32_t n_gates,
                                  const tq_tn_leaf* leaves, const void* d_params, int32_t n_params,
-                                 const void* d_grad_leaves, void* d_grad_params, DevPgItem& it) {
+                                 const void* d_grad_leaves, void* d_grad_params, DevPgItem* it) {
   if (!plan || !leaves || !d_grad_leaves || !d_grad_params) return fail(TQ_EINVAL, "null argument");
   TQ_TRY(runnable(plan));
   if (n_params < 0) return fail(TQ_EINVAL, "negative n_params");
   TQ_TRY(validate_gates(gates, n_gates, 1 << 30, n_params));
   std::vector<DevLeaf> dl;
   TQ_TRY(leaf_table(ctx, plan, gates, n_gates, leaves, 1 << 30, dl));
+  if (!it) return TQ_OK;
   std::vector<std::vector<std::pair<int, int>>> by(n_params);
   for (int l = 0; l < plan->n_leaves; ++l) {
     if (leaves[l].kind == 0) continue;
@@ -2168,8 +2170,8 @@ static tq_status param_grad_item(tq_ctx* ctx, const tq_tn_plan* plan, const tq_g
   TQ_TRY(cached_table(ctx, gates, (size_t)n_gates * sizeof(tq_gate), &dg));
   TQ_TRY(cached_table(ctx, ptr.data(), ptr.size() * sizeof(int32_t), &dp));
   TQ_TRY(cached_table(ctx, ent.data(), std::max<size_t>(ent.size(), 1) * sizeof(int32_t), &de));
-  it = DevPgItem{(const DevLeaf*)dlv, (const tq_gate*)dg, d_params, (const int32_t*)dp, (const int32_t*)de,
-                 d_grad_leaves, d_grad_params, n_params, 0};
+  *it = DevPgItem{(const DevLeaf*)dlv, (const tq_gate*)dg, d_params, (const int32_t*)dp, (const int32_t*)de,
+                  d_grad_leaves, d_grad_params, n_params, 0};
   return TQ_OK;
 }
 
@@ -2499,7 +2501,7 @@ tq_status tq_tn_build_leaves(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate*
                              void* d_leaves, void* stream) {
   if (!ctx) return fail(TQ_EINVAL, "null argument");
   DevLeafItem it{};
-  TQ_TRY(leaf_build_item(ctx, plan, gates, n_gates, leaves, const_vals, n_const, d_params, d_leaves, it));
+  TQ_TRY(leaf_build_item(ctx, plan, gates, n_gates, leaves, const_vals, n_const, d_params, d_leaves, &it));
   const int nl = it.n_leaves;
   if (plan->dtype == TQ_C64)
     hipLaunchKernelGGL(tn_leaf_build_kernel<float>, dim3((nl + 127) / 128), dim3(128), 0, (hipStream_t)stream,
@@ -2516,7 +2518,7 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
                            const void* d_grad_leaves, void* d_grad_params, void* stream) {
   if (!ctx) return fail(TQ_EINVAL, "null argument");
   DevPgItem it{};
-  TQ_TRY(param_grad_item(ctx, plan, gates, n_gates, leaves, d_params, n_params, d_grad_leaves, d_grad_params, it));
+  TQ_TRY(param_grad_item(ctx, plan, gates, n_gates, leaves, d_params, n_params, d_grad_leaves, d_grad_params, &it));
   if (n_params == 0) return TQ_OK;
   if (plan->dtype == TQ_C64)
     hipLaunchKernelGGL(tn_param_grad_kernel<float>, dim3(n_params), dim3(kPgThreads), 0, (hipStream_t)stream,
@@ -2530,6 +2532,13 @@ tq_status tq_tn_param_grad(tq_ctx* ctx, const tq_tn_plan* plan, const tq_gate* g
   return TQ_OK;
 }
 
+// The batched leaf calls gather each network's device tables from the context's table cache
+// and launch once per chunk of networks. A chunk looks up at most 4 * kTnLeafChunk tables,
+// well under half the cache's entry bound, so the cache's least-recently-used eviction never
+// frees a table of the chunk being gathered; it synchronises the device before freeing, so
+// earlier chunks' launches have finished by then.
+constexpr int kTnLeafChunk = 256;
+
 tq_status tq_tn_build_leaves_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const* plans,
                                    const tq_gate* const* gates, const int32_t* n_gates,
                                    const tq_tn_leaf* const* leaves, const double* const* const_vals,
@@ -2538,32 +2547,35 @@ tq_status tq_tn_build_leaves_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* con
   if (!ctx || n < 0 || (n > 0 && (!plans || !gates || !n_gates || !leaves || !const_vals || !n_const || !d_params ||
                                   !d_leaves)))
     return fail(TQ_EINVAL, "null argument");
-  if (n == 0) return TQ_OK;
-  std::vector<DevLeafItem> items((size_t)n);
-  int blocks = 0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i) {  // every network is checked before anything is launched
     if (!plans[i]) return fail(TQ_EINVAL, "null plan for network " + std::to_string(i));
     if (plans[i]->dtype != plans[0]->dtype)
       return fail(TQ_EINVAL, "network " + std::to_string(i) + ": every network of a batch must have the same dtype");
     const tq_status st = leaf_build_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], const_vals[i], n_const[i],
-                                         d_params[i], d_leaves[i], items[(size_t)i]);
+                                         d_params[i], d_leaves[i], nullptr);
     if (st != TQ_OK) return fail(st, "network " + std::to_string(i) + ": " + tq_last_error());
-    blocks = std::max(blocks, (items[(size_t)i].n_leaves + 127) / 128);
   }
-  if (blocks == 0) return TQ_OK;
-  void* dev;
-  TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevLeafItem), (hipStream_t)stream, &dev));
-  for (int c0 = 0; c0 < n; c0 += 65535) {
-    const int cn = std::min(65535, n - c0);
-    const DevLeafItem* di = (const DevLeafItem*)dev + c0;
+  for (int c0 = 0; c0 < n; c0 += kTnLeafChunk) {
+    const int cn = std::min(kTnLeafChunk, n - c0);
+    std::vector<DevLeafItem> items((size_t)cn);
+    int blocks = 0;
+    for (int k = 0; k < cn; ++k) {
+      const int i = c0 + k;
+      TQ_TRY(leaf_build_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], const_vals[i], n_const[i], d_params[i],
+                             d_leaves[i], &items[(size_t)k]));
+      blocks = std::max(blocks, (items[(size_t)k].n_leaves + 127) / 128);
+    }
+    if (blocks == 0) continue;
+    void* dev;
+    TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevLeafItem), (hipStream_t)stream, &dev));
     if (plans[0]->dtype == TQ_C64)
       hipLaunchKernelGGL(tn_leaf_build_multi_kernel<float>, dim3((unsigned)blocks, (unsigned)cn), dim3(128), 0,
-                         (hipStream_t)stream, di);
+                         (hipStream_t)stream, (const DevLeafItem*)dev);
     else
       hipLaunchKernelGGL(tn_leaf_build_multi_kernel<double>, dim3((unsigned)blocks, (unsigned)cn), dim3(128), 0,
-                         (hipStream_t)stream, di);
+                         (hipStream_t)stream, (const DevLeafItem*)dev);
+    TQ_HIP(hipGetLastError());
   }
-  TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
 
@@ -2574,32 +2586,35 @@ tq_status tq_tn_param_grad_batch(tq_ctx* ctx, int32_t n, const tq_tn_plan* const
   if (!ctx || n < 0 || (n > 0 && (!plans || !gates || !n_gates || !leaves || !d_params || !n_params ||
                                   !d_grad_leaves || !d_grad_params)))
     return fail(TQ_EINVAL, "null argument");
-  if (n == 0) return TQ_OK;
-  std::vector<DevPgItem> items((size_t)n);
-  int blocks = 0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i) {  // every network is checked before anything is launched
     if (!plans[i]) return fail(TQ_EINVAL, "null plan for network " + std::to_string(i));
     if (plans[i]->dtype != plans[0]->dtype)
       return fail(TQ_EINVAL, "network " + std::to_string(i) + ": every network of a batch must have the same dtype");
     const tq_status st = param_grad_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], d_params[i], n_params[i],
-                                         d_grad_leaves[i], d_grad_params[i], items[(size_t)i]);
+                                         d_grad_leaves[i], d_grad_params[i], nullptr);
     if (st != TQ_OK) return fail(st, "network " + std::to_string(i) + ": " + tq_last_error());
-    blocks = std::max(blocks, n_params[i]);
   }
-  if (blocks == 0) return TQ_OK;
-  void* dev;
-  TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevPgItem), (hipStream_t)stream, &dev));
-  for (int c0 = 0; c0 < n; c0 += 65535) {
-    const int cn = std::min(65535, n - c0);
-    const DevPgItem* di = (const DevPgItem*)dev + c0;
+  for (int c0 = 0; c0 < n; c0 += kTnLeafChunk) {
+    const int cn = std::min(kTnLeafChunk, n - c0);
+    std::vector<DevPgItem> items((size_t)cn);
+    int blocks = 0;
+    for (int k = 0; k < cn; ++k) {
+      const int i = c0 + k;
+      TQ_TRY(param_grad_item(ctx, plans[i], gates[i], n_gates[i], leaves[i], d_params[i], n_params[i],
+                             d_grad_leaves[i], d_grad_params[i], &items[(size_t)k]));
+      blocks = std::max(blocks, n_params[i]);
+    }
+    if (blocks == 0) continue;
+    void* dev;
+    TQ_TRY(stage_upload(ctx, S_TNB, items.data(), items.size() * sizeof(DevPgItem), (hipStream_t)stream, &dev));
     if (plans[0]->dtype == TQ_C64)
       hipLaunchKernelGGL(tn_param_grad_multi_kernel<float>, dim3((unsigned)blocks, (unsigned)cn), dim3(kPgThreads), 0,
-                         (hipStream_t)stream, di);
+                         (hipStream_t)stream, (const DevPgItem*)dev);
     else
       hipLaunchKernelGGL(tn_param_grad_multi_kernel<double>, dim3((unsigned)blocks, (unsigned)cn), dim3(kPgThreads),
-                         0, (hipStream_t)stream, di);
+                         0, (hipStream_t)stream, (const DevPgItem*)dev);
+    TQ_HIP(hipGetLastError());
   }
-  TQ_HIP(hipGetLastError());
   return TQ_OK;
 }
 

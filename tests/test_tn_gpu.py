@@ -312,6 +312,11 @@ def test_batched_leaves_and_param_grads_equal_single_calls(c128):
         gs = lib.tn_param_grad(pg.plan, pg.net.gates, pg.specs, pt, envs[k])
         assert torch.equal(Gb[k], gs), k
         assert bool(torch.isfinite(gs).all()) and float(gs.abs().max()) > 0, k
+    # 300 networks: two launch chunks of the batched calls
+    L4 = lib.tn_build_leaves_batch(plans * 4, gates * 4, specs * 4, [p.consts for p in progs] * 4, pars * 4)
+    G4 = lib.tn_param_grad_batch(plans * 4, gates * 4, specs * 4, pars * 4, envs * 4)
+    for k in range(300):
+        assert torch.equal(L4[k], Lb[k % 75]) and torch.equal(G4[k], Gb[k % 75]), k
     other = tn.TNProgram(progs[0].net, progs[0].tree, c128=not c128)
     with pytest.raises(RuntimeError, match="same dtype"):
         lib.tn_build_leaves_batch([plans[0], other.plan], gates[:1] * 2, specs[:1] * 2,
