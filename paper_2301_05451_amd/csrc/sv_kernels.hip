@@ -447,8 +447,9 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
   // One circuit's stage: the tile's loads are issued at raised wave priority. A work-group
   // that starts while the CU's other groups compute would otherwise wait for issue slots
   // behind them (issue goes to the oldest wave first) and stall on its loads later, with
-  // nothing to overlap (2.5 % on the 24-qubit step). The batched kernel's short groups of
-  // many circuits ran about 10 % slower with it, so it keeps the default priority.
+  // nothing to overlap (2.5 % on the 24-qubit step; the exchanges below at priority 1 gave
+  // another 2.6 %). The batched kernel's short groups of many circuits ran about 10 % slower
+  // with raised load priority, so it keeps the default priority throughout.
   if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
   for (int j = 0; j < (1 << R); ++j) {
@@ -473,6 +474,9 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
   for (int p = (int)sw[1]; p < p_end; ++p) {
     const gword* const pw = reinterpret_cast<const gword*>(gptr(phases)) + (int64_t)p * kPhaseWords;
     if (pw[2]) {
+      // an exchange at priority 1: the group's waves reach its barriers sooner, instead of
+      // queueing for issue behind other groups' arithmetic while their partners wait
+      if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(1);
       if (!first_x) __syncthreads();
       first_x = false;
       if (act)
@@ -491,6 +495,7 @@ __device__ __forceinline__ void stage_tile(const DevStage* __restrict__ stg, con
       if (act)
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) v[j] = *reinterpret_cast<const C*>(lb + (ta ^ ra[j]));
+      if constexpr (kLoadPrio) __builtin_amdgcn_s_setprio(0);
     }
     apply_phase_ops<T, R>(v, tp, ops, (int)pw[0], (int)pw[1], M, t, tile);
   }
